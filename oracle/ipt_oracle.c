@@ -1,0 +1,992 @@
+/*
+ * Inverse Path Tracing -- FP64 CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU path is checked against.  Only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no source with the HIP library (no headers, no helpers, no tables)
+ * and the library never calls it.
+ *
+ * What it computes (paper: "Inverse Path Tracing for Joint Material and
+ * Lighting Estimation", Azinovic, Li, Kaplanyan, Niessner, CVPR 2019):
+ *   - the Monte Carlo estimate of the pixel integral (Sec. 3.1, Eq. 1) of the
+ *     measurement contribution (Sec. 3.1, Eq. 2) by unidirectional path
+ *     tracing with BRDF sampling and explicit light sampling combined by
+ *     multiple importance sampling (Appendix A.2 "Variance Reduction";
+ *     Appendix E "Implementation Details"),
+ *   - the derivative of every sampled path contribution with respect to the
+ *     emission (Sec. 3.3, Eq. 5) and material (Sec. 3.3, Eq. 6) unknowns by
+ *     the product rule, written out factor by factor with no division, so it
+ *     stays exact when an albedo or an emission is zero (the paper starts
+ *     from zero, Appendix E),
+ *   - the loss and its adjoint image (Sec. 3.2, Eq. 3; Sec. 3.3, Eq. 4) and
+ *     the Adam update (Sec. 4.5).
+ * Everything is double precision.  Uniform random numbers come from
+ * Philox4x32-10 (Salmon et al., SC'11) mapped to 24-bit uniforms, so that a
+ * float implementation can consume bit-identical uniforms.
+ *
+ * Readings of points the paper leaves open (they are listed with reasons in
+ * the design notes of the repository):
+ *   - Eq. 2 is printed without geometry terms; the standard path-space form
+ *     (Veach 1997) is used.  Geometry terms and pdfs do not depend on the
+ *     unknowns, so the structure of Eqs. 5-6 is unchanged.
+ *   - BRDF: Lambert plus a GGX microfacet lobe with separable Smith shadowing
+ *     and no Fresnel; alpha = roughness clamped to [1e-3, 1].  The paper uses
+ *     the Disney model (Sec. 4.1); the parameter set here is diffuse RGB,
+ *     specular RGB and roughness.
+ *   - Emission: constant radiance by default; the paper's cosine profile
+ *     e (w.n)_+ (Sec. 4.3) is an option.  Emitters are one-sided.
+ *   - Depth D counts scattering vertices; the ray leaving vertex D is still
+ *     traced, for its emitter hit only.
+ *   - Every pdf, MIS weight, lobe probability, Russian-roulette probability
+ *     and the light-selection distribution is evaluated at "sampling
+ *     parameters" and treated as a constant: Eqs. 5-6 differentiate only the
+ *     measurement contribution.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as    */
+/* easy as 1, 2, 3", SC 2011).                                                */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 24-bit uniform in [0,1): exactly representable in float and double. */
+static double u24(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+/* The eight uniforms of vertex k of a path.  key = (seed_lo ^ tag*golden,
+ * seed_hi); counter = (path_lo, path_hi, 2k + half, iteration).  Slot use:
+ *   k = 0 : [0],[1] pixel jitter
+ *   k >= 1: [0] light triangle, [1],[2] point on it, [3] lobe / guide lobe,
+ *           [4],[5] direction, [6] Russian roulette, [7] guide-vs-BRDF. */
+static void vertex_uniforms(uint64_t seed, uint32_t tag, uint32_t iteration,
+                            uint64_t path_id, int k, double u[8])
+{
+    uint32_t key[2] = { (uint32_t)seed ^ (tag * 0x9E3779B9u), (uint32_t)(seed >> 32) };
+    for (int half = 0; half < 2; ++half) {
+        uint32_t ctr[4] = { (uint32_t)path_id, (uint32_t)(path_id >> 32),
+                            (uint32_t)(2 * k + half), iteration };
+        uint32_t o[4];
+        orc_philox4x32_10(ctr, key, o);
+        for (int i = 0; i < 4; ++i) u[4 * half + i] = u24(o[i]);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Small vector helpers.                                                      */
+/* ------------------------------------------------------------------------- */
+typedef struct { double x, y, z; } v3;
+static v3 mk(double x, double y, double z) { v3 r = { x, y, z }; return r; }
+static v3 add(v3 a, v3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static v3 sub(v3 a, v3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static v3 scl(v3 a, double s) { return mk(a.x * s, a.y * s, a.z * s); }
+static double dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static v3 cross(v3 a, v3 b)
+{
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+static v3 nrm(v3 a) { double l = sqrt(dot(a, a)); return scl(a, 1.0 / l); }
+static double comp(v3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+
+/* ------------------------------------------------------------------------- */
+/* Scene.                                                                     */
+/* ------------------------------------------------------------------------- */
+typedef struct { double lo[3], hi[3]; int left, right, first, count; } onode;
+
+typedef struct orc_scene {
+    int64_t nv, nt;
+    int32_t ns, ne;
+    double *P;          /* nv*3 positions */
+    double *N;          /* nv*3 normals or NULL */
+    int32_t *F;         /* nt*3 */
+    int32_t *seg;       /* nt */
+    int32_t *emitter_seg; /* ne */
+    int32_t *seg_emitter; /* ns: emitter index or -1 */
+    int64_t nlt;        /* number of emitter triangles */
+    int32_t *light_tri; /* emitter triangles in ascending id order */
+    double *light_area;
+    double diag;        /* scene bounding-box diagonal */
+    /* median-split BVH over triangles */
+    onode *nodes; int64_t nnodes; int32_t *order;
+} orc_scene;
+
+static v3 vtx(const orc_scene *s, int64_t i)
+{
+    return mk(s->P[3 * i], s->P[3 * i + 1], s->P[3 * i + 2]);
+}
+
+static double cent(const orc_scene *s, int32_t t, int ax)
+{
+    double c = 0;
+    for (int j = 0; j < 3; ++j) c += s->P[3 * (int64_t)s->F[3 * (int64_t)t + j] + ax];
+    return c / 3.0;
+}
+
+static int g_sort_axis;
+static const orc_scene *g_sort_scene;
+static int cmp_cent(const void *a, const void *b)
+{
+    double ca = cent(g_sort_scene, *(const int32_t *)a, g_sort_axis);
+    double cb = cent(g_sort_scene, *(const int32_t *)b, g_sort_axis);
+    if (ca < cb) return -1;
+    if (ca > cb) return 1;
+    return (*(const int32_t *)a) - (*(const int32_t *)b);
+}
+
+/* Median split on the widest centroid axis, leaves of at most 4 triangles. */
+static int build_node(orc_scene *s, int first, int count)
+{
+    int id = (int)s->nnodes++;
+    onode *nd = &s->nodes[id];
+    for (int a = 0; a < 3; ++a) { nd->lo[a] = INFINITY; nd->hi[a] = -INFINITY; }
+    double clo[3] = { INFINITY, INFINITY, INFINITY }, chi[3] = { -INFINITY, -INFINITY, -INFINITY };
+    for (int i = first; i < first + count; ++i) {
+        int32_t t = s->order[i];
+        for (int j = 0; j < 3; ++j) {
+            int64_t vi = s->F[3 * (int64_t)t + j];
+            for (int a = 0; a < 3; ++a) {
+                double p = s->P[3 * vi + a];
+                if (p < nd->lo[a]) nd->lo[a] = p;
+                if (p > nd->hi[a]) nd->hi[a] = p;
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            double c = cent(s, t, a);
+            if (c < clo[a]) clo[a] = c;
+            if (c > chi[a]) chi[a] = c;
+        }
+    }
+    /* pad the box so the slab test can never reject a triangle that lies on it */
+    for (int a = 0; a < 3; ++a) {
+        double pad = 1e-9 * (fabs(nd->lo[a]) + fabs(nd->hi[a]) + 1.0);
+        nd->lo[a] -= pad; nd->hi[a] += pad;
+    }
+    if (count <= 4) {
+        nd->left = nd->right = -1; nd->first = first; nd->count = count;
+        return id;
+    }
+    int ax = 0;
+    for (int a = 1; a < 3; ++a) if (chi[a] - clo[a] > chi[ax] - clo[ax]) ax = a;
+    g_sort_axis = ax; g_sort_scene = s;
+    qsort(s->order + first, (size_t)count, sizeof(int32_t), cmp_cent);
+    int half = count / 2;
+    int l = build_node(s, first, half);
+    int r = build_node(s, first + half, count - half);
+    nd = &s->nodes[id];
+    nd->left = l; nd->right = r; nd->first = 0; nd->count = 0;
+    return id;
+}
+
+orc_scene *orc_scene_create(const float *verts, int64_t nv, const float *normals,
+                            const int32_t *tris, const int32_t *tri_seg, int64_t nt,
+                            int32_t num_segments, const int32_t *emitter_seg, int32_t num_emitters)
+{
+    orc_scene *s = (orc_scene *)calloc(1, sizeof(orc_scene));
+    s->nv = nv; s->nt = nt; s->ns = num_segments; s->ne = num_emitters;
+    s->P = (double *)malloc(sizeof(double) * 3 * (size_t)nv);
+    for (int64_t i = 0; i < 3 * nv; ++i) s->P[i] = (double)verts[i];
+    if (normals) {
+        s->N = (double *)malloc(sizeof(double) * 3 * (size_t)nv);
+        for (int64_t i = 0; i < 3 * nv; ++i) s->N[i] = (double)normals[i];
+    }
+    s->F = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)nt);
+    memcpy(s->F, tris, sizeof(int32_t) * 3 * (size_t)nt);
+    s->seg = (int32_t *)malloc(sizeof(int32_t) * (size_t)nt);
+    memcpy(s->seg, tri_seg, sizeof(int32_t) * (size_t)nt);
+    s->emitter_seg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(num_emitters > 0 ? num_emitters : 1));
+    for (int32_t k = 0; k < num_emitters; ++k) s->emitter_seg[k] = emitter_seg[k];
+    s->seg_emitter = (int32_t *)malloc(sizeof(int32_t) * (size_t)num_segments);
+    for (int i = 0; i < num_segments; ++i) s->seg_emitter[i] = -1;
+    for (int k = 0; k < num_emitters; ++k) s->seg_emitter[emitter_seg[k]] = k;
+    s->nlt = 0;
+    for (int64_t t = 0; t < nt; ++t) if (s->seg_emitter[tri_seg[t]] >= 0) s->nlt++;
+    s->light_tri = (int32_t *)malloc(sizeof(int32_t) * (size_t)(s->nlt + 1));
+    s->light_area = (double *)malloc(sizeof(double) * (size_t)(s->nlt + 1));
+    int64_t j = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        if (s->seg_emitter[tri_seg[t]] < 0) continue;
+        v3 a = vtx(s, tris[3 * t]), b = vtx(s, tris[3 * t + 1]), c = vtx(s, tris[3 * t + 2]);
+        v3 cr = cross(sub(b, a), sub(c, a));
+        s->light_tri[j] = (int32_t)t;
+        s->light_area[j] = 0.5 * sqrt(dot(cr, cr));
+        ++j;
+    }
+    double lo[3] = { INFINITY, INFINITY, INFINITY }, hi[3] = { -INFINITY, -INFINITY, -INFINITY };
+    for (int64_t i = 0; i < nv; ++i)
+        for (int a = 0; a < 3; ++a) {
+            if (s->P[3 * i + a] < lo[a]) lo[a] = s->P[3 * i + a];
+            if (s->P[3 * i + a] > hi[a]) hi[a] = s->P[3 * i + a];
+        }
+    s->diag = sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                   (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    s->order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nt > 0 ? nt : 1));
+    for (int64_t t = 0; t < nt; ++t) s->order[t] = (int32_t)t;
+    s->nodes = (onode *)malloc(sizeof(onode) * (size_t)(2 * nt + 1));
+    s->nnodes = 0;
+    if (nt > 0) build_node(s, 0, (int)nt);
+    return s;
+}
+
+void orc_scene_free(orc_scene *s)
+{
+    if (!s) return;
+    free(s->P); free(s->N); free(s->F); free(s->seg); free(s->emitter_seg);
+    free(s->seg_emitter); free(s->light_tri); free(s->light_area);
+    free(s->nodes); free(s->order); free(s);
+}
+
+double orc_scene_diag(const orc_scene *s) { return s->diag; }
+int64_t orc_scene_num_light_tris(const orc_scene *s) { return s->nlt; }
+
+/* ------------------------------------------------------------------------- */
+/* Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013), in double.  */
+/* Returns 1 on a hit with tmin < t < tmax; (u,v) weight vertices 1 and 2.    */
+/* ------------------------------------------------------------------------- */
+typedef struct { int kx, ky, kz; double Sx, Sy, Sz; v3 o, d; } wray;
+
+static wray make_wray(v3 o, v3 d)
+{
+    wray r; r.o = o; r.d = d;
+    double ad[3] = { fabs(d.x), fabs(d.y), fabs(d.z) };
+    int kz = 0;
+    if (ad[1] > ad[kz]) kz = 1;
+    if (ad[2] > ad[kz]) kz = 2;
+    int kx = (kz + 1) % 3, ky = (kx + 1) % 3;
+    if (comp(d, kz) < 0) { int t = kx; kx = ky; ky = t; }
+    r.kx = kx; r.ky = ky; r.kz = kz;
+    r.Sx = comp(d, kx) / comp(d, kz);
+    r.Sy = comp(d, ky) / comp(d, kz);
+    r.Sz = 1.0 / comp(d, kz);
+    return r;
+}
+
+static int tri_hit(const wray *r, v3 p0, v3 p1, v3 p2, double tmin, double tmax,
+                   double *t_out, double *u_out, double *v_out)
+{
+    v3 A = sub(p0, r->o), B = sub(p1, r->o), C = sub(p2, r->o);
+    double Ax = comp(A, r->kx) - r->Sx * comp(A, r->kz);
+    double Ay = comp(A, r->ky) - r->Sy * comp(A, r->kz);
+    double Bx = comp(B, r->kx) - r->Sx * comp(B, r->kz);
+    double By = comp(B, r->ky) - r->Sy * comp(B, r->kz);
+    double Cx = comp(C, r->kx) - r->Sx * comp(C, r->kz);
+    double Cy = comp(C, r->ky) - r->Sy * comp(C, r->kz);
+    double U = Cx * By - Cy * Bx;
+    double V = Ax * Cy - Ay * Cx;
+    double W = Bx * Ay - By * Ax;
+    if ((U < 0 || V < 0 || W < 0) && (U > 0 || V > 0 || W > 0)) return 0;
+    double det = U + V + W;
+    if (det == 0) return 0;
+    double Az = r->Sz * comp(A, r->kz), Bz = r->Sz * comp(B, r->kz), Cz = r->Sz * comp(C, r->kz);
+    double T = U * Az + V * Bz + W * Cz;
+    double t = T / det;
+    if (!(t > tmin && t < tmax)) return 0;
+    *t_out = t; *u_out = V / det; *v_out = W / det;
+    return 1;
+}
+
+int orc_ray_triangle(const double o[3], const double d[3], const double p0[3], const double p1[3],
+                     const double p2[3], double tmin, double tmax, double out[3])
+{
+    wray r = make_wray(mk(o[0], o[1], o[2]), mk(d[0], d[1], d[2]));
+    double t, u, v;
+    int h = tri_hit(&r, mk(p0[0], p0[1], p0[2]), mk(p1[0], p1[1], p1[2]), mk(p2[0], p2[1], p2[2]),
+                    tmin, tmax, &t, &u, &v);
+    if (h) { out[0] = t; out[1] = u; out[2] = v; }
+    return h;
+}
+
+typedef struct { int32_t tri; double t, u, v; } ohit;
+
+static int box_hit(const onode *n, v3 o, v3 d, double tmin, double tmax)
+{
+    double t0 = tmin, t1 = tmax;
+    for (int a = 0; a < 3; ++a) {
+        double oa = comp(o, a), da = comp(d, a);
+        if (da == 0.0) {
+            if (oa < n->lo[a] || oa > n->hi[a]) return 0;
+            continue;
+        }
+        double ta = (n->lo[a] - oa) / da, tb = (n->hi[a] - oa) / da;
+        if (ta > tb) { double x = ta; ta = tb; tb = x; }
+        if (ta > t0) t0 = ta;
+        if (tb < t1) t1 = tb;
+        if (t0 > t1) return 0;
+    }
+    return 1;
+}
+
+/* Accept a candidate if nearer, or equally near with a smaller triangle id:
+ * the answer then does not depend on the visiting order. */
+static void consider(const orc_scene *s, const wray *r, int32_t t, double tmin, int32_t skip0,
+                     int32_t skip1, ohit *best)
+{
+    if (t == skip0 || t == skip1) return;
+    const int32_t *f = &s->F[3 * (int64_t)t];
+    double th, u, v;
+    double tmax = best->tri >= 0 ? best->t : INFINITY;
+    if (best->tri >= 0) {
+        /* allow equality for the id tie rule */
+        if (!tri_hit(r, vtx(s, f[0]), vtx(s, f[1]), vtx(s, f[2]), tmin, INFINITY, &th, &u, &v)) return;
+        if (th > tmax) return;
+        if (th == tmax && t > best->tri) return;
+    } else {
+        if (!tri_hit(r, vtx(s, f[0]), vtx(s, f[1]), vtx(s, f[2]), tmin, INFINITY, &th, &u, &v)) return;
+    }
+    best->tri = t; best->t = th; best->u = u; best->v = v;
+}
+
+static ohit closest(const orc_scene *s, v3 o, v3 d, double tmin, double tmax, int32_t skip0,
+                    int32_t skip1, int brute)
+{
+    ohit best; best.tri = -1; best.t = INFINITY; best.u = best.v = 0;
+    wray r = make_wray(o, d);
+    if (brute || s->nnodes == 0) {
+        for (int64_t t = 0; t < s->nt; ++t) consider(s, &r, (int32_t)t, tmin, skip0, skip1, &best);
+    } else {
+        int stack[256]; int sp = 0; stack[sp++] = 0;
+        while (sp) {
+            const onode *n = &s->nodes[stack[--sp]];
+            double lim = best.tri >= 0 ? best.t : tmax;
+            if (!box_hit(n, o, d, tmin, lim)) continue;
+            if (n->left < 0) {
+                for (int i = n->first; i < n->first + n->count; ++i)
+                    consider(s, &r, s->order[i], tmin, skip0, skip1, &best);
+            } else {
+                stack[sp++] = n->left; stack[sp++] = n->right;
+            }
+        }
+    }
+    if (best.tri >= 0 && !(best.t < tmax)) best.tri = -1;
+    return best;
+}
+
+int orc_closest_hit(const orc_scene *s, const double o[3], const double d[3], double tmin,
+                    double tmax, int32_t skip, int brute, double out[3])
+{
+    ohit h = closest(s, mk(o[0], o[1], o[2]), mk(d[0], d[1], d[2]), tmin, tmax, skip, -1, brute);
+    if (h.tri >= 0) { out[0] = h.t; out[1] = h.u; out[2] = h.v; }
+    return h.tri;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cameras: pinhole, box pixel filter (Sec. 3.1, pixel filter h_j of Eq. 1).  */
+/* cam_to_world is row-major 4x4 acting on column vectors; the camera looks   */
+/* down its -z axis with +y up; image row 0 is the top row.                   */
+/* ------------------------------------------------------------------------- */
+static void camera_ray(const float *c2w, double fov_y, int W, int H, double px, double py, v3 *o,
+                       v3 *d)
+{
+    double th = tan(0.5 * fov_y), asp = (double)W / (double)H;
+    double cx = (2.0 * px / W - 1.0) * th * asp;
+    double cy = (1.0 - 2.0 * py / H) * th;
+    double cz = -1.0;
+    v3 dw = mk(c2w[0] * cx + c2w[1] * cy + c2w[2] * cz, c2w[4] * cx + c2w[5] * cy + c2w[6] * cz,
+               c2w[8] * cx + c2w[9] * cy + c2w[10] * cz);
+    *o = mk(c2w[3], c2w[7], c2w[11]);
+    *d = nrm(dw);
+}
+
+void orc_camera_ray(const float *c2w, double fov_y, int W, int H, double px, double py, double out[6])
+{
+    v3 o, d;
+    camera_ray(c2w, fov_y, W, H, px, py, &o, &d);
+    out[0] = o.x; out[1] = o.y; out[2] = o.z; out[3] = d.x; out[4] = d.y; out[5] = d.z;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Material model: Lambert + GGX (Walter et al. 2007) with separable Smith    */
+/* shadowing, no Fresnel.  Parameters of a segment: kd[3], ks[3], alpha.      */
+/* ------------------------------------------------------------------------- */
+static double clamp_alpha(double a) { return a < 1e-3 ? 1e-3 : (a > 1.0 ? 1.0 : a); }
+static double alpha_live(double a) { return (a > 1e-3 && a < 1.0) ? 1.0 : 0.0; }
+
+static double ggx_D(double ch, double a)
+{
+    if (ch <= 0) return 0;
+    double a2 = a * a, d = ch * ch * (a2 - 1.0) + 1.0;
+    return a2 / (ORC_PI * d * d);
+}
+static double ggx_dD(double ch, double a)
+{
+    if (ch <= 0) return 0;
+    double a2 = a * a, d = ch * ch * (a2 - 1.0) + 1.0;
+    return 2.0 * a * (1.0 - ch * ch * (1.0 + a2)) / (ORC_PI * d * d * d);
+}
+static double smith_G1(double c, double a)
+{
+    double s = sqrt(a * a + (1.0 - a * a) * c * c);
+    return 2.0 * c / (c + s);
+}
+static double smith_dG1(double c, double a)
+{
+    double s = sqrt(a * a + (1.0 - a * a) * c * c);
+    return -2.0 * c * a * (1.0 - c * c) / (s * (c + s) * (c + s));
+}
+
+/* Specular lobe without ks: spec = D G1(o) G1(i) / (4 co ci), and d spec / d alpha. */
+static void spec_term(v3 n, v3 wo, v3 wi, double alpha_raw, double *spec, double *dspec)
+{
+    double co = dot(n, wo), ci = dot(n, wi);
+    *spec = 0; *dspec = 0;
+    if (co <= 0 || ci <= 0) return;
+    v3 h = nrm(add(wo, wi));
+    double ch = dot(n, h);
+    double a = clamp_alpha(alpha_raw);
+    double D = ggx_D(ch, a), dD = ggx_dD(ch, a);
+    double Go = smith_G1(co, a), Gi = smith_G1(ci, a);
+    double dGo = smith_dG1(co, a), dGi = smith_dG1(ci, a);
+    double den = 4.0 * co * ci;
+    *spec = D * Go * Gi / den;
+    *dspec = alpha_live(alpha_raw) * (dD * Go * Gi + D * dGo * Gi + D * Go * dGi) / den;
+}
+
+static double lum3(const double *c) { return (c[0] + c[1] + c[2]) / 3.0; }
+
+/* Probability of choosing the specular lobe (evaluated at sampling params). */
+static double lobe_prob(const double *mp)
+{
+    double ld = lum3(mp), ls = lum3(mp + 3);
+    if (ld + ls <= 0) return 0.5;
+    return ls / (ld + ls);
+}
+
+/* Solid-angle pdf of the BRDF sampler for direction wi. */
+static double brdf_pdf(const double *mp, v3 n, v3 wo, v3 wi)
+{
+    double ci = dot(n, wi), co = dot(n, wo);
+    if (ci <= 0 || co <= 0) return 0;
+    double ps = lobe_prob(mp);
+    double pd = ci / ORC_PI;
+    double pspec = 0;
+    v3 h = nrm(add(wo, wi));
+    double ch = dot(n, h), oh = dot(wo, h);
+    if (ch > 0 && oh > 0) pspec = ggx_D(ch, clamp_alpha(mp[6])) * ch / (4.0 * oh);
+    return (1.0 - ps) * pd + ps * pspec;
+}
+
+/* Orthonormal basis around n (Duff et al., JCGT 2017). */
+static void onb(v3 n, v3 *t, v3 *b)
+{
+    double sg = n.z >= 0 ? 1.0 : -1.0;
+    double a = -1.0 / (sg + n.z);
+    double bb = n.x * n.y * a;
+    *t = mk(1.0 + sg * n.x * n.x * a, sg * bb, -sg * n.x);
+    *b = mk(bb, sg + n.y * n.y * a, -n.y);
+}
+
+/* Sample a direction from the lobe mixture: u3 picks the lobe, (u4,u5) the
+ * direction.  Returns 0 if the sample is invalid (then the path ends). */
+static int brdf_sample(const double *mp, v3 n, v3 wo, double u3, double u4, double u5, v3 *wi,
+                       int *lobe)
+{
+    v3 t, b;
+    onb(n, &t, &b);
+    double ps = lobe_prob(mp);
+    double phi = 2.0 * ORC_PI * u5;
+    if (u3 < ps) {
+        *lobe = 1;
+        double a = clamp_alpha(mp[6]);
+        double c2 = (1.0 - u4) / (1.0 + (a * a - 1.0) * u4);
+        double ch = sqrt(c2), sh = sqrt(fmax(0.0, 1.0 - c2));
+        v3 h = add(add(scl(t, sh * cos(phi)), scl(b, sh * sin(phi))), scl(n, ch));
+        double oh = dot(wo, h);
+        if (oh <= 0) return 0;
+        *wi = sub(scl(h, 2.0 * oh), wo);
+    } else {
+        *lobe = 0;
+        double r = sqrt(u4), z = sqrt(fmax(0.0, 1.0 - u4));
+        *wi = add(add(scl(t, r * cos(phi)), scl(b, r * sin(phi))), scl(n, z));
+    }
+    return 1;
+}
+
+/* Exported for the BRDF/pdf unit checks.  mp = [kd3, ks3, alpha]. */
+void orc_brdf_eval(const double *mp, const double n_[3], const double wo_[3], const double wi_[3],
+                   double out[6])
+{
+    v3 n = mk(n_[0], n_[1], n_[2]), wo = mk(wo_[0], wo_[1], wo_[2]), wi = mk(wi_[0], wi_[1], wi_[2]);
+    double spec, dspec;
+    spec_term(n, wo, wi, mp[6], &spec, &dspec);
+    double ok = (dot(n, wo) > 0 && dot(n, wi) > 0) ? 1.0 : 0.0;
+    for (int c = 0; c < 3; ++c) out[c] = ok * (mp[c] / ORC_PI + mp[3 + c] * spec);
+    out[3] = brdf_pdf(mp, n, wo, wi);
+    out[4] = spec;
+    out[5] = dspec;
+}
+
+int orc_brdf_sample(const double *mp, const double n_[3], const double wo_[3], double u3,
+                    double u4, double u5, double wi_out[3])
+{
+    v3 wi;
+    int lobe;
+    v3 n = mk(n_[0], n_[1], n_[2]), wo = mk(wo_[0], wo_[1], wo_[2]);
+    if (!brdf_sample(mp, n, wo, u3, u4, u5, &wi, &lobe)) return -1;
+    wi_out[0] = wi.x; wi_out[1] = wi.y; wi_out[2] = wi.z;
+    return lobe;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Light selection: discrete distribution over emitter triangles with weight  */
+/* area * max(lum(e), 1e-3 * max_k lum(e_k)); uniform over area if every      */
+/* emission is zero.  The paper keeps per-object probabilities proportional   */
+/* to the current emission in a Fenwick tree (Appendix E); with few emitter   */
+/* triangles a plain cumulative table is rebuilt every call instead.          */
+/* ------------------------------------------------------------------------- */
+typedef struct { double *cdf; double total; } lightdist;
+
+static lightdist build_lights(const orc_scene *s, const double *sp)
+{
+    lightdist L;
+    L.cdf = (double *)malloc(sizeof(double) * (size_t)(s->nlt + 1));
+    double maxl = 0;
+    for (int k = 0; k < s->ne; ++k) {
+        double l = lum3(sp + 7 * s->ns + 3 * k);
+        if (l > maxl) maxl = l;
+    }
+    double acc = 0;
+    for (int64_t j = 0; j < s->nlt; ++j) {
+        int k = s->seg_emitter[s->seg[s->light_tri[j]]];
+        double l = lum3(sp + 7 * s->ns + 3 * k);
+        double w = maxl > 0 ? s->light_area[j] * fmax(l, 1e-3 * maxl) : s->light_area[j];
+        acc += w;
+        L.cdf[j] = acc;
+    }
+    L.total = acc;
+    return L;
+}
+
+static int64_t pick_light(const lightdist *L, int64_t n, double u)
+{
+    double x = u * L->total;
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {          /* first j with cdf[j] > x */
+        int64_t mid = (lo + hi) / 2;
+        if (L->cdf[mid] > x) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+static double light_prob(const lightdist *L, int64_t j)
+{
+    double prev = j > 0 ? L->cdf[j - 1] : 0.0;
+    return (L->cdf[j] - prev) / L->total;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Path tracing with per-factor derivative bookkeeping.                       */
+/* ------------------------------------------------------------------------- */
+#define ORC_MAXD 16
+#define ORC_MAXDER 12
+
+/* A 3-channel factor of a path contribution with its sparse derivative. */
+typedef struct {
+    double v[3];
+    int n;
+    int32_t idx[ORC_MAXDER];
+    double d[ORC_MAXDER][3];
+} factor;
+
+typedef struct {
+    uint64_t seed; uint32_t stream_tag, iteration;
+    int32_t spp, max_depth, rr_depth, mis, emission_profile, jitter, brute_force;
+    const int64_t *pixel_list; int64_t num_pixels;
+} orc_opts;
+
+typedef struct { int32_t num_views, width, height; const float *cam_to_world; const float *fov_y; } orc_cams;
+
+static void fadd(factor *f, int32_t idx, double d0, double d1, double d2)
+{
+    f->idx[f->n] = idx; f->d[f->n][0] = d0; f->d[f->n][1] = d1; f->d[f->n][2] = d2; f->n++;
+}
+
+/* Accumulate the derivative of one radiance term tau = prod_i a_i (.) phi into
+ * grad, weighted by wc (per channel), using the product rule of Eqs. 5-6
+ * written out without division.  Also returns tau. */
+static void term_grad(const factor *a, int na, const factor *phi, const double *wc, double *grad,
+                      double tau[3])
+{
+    for (int c = 0; c < 3; ++c) {
+        double p = phi->v[c];
+        for (int i = 0; i < na; ++i) p *= a[i].v[c];
+        tau[c] = p;
+    }
+    if (!grad) return;
+    /* derivative through the continuation factors */
+    for (int i = 0; i < na; ++i) {
+        for (int e = 0; e < a[i].n; ++e) {
+            double g = 0;
+            for (int c = 0; c < 3; ++c) {
+                double p = a[i].d[e][c] * phi->v[c];
+                for (int j = 0; j < na; ++j) if (j != i) p *= a[j].v[c];
+                g += wc[c] * p;
+            }
+            grad[a[i].idx[e]] += g;
+        }
+    }
+    /* derivative through the local term */
+    for (int e = 0; e < phi->n; ++e) {
+        double g = 0;
+        for (int c = 0; c < 3; ++c) {
+            double p = phi->d[e][c];
+            for (int j = 0; j < na; ++j) p *= a[j].v[c];
+            g += wc[c] * p;
+        }
+        grad[phi->idx[e]] += g;
+    }
+}
+
+static uint64_t fnv(uint64_t h, uint32_t x)
+{
+    for (int i = 0; i < 4; ++i) { h ^= (x >> (8 * i)) & 0xFFu; h *= 0x100000001B3ull; }
+    return h;
+}
+
+static double mis_w(double a, double b, int mode)
+{
+    if (mode == 3) { a *= a; b *= b; }
+    return a / (a + b);
+}
+
+typedef struct {
+    const orc_scene *s;
+    const double *p, *sp;
+    const lightdist *L;
+    const orc_opts *o;
+} ctx;
+
+/* One path.  Returns radiance in L; adds w-weighted derivatives into grad if
+ * grad != NULL.  Event hash in *hash. */
+static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const double *wc,
+                       double *grad, double Lout[3], uint64_t *hash)
+{
+    const orc_scene *s = C->s;
+    const double *p = C->p, *sp = C->sp;
+    const int D = C->o->max_depth;
+    const int mis = C->o->mis;
+    const double tmin = 1e-6 * s->diag;
+    factor a[ORC_MAXD + 2];
+    int na = 0;
+    double Ts[3] = { 1, 1, 1 };     /* throughput at sampling params (for RR) */
+    double L[3] = { 0, 0, 0 };
+    uint64_t h = 0xCBF29CE484222325ull;
+    int32_t prev_tri = -1;
+    double prev_pdf = 0;            /* pdf of the direction that produced this ray */
+    int prev_specular_only = 0;
+    (void)prev_specular_only;
+    v3 o = org, d = dir;
+    for (int k = 1; k <= D + 1; ++k) {
+        ohit hit = closest(s, o, d, tmin, INFINITY, prev_tri, -1, C->o->brute_force);
+        h = fnv(h, (uint32_t)hit.tri);
+        if (hit.tri < 0) break;
+        const int32_t *f = &s->F[3 * (int64_t)hit.tri];
+        v3 p0 = vtx(s, f[0]), p1 = vtx(s, f[1]), p2 = vtx(s, f[2]);
+        v3 e1 = sub(p1, p0), e2 = sub(p2, p0);
+        v3 x = add(p0, add(scl(e1, hit.u), scl(e2, hit.v)));
+        v3 ng = nrm(cross(e1, e2));
+        int seg = s->seg[hit.tri];
+        int em = s->seg_emitter[seg];
+        double cos_emit = -dot(d, ng);     /* > 0: ray arrives at the emitting side */
+        uint32_t ev = 0;
+        /* --- emitter hit --- */
+        if (em >= 0 && cos_emit > 0) {
+            double w = 1.0;
+            if (k > 1) {
+                if (mis == 1) w = 0.0;
+                else if (mis >= 2) {
+                    int64_t lj = -1;
+                    for (int64_t j = 0; j < s->nlt; ++j) if (s->light_tri[j] == hit.tri) lj = j;
+                    double pa = light_prob(C->L, lj) / s->light_area[lj];
+                    double pl = pa * hit.t * hit.t / cos_emit;
+                    w = mis_w(prev_pdf, pl, mis);
+                }
+            }
+            if (w > 0) {
+                double prof = C->o->emission_profile ? cos_emit : 1.0;
+                factor phi; phi.n = 0;
+                const double *e = p + 7 * s->ns + 3 * em;
+                for (int c = 0; c < 3; ++c) phi.v[c] = e[c] * prof * w;
+                int base = 7 * s->ns + 3 * em;
+                fadd(&phi, base + 0, prof * w, 0, 0);
+                fadd(&phi, base + 1, 0, prof * w, 0);
+                fadd(&phi, base + 2, 0, 0, prof * w);
+                double tau[3];
+                term_grad(a, na, &phi, wc, grad, tau);
+                for (int c = 0; c < 3; ++c) L[c] += tau[c];
+            }
+            ev |= 1u;
+        }
+        if (k == D + 1) { h = fnv(h, ev); break; }
+        /* --- shading frame: two-sided, flipped toward the viewer --- */
+        v3 wo = scl(d, -1.0);
+        v3 ns = ng;
+        if (s->N) {
+            v3 n0 = mk(s->N[3 * (int64_t)f[0]], s->N[3 * (int64_t)f[0] + 1], s->N[3 * (int64_t)f[0] + 2]);
+            v3 n1 = mk(s->N[3 * (int64_t)f[1]], s->N[3 * (int64_t)f[1] + 1], s->N[3 * (int64_t)f[1] + 2]);
+            v3 n2 = mk(s->N[3 * (int64_t)f[2]], s->N[3 * (int64_t)f[2] + 1], s->N[3 * (int64_t)f[2] + 2]);
+            ns = nrm(add(scl(n0, 1.0 - hit.u - hit.v), add(scl(n1, hit.u), scl(n2, hit.v))));
+        }
+        v3 ngf = ng;
+        if (dot(ng, wo) < 0) { ngf = scl(ng, -1.0); ns = scl(ns, -1.0); }
+        if (dot(ns, wo) <= 0) { h = fnv(h, ev | 2u); break; }   /* shading normal faces away */
+        const double *mp = p + 7 * seg, *msp = sp + 7 * seg;
+        double u[8];
+        vertex_uniforms(C->o->seed, C->o->stream_tag, C->o->iteration, path_id, k, u);
+        /* --- explicit light sampling (next-event estimation) --- */
+        if (mis != 0 && s->nlt > 0) {
+            int64_t lj = pick_light(C->L, s->nlt, u[0]);
+            int32_t lt = s->light_tri[lj];
+            const int32_t *lf = &s->F[3 * (int64_t)lt];
+            v3 q0 = vtx(s, lf[0]), q1 = vtx(s, lf[1]), q2 = vtx(s, lf[2]);
+            double su = sqrt(u[1]);
+            double b1 = (1.0 - u[2]) * su, b2 = u[2] * su;
+            v3 y = add(q0, add(scl(sub(q1, q0), b1), scl(sub(q2, q0), b2)));
+            v3 lng = nrm(cross(sub(q1, q0), sub(q2, q0)));
+            v3 dl = sub(y, x);
+            double d2 = dot(dl, dl), dist = sqrt(d2);
+            v3 wl = scl(dl, 1.0 / dist);
+            double cy = -dot(wl, lng);
+            double cxg = dot(wl, ngf);
+            uint32_t vis = 0;
+            if (cy > 0 && cxg > 0 && lt != hit.tri) {
+                ohit sh = closest(s, x, wl, tmin, dist * (1.0 - 1e-5), hit.tri, lt, C->o->brute_force);
+                vis = sh.tri < 0;
+            }
+            ev |= (uint32_t)(lj << 8) | (vis << 2);
+            if (vis) {
+                double spec, dspec;
+                spec_term(ns, wo, wl, mp[6], &spec, &dspec);
+                double cx = dot(ns, wl);
+                if (cx > 0) {
+                    int lk = s->seg_emitter[s->seg[lt]];
+                    double parea = light_prob(C->L, lj) / s->light_area[lj];
+                    double w = 1.0;
+                    if (mis >= 2) {
+                        double pl = parea * d2 / cy;
+                        double pb = brdf_pdf(msp, ns, wo, wl);
+                        w = mis_w(pl, pb, mis);
+                    }
+                    double prof = C->o->emission_profile ? cy : 1.0;
+                    double g = cx * cy / d2 * w / parea * prof;   /* everything but f and e */
+                    const double *e = p + 7 * s->ns + 3 * lk;
+                    factor phi; phi.n = 0;
+                    for (int c = 0; c < 3; ++c)
+                        phi.v[c] = (mp[c] / ORC_PI + mp[3 + c] * spec) * e[c] * g;
+                    int mb = 7 * seg, eb = 7 * s->ns + 3 * lk;
+                    fadd(&phi, mb + 0, e[0] * g / ORC_PI, 0, 0);
+                    fadd(&phi, mb + 1, 0, e[1] * g / ORC_PI, 0);
+                    fadd(&phi, mb + 2, 0, 0, e[2] * g / ORC_PI);
+                    fadd(&phi, mb + 3, spec * e[0] * g, 0, 0);
+                    fadd(&phi, mb + 4, 0, spec * e[1] * g, 0);
+                    fadd(&phi, mb + 5, 0, 0, spec * e[2] * g);
+                    fadd(&phi, mb + 6, mp[3] * dspec * e[0] * g, mp[4] * dspec * e[1] * g,
+                         mp[5] * dspec * e[2] * g);
+                    fadd(&phi, eb + 0, (mp[0] / ORC_PI + mp[3] * spec) * g, 0, 0);
+                    fadd(&phi, eb + 1, 0, (mp[1] / ORC_PI + mp[4] * spec) * g, 0);
+                    fadd(&phi, eb + 2, 0, 0, (mp[2] / ORC_PI + mp[5] * spec) * g);
+                    double tau[3];
+                    term_grad(a, na, &phi, wc, grad, tau);
+                    for (int c = 0; c < 3; ++c) L[c] += tau[c];
+                }
+            }
+        }
+        /* --- continue the path by sampling the BRDF --- */
+        v3 wi;
+        int lobe = 0;
+        int ok = brdf_sample(msp, ns, wo, u[3], u[4], u[5], &wi, &lobe);
+        ev |= (uint32_t)lobe << 3;
+        if (!ok || dot(wi, ngf) <= 0 || dot(wi, ns) <= 0) { h = fnv(h, ev | 16u); break; }
+        double pdf = brdf_pdf(msp, ns, wo, wi);
+        if (!(pdf > 0)) { h = fnv(h, ev | 16u); break; }
+        double spec, dspec, specs, dspecs;
+        spec_term(ns, wo, wi, mp[6], &spec, &dspec);
+        spec_term(ns, wo, wi, msp[6], &specs, &dspecs);
+        double ci = dot(ns, wi);
+        double g = ci / pdf;
+        factor *ak = &a[na];
+        ak->n = 0;
+        for (int c = 0; c < 3; ++c) ak->v[c] = (mp[c] / ORC_PI + mp[3 + c] * spec) * g;
+        double ts[3];
+        for (int c = 0; c < 3; ++c) ts[c] = (msp[c] / ORC_PI + msp[3 + c] * specs) * g;
+        /* Russian roulette on the sampling-parameter throughput (detached). */
+        double q = 1.0;
+        if (C->o->rr_depth >= 0 && k >= C->o->rr_depth) {
+            double m = 0;
+            for (int c = 0; c < 3; ++c) { double tc = Ts[c] * ts[c]; if (tc > m) m = tc; }
+            q = m < 0.1 ? 0.1 : (m > 0.95 ? 0.95 : m);
+            if (!(u[6] < q)) { h = fnv(h, ev | 32u); break; }
+        }
+        g /= q;
+        for (int c = 0; c < 3; ++c) { ak->v[c] /= q; Ts[c] *= ts[c] / q; }
+        int mb = 7 * seg;
+        fadd(ak, mb + 0, g / ORC_PI, 0, 0);
+        fadd(ak, mb + 1, 0, g / ORC_PI, 0);
+        fadd(ak, mb + 2, 0, 0, g / ORC_PI);
+        fadd(ak, mb + 3, spec * g, 0, 0);
+        fadd(ak, mb + 4, 0, spec * g, 0);
+        fadd(ak, mb + 5, 0, 0, spec * g);
+        fadd(ak, mb + 6, mp[3] * dspec * g, mp[4] * dspec * g, mp[5] * dspec * g);
+        na++;
+        h = fnv(h, ev);
+        prev_pdf = pdf;
+        prev_tri = hit.tri;
+        o = x; d = wi;
+    }
+    for (int c = 0; c < 3; ++c) Lout[c] = L[c];
+    *hash = h;
+}
+
+/* Render (and, when w != NULL and grad != NULL, differentiate) a set of
+ * pixels.  image[npix*3] receives the per-pixel mean over spp; grad[P]
+ * receives sum_j sum_c (w_jc / spp) d(sum_s L_sc)/dtheta.  path_mask (if not
+ * NULL) removes paths from both.  Returns the number of paths dropped for a
+ * non-finite contribution. */
+int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
+                const double *sampling_params, const orc_opts *o, const double *w,
+                const uint8_t *path_mask, double *image, double *grad, uint64_t *hashes,
+                double *path_L)
+{
+    const double *sp = sampling_params ? sampling_params : params;
+    int64_t P = 7 * (int64_t)s->ns + 3 * (int64_t)s->ne;
+    lightdist L = build_lights(s, sp);
+    ctx C = { s, params, sp, &L, o };
+    int64_t npix = o->pixel_list ? o->num_pixels
+                                 : (int64_t)cams->num_views * cams->width * cams->height;
+    int64_t dropped = 0;
+    if (grad) memset(grad, 0, sizeof(double) * (size_t)P);
+    int nthr = 1;
+#ifdef _OPENMP
+    nthr = omp_get_max_threads();
+#endif
+    double *gpriv = grad ? (double *)calloc((size_t)nthr * (size_t)P, sizeof(double)) : NULL;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : dropped)
+    for (int64_t i = 0; i < npix; ++i) {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *gt = gpriv ? gpriv + (size_t)tid * (size_t)P : NULL;
+        int64_t pix = o->pixel_list ? o->pixel_list[i] : i;
+        int64_t W = cams->width, H = cams->height;
+        int64_t v = pix / (W * H), rem = pix % (W * H);
+        int64_t y = rem / W, x = rem % W;
+        double acc[3] = { 0, 0, 0 };
+        double wc[3] = { 0, 0, 0 };
+        if (w) for (int c = 0; c < 3; ++c) wc[c] = w[3 * i + c] / o->spp;
+        for (int sidx = 0; sidx < o->spp; ++sidx) {
+            uint64_t pid = (uint64_t)pix * (uint64_t)o->spp + (uint64_t)sidx;
+            double u[8];
+            vertex_uniforms(o->seed, o->stream_tag, o->iteration, pid, 0, u);
+            double jx = o->jitter ? u[0] : 0.5, jy = o->jitter ? u[1] : 0.5;
+            v3 org, dir;
+            camera_ray(cams->cam_to_world + 16 * v, (double)cams->fov_y[v], (int)W, (int)H,
+                       (double)x + jx, (double)y + jy, &org, &dir);
+            double Lp[3];
+            uint64_t hsh;
+            int use = path_mask ? path_mask[i * o->spp + sidx] : 1;
+            /* gradient into a per-path scratch first, so a non-finite path
+             * can be dropped whole */
+            double *gp = NULL;
+            double gbuf_local[1];
+            (void)gbuf_local;
+            if (gt && use) gp = (double *)calloc((size_t)P, sizeof(double));
+            trace_path(&C, org, dir, pid, wc, gp, Lp, &hsh);
+            int fin = isfinite(Lp[0]) && isfinite(Lp[1]) && isfinite(Lp[2]);
+            if (gp) for (int64_t q = 0; q < P && fin; ++q) if (!isfinite(gp[q])) fin = 0;
+            if (!fin) { dropped++; Lp[0] = Lp[1] = Lp[2] = 0; }
+            if (use && fin) {
+                for (int c = 0; c < 3; ++c) acc[c] += Lp[c];
+                if (gp) for (int64_t q = 0; q < P; ++q) gt[q] += gp[q];
+            }
+            if (gp) free(gp);
+            if (hashes) hashes[i * o->spp + sidx] = hsh;
+            if (path_L) for (int c = 0; c < 3; ++c) path_L[3 * (i * o->spp + sidx) + c] = Lp[c];
+        }
+        if (image) for (int c = 0; c < 3; ++c) image[3 * i + c] = acc[c] / o->spp;
+    }
+    if (grad) {
+        for (int t = 0; t < nthr; ++t)
+            for (int64_t q = 0; q < P; ++q) grad[q] += gpriv[(size_t)t * (size_t)P + q];
+        free(gpriv);
+    }
+    free(L.cdf);
+    return dropped;
+}
+
+/* Light-selection probabilities per emitter triangle (for tests). */
+void orc_light_probs(const orc_scene *s, const double *sampling_params, double *out)
+{
+    lightdist L = build_lights(s, sampling_params);
+    for (int64_t j = 0; j < s->nlt; ++j) out[j] = light_prob(&L, j);
+    free(L.cdf);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Loss and adjoint image (Sec. 3.2 Eq. 3, Sec. 3.3 Eq. 4).  kind 0: L2 mean  */
+/* squared error over all pixels and channels; kind 1: the paper's L1.        */
+/* The adjoint is dE/dI (the sign in Eq. 4 as printed is that of -dE/dI).     */
+/* ------------------------------------------------------------------------- */
+double orc_loss_adjoint(const double *img, const double *target, int64_t n3, int kind, double *w)
+{
+    double E = 0;
+    for (int64_t i = 0; i < n3; ++i) {
+        double r = img[i] - target[i];
+        if (kind == 0) {
+            E += r * r;
+            if (w) w[i] = 2.0 * r / (double)n3;
+        } else {
+            E += fabs(r);
+            if (w) w[i] = (r > 0 ? 1.0 : (r < 0 ? -1.0 : 0.0)) / (double)n3;
+        }
+    }
+    return E / (double)n3;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Adam (Kingma & Ba 2015; Sec. 4.5) on normalised parameters theta = p/scale */
+/* with bias correction, followed by a clamp of theta to [lo, hi].  Entries   */
+/* with trainable[i] == 0 are left as they are.  step counts from 1.          */
+/* ------------------------------------------------------------------------- */
+void orc_adam(double *params, const double *grad, double *m, double *v, int64_t n, int step,
+              double lr, double b1, double b2, double eps, const double *scale, const double *lo,
+              const double *hi, const uint8_t *trainable)
+{
+    double c1 = 1.0 - pow(b1, step), c2 = 1.0 - pow(b2, step);
+    for (int64_t i = 0; i < n; ++i) {
+        if (trainable && !trainable[i]) continue;
+        double sc = scale ? scale[i] : 1.0;
+        double g = grad[i] * sc;
+        m[i] = b1 * m[i] + (1.0 - b1) * g;
+        v[i] = b2 * v[i] + (1.0 - b2) * g * g;
+        double mh = m[i] / c1, vh = v[i] / c2;
+        double th = params[i] / sc - lr * mh / (sqrt(vh) + eps);
+        if (lo && th < lo[i]) th = lo[i];
+        if (hi && th > hi[i]) th = hi[i];
+        params[i] = th * sc;
+    }
+}
