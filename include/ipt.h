@@ -1,0 +1,211 @@
+/*
+ * ipt.h -- C ABI of the MI355X (gfx950) inverse path tracing library.
+ *
+ * The library implements the hot path of "Inverse Path Tracing for Joint
+ * Material and Lighting Estimation" (Azinovic et al., CVPR 2019): a Monte
+ * Carlo path tracer whose image estimate (Sec. 3.1, Eq. 1-2) and whose
+ * gradient with respect to per-object material and emission unknowns
+ * (Sec. 3.3, Eq. 4-6) are nested inside stochastic gradient descent
+ * (Sec. 3.2, Eq. 3; Sec. 4.5).
+ *
+ * Conventions shared by every call:
+ *   - Unless stated otherwise, pointers to arrays are DEVICE pointers (HIP
+ *     global memory on the device that is current when the call is made);
+ *     the caller owns them and the library never frees them.  Scene inputs of
+ *     ipt_scene_build are HOST pointers (copied).
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  All device
+ *     work is enqueued on it; no call synchronises the stream except
+ *     ipt_scene_build and ipt_scene_info.
+ *   - Every call returns an ipt_status and never aborts.  Arguments are
+ *     validated on the host before anything is enqueued; on error nothing is
+ *     enqueued and ipt_last_error() returns a message (thread-local).
+ *   - The library allocates device memory only in ipt_scene_build and
+ *     ipt_guide_create (owned by the handle, freed by the matching _free).
+ *     Per-call scratch space is the caller's workspace.
+ *
+ * Parameter vector (float32, raw physical values, length P = 7 S + 3 E):
+ *   segment s   [7s .. 7s+6]  kd_r kd_g kd_b  ks_r ks_g ks_b  alpha
+ *   emitter k   [7S+3k .. +2] e_r e_g e_b     (radiance of segment emitter_seg[k])
+ * Material model: f = kd/pi + ks D(h) G1(o) G1(i) / (4 cos_o cos_i), GGX D with
+ * alpha = roughness clamped to [1e-3, 1], separable Smith G1, no Fresnel (a
+ * reduced stand-in for the Disney model of Sec. 4.1).  Emission: constant
+ * radiance e, or the profile e (w.n)_+ of Sec. 4.3 (emission_profile = 1);
+ * emitters emit on the side their triangle winding faces.
+ *
+ * Random numbers: Philox4x32-10, key = (seed_lo ^ stream_tag*0x9E3779B9,
+ * seed_hi), counter = (path_lo, path_hi, 2*vertex + half, iteration), uniform
+ * = (x >> 8) * 2^-24.  path id = pixel * spp + sample, pixel =
+ * (view * height + y) * width + x (row 0 is the top row).  Identical inputs
+ * give identical paths, which is what lets the adjoint pass replay them.
+ */
+#ifndef IPT_H
+#define IPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ipt_scene_s *ipt_scene_t;
+typedef struct ipt_guide_s *ipt_guide_t;
+
+typedef enum {
+    IPT_OK = 0,
+    IPT_ERR_INVALID_ARG = 1,
+    IPT_ERR_BAD_SCENE = 2,
+    IPT_ERR_OUT_OF_MEMORY = 3,
+    IPT_ERR_WORKSPACE_TOO_SMALL = 4,
+    IPT_ERR_HIP = 5,
+    IPT_ERR_NOT_SUPPORTED = 6
+} ipt_status;
+
+/* Pinhole cameras (Sec. 3.4: several calibrated views).  cam_to_world is a
+ * DEVICE array [num_views][4][4] (row-major, acting on column vectors; the
+ * camera looks down its -z axis, +y up); fov_y is a DEVICE array
+ * [num_views] of vertical fields of view in radians. */
+typedef struct {
+    int32_t num_views, width, height;
+    const float *cam_to_world;
+    const float *fov_y;
+} ipt_cameras;
+
+/* One estimator configuration (one "stream" of independent samples). */
+typedef struct {
+    uint64_t seed;
+    uint32_t stream_tag;      /* 0 target, 1 colour (A), 2 gradient (B), 3 guide */
+    uint32_t iteration;       /* SGD iteration: fresh samples every step */
+    int32_t spp;              /* samples per pixel, >= 1 */
+    int32_t max_depth;        /* D: scattering vertices per path, 1..16 */
+    int32_t rr_depth;         /* Russian roulette at vertices >= rr_depth; < 0 off */
+    int32_t mis;              /* 0 BRDF only, 1 light only, 2 balance, 3 power heuristic */
+    int32_t emission_profile; /* 0 constant radiance, 1 e (w.n)_+ */
+    int32_t jitter;           /* 1 box pixel filter, 0 pixel centres */
+    int32_t replay_traverse;  /* gradient only: 1 = adjoint re-traces rays instead of
+                                 reading vertex checkpoints */
+    const int64_t *pixel_list;/* DEVICE [num_pixels] or NULL = every pixel of every view */
+    int64_t num_pixels;
+    ipt_guide_t guide;        /* NULL = BRDF sampling only */
+    float guide_mix;          /* probability of sampling the guide when guide != NULL */
+    uint64_t *debug_path_hash;/* DEVICE [pixels*spp] or NULL: FNV-1a of each path's events */
+    const uint8_t *path_mask; /* DEVICE [pixels*spp] or NULL: 0 removes the path */
+} ipt_render_opts;
+
+typedef struct {
+    float lr, beta1, beta2, eps;
+} ipt_adam_opts;
+
+typedef struct {
+    int64_t num_triangles, num_vertices, num_nodes, num_light_triangles;
+    int32_t num_segments, num_emitters, bvh_depth, has_normals;
+    double sah_cost;          /* SAH cost of the BVH (C_trav = C_isect = 1) */
+    double build_ms;          /* wall time of the BVH build */
+    float scene_diag;
+    uint64_t nonfinite_paths; /* paths dropped for a non-finite contribution */
+    uint64_t stack_overflows; /* traversals that ran out of stack */
+} ipt_scene_info_t;
+
+/* Build a scene: upload geometry, build the BVH (binned SAH, leaves of at
+ * most 4 triangles), the leaf-ordered triangle layout and the emitter table.
+ * Inputs are HOST arrays: verts [nv][3], normals [nv][3] or NULL (flat
+ * shading), tris [nt][3] vertex indices, tri_seg [nt] segment ids in
+ * [0, num_segments), emitter_seg [num_emitters] distinct segment ids.  The
+ * triangles of an emitter segment emit; every segment reflects.
+ * Sec. 4.2 (per-vertex normals, per-object constant parameters).
+ * Errors: IPT_ERR_INVALID_ARG (NULL/size), IPT_ERR_BAD_SCENE (index out of
+ * range, non-finite vertex, degenerate emitter triangle, duplicate emitter). */
+ipt_status ipt_scene_build(const float *verts, int64_t nv, const float *normals,
+                           const int32_t *tris, const int32_t *tri_seg, int64_t nt,
+                           int32_t num_segments, const int32_t *emitter_seg,
+                           int32_t num_emitters, void *hip_stream, ipt_scene_t *out);
+ipt_status ipt_scene_free(ipt_scene_t scene);
+/* Sizes, BVH statistics and device error counters (synchronises). */
+ipt_status ipt_scene_info(ipt_scene_t scene, ipt_scene_info_t *out);
+
+/* Workspace bytes for ipt_render / ipt_render_grad / ipt_loss_grad with these
+ * options: *min_bytes lets the gradient run in chunks; *full_bytes keeps the
+ * vertex checkpoints of every gradient path at once. */
+ipt_status ipt_workspace_query(ipt_scene_t scene, const ipt_cameras *cams,
+                               const ipt_render_opts *opts, size_t *min_bytes,
+                               size_t *full_bytes);
+
+/* Image estimate (Sec. 3.1, Eq. 1): image [pixels][3] float32 receives the
+ * mean over spp of each path's radiance.  params [P] are the values to
+ * render with; sampling_params [P] (NULL = params) fix every sampling
+ * decision, pdf, MIS weight and the light-selection distribution. */
+ipt_status ipt_render(ipt_scene_t scene, const ipt_cameras *cams, const float *params,
+                      const float *sampling_params, const ipt_render_opts *opts, float *image,
+                      void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Vector-Jacobian product of the image estimate (Sec. 3.3, Eq. 5-6):
+ * grad [P] = sum_j sum_c w[j][c] d I_jc / d theta, with w [pixels][3] the
+ * adjoint image.  The estimate uses the samples of opts (stream B); pdfs are
+ * held at sampling_params.  The forward pass stores per-vertex checkpoints and
+ * the division-free suffix radiance; the adjoint pass replays each path from
+ * its Philox counter.  grad is overwritten. */
+ipt_status ipt_render_grad(ipt_scene_t scene, const ipt_cameras *cams, const float *params,
+                           const float *sampling_params, const ipt_render_opts *opts,
+                           const float *w, float *grad, void *workspace,
+                           size_t workspace_bytes, void *hip_stream);
+
+/* One SGD evaluation (Sec. 3.2-3.3): render the colour estimate with
+ * color_opts, form the loss against target [pixels][3] (loss_kind 0: mean
+ * squared error over pixels and channels; 1: mean absolute error, Eq. 3) and
+ * its adjoint dE/dI, then the gradient from independent samples (grad_opts,
+ * Sec. 3.3: the two estimates must be independent).  loss: DEVICE scalar.
+ * image_A [pixels][3] (nullable) receives the colour estimate. */
+ipt_status ipt_loss_grad(ipt_scene_t scene, const ipt_cameras *cams, const float *params,
+                         const float *target, const ipt_render_opts *color_opts,
+                         const ipt_render_opts *grad_opts, int32_t loss_kind, float *loss,
+                         float *grad, float *image_A, void *workspace, size_t workspace_bytes,
+                         void *hip_stream);
+
+/* Adam (Sec. 4.5) on theta = params/scale with bias correction (step >= 1),
+ * then theta is clamped to [lo, hi].  m, v [P] are the moment buffers
+ * (theta units).  scale/lo/hi/trainable may be NULL (1, -inf, +inf, all). */
+ipt_status ipt_sgd_step(float *params, const float *grad, float *m, float *v, int32_t P,
+                        int32_t step, const ipt_adam_opts *adam, const float *scale,
+                        const float *lo, const float *hi, const uint8_t *trainable,
+                        void *hip_stream);
+
+/* Closest hits of a batch of rays (the ray-casting step of every path
+ * vertex).  origins/dirs [n][3]; out_tri [n] original triangle id or -1;
+ * out_tuv [n][3] (t, u, v) with u, v the weights of vertices 1 and 2;
+ * skip_tri [n] (nullable) excludes one triangle per ray; brute_force = 1
+ * tests every triangle (checks the BVH).  Ties in t go to the smaller id. */
+ipt_status ipt_trace_rays(ipt_scene_t scene, const float *origins, const float *dirs,
+                          const int32_t *skip_tri, int64_t n, float tmin, int32_t brute_force,
+                          int32_t *out_tri, float *out_tuv, void *hip_stream);
+
+/* Learned path-guiding proposal (an MLP mapping position, normal and
+ * outgoing direction plus a per-segment embedding to an 8-lobe von
+ * Mises-Fisher mixture).  It only changes how directions are sampled: it is
+ * mixed with BRDF sampling by one-sample MIS, so estimates stay unbiased. */
+typedef struct {
+    uint64_t seed;
+    float lr;               /* Adam learning rate of the network */
+    int32_t batch;          /* training records per step */
+    int32_t ring_capacity;  /* training records kept */
+} ipt_guide_opts;
+
+ipt_status ipt_guide_create(ipt_scene_t scene, const ipt_guide_opts *opts, void *hip_stream,
+                            ipt_guide_t *out);
+ipt_status ipt_guide_free(ipt_guide_t guide);
+/* Evaluate the mixture for n queries: feat [n][9] (position in scene-box
+ * units [-1,1]^3, normal, outgoing direction), seg [n]; out [n][40]
+ * (per lobe: mu xyz, kappa, weight) after normalisation. */
+ipt_status ipt_guide_eval(ipt_guide_t guide, const float *feat, const int32_t *seg, int64_t n,
+                          float *out, void *hip_stream);
+/* Render `paths` guide-training samples with opts (stream tag 3) into the
+ * record ring, then take `steps` Adam steps on minibatches of it. */
+ipt_status ipt_guide_train(ipt_guide_t guide, const ipt_cameras *cams, const float *params,
+                           const ipt_render_opts *opts, int32_t steps, void *workspace,
+                           size_t workspace_bytes, void *hip_stream);
+
+const char *ipt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPT_H */

@@ -1,0 +1,497 @@
+// C ABI of the inverse path tracing library: validation, scene upload,
+// workspace layout and launch sequencing on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ipt.h"
+#include "bvh_host.h"
+#include "ipt_internal.h"
+
+using namespace ipt;
+
+static thread_local std::string g_err;
+
+static ipt_status fail(ipt_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_OK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            return fail(IPT_ERR_HIP, "%s failed: %s", #x, hipGetErrorString(e_));          \
+    } while (0)
+
+extern "C" const char* ipt_last_error(void) { return g_err.c_str(); }
+
+struct ipt_scene_s {
+    int device = 0;
+    int num_cu = 0;
+    SceneDev dev{};
+    float4* d_nodes = nullptr;
+    float4* d_tris = nullptr;
+    float4* d_nrm = nullptr;
+    int4* d_lights = nullptr;
+    int* d_segemit = nullptr;
+    int* d_pos_of = nullptr;
+    Counters* d_err = nullptr;
+    int* d_ovf_rays = nullptr;   // overflow stacks of ipt_trace_rays
+    int64_t nt = 0, nv = 0, nnodes = 0;
+    int S = 0, E = 0, nlt = 0, depth = 0, has_normals = 0;
+    double sah = 0.0, build_ms = 0.0;
+    float diag = 0.0f;
+    float bb_lo[3] = {0, 0, 0}, bb_hi[3] = {0, 0, 0};
+};
+
+// ---------------------------------------------------------------------------
+// Scene build.
+// ---------------------------------------------------------------------------
+extern "C" ipt_status ipt_scene_free(ipt_scene_t s) {
+    if (!s) return IPT_OK;
+    hipFree(s->d_nodes);
+    hipFree(s->d_tris);
+    hipFree(s->d_nrm);
+    hipFree(s->d_lights);
+    hipFree(s->d_segemit);
+    hipFree(s->d_pos_of);
+    hipFree(s->d_err);
+    hipFree(s->d_ovf_rays);
+    delete s;
+    return IPT_OK;
+}
+
+extern "C" ipt_status ipt_scene_build(const float* verts, int64_t nv, const float* normals,
+                                      const int32_t* tris, const int32_t* tri_seg, int64_t nt,
+                                      int32_t num_segments, const int32_t* emitter_seg,
+                                      int32_t num_emitters, void* hip_stream, ipt_scene_t* out) {
+    (void)hip_stream;
+    if (!out) return fail(IPT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!verts || !tris || !tri_seg) return fail(IPT_ERR_INVALID_ARG, "verts/tris/tri_seg is NULL");
+    if (nv < 3 || nt < 1) return fail(IPT_ERR_INVALID_ARG, "need nv >= 3 and nt >= 1");
+    if (nt >= (int64_t)kCkTriMask) return fail(IPT_ERR_NOT_SUPPORTED, "too many triangles (%lld)", (long long)nt);
+    if (num_segments < 1) return fail(IPT_ERR_INVALID_ARG, "num_segments < 1");
+    if (num_emitters < 0 || (num_emitters > 0 && !emitter_seg))
+        return fail(IPT_ERR_INVALID_ARG, "bad emitter list");
+    for (int64_t i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(verts[i])) return fail(IPT_ERR_BAD_SCENE, "vertex %lld is not finite", (long long)(i / 3));
+    if (normals)
+        for (int64_t i = 0; i < nv; ++i) {
+            float x = normals[3 * i], y = normals[3 * i + 1], z = normals[3 * i + 2];
+            if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z) || !(x * x + y * y + z * z > 0.0f))
+                return fail(IPT_ERR_BAD_SCENE, "normal %lld is not a finite nonzero vector", (long long)i);
+        }
+    for (int64_t t = 0; t < nt; ++t) {
+        for (int j = 0; j < 3; ++j)
+            if (tris[3 * t + j] < 0 || tris[3 * t + j] >= nv)
+                return fail(IPT_ERR_BAD_SCENE, "triangle %lld references vertex %d out of range", (long long)t,
+                            tris[3 * t + j]);
+        if (tri_seg[t] < 0 || tri_seg[t] >= num_segments)
+            return fail(IPT_ERR_BAD_SCENE, "triangle %lld has segment %d out of range", (long long)t, tri_seg[t]);
+    }
+    std::vector<int> seg_emitter(num_segments, -1);
+    for (int k = 0; k < num_emitters; ++k) {
+        int s = emitter_seg[k];
+        if (s < 0 || s >= num_segments) return fail(IPT_ERR_BAD_SCENE, "emitter %d segment %d out of range", k, s);
+        if (seg_emitter[s] >= 0) return fail(IPT_ERR_BAD_SCENE, "segment %d listed twice as emitter", s);
+        seg_emitter[s] = k;
+    }
+    int64_t P = 7 * (int64_t)num_segments + 3 * (int64_t)num_emitters;
+    if (P > 8192) return fail(IPT_ERR_NOT_SUPPORTED, "parameter vector too long (%lld > 8192)", (long long)P);
+
+    auto t0 = std::chrono::steady_clock::now();
+    BvhOut bvh;
+    if (!build_bvh_host(verts, tris, nt, bvh)) return fail(IPT_ERR_BAD_SCENE, "BVH build failed");
+    if (bvh.depth > kShortStack + kOvfDepth)
+        return fail(IPT_ERR_NOT_SUPPORTED, "BVH depth %d exceeds the traversal stack", bvh.depth);
+    auto t1 = std::chrono::steady_clock::now();
+
+    // leaf-ordered triangle records; light table in ascending input-id order
+    std::vector<int> pos_of(nt);
+    for (int64_t p = 0; p < nt; ++p) pos_of[bvh.leaf_order[p]] = (int)p;
+    std::vector<int4> lights;
+    std::vector<int> light_of_tri(nt, -1);
+    for (int64_t t = 0; t < nt; ++t) {
+        int k = seg_emitter[tri_seg[t]];
+        if (k < 0) continue;
+        const float* a = verts + 3 * (int64_t)tris[3 * t];
+        const float* b = verts + 3 * (int64_t)tris[3 * t + 1];
+        const float* c = verts + 3 * (int64_t)tris[3 * t + 2];
+        double e1[3], e2[3];
+        for (int i = 0; i < 3; ++i) { e1[i] = (double)b[i] - a[i]; e2[i] = (double)c[i] - a[i]; }
+        double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+               cz = e1[0] * e2[1] - e1[1] * e2[0];
+        float area = (float)(0.5 * std::sqrt(cx * cx + cy * cy + cz * cz));
+        if (!(area > 0.0f)) return fail(IPT_ERR_BAD_SCENE, "emitter triangle %lld has zero area", (long long)t);
+        int4 L;
+        L.x = pos_of[t];
+        L.y = k;
+        std::memcpy(&L.z, &area, 4);
+        L.w = (int)t;
+        light_of_tri[t] = (int)lights.size();
+        lights.push_back(L);
+    }
+    std::vector<float4> trec(3 * nt);
+    std::vector<float4> nrec;
+    if (normals) nrec.resize(3 * nt);
+    for (int64_t p = 0; p < nt; ++p) {
+        int t = bvh.leaf_order[p];
+        for (int j = 0; j < 3; ++j) {
+            const float* v = verts + 3 * (int64_t)tris[3 * (int64_t)t + j];
+            int tag = j == 0 ? t : (j == 1 ? tri_seg[t] : light_of_tri[t]);
+            float tf;
+            std::memcpy(&tf, &tag, 4);
+            trec[3 * p + j] = make_float4(v[0], v[1], v[2], tf);
+            if (normals) {
+                const float* n = normals + 3 * (int64_t)tris[3 * (int64_t)t + j];
+                nrec[3 * p + j] = make_float4(n[0], n[1], n[2], 0.0f);
+            }
+        }
+    }
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < nv; ++i)
+        for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], verts[3 * i + a]); hi[a] = std::max(hi[a], verts[3 * i + a]); }
+    double diag = std::sqrt((double)(hi[0] - lo[0]) * (hi[0] - lo[0]) + (double)(hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                            (double)(hi[2] - lo[2]) * (hi[2] - lo[2]));
+
+    ipt_scene_t s = new ipt_scene_s();
+    HIP_OK(hipGetDevice(&s->device));
+    HIP_OK(hipDeviceGetAttribute(&s->num_cu, hipDeviceAttributeMultiprocessorCount, s->device));
+    auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess) return e;
+        if (bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up((void**)&s->d_nodes, bvh.nodes.data(), bvh.nodes.size() * sizeof(float));
+    if (e == hipSuccess) e = up((void**)&s->d_tris, trec.data(), trec.size() * sizeof(float4));
+    if (e == hipSuccess && normals) e = up((void**)&s->d_nrm, nrec.data(), nrec.size() * sizeof(float4));
+    if (e == hipSuccess) e = up((void**)&s->d_lights, lights.data(), lights.size() * sizeof(int4));
+    if (e == hipSuccess) e = up((void**)&s->d_segemit, seg_emitter.data(), seg_emitter.size() * sizeof(int));
+    if (e == hipSuccess) e = up((void**)&s->d_pos_of, pos_of.data(), pos_of.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_err, sizeof(Counters));
+    if (e == hipSuccess) e = hipMemset(s->d_err, 0, sizeof(Counters));
+    if (e == hipSuccess)
+        e = hipMalloc((void**)&s->d_ovf_rays,
+                      sizeof(int) * (size_t)kOvfDepth * trace_rays_grid(s->num_cu) * kBlock);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        ipt_scene_free(s);
+        return fail(e == hipErrorOutOfMemory ? IPT_ERR_OUT_OF_MEMORY : IPT_ERR_HIP, "scene upload: %s",
+                    hipGetErrorString(e));
+    }
+    s->nt = nt;
+    s->nv = nv;
+    s->nnodes = bvh.num_nodes;
+    s->S = num_segments;
+    s->E = num_emitters;
+    s->nlt = (int)lights.size();
+    s->depth = bvh.depth;
+    s->has_normals = normals != nullptr;
+    s->sah = bvh.sah_cost;
+    s->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    s->diag = (float)diag;
+    for (int a = 0; a < 3; ++a) { s->bb_lo[a] = lo[a]; s->bb_hi[a] = hi[a]; }
+    s->dev.nodes = s->d_nodes;
+    s->dev.tris = s->d_tris;
+    s->dev.nrm = s->d_nrm;
+    s->dev.lights = s->d_lights;
+    s->dev.seg_emitter = s->d_segemit;
+    s->dev.pos_of = s->d_pos_of;
+    s->dev.S = num_segments;
+    s->dev.E = num_emitters;
+    s->dev.nlt = s->nlt;
+    s->dev.tmin = (float)(1e-6 * diag);
+    *out = s;
+    return IPT_OK;
+}
+
+extern "C" ipt_status ipt_scene_info(ipt_scene_t s, ipt_scene_info_t* out) {
+    if (!s || !out) return fail(IPT_ERR_INVALID_ARG, "NULL scene or out");
+    Counters c;
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(&c, s->d_err, sizeof(Counters), hipMemcpyDeviceToHost));
+    out->num_triangles = s->nt;
+    out->num_vertices = s->nv;
+    out->num_nodes = s->nnodes;
+    out->num_light_triangles = s->nlt;
+    out->num_segments = s->S;
+    out->num_emitters = s->E;
+    out->bvh_depth = s->depth;
+    out->has_normals = s->has_normals;
+    out->sah_cost = s->sah;
+    out->build_ms = s->build_ms;
+    out->scene_diag = s->diag;
+    out->nonfinite_paths = c.nonfinite;
+    out->stack_overflows = c.overflow;
+    return IPT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Options and workspace.
+// ---------------------------------------------------------------------------
+static ipt_status check_opts(const ipt_scene_s* s, const ipt_cameras* cams, const ipt_render_opts* o,
+                             int64_t* npix) {
+    if (!cams || !o) return fail(IPT_ERR_INVALID_ARG, "NULL cameras or options");
+    if (cams->num_views < 1 || cams->width < 1 || cams->height < 1 || !cams->cam_to_world || !cams->fov_y)
+        return fail(IPT_ERR_INVALID_ARG, "bad cameras");
+    if (o->spp < 1) return fail(IPT_ERR_INVALID_ARG, "spp must be >= 1");
+    if (o->max_depth < 1 || o->max_depth > kMaxDepth) return fail(IPT_ERR_INVALID_ARG, "max_depth must be in [1, %d]", kMaxDepth);
+    if (o->mis < 0 || o->mis > 3) return fail(IPT_ERR_INVALID_ARG, "mis must be 0..3");
+    if (o->emission_profile < 0 || o->emission_profile > 1) return fail(IPT_ERR_INVALID_ARG, "emission_profile must be 0/1");
+    if (o->guide) return fail(IPT_ERR_NOT_SUPPORTED, "guided sampling is not available in this call");
+    int64_t all = (int64_t)cams->num_views * cams->width * cams->height;
+    if (o->pixel_list) {
+        if (o->num_pixels < 1) return fail(IPT_ERR_INVALID_ARG, "num_pixels must be >= 1 with a pixel list");
+        *npix = o->num_pixels;
+    } else {
+        *npix = all;
+    }
+    (void)s;
+    return IPT_OK;
+}
+
+static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Plan {
+    int grid = 0;
+    size_t off_counters = 0, off_cdf = 0, off_loss = 0, off_w = 0, off_img = 0, off_gpart = 0, off_ovf = 0,
+           off_ck = 0, end_fixed = 0;
+    int64_t chunk = 0;         // work pixels per gradient chunk
+    size_t ck_per_pixel = 0;   // checkpoint bytes per work pixel
+};
+
+static int path_grid(const ipt_scene_s* s, int P, int frozen) {
+    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt));
+    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt)));
+    occ = std::min(occ, path_blocks_per_cu(kReplay, path_lds_bytes(kReplay, P, frozen, s->S, s->nlt)));
+    occ = std::max(1, std::min(occ, 8));
+    return s->num_cu * occ;
+}
+
+static void make_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t npix, bool with_loss, Plan& pl) {
+    int P = 7 * s->S + 3 * s->E;
+    pl.grid = path_grid(s, P, 1);
+    size_t off = 0;
+    pl.off_counters = off; off = al256(off + 64 * sizeof(unsigned));
+    pl.off_cdf = off; off = al256(off + sizeof(float) * std::max(1, s->nlt));
+    pl.off_loss = off; off = al256(off + sizeof(float) * 1024);
+    pl.off_w = off; off = al256(off + (with_loss ? sizeof(float) * 3 * npix : 0));
+    pl.off_img = off; off = al256(off + (with_loss ? sizeof(float) * 3 * npix : 0));
+    pl.off_gpart = off; off = al256(off + sizeof(float) * (size_t)pl.grid * P);
+    pl.off_ovf = off; off = al256(off + sizeof(int) * (size_t)kOvfDepth * pl.grid * kBlock);
+    pl.off_ck = off;
+    pl.end_fixed = off;
+    pl.ck_per_pixel = (size_t)(o->max_depth + 1) * o->spp * (sizeof(int4) + 2 * sizeof(float4));
+}
+
+static size_t plan_min(const Plan& pl, int64_t npix) {
+    int64_t c = std::min<int64_t>(npix, kBlock);
+    return pl.end_fixed + 3 * 256 + (size_t)c * pl.ck_per_pixel;
+}
+static size_t plan_full(const Plan& pl, int64_t npix) { return pl.end_fixed + 3 * 256 + (size_t)npix * pl.ck_per_pixel; }
+
+extern "C" ipt_status ipt_workspace_query(ipt_scene_t s, const ipt_cameras* cams, const ipt_render_opts* o,
+                                          size_t* min_bytes, size_t* full_bytes) {
+    if (!s || !min_bytes || !full_bytes) return fail(IPT_ERR_INVALID_ARG, "NULL argument");
+    int64_t npix = 0;
+    ipt_status st = check_opts(s, cams, o, &npix);
+    if (st != IPT_OK) return st;
+    Plan pl;
+    make_plan(s, o, npix, true, pl);
+    *min_bytes = plan_min(pl, npix);
+    *full_bytes = plan_full(pl, npix);
+    return IPT_OK;
+}
+
+static PathArgs base_args(const ipt_scene_s* s, const ipt_cameras* cams, const float* params, const float* sp,
+                          const ipt_render_opts* o, unsigned char* ws, const Plan& pl) {
+    PathArgs a{};
+    a.sc = s->dev;
+    a.c2w = cams->cam_to_world;
+    a.fov = cams->fov_y;
+    a.V = cams->num_views;
+    a.W = cams->width;
+    a.H = cams->height;
+    a.params = params;
+    a.sparams = sp ? sp : params;
+    a.frozen = (sp && sp != params) ? 1 : 0;
+    a.P = 7 * s->S + 3 * s->E;
+    a.cdf = (const float*)(ws + pl.off_cdf);
+    a.rng.k0 = (uint32_t)o->seed ^ (o->stream_tag * 0x9E3779B9u);
+    a.rng.k1 = (uint32_t)(o->seed >> 32);
+    a.rng.iteration = o->iteration;
+    a.spp = o->spp;
+    a.D = o->max_depth;
+    a.rr_depth = o->rr_depth;
+    a.mis = o->mis;
+    a.profile = o->emission_profile;
+    a.jitter = o->jitter;
+    a.pixel_list = o->pixel_list;
+    a.hash = o->debug_path_hash;
+    a.mask = o->path_mask;
+    a.work = (unsigned*)(ws + pl.off_counters);
+    a.err = s->d_err;
+    a.ovf = (int*)(ws + pl.off_ovf);
+    a.grad_part = (float*)(ws + pl.off_gpart);
+    a.replay_traverse = o->replay_traverse;
+    a.gmix = 0.0f;
+    return a;
+}
+
+static ipt_status do_render(ipt_scene_t s, const ipt_cameras* cams, const float* params, const float* sp,
+                            const ipt_render_opts* o, int64_t npix, float* image, unsigned char* ws,
+                            const Plan& pl, hipStream_t st) {
+    PathArgs a = base_args(s, cams, params, sp, o, ws, pl);
+    a.image = image;
+    a.pix_begin = 0;
+    a.pix_count = npix;
+    HIP_OK(launch_light_cdf(s->dev, a.sparams, (float*)(ws + pl.off_cdf), st));
+    HIP_OK(launch_zero_u32(a.work, 1, st));
+    size_t lds = path_lds_bytes(kColor, a.P, a.frozen, s->S, s->nlt);
+    int grid = std::min<int64_t>(pl.grid, (npix + kBlock - 1) / kBlock);
+    HIP_OK(launch_paths(kColor, a, std::max(1, grid), lds, st));
+    return IPT_OK;
+}
+
+static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* params, const float* sp,
+                          const ipt_render_opts* o, int64_t npix, const float* w, float* grad, unsigned char* ws,
+                          size_t ws_bytes, const Plan& pl, hipStream_t st) {
+    PathArgs a = base_args(s, cams, params, sp, o, ws, pl);
+    a.w = w;
+    // chunk size from the space left for checkpoints
+    size_t avail = ws_bytes > pl.end_fixed + 3 * 256 ? ws_bytes - pl.end_fixed - 3 * 256 : 0;
+    int64_t chunk = (int64_t)(avail / pl.ck_per_pixel);
+    if (chunk < npix) chunk = (chunk / kBlock) * kBlock;
+    chunk = std::min<int64_t>(chunk, npix);
+    if (chunk < 1) return fail(IPT_ERR_WORKSPACE_TOO_SMALL, "workspace too small for one gradient chunk");
+    size_t rec = (size_t)(o->max_depth + 1) * o->spp * (size_t)chunk;
+    unsigned char* ck = ws + pl.off_ck;
+    a.ck_hit = (int4*)ck;
+    a.ck_a = (float4*)(ck + al256(rec * sizeof(int4)));
+    a.ck_c = (float4*)(ck + al256(rec * sizeof(int4)) + al256(rec * sizeof(float4)));
+    HIP_OK(launch_light_cdf(s->dev, a.sparams, (float*)(ws + pl.off_cdf), st));
+    size_t lds_f = path_lds_bytes(kGradFwd, a.P, a.frozen, s->S, s->nlt);
+    size_t lds_r = path_lds_bytes(kReplay, a.P, a.frozen, s->S, s->nlt);
+    for (int64_t b = 0; b < npix; b += chunk) {
+        a.pix_begin = b;
+        a.pix_count = std::min<int64_t>(chunk, npix - b);
+        int grid = (int)std::max<int64_t>(1, std::min<int64_t>(pl.grid, (a.pix_count + kBlock - 1) / kBlock));
+        HIP_OK(launch_zero_u32(a.work, 1, st));
+        HIP_OK(launch_paths(kGradFwd, a, grid, lds_f, st));
+        HIP_OK(launch_zero_u32(a.work, 1, st));
+        HIP_OK(launch_paths(kReplay, a, grid, lds_r, st));
+        HIP_OK(launch_grad_reduce(a.grad_part, grid, a.P, grad, b > 0 ? 1 : 0, st));
+    }
+    return IPT_OK;
+}
+
+extern "C" ipt_status ipt_render(ipt_scene_t s, const ipt_cameras* cams, const float* params,
+                                 const float* sampling_params, const ipt_render_opts* o, float* image,
+                                 void* workspace, size_t workspace_bytes, void* hip_stream) {
+    if (!s || !params || !image) return fail(IPT_ERR_INVALID_ARG, "NULL scene/params/image");
+    int64_t npix = 0;
+    ipt_status stt = check_opts(s, cams, o, &npix);
+    if (stt != IPT_OK) return stt;
+    Plan pl;
+    make_plan(s, o, npix, false, pl);
+    if (!workspace || workspace_bytes < pl.end_fixed)
+        return fail(IPT_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", pl.end_fixed);
+    return do_render(s, cams, params, sampling_params, o, npix, image, (unsigned char*)workspace, pl,
+                     (hipStream_t)hip_stream);
+}
+
+extern "C" ipt_status ipt_render_grad(ipt_scene_t s, const ipt_cameras* cams, const float* params,
+                                      const float* sampling_params, const ipt_render_opts* o, const float* w,
+                                      float* grad, void* workspace, size_t workspace_bytes, void* hip_stream) {
+    if (!s || !params || !w || !grad) return fail(IPT_ERR_INVALID_ARG, "NULL scene/params/w/grad");
+    int64_t npix = 0;
+    ipt_status stt = check_opts(s, cams, o, &npix);
+    if (stt != IPT_OK) return stt;
+    Plan pl;
+    make_plan(s, o, npix, false, pl);
+    if (!workspace || workspace_bytes < plan_min(pl, npix))
+        return fail(IPT_ERR_WORKSPACE_TOO_SMALL, "workspace needs at least %zu bytes", plan_min(pl, npix));
+    return do_grad(s, cams, params, sampling_params, o, npix, w, grad, (unsigned char*)workspace, workspace_bytes,
+                   pl, (hipStream_t)hip_stream);
+}
+
+extern "C" ipt_status ipt_loss_grad(ipt_scene_t s, const ipt_cameras* cams, const float* params,
+                                    const float* target, const ipt_render_opts* co, const ipt_render_opts* go,
+                                    int32_t loss_kind, float* loss, float* grad, float* image_A, void* workspace,
+                                    size_t workspace_bytes, void* hip_stream) {
+    if (!s || !params || !target || !loss || !grad) return fail(IPT_ERR_INVALID_ARG, "NULL argument");
+    if (loss_kind != 0 && loss_kind != 1) return fail(IPT_ERR_INVALID_ARG, "loss_kind must be 0 or 1");
+    int64_t npa = 0, npb = 0;
+    ipt_status stt = check_opts(s, cams, co, &npa);
+    if (stt != IPT_OK) return stt;
+    stt = check_opts(s, cams, go, &npb);
+    if (stt != IPT_OK) return stt;
+    if (npa != npb || (co->pixel_list == nullptr) != (go->pixel_list == nullptr))
+        return fail(IPT_ERR_INVALID_ARG, "colour and gradient options must cover the same pixels");
+    Plan pl;
+    make_plan(s, go, npb, true, pl);
+    if (!workspace || workspace_bytes < plan_min(pl, npb))
+        return fail(IPT_ERR_WORKSPACE_TOO_SMALL, "workspace needs at least %zu bytes", plan_min(pl, npb));
+    unsigned char* ws = (unsigned char*)workspace;
+    hipStream_t st = (hipStream_t)hip_stream;
+    float* img = image_A ? image_A : (float*)(ws + pl.off_img);
+    float* w = (float*)(ws + pl.off_w);
+    stt = do_render(s, cams, params, nullptr, co, npa, img, ws, pl, st);
+    if (stt != IPT_OK) return stt;
+    HIP_OK(launch_loss_adjoint(img, target, 3 * npa, loss_kind, w, (float*)(ws + pl.off_loss), 1024, loss, st));
+    return do_grad(s, cams, params, nullptr, go, npb, w, grad, ws, workspace_bytes, pl, st);
+}
+
+extern "C" ipt_status ipt_sgd_step(float* params, const float* grad, float* m, float* v, int32_t P, int32_t step,
+                                   const ipt_adam_opts* adam, const float* scale, const float* lo, const float* hi,
+                                   const uint8_t* trainable, void* hip_stream) {
+    if (!params || !grad || !m || !v || !adam) return fail(IPT_ERR_INVALID_ARG, "NULL argument");
+    if (P < 1 || step < 1) return fail(IPT_ERR_INVALID_ARG, "need P >= 1 and step >= 1");
+    if (!(adam->lr > 0.0f) || !(adam->beta1 >= 0.0f && adam->beta1 < 1.0f) ||
+        !(adam->beta2 >= 0.0f && adam->beta2 < 1.0f) || !(adam->eps > 0.0f))
+        return fail(IPT_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+    HIP_OK(launch_adam(params, grad, m, v, P, step, adam->lr, adam->beta1, adam->beta2, adam->eps, scale, lo, hi,
+                       trainable, (hipStream_t)hip_stream));
+    return IPT_OK;
+}
+
+extern "C" ipt_status ipt_trace_rays(ipt_scene_t s, const float* origins, const float* dirs, const int32_t* skip_tri,
+                                     int64_t n, float tmin, int32_t brute_force, int32_t* out_tri, float* out_tuv,
+                                     void* hip_stream) {
+    if (!s || !origins || !dirs || !out_tri || !out_tuv) return fail(IPT_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(IPT_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return IPT_OK;
+    HIP_OK(launch_trace_rays(s->dev, origins, dirs, skip_tri, n, tmin, brute_force, s->nt, out_tri, out_tuv,
+                             s->d_ovf_rays, trace_rays_grid(s->num_cu), s->d_err, (hipStream_t)hip_stream));
+    return IPT_OK;
+}
+
+// Guide entry points (not yet available).
+extern "C" ipt_status ipt_guide_create(ipt_scene_t, const ipt_guide_opts*, void*, ipt_guide_t* out) {
+    if (out) *out = nullptr;
+    return fail(IPT_ERR_NOT_SUPPORTED, "guide not available");
+}
+extern "C" ipt_status ipt_guide_free(ipt_guide_t) { return IPT_OK; }
+extern "C" ipt_status ipt_guide_eval(ipt_guide_t, const float*, const int32_t*, int64_t, float*, void*) {
+    return fail(IPT_ERR_NOT_SUPPORTED, "guide not available");
+}
+extern "C" ipt_status ipt_guide_train(ipt_guide_t, const ipt_cameras*, const float*, const ipt_render_opts*,
+                                      int32_t, void*, size_t, void*) {
+    return fail(IPT_ERR_NOT_SUPPORTED, "guide not available");
+}

@@ -1,0 +1,97 @@
+// Internal host/device interface between the C ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ipt_math.h"
+
+namespace ipt {
+
+constexpr int kBlock = 256;       // threads per block of the path kernels
+constexpr int kShortStack = 16;   // per-lane LDS stack entries (power of two)
+constexpr int kOvfDepth = 48;     // per-lane global overflow entries
+constexpr int kNone = 0x7FFFFFFF; // empty child slot
+constexpr int kMaxDepth = 16;     // max scattering vertices per path
+constexpr int kMaxLdsLights = 1024;
+
+// Checkpoint record flags (packed with tri+1 in the low 28 bits).
+constexpr uint32_t kCkTriMask = 0x0FFFFFFFu;
+constexpr uint32_t kCkVis = 1u << 28;    // next-event shadow ray unoccluded
+constexpr uint32_t kCkCont = 1u << 29;   // path continued from this vertex
+constexpr uint32_t kCkDrop = 1u << 30;   // (vertex 1) path dropped: non-finite
+
+// Device view of a built scene.
+struct SceneDev {
+    const float4* nodes;   // 4 x float4 per node: child boxes + (child0, child1)
+    const float4* tris;    // 3 x float4 per leaf-ordered triangle:
+                           //   (v0, orig id), (v1, segment), (v2, light index or -1)
+    const float4* nrm;     // 3 x float4 per leaf-ordered triangle, or NULL
+    const int4* lights;    // [nlt]: (leaf tri, emitter index, area bits, orig id)
+    const int* seg_emitter;// [S]: emitter index or -1
+    const int* pos_of;     // [nt]: input triangle id -> leaf position
+    int S, E, nlt;
+    float tmin;            // ray epsilon (1e-6 of the scene diagonal)
+};
+
+struct Counters {
+    unsigned long long nonfinite;
+    unsigned long long overflow;
+};
+
+enum Mode { kColor = 0, kGradFwd = 1, kReplay = 2 };
+
+struct PathArgs {
+    SceneDev sc;
+    const float* c2w;
+    const float* fov;
+    int V, W, H;
+    const float* params;
+    const float* sparams;
+    int P;
+    int frozen;              // sparams differs from params
+    const float* cdf;        // [nlt] inclusive prefix sums of light weights
+    Rng rng;
+    int spp, D, rr_depth, mis, profile, jitter;
+    const int64_t* pixel_list;
+    int64_t pix_begin, pix_count;  // work-pixel chunk
+    float* image;                  // colour: [pixels][3]
+    uint64_t* hash;                // [pixels*spp] or NULL
+    const uint8_t* mask;           // [pixels*spp] or NULL
+    int4* ck_hit;                  // checkpoint planes, [(k-1)*spp + s][pix_count]
+    float4* ck_a;
+    float4* ck_c;
+    const float* w;                // replay: adjoint image [pixels][3]
+    float* grad_part;              // replay: [gridDim.x][P]
+    unsigned* work;                // dynamic tile counter (zeroed before launch)
+    Counters* err;
+    int* ovf;                      // [kOvfDepth][grid threads]
+    int replay_traverse;
+    // guide (one-sample MIS with BRDF sampling); gmix = 0 disables it
+    const void* guide;
+    float gmix;
+    float* guide_rec;              // training records or NULL
+    unsigned* guide_rec_count;
+    int guide_rec_cap;
+    float3 bb_lo, bb_inv;          // scene box for guide features
+};
+
+size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt);
+int path_blocks_per_cu(int mode, size_t lds);
+hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
+hipError_t launch_light_cdf(const SceneDev& sc, const float* sparams, float* cdf, hipStream_t st);
+hipError_t launch_loss_adjoint(const float* img, const float* target, int64_t n3, int kind,
+                               float* w, float* partials, int nparts, float* loss,
+                               hipStream_t st);
+hipError_t launch_grad_reduce(const float* part, int nblocks, int P, float* grad, int accumulate,
+                              hipStream_t st);
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int P, int step,
+                       float lr, float b1, float b2, float eps, const float* scale,
+                       const float* lo, const float* hi, const uint8_t* trainable,
+                       hipStream_t st);
+hipError_t launch_trace_rays(const SceneDev& sc, const float* o, const float* d, const int* skip,
+                             int64_t n, float tmin, int brute, int64_t nt, int* out_tri,
+                             float* out_tuv, int* ovf, int grid, Counters* err, hipStream_t st);
+int trace_rays_grid(int num_cu);
+
+}  // namespace ipt

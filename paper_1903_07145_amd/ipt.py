@@ -1,0 +1,254 @@
+"""ctypes binding of libipt.so (the C ABI in include/ipt.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libipt.so.  Device buffers are torch tensors on the current HIP device; the
+work is enqueued on torch's current stream.  There is no CPU fallback: if the
+library is missing or no GPU is present, calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libipt.so")
+
+IPT_OK = 0
+_STATUS = {0: "IPT_OK", 1: "IPT_ERR_INVALID_ARG", 2: "IPT_ERR_BAD_SCENE", 3: "IPT_ERR_OUT_OF_MEMORY",
+           4: "IPT_ERR_WORKSPACE_TOO_SMALL", 5: "IPT_ERR_HIP", 6: "IPT_ERR_NOT_SUPPORTED"}
+
+EXPORTS = ["ipt_scene_build", "ipt_scene_free", "ipt_scene_info", "ipt_workspace_query", "ipt_render",
+           "ipt_render_grad", "ipt_loss_grad", "ipt_sgd_step", "ipt_trace_rays", "ipt_guide_create",
+           "ipt_guide_free", "ipt_guide_eval", "ipt_guide_train", "ipt_last_error"]
+
+
+class IPTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Cameras(ctypes.Structure):
+    _fields_ = [("num_views", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("cam_to_world", ctypes.c_void_p), ("fov_y", ctypes.c_void_p)]
+
+
+class RenderOpts(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("stream_tag", ctypes.c_uint32), ("iteration", ctypes.c_uint32),
+                ("spp", ctypes.c_int32), ("max_depth", ctypes.c_int32), ("rr_depth", ctypes.c_int32),
+                ("mis", ctypes.c_int32), ("emission_profile", ctypes.c_int32), ("jitter", ctypes.c_int32),
+                ("replay_traverse", ctypes.c_int32), ("pixel_list", ctypes.c_void_p),
+                ("num_pixels", ctypes.c_int64), ("guide", ctypes.c_void_p), ("guide_mix", ctypes.c_float),
+                ("debug_path_hash", ctypes.c_void_p), ("path_mask", ctypes.c_void_p)]
+
+
+class AdamOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+class SceneInfo(ctypes.Structure):
+    _fields_ = [("num_triangles", ctypes.c_int64), ("num_vertices", ctypes.c_int64),
+                ("num_nodes", ctypes.c_int64), ("num_light_triangles", ctypes.c_int64),
+                ("num_segments", ctypes.c_int32), ("num_emitters", ctypes.c_int32),
+                ("bvh_depth", ctypes.c_int32), ("has_normals", ctypes.c_int32),
+                ("sah_cost", ctypes.c_double), ("build_ms", ctypes.c_double), ("scene_diag", ctypes.c_float),
+                ("nonfinite_paths", ctypes.c_uint64), ("stack_overflows", ctypes.c_uint64)]
+
+
+class GuideOpts(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("lr", ctypes.c_float), ("batch", ctypes.c_int32),
+                ("ring_capacity", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libipt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libipt.so not built: run __graft_entry__.build() or "
+                               "python -m paper_1903_07145_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        sig = {
+            "ipt_scene_build": [P, I64, P, P, P, I64, I32, P, I32, P, P],
+            "ipt_scene_free": [P],
+            "ipt_scene_info": [P, P],
+            "ipt_workspace_query": [P, P, P, P, P],
+            "ipt_render": [P, P, P, P, P, P, P, SZ, P],
+            "ipt_render_grad": [P, P, P, P, P, P, P, P, SZ, P],
+            "ipt_loss_grad": [P, P, P, P, P, P, I32, P, P, P, P, SZ, P],
+            "ipt_sgd_step": [P, P, P, P, I32, I32, P, P, P, P, P, P],
+            "ipt_trace_rays": [P, P, P, P, I64, ctypes.c_float, I32, P, P, P],
+            "ipt_guide_create": [P, P, P, P],
+            "ipt_guide_free": [P],
+            "ipt_guide_eval": [P, P, P, I64, P, P],
+            "ipt_guide_train": [P, P, P, P, I32, P, SZ, P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.ipt_last_error.restype = ctypes.c_char_p
+        L.ipt_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != IPT_OK:
+        raise IPTError(status, lib().ipt_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_cuda:
+            raise ValueError("expected a device tensor")
+        if not t.is_contiguous():
+            raise ValueError("expected a contiguous tensor")
+        return ctypes.c_void_p(t.data_ptr())
+    return t
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, dtype):
+    if isinstance(x, torch.Tensor):
+        return x.to(device="cuda", dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda").contiguous()
+
+
+def make_cameras(cams):
+    """Device copies of a camera dict (cam_to_world [V,4,4], fov_y [V], width, height)."""
+    c2w = _dev(np.asarray(cams["cam_to_world"], np.float32).reshape(-1, 16), torch.float32)
+    fov = _dev(np.asarray(cams["fov_y"], np.float32).reshape(-1), torch.float32)
+    return dict(c2w=c2w, fov=fov, num_views=int(c2w.shape[0]), width=int(cams["width"]),
+                height=int(cams["height"]))
+
+
+def _cams_struct(dc):
+    return Cameras(dc["num_views"], dc["width"], dc["height"], dc["c2w"].data_ptr(), dc["fov"].data_ptr())
+
+
+def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=-1, mis=2,
+                emission_profile=0, jitter=1, replay_traverse=0, pixel_list=None, guide=None,
+                guide_mix=0.0, debug_path_hash=None, path_mask=None):
+    o = RenderOpts()
+    o.seed, o.stream_tag, o.iteration = int(seed), int(stream_tag), int(iteration)
+    o.spp, o.max_depth, o.rr_depth, o.mis = int(spp), int(max_depth), int(rr_depth), int(mis)
+    o.emission_profile, o.jitter, o.replay_traverse = int(emission_profile), int(jitter), int(replay_traverse)
+    o.pixel_list = None if pixel_list is None else pixel_list.data_ptr()
+    o.num_pixels = 0 if pixel_list is None else int(pixel_list.numel())
+    o.guide = None if guide is None else guide.handle
+    o.guide_mix = float(guide_mix)
+    o.debug_path_hash = None if debug_path_hash is None else debug_path_hash.data_ptr()
+    o.path_mask = None if path_mask is None else path_mask.data_ptr()
+    o._keep = (pixel_list, debug_path_hash, path_mask)
+    return o
+
+
+class Scene:
+    """A built scene on the current device (ipt_scene_build)."""
+
+    def __init__(self, verts, tris, tri_seg, num_segments, emitter_seg, normals=None):
+        v = np.ascontiguousarray(verts, np.float32)
+        t = np.ascontiguousarray(tris, np.int32)
+        s = np.ascontiguousarray(tri_seg, np.int32)
+        e = np.ascontiguousarray(emitter_seg, np.int32)
+        n = None if normals is None else np.ascontiguousarray(normals, np.float32)
+        self.num_segments = int(num_segments)
+        self.num_emitters = int(e.size)
+        self.P = 7 * self.num_segments + 3 * self.num_emitters
+        h = ctypes.c_void_p()
+        torch.cuda.init()
+        _check(lib().ipt_scene_build(v.ctypes.data_as(ctypes.c_void_p), v.shape[0],
+                                     None if n is None else n.ctypes.data_as(ctypes.c_void_p),
+                                     t.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p),
+                                     t.shape[0], self.num_segments, e.ctypes.data_as(ctypes.c_void_p),
+                                     e.size, _stream(), ctypes.byref(h)))
+        self.handle = h
+        self._ws = None
+
+    @classmethod
+    def from_dict(cls, sc):
+        return cls(sc["verts"], sc["tris"], sc["tri_seg"], sc["num_segments"], sc["emitter_seg"],
+                   sc.get("normals"))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ipt_scene_free(self.handle)
+            self.handle = None
+
+    def info(self):
+        inf = SceneInfo()
+        _check(lib().ipt_scene_info(self.handle, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in SceneInfo._fields_}
+
+    def workspace_query(self, dcams, opts):
+        mn, full = ctypes.c_size_t(), ctypes.c_size_t()
+        C = _cams_struct(dcams)
+        _check(lib().ipt_workspace_query(self.handle, ctypes.byref(C), ctypes.byref(opts), ctypes.byref(mn),
+                                         ctypes.byref(full)))
+        return mn.value, full.value
+
+    def workspace(self, dcams, opts, budget=48 << 30):
+        mn, full = self.workspace_query(dcams, opts)
+        need = max(mn, min(full, budget))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            torch.cuda.empty_cache()
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def render(self, dcams, params, opts, sampling_params=None, out=None):
+        npix = opts.num_pixels or dcams["num_views"] * dcams["width"] * dcams["height"]
+        img = out if out is not None else torch.empty((npix, 3), dtype=torch.float32, device="cuda")
+        ws = self.workspace(dcams, opts)
+        C = _cams_struct(dcams)
+        _check(lib().ipt_render(self.handle, ctypes.byref(C), _ptr(params), _ptr(sampling_params),
+                                ctypes.byref(opts), _ptr(img), _ptr(ws), ws.numel(), _stream()))
+        return img
+
+    def render_grad(self, dcams, params, w, opts, sampling_params=None, out=None, workspace_bytes=None):
+        grad = out if out is not None else torch.empty(self.P, dtype=torch.float32, device="cuda")
+        ws = self.workspace(dcams, opts)
+        nb = ws.numel() if workspace_bytes is None else min(ws.numel(), int(workspace_bytes))
+        C = _cams_struct(dcams)
+        _check(lib().ipt_render_grad(self.handle, ctypes.byref(C), _ptr(params), _ptr(sampling_params),
+                                     ctypes.byref(opts), _ptr(w), _ptr(grad), _ptr(ws), nb, _stream()))
+        return grad
+
+    def loss_grad(self, dcams, params, target, color_opts, grad_opts, loss_kind=0, loss=None, grad=None,
+                  image=None):
+        loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device="cuda")
+        grad = grad if grad is not None else torch.empty(self.P, dtype=torch.float32, device="cuda")
+        ws = self.workspace(dcams, grad_opts)
+        C = _cams_struct(dcams)
+        _check(lib().ipt_loss_grad(self.handle, ctypes.byref(C), _ptr(params), _ptr(target),
+                                   ctypes.byref(color_opts), ctypes.byref(grad_opts), int(loss_kind), _ptr(loss),
+                                   _ptr(grad), _ptr(image), _ptr(ws), ws.numel(), _stream()))
+        return loss, grad
+
+    def trace_rays(self, origins, dirs, skip=None, tmin=0.0, brute_force=False):
+        n = origins.shape[0]
+        tri = torch.empty(n, dtype=torch.int32, device="cuda")
+        tuv = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+        _check(lib().ipt_trace_rays(self.handle, _ptr(origins), _ptr(dirs), _ptr(skip), n, float(tmin),
+                                    int(brute_force), _ptr(tri), _ptr(tuv), _stream()))
+        return tri, tuv
+
+
+def sgd_step(params, grad, m, v, step, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, scale=None, lo=None,
+             hi=None, trainable=None):
+    """Projected Adam step on the device (ipt_sgd_step), in place."""
+    a = AdamOpts(lr, beta1, beta2, eps)
+    _check(lib().ipt_sgd_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(step),
+                              ctypes.byref(a), _ptr(scale), _ptr(lo), _ptr(hi), _ptr(trainable), _stream()))

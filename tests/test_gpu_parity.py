@@ -1,0 +1,225 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle on
+the same seeded inputs and the same Philox streams.
+
+Bars: hit/event mismatches <= 1e-5 of rays (paths whose event hashes differ
+are excluded from the value comparisons); per-pixel radiance relative error
+<= 1e-4 in FP32 against FP64; gradient relative error <= 1e-3 (relative to
+max(|g|, 1e-2 rms(g))) with the mismatching paths masked on both sides."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from _gpu import banner, both, dev, gpu_grad, gpu_render, image_parity, oracle_opts
+from paper_1903_07145_amd import ipt, scenes
+
+pytestmark = pytest.mark.gpu
+
+RAY_BAR = 1e-5
+PIX_REL = 1e-4
+GRAD_REL = 1e-3
+
+
+def _rays(D, paths):
+    # lower bound on rays per path: camera ray plus the shadow and continuation
+    # rays of the first vertex
+    return paths * 3
+
+
+def _grad_parity(g_gpu, g_orc, rel=GRAD_REL):
+    rms = math.sqrt(np.mean(g_orc ** 2)) + 1e-30
+    err = np.abs(g_gpu - g_orc) / np.maximum(np.abs(g_orc), 1e-2 * rms)
+    return err.max(), err
+
+
+@pytest.fixture(scope="module")
+def cornell():
+    sc = scenes.cornell()
+    g, o = both(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    return sc, g, o, dc
+
+
+def test_hits_bvh_equals_brute_and_oracle(cornell):
+    banner("hits: cornell BVH vs brute force vs oracle")
+    sc, g, o, dc = cornell
+    rng = np.random.default_rng(0)
+    n = 20000
+    org = rng.uniform(0.02, 0.98, size=(n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    tri_b, tuv_b = g.trace_rays(dev(org), dev(d))
+    tri_f, tuv_f = g.trace_rays(dev(org), dev(d), brute_force=True)
+    torch.cuda.synchronize()
+    tri_b, tri_f = tri_b.cpu().numpy(), tri_f.cpu().numpy()
+    assert np.array_equal(tri_b, tri_f)
+    assert np.array_equal(tuv_b.cpu().numpy(), tuv_f.cpu().numpy())
+    mism = 0
+    tb = tuv_b.cpu().numpy()
+    for i in range(0, n, 4):
+        t_o, h_o = o.closest_hit(org[i].astype(np.float64), d[i].astype(np.float64))
+        if t_o != tri_b[i]:
+            mism += 1
+        elif t_o >= 0:
+            assert abs(tb[i, 0] - h_o[0]) <= 1e-5 * max(1.0, h_o[0])
+    assert mism <= max(1, int(RAY_BAR * n / 4))
+
+
+@pytest.mark.parametrize("mis", [0, 1, 2, 3])
+def test_render_parity_cornell(cornell, mis):
+    banner("render parity cornell mis=%d" % mis)
+    sc, g, o, dc = cornell
+    kw = dict(seed=11, stream_tag=1, iteration=3, spp=4, max_depth=3, mis=mis)
+    img_g, h_g = gpu_render(g, dc, sc["params"], kw)
+    r = o.run(sc["cams"], sc["params"], want_hash=True, **oracle_opts(kw))
+    ok, mfrac, emax, _ = image_parity(img_g, r["image"], h_g, r["hash"])
+    n_mis = int(round(mfrac * h_g.size))
+    assert n_mis <= max(1, RAY_BAR * _rays(3, h_g.size)), n_mis
+    assert emax <= PIX_REL, emax
+    assert ok.mean() > 0.99
+
+
+def test_render_parity_cornell_rr_profile_spp1(cornell):
+    sc, g, o, dc = cornell
+    kw = dict(seed=5, stream_tag=1, iteration=0, spp=1, max_depth=6, rr_depth=2, mis=2, emission_profile=1)
+    img_g, h_g = gpu_render(g, dc, sc["params"], kw)
+    r = o.run(sc["cams"], sc["params"], want_hash=True, **oracle_opts(kw))
+    ok, mfrac, emax, _ = image_parity(img_g, r["image"], h_g, r["hash"])
+    assert mfrac * h_g.size <= 2
+    assert emax <= PIX_REL
+
+
+def test_grad_parity_cornell(cornell):
+    banner("gradient parity cornell")
+    sc, g, o, dc = cornell
+    rng = np.random.default_rng(1)
+    kw = dict(seed=12, stream_tag=2, iteration=7, spp=4, max_depth=3, mis=2)
+    _, h_g = gpu_render(g, dc, sc["params"], kw)
+    r = o.run(sc["cams"], sc["params"], want_hash=True, **oracle_opts(kw))
+    mask = (h_g == r["hash"]).astype(np.uint8)
+    w = rng.normal(size=(64 * 64, 3))
+    gg = gpu_grad(g, dc, sc["params"], w, kw, mask=mask)
+    go = o.run(sc["cams"], sc["params"], w=w, path_mask=mask, want_grad=True, **oracle_opts(kw))["grad"]
+    emax, err = _grad_parity(gg, go)
+    assert emax <= GRAD_REL, (emax, np.argmax(err), gg[np.argmax(err)], go[np.argmax(err)])
+
+
+def test_grad_parity_zero_params_and_frozen_sampling(cornell):
+    """kd = 0 and e = 0 channels keep live derivatives; sampling parameters
+    different from the rendered ones (the finite-difference setting)."""
+    sc, g, o, dc = cornell
+    p = sc["params"].copy()
+    p[0:3] = 0.0
+    p[56:59] = [4.0, 0.0, 2.0]
+    sp = sc["params"].copy()
+    rng = np.random.default_rng(2)
+    kw = dict(seed=3, stream_tag=2, iteration=1, spp=4, max_depth=3, mis=2)
+    _, h_g = gpu_render(g, dc, p, kw, sampling_params=sp)
+    r = o.run(sc["cams"], p, sampling_params=sp, want_hash=True, **oracle_opts(kw))
+    mask = (h_g == r["hash"]).astype(np.uint8)
+    w = rng.normal(size=(64 * 64, 3))
+    gg = gpu_grad(g, dc, p, w, kw, mask=mask, sampling_params=sp)
+    go = o.run(sc["cams"], p, sampling_params=sp, w=w, path_mask=mask, want_grad=True,
+               **oracle_opts(kw))["grad"]
+    emax, _ = _grad_parity(gg, go)
+    assert emax <= GRAD_REL
+    assert abs(gg[0]) > 0 and abs(gg[57]) > 0
+
+
+def test_replay_traverse_equals_checkpoints_and_chunking(cornell):
+    sc, g, o, dc = cornell
+    rng = np.random.default_rng(3)
+    w = rng.normal(size=(64 * 64, 3))
+    kw = dict(seed=4, stream_tag=2, iteration=0, spp=4, max_depth=3, mis=2)
+    a = gpu_grad(g, dc, sc["params"], w, kw)
+    b = gpu_grad(g, dc, sc["params"], w, dict(kw, replay_traverse=1))
+    mn, full = g.workspace_query(dc, ipt.render_opts(**kw))
+    c = gpu_grad(g, dc, sc["params"], w, kw, workspace_bytes=mn + 3 * 256 * 48 * 16)
+    rms = np.sqrt(np.mean(a ** 2))
+    assert np.max(np.abs(a - b)) <= 1e-5 * rms
+    assert np.max(np.abs(a - c)) <= 1e-5 * rms
+
+
+def test_furnace_closed_form_gpu():
+    banner("furnace closed form")
+    rho, E = 0.6, 2.0
+    sc = scenes.furnace(rho, E)
+    rho, E = float(sc["params"][0]), float(sc["params"][7])
+    g, _ = both(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    for D in (1, 4):
+        img, _ = gpu_render(g, dc, sc["params"], dict(spp=8, max_depth=D, mis=0))
+        L = E * sum(rho ** k for k in range(D + 1))
+        assert np.allclose(img, L, rtol=2e-6)
+        w = np.zeros((64, 3))
+        w[:, 1] = 1.0
+        gr = gpu_grad(g, dc, sc["params"], w, dict(spp=8, max_depth=D, mis=0, stream_tag=2))
+        assert abs(gr[1] - 64 * E * sum(k * rho ** (k - 1) for k in range(1, D + 1))) < 1e-5 * 64 * E * D
+        assert abs(gr[8] - 64 * sum(rho ** k for k in range(D + 1))) < 1e-5 * 64 * (D + 1)
+
+
+def test_room_parity_crop():
+    banner("room (50k triangles, GGX) parity on a crop")
+    sc = scenes.room()
+    g, o = both(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    W, H = sc["cams"]["width"], sc["cams"]["height"]
+    rng = np.random.default_rng(4)
+    pix = np.sort(rng.choice(4 * W * H, size=1500, replace=False)).astype(np.int64)
+    kw = dict(seed=21, stream_tag=2, iteration=2, spp=16, max_depth=5, mis=2)
+    img_g, h_g = gpu_render(g, dc, sc["params"], kw, pixel_list=pix)
+    r = o.run(sc["cams"], sc["params"], pixel_list=pix, want_hash=True, **oracle_opts(kw))
+    ok, mfrac, emax, _ = image_parity(img_g, r["image"], h_g, r["hash"])
+    n_mis = mfrac * h_g.size
+    assert n_mis <= max(2, RAY_BAR * _rays(5, h_g.size)), n_mis
+    assert emax <= PIX_REL, emax
+    mask = (h_g == r["hash"]).astype(np.uint8)
+    w = rng.normal(size=(pix.size, 3))
+    gg = gpu_grad(g, dc, sc["params"], w, kw, pixel_list=pix, mask=mask)
+    go = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, path_mask=mask, want_grad=True,
+               **oracle_opts(kw))["grad"]
+    emax, err = _grad_parity(gg, go)
+    assert emax <= GRAD_REL, (emax, np.argmax(err))
+
+
+def test_loss_grad_and_adam_vs_oracle(cornell):
+    banner("loss_grad + sgd_step vs oracle")
+    sc, g, o, dc = cornell
+    target = o.run(sc["cams"], sc["params"], spp=16, max_depth=3, stream_tag=0, seed=1)["image"]
+    p0 = scenes.init_theta(sc, "half")
+    co = dict(seed=9, stream_tag=1, iteration=5, spp=4, max_depth=3, mis=2)
+    go_ = dict(co, stream_tag=2)
+    loss, grad = g.loss_grad(dc, dev(p0), dev(target), ipt.render_opts(**co), ipt.render_opts(**go_), 0)
+    torch.cuda.synchronize()
+    rA = o.run(sc["cams"], p0, want_hash=True, **oracle_opts(co))
+    E, w = __import__("oracle").oracle.loss_adjoint(rA["image"], target, 0)
+    assert abs(loss.item() - E) <= 1e-3 * E
+    rB = o.run(sc["cams"], p0, w=w, want_grad=True, **oracle_opts(go_))
+    emax, _ = _grad_parity(grad.cpu().numpy().astype(np.float64), rB["grad"], rel=5e-3)
+    assert emax <= 5e-3   # w itself carries the FP32 colour estimate
+    # Adam on the device vs the oracle's Adam
+    pg = dev(p0)
+    m = torch.zeros_like(pg)
+    v = torch.zeros_like(pg)
+    gr = dev(rB["grad"])
+    ipt.sgd_step(pg, gr, m, v, 1, lr=1e-2, scale=dev(sc["scale"]), lo=dev(sc["lo"]), hi=dev(sc["hi"]),
+                 trainable=dev(sc["trainable"], torch.uint8))
+    pp = p0.astype(np.float64)
+    mm, vv = np.zeros_like(pp), np.zeros_like(pp)
+    __import__("oracle").oracle.adam(pp, rB["grad"], mm, vv, 1, 1e-2, scale=sc["scale"], lo=sc["lo"],
+                                     hi=sc["hi"], trainable=sc["trainable"])
+    assert np.allclose(pg.cpu().numpy(), pp, rtol=1e-5, atol=1e-6)
+
+
+def test_pixel_list_edge_cases(cornell):
+    sc, g, o, dc = cornell
+    kw = dict(seed=2, stream_tag=1, iteration=0, spp=3, max_depth=1, mis=2)
+    pix = np.array([0, 4095, 2080], np.int64)
+    img_g, h_g = gpu_render(g, dc, sc["params"], kw, pixel_list=pix)
+    r = o.run(sc["cams"], sc["params"], pixel_list=pix, want_hash=True, **oracle_opts(kw))
+    ok, mfrac, emax, _ = image_parity(img_g, r["image"], h_g, r["hash"])
+    assert mfrac == 0 and emax <= PIX_REL
+    one = np.array([1234], np.int64)
+    img1, _ = gpu_render(g, dc, sc["params"], dict(kw, spp=1), pixel_list=one)
+    assert img1.shape == (1, 3)
