@@ -342,11 +342,61 @@ static int box_hit(const onode *n, v3 o, v3 d, double tmin, double tmax)
 }
 
 /* Accept a candidate if nearer, or equally near with a smaller triangle id:
- * the answer then does not depend on the visiting order. */
+ * the answer then does not depend on the visiting order.
+ *
+ * Near-tie margin (parity bookkeeping only; it never changes the answer):
+ * for every tested triangle whose plane is crossed inside the ray interval,
+ * the distance of the crossing to the triangle's boundary (relative to the
+ * coordinate magnitude), the distance of t to the interval ends, and the gap
+ * between the two nearest hits.  A float32 implementation can only disagree
+ * with this double-precision answer where such a margin is small. */
+typedef struct { double m; double t1, t2; int32_t id1; } tiemargin;
+
+static double rel_scale(v3 x) { return fmax(fmax(fabs(x.x), fabs(x.y)), fabs(x.z)) + 1.0; }
+
+static void plane_margin(const orc_scene *s, const wray *r, int32_t t, double tmin, double tmax,
+                         tiemargin *tm)
+{
+    const int32_t *f = &s->F[3 * (int64_t)t];
+    v3 p0 = vtx(s, f[0]), p1 = vtx(s, f[1]), p2 = vtx(s, f[2]);
+    v3 e1 = sub(p1, p0), e2 = sub(p2, p0);
+    v3 n = cross(e1, e2);
+    double dn = dot(n, r->d);
+    if (dn == 0.0) return;
+    double th = dot(n, sub(p0, r->o)) / dn;
+    v3 x = add(r->o, scl(r->d, th));
+    double sc = rel_scale(x);
+    double lim_lo = tmin - 1e-4 * sc, lim_hi = tmax + 1e-4 * sc;
+    if (!(th > lim_lo && th < lim_hi)) return;
+    double nn = dot(n, n);
+    if (nn == 0.0) return;
+    /* barycentrics of the plane point and distances to the three edges */
+    v3 q = sub(x, p0);
+    double b1 = dot(cross(q, e2), n) / nn, b2 = dot(cross(e1, q), n) / nn, b0 = 1.0 - b1 - b2;
+    double area2 = sqrt(nn);
+    v3 p12 = sub(p2, p1);
+    double h0 = area2 / sqrt(dot(p12, p12)), h1 = area2 / sqrt(dot(e2, e2)), h2 = area2 / sqrt(dot(e1, e1));
+    /* The answer for this triangle flips only if the crossing moves across the
+     * triangle boundary (distance de) or across an end of the ray interval
+     * (distance dt); outside both, both must move. */
+    double de = fmin(fmin(fabs(b0) * h0, fabs(b1) * h1), fabs(b2) * h2) / sc;
+    double dt = fabs(th - tmin) / sc;
+    if (isfinite(tmax) && fabs(th - tmax) / sc < dt) dt = fabs(th - tmax) / sc;
+    int inside = b0 >= 0 && b1 >= 0 && b2 >= 0;
+    int inrange = th > tmin && th < tmax;
+    double m = (inside && inrange) ? fmin(de, dt) : (inside ? dt : (inrange ? de : fmax(de, dt)));
+    if (m < tm->m) tm->m = m;
+    if (b0 >= 0 && b1 >= 0 && b2 >= 0 && th > tmin && th < tmax) {
+        if (th < tm->t1 || (th == tm->t1 && t < tm->id1)) { tm->t2 = tm->t1; tm->t1 = th; tm->id1 = t; }
+        else if (th < tm->t2) tm->t2 = th;
+    }
+}
+
 static void consider(const orc_scene *s, const wray *r, int32_t t, double tmin, int32_t skip0,
-                     int32_t skip1, ohit *best)
+                     int32_t skip1, ohit *best, tiemargin *tm, double tmax_all)
 {
     if (t == skip0 || t == skip1) return;
+    if (tm) plane_margin(s, r, t, tmin, tmax_all, tm);
     const int32_t *f = &s->F[3 * (int64_t)t];
     double th, u, v;
     double tmax = best->tri >= 0 ? best->t : INFINITY;
@@ -361,35 +411,55 @@ static void consider(const orc_scene *s, const wray *r, int32_t t, double tmin, 
     best->tri = t; best->t = th; best->u = u; best->v = v;
 }
 
-static ohit closest(const orc_scene *s, v3 o, v3 d, double tmin, double tmax, int32_t skip0,
-                    int32_t skip1, int brute)
+/* margin (nullable) receives min(*margin, near-tie margin of this query). */
+static ohit closest_m(const orc_scene *s, v3 o, v3 d, double tmin, double tmax, int32_t skip0,
+                      int32_t skip1, int brute, double *margin)
 {
     ohit best; best.tri = -1; best.t = INFINITY; best.u = best.v = 0;
     wray r = make_wray(o, d);
+    tiemargin tmv = { INFINITY, INFINITY, INFINITY, -1 };
+    tiemargin *tm = margin ? &tmv : NULL;
     if (brute || s->nnodes == 0) {
-        for (int64_t t = 0; t < s->nt; ++t) consider(s, &r, (int32_t)t, tmin, skip0, skip1, &best);
+        for (int64_t t = 0; t < s->nt; ++t) consider(s, &r, (int32_t)t, tmin, skip0, skip1, &best, tm, tmax);
     } else {
         int stack[256]; int sp = 0; stack[sp++] = 0;
         while (sp) {
             const onode *n = &s->nodes[stack[--sp]];
             double lim = best.tri >= 0 ? best.t : tmax;
-            if (!box_hit(n, o, d, tmin, lim)) continue;
+            if (tm) lim = (isfinite(lim) ? lim : 1e300) + 1e-4 * rel_scale(o) + 1e-4 * lim;
+            if (!box_hit(n, o, d, tmin - (tm ? 1e-4 * rel_scale(o) : 0.0), lim)) continue;
             if (n->left < 0) {
                 for (int i = n->first; i < n->first + n->count; ++i)
-                    consider(s, &r, s->order[i], tmin, skip0, skip1, &best);
+                    consider(s, &r, s->order[i], tmin, skip0, skip1, &best, tm, tmax);
             } else {
                 stack[sp++] = n->left; stack[sp++] = n->right;
             }
         }
     }
     if (best.tri >= 0 && !(best.t < tmax)) best.tri = -1;
+    if (tm) {
+        double m = tmv.m;
+        if (isfinite(tmv.t2)) {
+            double g = (tmv.t2 - tmv.t1) / rel_scale(add(o, scl(d, tmv.t1)));
+            if (g < m) m = g;
+        }
+        if (m < *margin) *margin = m;
+    }
     return best;
 }
 
-int orc_closest_hit(const orc_scene *s, const double o[3], const double d[3], double tmin,
-                    double tmax, int32_t skip, int brute, double out[3])
+static ohit closest(const orc_scene *s, v3 o, v3 d, double tmin, double tmax, int32_t skip0,
+                    int32_t skip1, int brute)
 {
-    ohit h = closest(s, mk(o[0], o[1], o[2]), mk(d[0], d[1], d[2]), tmin, tmax, skip, -1, brute);
+    return closest_m(s, o, d, tmin, tmax, skip0, skip1, brute, NULL);
+}
+
+int orc_closest_hit(const orc_scene *s, const double o[3], const double d[3], double tmin,
+                    double tmax, int32_t skip, int brute, double out[3], double *margin)
+{
+    if (margin) *margin = INFINITY;
+    ohit h = closest_m(s, mk(o[0], o[1], o[2]), mk(d[0], d[1], d[2]), tmin, tmax, skip, -1, brute,
+                       margin);
     if (h.tri >= 0) { out[0] = h.t; out[1] = h.u; out[2] = h.v; }
     return h.tri;
 }
@@ -683,8 +753,11 @@ typedef struct {
 /* One path.  Returns radiance in L; adds w-weighted derivatives into grad if
  * grad != NULL.  Event hash in *hash. */
 static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const double *wc,
-                       double *grad, double Lout[3], uint64_t *hash)
+                       double *grad, double Lout[3], uint64_t *hash, double *margin)
 {
+    double mg = INFINITY;
+    double *M = margin ? &mg : NULL;
+#define NEAR(v) do { if (M && fabs(v) < mg) mg = fabs(v); } while (0)
     const orc_scene *s = C->s;
     const double *p = C->p, *sp = C->sp;
     const int D = C->o->max_depth;
@@ -701,7 +774,7 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
     (void)prev_specular_only;
     v3 o = org, d = dir;
     for (int k = 1; k <= D + 1; ++k) {
-        ohit hit = closest(s, o, d, tmin, INFINITY, prev_tri, -1, C->o->brute_force);
+        ohit hit = closest_m(s, o, d, tmin, INFINITY, prev_tri, -1, C->o->brute_force, M);
         h = fnv(h, (uint32_t)hit.tri);
         if (hit.tri < 0) break;
         const int32_t *f = &s->F[3 * (int64_t)hit.tri];
@@ -713,6 +786,7 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
         int em = s->seg_emitter[seg];
         double cos_emit = -dot(d, ng);     /* > 0: ray arrives at the emitting side */
         uint32_t ev = 0;
+        if (em >= 0) NEAR(cos_emit);
         /* --- emitter hit --- */
         if (em >= 0 && cos_emit > 0) {
             double w = 1.0;
@@ -753,6 +827,7 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
         }
         v3 ngf = ng;
         if (dot(ng, wo) < 0) { ngf = scl(ng, -1.0); ns = scl(ns, -1.0); }
+        NEAR(dot(ns, wo));
         if (dot(ns, wo) <= 0) { h = fnv(h, ev | 2u); break; }   /* shading normal faces away */
         const double *mp = p + 7 * seg, *msp = sp + 7 * seg;
         double u[8];
@@ -760,6 +835,7 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
         /* --- explicit light sampling (next-event estimation) --- */
         if (mis != 0 && s->nlt > 0) {
             int64_t lj = pick_light(C->L, s->nlt, u[0]);
+            if (M) for (int64_t j = 0; j < s->nlt - 1; ++j) NEAR((C->L->cdf[j] - u[0] * C->L->total) / C->L->total);
             int32_t lt = s->light_tri[lj];
             const int32_t *lf = &s->F[3 * (int64_t)lt];
             v3 q0 = vtx(s, lf[0]), q1 = vtx(s, lf[1]), q2 = vtx(s, lf[2]);
@@ -773,8 +849,13 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
             double cy = -dot(wl, lng);
             double cxg = dot(wl, ngf);
             uint32_t vis = 0;
-            if (cy > 0 && cxg > 0 && lt != hit.tri) {
-                ohit sh = closest(s, x, wl, tmin, dist * (1.0 - 1e-5), hit.tri, lt, C->o->brute_force);
+            if (s->seg[lt] != seg) { NEAR(cy - 1e-6); NEAR(cxg - 1e-6); }
+            /* An emitter does not light its own (planar) segment, and grazing
+             * configurations (cosines below 1e-6, e.g. two coplanar emitter
+             * quads) are skipped: their contribution is ~0 and their sign is
+             * decided by rounding. */
+            if (cy > 1e-6 && cxg > 1e-6 && s->seg[lt] != seg) {
+                ohit sh = closest_m(s, x, wl, tmin, dist * (1.0 - 1e-5), hit.tri, lt, C->o->brute_force, M);
                 vis = sh.tri < 0;
             }
             ev |= (uint32_t)(lj << 8) | (vis << 2);
@@ -782,6 +863,7 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
                 double spec, dspec;
                 spec_term(ns, wo, wl, mp[6], &spec, &dspec);
                 double cx = dot(ns, wl);
+                NEAR(cx);
                 if (cx > 0) {
                     int lk = s->seg_emitter[s->seg[lt]];
                     double parea = light_prob(C->L, lj) / s->light_area[lj];
@@ -820,6 +902,12 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
         int lobe = 0;
         int ok = brdf_sample(msp, ns, wo, u[3], u[4], u[5], &wi, &lobe);
         ev |= (uint32_t)lobe << 3;
+        {
+            double ps = lobe_prob(msp);
+            if (ps > 0 && ps < 1) NEAR(u[3] - ps);
+            if (ok) { NEAR(dot(wi, ngf)); NEAR(dot(wi, ns)); }
+            if (lobe == 1) { v3 hh = nrm(add(wo, ok ? wi : wo)); NEAR(dot(wo, hh)); }
+        }
         if (!ok || dot(wi, ngf) <= 0 || dot(wi, ns) <= 0) { h = fnv(h, ev | 16u); break; }
         double pdf = brdf_pdf(msp, ns, wo, wi);
         if (!(pdf > 0)) { h = fnv(h, ev | 16u); break; }
@@ -839,6 +927,7 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
             double m = 0;
             for (int c = 0; c < 3; ++c) { double tc = Ts[c] * ts[c]; if (tc > m) m = tc; }
             q = m < 0.1 ? 0.1 : (m > 0.95 ? 0.95 : m);
+            NEAR(u[6] - q);
             if (!(u[6] < q)) { h = fnv(h, ev | 32u); break; }
         }
         g /= q;
@@ -859,6 +948,8 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
     }
     for (int c = 0; c < 3; ++c) Lout[c] = L[c];
     *hash = h;
+    if (margin) *margin = mg;
+#undef NEAR
 }
 
 /* Render (and, when w != NULL and grad != NULL, differentiate) a set of
@@ -869,7 +960,7 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
 int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
                 const double *sampling_params, const orc_opts *o, const double *w,
                 const uint8_t *path_mask, double *image, double *grad, uint64_t *hashes,
-                double *path_L)
+                double *path_L, double *margins)
 {
     const double *sp = sampling_params ? sampling_params : params;
     int64_t P = 7 * (int64_t)s->ns + 3 * (int64_t)s->ne;
@@ -915,7 +1006,9 @@ int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
             double gbuf_local[1];
             (void)gbuf_local;
             if (gt && use) gp = (double *)calloc((size_t)P, sizeof(double));
-            trace_path(&C, org, dir, pid, wc, gp, Lp, &hsh);
+            double mgn = INFINITY;
+            trace_path(&C, org, dir, pid, wc, gp, Lp, &hsh, margins ? &mgn : NULL);
+            if (margins) margins[i * o->spp + sidx] = mgn;
             int fin = isfinite(Lp[0]) && isfinite(Lp[1]) && isfinite(Lp[2]);
             if (gp) for (int64_t q = 0; q < P && fin; ++q) if (!isfinite(gp[q])) fin = 0;
             if (!fin) { dropped++; Lp[0] = Lp[1] = Lp[2] = 0; }

@@ -48,13 +48,13 @@ def lib():
         L.orc_scene_num_light_tris.restype = ctypes.c_int64
         L.orc_scene_num_light_tris.argtypes = [P]
         L.orc_run.restype = ctypes.c_int64
-        L.orc_run.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_run.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_ray_triangle.restype = ctypes.c_int
         L.orc_ray_triangle.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
         L.orc_closest_hit.restype = ctypes.c_int
         L.orc_closest_hit.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double,
-                                      ctypes.c_int32, ctypes.c_int, P]
+                                      ctypes.c_int32, ctypes.c_int, P, P]
         L.orc_camera_ray.argtypes = [P, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_double, P]
         L.orc_brdf_eval.argtypes = [P, P, P, P, P]
@@ -176,12 +176,17 @@ class Scene:
     def num_light_tris(self):
         return lib().orc_scene_num_light_tris(self.h)
 
-    def closest_hit(self, o, d, tmin=0.0, tmax=np.inf, skip=-1, brute=False):
+    def closest_hit(self, o, d, tmin=0.0, tmax=np.inf, skip=-1, brute=False, want_margin=False):
+        """(input triangle id or -1, [t, u, v]) and, with want_margin, the
+        near-tie margin of the query (small: a float32 caster may disagree)."""
         o = np.ascontiguousarray(o, dtype=np.float64)
         d = np.ascontiguousarray(d, dtype=np.float64)
         out = np.zeros(3)
+        mg = np.zeros(1)
         tri = lib().orc_closest_hit(self.h, _ptr(o), _ptr(d), tmin, tmax, skip, int(brute),
-                                    _ptr(out))
+                                    _ptr(out), _ptr(mg) if want_margin else None)
+        if want_margin:
+            return tri, out, float(mg[0])
         return tri, out
 
     def light_probs(self, sampling_params):
@@ -193,12 +198,12 @@ class Scene:
     def run(self, cams, params, sampling_params=None, *, seed=0, stream_tag=1, iteration=0,
             spp=4, max_depth=3, rr_depth=-1, mis=2, emission_profile=0, jitter=1,
             brute_force=False, pixel_list=None, w=None, path_mask=None, want_grad=False,
-            want_hash=False, want_path_L=False):
+            want_hash=False, want_path_L=False, want_margin=False):
         """Render (and optionally differentiate) pixels.
 
         cams: dict with cam_to_world [V,4,4] float32, fov_y [V], width, height.
         Returns dict(image [npix,3], grad [P] or None, hash [npix,spp] or None,
-        path_L, dropped).
+        path_L, margin [npix,spp] (near-tie margin of each path), dropped).
         """
         c2w = np.ascontiguousarray(cams["cam_to_world"], dtype=np.float32)
         fov = np.ascontiguousarray(cams["fov_y"], dtype=np.float32)
@@ -218,6 +223,8 @@ class Scene:
         grad = np.zeros(self.P) if want_grad else None
         hsh = np.zeros((npix, spp), dtype=np.uint64) if want_hash else None
         pL = np.zeros((npix, spp, 3)) if want_path_L else None
+        mg = np.zeros((npix, spp)) if want_margin else None
         dropped = lib().orc_run(self.h, ctypes.byref(C), _ptr(p), _ptr(sp), ctypes.byref(O),
-                                _ptr(ww), _ptr(pm), _ptr(img), _ptr(grad), _ptr(hsh), _ptr(pL))
-        return dict(image=img, grad=grad, hash=hsh, path_L=pL, dropped=int(dropped))
+                                _ptr(ww), _ptr(pm), _ptr(img), _ptr(grad), _ptr(hsh), _ptr(pL),
+                                _ptr(mg))
+        return dict(image=img, grad=grad, hash=hsh, path_L=pL, margin=mg, dropped=int(dropped))

@@ -246,6 +246,7 @@ __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, uint64_t pi
         if (hit.tri < 0) {
             h = fnv1a(h, 0xFFFFFFFFu);
             if (MODE == kGradFwd) a.ck_hit[ck] = make_int4(0, 0, 0, 0);
+            klast = k - 1;   // a miss contributes nothing: the sweep starts below it
             break;
         }
         V3 p0, p1, p2;
@@ -330,7 +331,9 @@ __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, uint64_t pi
                 float cy = -dot(wl, lng);
                 float cxg = dot(wl, ngf);
                 bool vis = false;
-                if (cy > 0.0f && cxg > 0.0f && lrec.x != hit.tri) {
+                // an emitter does not light its own (planar) segment; grazing
+                // configurations (cosines below 1e-6) are skipped
+                if (cy > 1e-6f && cxg > 1e-6f && lseg != seg) {
                     if (MODE == kReplay && !a.replay_traverse) {
                         vis = (ckflags & kCkVis) != 0;
                     } else {

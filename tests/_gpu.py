@@ -55,6 +55,15 @@ def oracle_opts(kw):
     return {k: v for k, v in kw.items() if k in keys}
 
 
+NEAR_TIE = 1e-5   # relative margin under which float32 and float64 may legitimately disagree
+
+
+def mismatch_stats(hash_g, hash_o, margin):
+    """(paths mismatching, of which not near-tie)."""
+    mism = hash_g != hash_o
+    return int(mism.sum()), int((mism & (margin >= NEAR_TIE)).sum())
+
+
 def image_parity(img_g, img_o, hash_g, hash_o, rel=1e-4):
     """Per-pixel check on pixels whose paths all agree.  Returns (ok_pixels,
     path mismatch fraction, max relative error)."""

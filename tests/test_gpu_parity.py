@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 import torch
 
-from _gpu import banner, both, dev, gpu_grad, gpu_render, image_parity, oracle_opts
+from _gpu import (NEAR_TIE, banner, both, dev, gpu_grad, gpu_render, image_parity, mismatch_stats,
+                  oracle_opts)
 from paper_1903_07145_amd import ipt, scenes
 
 pytestmark = pytest.mark.gpu
@@ -55,15 +56,17 @@ def test_hits_bvh_equals_brute_and_oracle(cornell):
     tri_b, tri_f = tri_b.cpu().numpy(), tri_f.cpu().numpy()
     assert np.array_equal(tri_b, tri_f)
     assert np.array_equal(tuv_b.cpu().numpy(), tuv_f.cpu().numpy())
-    mism = 0
+    mism = hard = 0
     tb = tuv_b.cpu().numpy()
     for i in range(0, n, 4):
-        t_o, h_o = o.closest_hit(org[i].astype(np.float64), d[i].astype(np.float64))
+        t_o, h_o, mg = o.closest_hit(org[i].astype(np.float64), d[i].astype(np.float64), want_margin=True)
         if t_o != tri_b[i]:
             mism += 1
+            hard += mg >= NEAR_TIE
         elif t_o >= 0:
             assert abs(tb[i, 0] - h_o[0]) <= 1e-5 * max(1.0, h_o[0])
-    assert mism <= max(1, int(RAY_BAR * n / 4))
+    print("hit mismatches %d of %d rays, %d not near-tie" % (mism, n // 4, hard))
+    assert hard <= RAY_BAR * n / 4
 
 
 @pytest.mark.parametrize("mis", [0, 1, 2, 3])
@@ -72,10 +75,11 @@ def test_render_parity_cornell(cornell, mis):
     sc, g, o, dc = cornell
     kw = dict(seed=11, stream_tag=1, iteration=3, spp=4, max_depth=3, mis=mis)
     img_g, h_g = gpu_render(g, dc, sc["params"], kw)
-    r = o.run(sc["cams"], sc["params"], want_hash=True, **oracle_opts(kw))
+    r = o.run(sc["cams"], sc["params"], want_hash=True, want_margin=True, **oracle_opts(kw))
     ok, mfrac, emax, _ = image_parity(img_g, r["image"], h_g, r["hash"])
-    n_mis = int(round(mfrac * h_g.size))
-    assert n_mis <= max(1, RAY_BAR * _rays(3, h_g.size)), n_mis
+    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"])
+    print("paths %d mismatching %d (not near-tie %d), max rel err %.2e" % (h_g.size, n_mis, n_hard, emax))
+    assert n_hard <= RAY_BAR * _rays(3, h_g.size), n_hard
     assert emax <= PIX_REL, emax
     assert ok.mean() > 0.99
 
@@ -84,9 +88,10 @@ def test_render_parity_cornell_rr_profile_spp1(cornell):
     sc, g, o, dc = cornell
     kw = dict(seed=5, stream_tag=1, iteration=0, spp=1, max_depth=6, rr_depth=2, mis=2, emission_profile=1)
     img_g, h_g = gpu_render(g, dc, sc["params"], kw)
-    r = o.run(sc["cams"], sc["params"], want_hash=True, **oracle_opts(kw))
+    r = o.run(sc["cams"], sc["params"], want_hash=True, want_margin=True, **oracle_opts(kw))
     ok, mfrac, emax, _ = image_parity(img_g, r["image"], h_g, r["hash"])
-    assert mfrac * h_g.size <= 2
+    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"])
+    assert n_hard <= RAY_BAR * _rays(6, h_g.size), n_hard
     assert emax <= PIX_REL
 
 
@@ -169,10 +174,11 @@ def test_room_parity_crop():
     pix = np.sort(rng.choice(4 * W * H, size=1500, replace=False)).astype(np.int64)
     kw = dict(seed=21, stream_tag=2, iteration=2, spp=16, max_depth=5, mis=2)
     img_g, h_g = gpu_render(g, dc, sc["params"], kw, pixel_list=pix)
-    r = o.run(sc["cams"], sc["params"], pixel_list=pix, want_hash=True, **oracle_opts(kw))
+    r = o.run(sc["cams"], sc["params"], pixel_list=pix, want_hash=True, want_margin=True, **oracle_opts(kw))
     ok, mfrac, emax, _ = image_parity(img_g, r["image"], h_g, r["hash"])
-    n_mis = mfrac * h_g.size
-    assert n_mis <= max(2, RAY_BAR * _rays(5, h_g.size)), n_mis
+    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"])
+    print("paths %d mismatching %d (not near-tie %d), max rel err %.2e" % (h_g.size, n_mis, n_hard, emax))
+    assert n_hard <= RAY_BAR * _rays(5, h_g.size), n_hard
     assert emax <= PIX_REL, emax
     mask = (h_g == r["hash"]).astype(np.uint8)
     w = rng.normal(size=(pix.size, 3))
@@ -184,31 +190,47 @@ def test_room_parity_crop():
 
 
 def test_loss_grad_and_adam_vs_oracle(cornell):
+    """ipt_loss_grad = colour pass (stream A) -> loss and adjoint -> gradient
+    pass (stream B).  The oracle reproduces it from the GPU's colour image (so
+    the adjoint is the same) with the mismatching B paths masked on both
+    sides; the loss is checked against the oracle's own colour pass."""
     banner("loss_grad + sgd_step vs oracle")
+    from oracle import oracle as orc_mod
     sc, g, o, dc = cornell
     target = o.run(sc["cams"], sc["params"], spp=16, max_depth=3, stream_tag=0, seed=1)["image"]
     p0 = scenes.init_theta(sc, "half")
     co = dict(seed=9, stream_tag=1, iteration=5, spp=4, max_depth=3, mis=2)
     go_ = dict(co, stream_tag=2)
-    loss, grad = g.loss_grad(dc, dev(p0), dev(target), ipt.render_opts(**co), ipt.render_opts(**go_), 0)
+    _, h_b = gpu_render(g, dc, p0, go_)
+    rb = o.run(sc["cams"], p0, want_hash=True, **oracle_opts(go_))
+    mask = (h_b == rb["hash"]).astype(np.uint8)
+    imgA = torch.empty((64 * 64, 3), dtype=torch.float32, device="cuda")
+    pm = dev(mask.reshape(-1), torch.uint8)
+    loss, grad = g.loss_grad(dc, dev(p0), dev(target), ipt.render_opts(**co),
+                             ipt.render_opts(path_mask=pm, **go_), 0, image=imgA)
     torch.cuda.synchronize()
-    rA = o.run(sc["cams"], p0, want_hash=True, **oracle_opts(co))
-    E, w = __import__("oracle").oracle.loss_adjoint(rA["image"], target, 0)
+    rA = o.run(sc["cams"], p0, **oracle_opts(co))
+    E, _ = orc_mod.loss_adjoint(rA["image"], target, 0)
     assert abs(loss.item() - E) <= 1e-3 * E
-    rB = o.run(sc["cams"], p0, w=w, want_grad=True, **oracle_opts(go_))
-    emax, _ = _grad_parity(grad.cpu().numpy().astype(np.float64), rB["grad"], rel=5e-3)
-    assert emax <= 5e-3   # w itself carries the FP32 colour estimate
+    img_gpu = imgA.cpu().numpy().astype(np.float64)
+    Eg, w = orc_mod.loss_adjoint(img_gpu, target, 0)
+    assert abs(loss.item() - Eg) <= 1e-5 * Eg
+    rB = o.run(sc["cams"], p0, w=w, path_mask=mask, want_grad=True, **oracle_opts(go_))
+    emax, _ = _grad_parity(grad.cpu().numpy().astype(np.float64), rB["grad"])
+    assert emax <= GRAD_REL
     # Adam on the device vs the oracle's Adam
     pg = dev(p0)
     m = torch.zeros_like(pg)
     v = torch.zeros_like(pg)
     gr = dev(rB["grad"])
-    ipt.sgd_step(pg, gr, m, v, 1, lr=1e-2, scale=dev(sc["scale"]), lo=dev(sc["lo"]), hi=dev(sc["hi"]),
-                 trainable=dev(sc["trainable"], torch.uint8))
+    for step in (1, 2, 3):
+        ipt.sgd_step(pg, gr, m, v, step, lr=1e-2, scale=dev(sc["scale"]), lo=dev(sc["lo"]), hi=dev(sc["hi"]),
+                     trainable=dev(sc["trainable"], torch.uint8))
     pp = p0.astype(np.float64)
     mm, vv = np.zeros_like(pp), np.zeros_like(pp)
-    __import__("oracle").oracle.adam(pp, rB["grad"], mm, vv, 1, 1e-2, scale=sc["scale"], lo=sc["lo"],
-                                     hi=sc["hi"], trainable=sc["trainable"])
+    for step in (1, 2, 3):
+        orc_mod.adam(pp, rB["grad"].astype(np.float32).astype(np.float64), mm, vv, step, 1e-2,
+                     scale=sc["scale"], lo=sc["lo"], hi=sc["hi"], trainable=sc["trainable"])
     assert np.allclose(pg.cpu().numpy(), pp, rtol=1e-5, atol=1e-6)
 
 
