@@ -496,18 +496,22 @@ void orc_camera_ray(const float *c2w, double fov_y, int W, int H, double px, dou
 static double clamp_alpha(double a) { return a < 1e-3 ? 1e-3 : (a > 1.0 ? 1.0 : a); }
 static double alpha_live(double a) { return (a > 1e-3 && a < 1.0) ? 1.0 : 0.0; }
 
-static double ggx_D(double ch, double a)
+/* GGX distribution in the cancellation-free form a^2 / (pi (a^2 c^2 + s^2)^2)
+ * with c = n.h and s^2 = |n x h|^2 (equal to the textbook
+ * a^2 / (pi (c^2 (a^2 - 1) + 1)^2) since c^2 + s^2 = 1). */
+static double ggx_D(double ch, double sh2, double a)
 {
     if (ch <= 0) return 0;
-    double a2 = a * a, d = ch * ch * (a2 - 1.0) + 1.0;
+    double a2 = a * a, d = a2 * ch * ch + sh2;
     return a2 / (ORC_PI * d * d);
 }
-static double ggx_dD(double ch, double a)
+static double ggx_dD(double ch, double sh2, double a)
 {
     if (ch <= 0) return 0;
-    double a2 = a * a, d = ch * ch * (a2 - 1.0) + 1.0;
-    return 2.0 * a * (1.0 - ch * ch * (1.0 + a2)) / (ORC_PI * d * d * d);
+    double a2 = a * a, d = a2 * ch * ch + sh2;
+    return 2.0 * a * (sh2 - a2 * ch * ch) / (ORC_PI * d * d * d);
 }
+static double sin2(v3 n, v3 h) { v3 c = cross(n, h); return dot(c, c); }
 static double smith_G1(double c, double a)
 {
     double s = sqrt(a * a + (1.0 - a * a) * c * c);
@@ -526,9 +530,9 @@ static void spec_term(v3 n, v3 wo, v3 wi, double alpha_raw, double *spec, double
     *spec = 0; *dspec = 0;
     if (co <= 0 || ci <= 0) return;
     v3 h = nrm(add(wo, wi));
-    double ch = dot(n, h);
+    double ch = dot(n, h), sh2 = sin2(n, h);
     double a = clamp_alpha(alpha_raw);
-    double D = ggx_D(ch, a), dD = ggx_dD(ch, a);
+    double D = ggx_D(ch, sh2, a), dD = ggx_dD(ch, sh2, a);
     double Go = smith_G1(co, a), Gi = smith_G1(ci, a);
     double dGo = smith_dG1(co, a), dGi = smith_dG1(ci, a);
     double den = 4.0 * co * ci;
@@ -556,7 +560,7 @@ static double brdf_pdf(const double *mp, v3 n, v3 wo, v3 wi)
     double pspec = 0;
     v3 h = nrm(add(wo, wi));
     double ch = dot(n, h), oh = dot(wo, h);
-    if (ch > 0 && oh > 0) pspec = ggx_D(ch, clamp_alpha(mp[6])) * ch / (4.0 * oh);
+    if (ch > 0 && oh > 0) pspec = ggx_D(ch, sin2(n, h), clamp_alpha(mp[6])) * ch / (4.0 * oh);
     return (1.0 - ps) * pd + ps * pspec;
 }
 
@@ -582,8 +586,9 @@ static int brdf_sample(const double *mp, v3 n, v3 wo, double u3, double u4, doub
     if (u3 < ps) {
         *lobe = 1;
         double a = clamp_alpha(mp[6]);
-        double c2 = (1.0 - u4) / (1.0 + (a * a - 1.0) * u4);
-        double ch = sqrt(c2), sh = sqrt(fmax(0.0, 1.0 - c2));
+        /* Walter et al. 2007: tan^2 = a^2 u / (1 - u); cos^2 and sin^2 without cancellation */
+        double den = 1.0 + (a * a - 1.0) * u4;
+        double ch = sqrt((1.0 - u4) / den), sh = sqrt(a * a * u4 / den);
         v3 h = add(add(scl(t, sh * cos(phi)), scl(b, sh * sin(phi))), scl(n, ch));
         double oh = dot(wo, h);
         if (oh <= 0) return 0;
@@ -849,12 +854,12 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
             double cy = -dot(wl, lng);
             double cxg = dot(wl, ngf);
             uint32_t vis = 0;
-            if (s->seg[lt] != seg) { NEAR(cy - 1e-6); NEAR(cxg - 1e-6); }
-            /* An emitter does not light its own (planar) segment, and grazing
-             * configurations (cosines below 1e-6, e.g. two coplanar emitter
-             * quads) are skipped: their contribution is ~0 and their sign is
-             * decided by rounding. */
-            if (cy > 1e-6 && cxg > 1e-6 && s->seg[lt] != seg) {
+            NEAR(cy - 1e-6);
+            NEAR(cxg - 1e-6);
+            /* Grazing configurations (cosines below 1e-6: the light triangle
+             * itself, a coplanar emitter) are skipped: their contribution is ~0
+             * and their sign would be decided by rounding. */
+            if (cy > 1e-6 && cxg > 1e-6) {
                 ohit sh = closest_m(s, x, wl, tmin, dist * (1.0 - 1e-5), hit.tri, lt, C->o->brute_force, M);
                 vis = sh.tri < 0;
             }

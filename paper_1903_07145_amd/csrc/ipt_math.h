@@ -171,15 +171,21 @@ __device__ __forceinline__ float clamp_alpha(float a) { return fminf(fmaxf(a, 1e
 __device__ __forceinline__ float alpha_live(float a) { return (a > 1e-3f && a < 1.0f) ? 1.0f : 0.0f; }
 __device__ __forceinline__ float lum(V3 c) { return (c.x + c.y + c.z) * (1.0f / 3.0f); }
 
-__device__ __forceinline__ float ggx_D(float ch, float a) {
+// GGX in the cancellation-free form a^2 / (pi (a^2 c^2 + s^2)^2), c = n.h,
+// s^2 = |n x h|^2: near the lobe peak 1 - c^2 would lose all float32 digits.
+__device__ __forceinline__ float ggx_D(float ch, float sh2, float a) {
     if (ch <= 0.0f) return 0.0f;
-    float a2 = a * a, d = ch * ch * (a2 - 1.0f) + 1.0f;
+    float a2 = a * a, d = a2 * ch * ch + sh2;
     return a2 / (kPi * d * d);
 }
-__device__ __forceinline__ float ggx_dD(float ch, float a) {
+__device__ __forceinline__ float ggx_dD(float ch, float sh2, float a) {
     if (ch <= 0.0f) return 0.0f;
-    float a2 = a * a, d = ch * ch * (a2 - 1.0f) + 1.0f;
-    return 2.0f * a * (1.0f - ch * ch * (1.0f + a2)) / (kPi * d * d * d);
+    float a2 = a * a, d = a2 * ch * ch + sh2;
+    return 2.0f * a * (sh2 - a2 * ch * ch) / (kPi * d * d * d);
+}
+__device__ __forceinline__ float sin2(V3 n, V3 h) {
+    V3 c = cross(n, h);
+    return dot(c, c);
 }
 __device__ __forceinline__ float smith_G1(float c, float a) {
     float s = sqrtf(a * a + (1.0f - a * a) * c * c);
@@ -198,9 +204,9 @@ __device__ __forceinline__ void spec_term(V3 n, V3 wo, V3 wi, float alpha_raw, f
     dspec = 0.0f;
     if (co <= 0.0f || ci <= 0.0f) return;
     V3 h = normalize(wo + wi);
-    float ch = dot(n, h);
+    float ch = dot(n, h), sh2 = sin2(n, h);
     float a = clamp_alpha(alpha_raw);
-    float D = ggx_D(ch, a), dD = ggx_dD(ch, a);
+    float D = ggx_D(ch, sh2, a), dD = ggx_dD(ch, sh2, a);
     float Go = smith_G1(co, a), Gi = smith_G1(ci, a);
     float dGo = smith_dG1(co, a), dGi = smith_dG1(ci, a);
     float rden = 1.0f / (4.0f * co * ci);
@@ -212,7 +218,7 @@ __device__ __forceinline__ float spec_only(V3 n, V3 wo, V3 wi, float alpha_raw) 
     if (co <= 0.0f || ci <= 0.0f) return 0.0f;
     V3 h = normalize(wo + wi);
     float a = clamp_alpha(alpha_raw);
-    return ggx_D(dot(n, h), a) * smith_G1(co, a) * smith_G1(ci, a) / (4.0f * co * ci);
+    return ggx_D(dot(n, h), sin2(n, h), a) * smith_G1(co, a) * smith_G1(ci, a) / (4.0f * co * ci);
 }
 
 __device__ __forceinline__ float lobe_prob(const Mat& m) {
@@ -230,7 +236,7 @@ __device__ __forceinline__ float brdf_pdf(const Mat& m, V3 n, V3 wo, V3 wi) {
     float pspec = 0.0f;
     V3 h = normalize(wo + wi);
     float ch = dot(n, h), oh = dot(wo, h);
-    if (ch > 0.0f && oh > 0.0f) pspec = ggx_D(ch, clamp_alpha(m.alpha)) * ch / (4.0f * oh);
+    if (ch > 0.0f && oh > 0.0f) pspec = ggx_D(ch, sin2(n, h), clamp_alpha(m.alpha)) * ch / (4.0f * oh);
     return (1.0f - ps) * pd + ps * pspec;
 }
 
@@ -255,8 +261,9 @@ __device__ __forceinline__ bool brdf_sample(const Mat& m, V3 n, V3 wo, float u3,
     if (u3 < ps) {
         lobe = 1;
         float a = clamp_alpha(m.alpha);
-        float c2 = (1.0f - u4) / (1.0f + (a * a - 1.0f) * u4);
-        float ch = sqrtf(c2), sh = sqrtf(fmaxf(0.0f, 1.0f - c2));
+        // Walter et al. 2007: tan^2 = a^2 u / (1 - u), cos^2 and sin^2 without cancellation
+        float den = 1.0f + (a * a - 1.0f) * u4;
+        float ch = sqrtf((1.0f - u4) / den), sh = sqrtf(a * a * u4 / den);
         V3 h = t * (sh * c) + b * (sh * s) + n * ch;
         float oh = dot(wo, h);
         if (oh <= 0.0f) return false;

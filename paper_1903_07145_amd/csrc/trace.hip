@@ -331,9 +331,9 @@ __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, uint64_t pi
                 float cy = -dot(wl, lng);
                 float cxg = dot(wl, ngf);
                 bool vis = false;
-                // an emitter does not light its own (planar) segment; grazing
-                // configurations (cosines below 1e-6) are skipped
-                if (cy > 1e-6f && cxg > 1e-6f && lseg != seg) {
+                // grazing configurations (cosines below 1e-6: the light
+                // triangle itself, a coplanar emitter) are skipped
+                if (cy > 1e-6f && cxg > 1e-6f) {
                     if (MODE == kReplay && !a.replay_traverse) {
                         vis = (ckflags & kCkVis) != 0;
                     } else {

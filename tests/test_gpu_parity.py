@@ -178,6 +178,11 @@ def test_room_parity_crop():
     ok, mfrac, emax, _ = image_parity(img_g, r["image"], h_g, r["hash"])
     n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"])
     print("paths %d mismatching %d (not near-tie %d), max rel err %.2e" % (h_g.size, n_mis, n_hard, emax))
+    mm = h_g != r["hash"]
+    print("margins of mismatching paths:", np.sort(r["margin"][mm])[:20])
+    _, _, _, err = image_parity(img_g, r["image"], h_g, r["hash"])
+    okp = (h_g == r["hash"]).all(axis=1)
+    print("pixel err percentiles (matched):", np.percentile(err[okp], [50, 99, 99.9, 100]))
     assert n_hard <= RAY_BAR * _rays(5, h_g.size), n_hard
     assert emax <= PIX_REL, emax
     mask = (h_g == r["hash"]).astype(np.uint8)
