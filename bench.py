@@ -1,0 +1,238 @@
+"""Benchmark of the inverse-path-tracing hot path on one MI355X.
+
+A step is one SGD iteration of the method over the full synthetic workload:
+colour estimate (stream A) -> loss and adjoint image -> gradient estimate
+(stream B: forward pass with vertex checkpoints + adjoint replay + block
+reduction) -> projected Adam.  Inputs (scene, BVH, target images, parameters)
+are resident on the device before the timed region.
+
+Prints ONE JSON line.  value = gradient paths per second of the whole step
+(B paths / step time); the breakdown gives colour paths/s and the
+fwd+adjoint-only gradient paths/s.  The roofline entry is for the dominant
+kernel, timed with HIP events inside the library on the stream it runs on;
+algorithmic bytes come from the kernels' own work counters (BVH nodes x 64 B
++ triangles x 48 B + checkpoint traffic).  cpu_baseline times the FP64 oracle
+on a bounded pixel sample on this host's cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NODE_B, TRI_B = 64, 48
+# checkpoint traffic of the gradient forward pass per path vertex: hit record,
+# a and c written (3 x 16 B), a and c read back by the backward sweep (32 B),
+# suffix radiance written (16 B)
+CK_FWD_B = 96
+# replay reads hit record + suffix radiance per vertex
+CK_REPLAY_B = 32
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="apartment", choices=["cornell", "room", "apartment", "office_floor"])
+    ap.add_argument("--target-spp", type=int, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: multi-GPU runs are not part of this build "
+              "(paths would shard by pixel tiles with one gradient all-reduce per step).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1903_07145_amd import ipt, scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    sc = scenes.WORKLOADS[args.workload]()
+    cfg = sc["render"]
+    log("scene %s: %d triangles, %d segments, %d emitters (%.1fs)" % (
+        sc["name"], sc["tris"].shape[0], sc["num_segments"], len(sc["emitter_seg"]), time.time() - t0))
+    t0 = time.time()
+    g = ipt.Scene.from_dict(sc)
+    info = g.info()
+    log("scene build %.1fs (BVH %.0f ms, %d nodes, depth %d, SAH %.1f)" % (
+        time.time() - t0, info["build_ms"], info["num_nodes"], info["bvh_depth"], info["sah_cost"]))
+    dc = ipt.make_cameras(sc["cams"])
+    V, W, H = dc["num_views"], dc["width"], dc["height"]
+    npix = V * W * H
+    spp, D, rr = cfg["spp"], cfg["max_depth"], cfg["rr_depth"]
+    p_true = torch.as_tensor(sc["params"], device="cuda")
+    # target images: the true parameters at target_spp (stream tag 0), in 16-spp passes
+    tspp = args.target_spp or cfg["target_spp"]
+    t0 = time.time()
+    target = torch.zeros((npix, 3), dtype=torch.float32, device="cuda")
+    npass = max(1, tspp // 16)
+    for i in range(npass):
+        o = ipt.render_opts(seed=1, stream_tag=0, iteration=i, spp=min(16, tspp), max_depth=D, rr_depth=rr, mis=2)
+        target += g.render(dc, p_true, o)
+    target /= npass
+    torch.cuda.synchronize()
+    log("target %d spp in %.1fs" % (npass * min(16, tspp), time.time() - t0))
+
+    params = torch.as_tensor(scenes.init_theta(sc, cfg["init"], seed=7), device="cuda")
+    scale = torch.as_tensor(sc["scale"], device="cuda")
+    lo = torch.as_tensor(sc["lo"], device="cuda")
+    hi = torch.as_tensor(sc["hi"], device="cuda")
+    tr = torch.as_tensor(sc["trainable"], device="cuda")
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    grad = torch.zeros_like(params)
+    lr = cfg["lr"]
+
+    def step(it):
+        co = ipt.render_opts(seed=11, stream_tag=1, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2)
+        go = ipt.render_opts(seed=11, stream_tag=2, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2)
+        g.loss_grad(dc, params, target, co, go, 0, loss=loss, grad=grad)
+        ipt.sgd_step(params, grad, m, v, it + 1, lr=lr, scale=scale, lo=lo, hi=hi, trainable=tr)
+
+    # workspace sized once, outside the timed region
+    g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr))
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    g.profile_reset()
+    g.profile(True)
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.time()
+    e0.record(st)
+    for i in range(args.steps):
+        step(args.warmup + i)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.time() - wall0
+    g.profile(False)
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    prof = {ipt.KERNELS[k]: g.profile_read(k) for k in range(3)}
+    paths_step = npix * spp
+    value = paths_step / (ms_step * 1e-3)
+    k_fwd, k_rep, k_col = prof["grad_forward"], prof["adjoint_replay"], prof["colour"]
+    ms_grad = (k_fwd["total_ms"] + k_rep["total_ms"]) / args.steps
+    ms_col = k_col["total_ms"] / args.steps
+    log("step %.1f ms (wall %.1f ms): colour %.1f ms, grad fwd %.1f ms, replay %.1f ms" % (
+        ms_step, 1e3 * wall / args.steps, ms_col, k_fwd["total_ms"] / args.steps, k_rep["total_ms"] / args.steps))
+
+    def kbytes(k, extra_per_vertex):
+        return k["nodes"] * NODE_B + k["tris"] * TRI_B + k["vertices"] * extra_per_vertex
+
+    per = {}
+    for name, k, extra in (("colour", k_col, 0), ("grad_forward", k_fwd, CK_FWD_B), ("adjoint_replay", k_rep, CK_REPLAY_B)):
+        launches = max(1, k["launches"])
+        avg_ms = k["total_ms"] / launches
+        b = kbytes(k, extra) / launches
+        per[name] = dict(avg_ms=avg_ms, bytes_per_launch=b, gbs=b / (avg_ms * 1e-3) / 1e9,
+                         rays_per_launch=k["rays"] / launches,
+                         nodes_per_ray=k["nodes"] / max(1, k["rays"]), tris_per_ray=k["tris"] / max(1, k["rays"]))
+    dom = max(per, key=lambda n: per[n]["avg_ms"])
+    d = per[dom]
+    roofline = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_ms": round(d["avg_ms"], 3), "algorithmic_bytes_per_launch": int(d["bytes_per_launch"]),
+                "nodes_per_ray": round(d["nodes_per_ray"], 2), "tris_per_ray": round(d["tris_per_ray"], 2)}
+    info2 = g.info()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(sc, cfg, params.cpu().numpy(), target.cpu().numpy(), args.cpu_seconds)
+
+    out = {
+        "metric": "grad paths/s (fwd+adjoint)",
+        "value": round(value, 1),
+        "unit": "grad paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d triangles, %d segments, %d emitters, %d views %dx%d, %d spp, depth %d%s" % (
+            sc["name"], sc["tris"].shape[0], sc["num_segments"], len(sc["emitter_seg"]), V, W, H, spp, D,
+            ", RR from %d" % rr if rr >= 0 else ""),
+            "step": "ipt_loss_grad (colour A + L2 loss/adjoint + gradient B fwd/replay/reduce) + ipt_sgd_step",
+            "paths_per_step": {"colour": paths_step, "gradient": paths_step},
+            "parallelism": "1 GPU"},
+        "breakdown": {"colour_paths_per_s": round(paths_step / (ms_col * 1e-3), 1),
+                      "grad_paths_per_s_fwd_adjoint": round(paths_step / (ms_grad * 1e-3), 1),
+                      "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in val.items()}
+                                  for k, val in per.items()},
+                      "nonfinite_paths": info2["nonfinite_paths"], "stack_overflows": info2["stack_overflows"],
+                      "final_loss": float(loss.item())},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(sc, cfg, params, target, budget_s):
+    """The FP64 oracle on this host's cores: gradient paths/s of its
+    forward+derivative pass (stream B) on a fixed pixel sample (every k-th
+    pixel of every view at full spp), sized to about budget_s seconds."""
+    from oracle import oracle
+
+    t0 = time.time()
+    o = oracle.Scene(sc["verts"], sc["tris"], sc["tri_seg"], sc["num_segments"], sc["emitter_seg"], sc["normals"])
+    log("oracle BVH %.1fs" % (time.time() - t0))
+    V, W, H = sc["cams"]["cam_to_world"].shape[0], sc["cams"]["width"], sc["cams"]["height"]
+    npix = V * W * H
+    kw = dict(seed=11, stream_tag=2, iteration=0, spp=cfg["spp"], max_depth=cfg["max_depth"],
+              rr_depth=cfg["rr_depth"], mis=2)
+    rng = np.random.default_rng(0)
+    # probe with a small sample, then size the timed sample to the budget
+    stride = max(1, npix // 500)
+    pix = np.arange(0, npix, stride, dtype=np.int64)
+    w = rng.normal(size=(pix.size, 3))
+    t0 = time.time()
+    o.run(sc["cams"], params, pixel_list=pix, w=w, want_grad=True, **kw)
+    t_probe = max(time.time() - t0, 1e-3)
+    n_target = int(pix.size * budget_s / t_probe)
+    stride = max(1, npix // max(1, n_target))
+    pix = np.arange(0, npix, stride, dtype=np.int64)
+    w = rng.normal(size=(pix.size, 3))
+    t0 = time.time()
+    o.run(sc["cams"], params, pixel_list=pix, w=w, want_grad=True, **kw)
+    dt = time.time() - t0
+    paths = pix.size * cfg["spp"]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    log("oracle: %d gradient paths in %.1fs on %d threads" % (paths, dt, threads))
+    return {"value": round(paths / dt, 1), "unit": "grad paths/s", "cores": threads, "kind": "oracle",
+            "sample": "every %d-th pixel of all %d views (%d pixels) at %d spp, forward+derivatives in FP64; "
+                      "%.1f s; %s" % (stride, V, pix.size, cfg["spp"], dt, cpu_model)}
+
+
+if __name__ == "__main__":
+    main()

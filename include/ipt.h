@@ -203,6 +203,22 @@ ipt_status ipt_guide_train(ipt_guide_t guide, const ipt_cameras *cams, const flo
                            const ipt_render_opts *opts, int32_t steps, void *workspace,
                            size_t workspace_bytes, void *hip_stream);
 
+/* Kernel timing and work counters of the path kernels of one scene (kernel
+ * 0: colour pass, 1: gradient forward pass, 2: adjoint replay).  While
+ * enabled, every launch is bracketed by HIP events on the stream it is
+ * launched on, and the kernels add their work (rays cast, BVH nodes fetched,
+ * triangles tested, paths, path vertices) into per-scene device counters.
+ * ipt_profile_read synchronises the device; ipt_profile_reset clears both. */
+typedef struct {
+    int64_t launches;
+    double total_ms;          /* sum of event-measured launch durations */
+    uint64_t rays, nodes, tris, paths, vertices;
+} ipt_kernel_profile;
+
+ipt_status ipt_profile_enable(ipt_scene_t scene, int32_t enable);
+ipt_status ipt_profile_read(ipt_scene_t scene, int32_t kernel, ipt_kernel_profile *out);
+ipt_status ipt_profile_reset(ipt_scene_t scene);
+
 const char *ipt_last_error(void);
 
 #ifdef __cplusplus

@@ -846,9 +846,11 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
             v3 q0 = vtx(s, lf[0]), q1 = vtx(s, lf[1]), q2 = vtx(s, lf[2]);
             double su = sqrt(u[1]);
             double b1 = (1.0 - u[2]) * su, b2 = u[2] * su;
-            v3 y = add(q0, add(scl(sub(q1, q0), b1), scl(sub(q2, q0), b2)));
+            /* y - x formed from vertex differences and edge terms (the same
+             * vector as (q0 + b1 (q1-q0) + b2 (q2-q0)) - (p0 + u e1 + v e2)) */
+            v3 dl = add(sub(q0, p0), add(add(scl(sub(q1, q0), b1), scl(sub(q2, q0), b2)),
+                                         scl(add(scl(e1, hit.u), scl(e2, hit.v)), -1.0)));
             v3 lng = nrm(cross(sub(q1, q0), sub(q2, q0)));
-            v3 dl = sub(y, x);
             double d2 = dot(dl, dl), dist = sqrt(d2);
             v3 wl = scl(dl, 1.0 / dist);
             double cy = -dot(wl, lng);

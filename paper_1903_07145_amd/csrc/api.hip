@@ -55,13 +55,42 @@ struct ipt_scene_s {
     double sah = 0.0, build_ms = 0.0;
     float diag = 0.0f;
     float bb_lo[3] = {0, 0, 0}, bb_hi[3] = {0, 0, 0};
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
 };
+
+static void prof_clear_events(ipt_scene_s* s) {
+    for (auto& v : s->ev) {
+        for (auto& p : v) {
+            hipEventDestroy(p.first);
+            hipEventDestroy(p.second);
+        }
+        v.clear();
+    }
+}
+
+// Launch a path kernel, bracketed by events when profiling is on.
+static hipError_t timed_launch(ipt_scene_s* s, int mode, PathArgs& a, int grid, size_t lds, hipStream_t st) {
+    a.count_stats = s->prof ? 1 : 0;
+    if (!s->prof) return launch_paths(mode, a, grid, lds, st);
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) return e;
+    hipEventRecord(e0, st);
+    e = launch_paths(mode, a, grid, lds, st);
+    hipEventRecord(e1, st);
+    s->ev[mode].push_back({e0, e1});
+    return e;
+}
 
 // ---------------------------------------------------------------------------
 // Scene build.
 // ---------------------------------------------------------------------------
 extern "C" ipt_status ipt_scene_free(ipt_scene_t s) {
     if (!s) return IPT_OK;
+    prof_clear_events(s);
     hipFree(s->d_nodes);
     hipFree(s->d_tris);
     hipFree(s->d_nrm);
@@ -365,7 +394,7 @@ static ipt_status do_render(ipt_scene_t s, const ipt_cameras* cams, const float*
     HIP_OK(launch_zero_u32(a.work, 1, st));
     size_t lds = path_lds_bytes(kColor, a.P, a.frozen, s->S, s->nlt);
     int grid = std::min<int64_t>(pl.grid, (npix + kBlock - 1) / kBlock);
-    HIP_OK(launch_paths(kColor, a, std::max(1, grid), lds, st));
+    HIP_OK(timed_launch(s, kColor, a, std::max(1, grid), lds, st));
     return IPT_OK;
 }
 
@@ -393,9 +422,9 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
         a.pix_count = std::min<int64_t>(chunk, npix - b);
         int grid = (int)std::max<int64_t>(1, std::min<int64_t>(pl.grid, (a.pix_count + kBlock - 1) / kBlock));
         HIP_OK(launch_zero_u32(a.work, 1, st));
-        HIP_OK(launch_paths(kGradFwd, a, grid, lds_f, st));
+        HIP_OK(timed_launch(s, kGradFwd, a, grid, lds_f, st));
         HIP_OK(launch_zero_u32(a.work, 1, st));
-        HIP_OK(launch_paths(kReplay, a, grid, lds_r, st));
+        HIP_OK(timed_launch(s, kReplay, a, grid, lds_r, st));
         HIP_OK(launch_grad_reduce(a.grad_part, grid, a.P, grad, b > 0 ? 1 : 0, st));
     }
     return IPT_OK;
@@ -479,6 +508,41 @@ extern "C" ipt_status ipt_trace_rays(ipt_scene_t s, const float* origins, const 
     if (n == 0) return IPT_OK;
     HIP_OK(launch_trace_rays(s->dev, origins, dirs, skip_tri, n, tmin, brute_force, s->nt, out_tri, out_tuv,
                              s->d_ovf_rays, trace_rays_grid(s->num_cu), s->d_err, (hipStream_t)hip_stream));
+    return IPT_OK;
+}
+
+extern "C" ipt_status ipt_profile_enable(ipt_scene_t s, int32_t enable) {
+    if (!s) return fail(IPT_ERR_INVALID_ARG, "NULL scene");
+    s->prof = enable != 0;
+    return IPT_OK;
+}
+
+extern "C" ipt_status ipt_profile_reset(ipt_scene_t s) {
+    if (!s) return fail(IPT_ERR_INVALID_ARG, "NULL scene");
+    HIP_OK(hipDeviceSynchronize());
+    prof_clear_events(s);
+    HIP_OK(hipMemset(&s->d_err->k[0], 0, sizeof(KStats) * 3));
+    return IPT_OK;
+}
+
+extern "C" ipt_status ipt_profile_read(ipt_scene_t s, int32_t kernel, ipt_kernel_profile* out) {
+    if (!s || !out || kernel < 0 || kernel > 2) return fail(IPT_ERR_INVALID_ARG, "bad argument");
+    HIP_OK(hipDeviceSynchronize());
+    double tot = 0.0;
+    for (auto& p : s->ev[kernel]) {
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, p.first, p.second));
+        tot += ms;
+    }
+    Counters c;
+    HIP_OK(hipMemcpy(&c, s->d_err, sizeof(Counters), hipMemcpyDeviceToHost));
+    out->launches = (int64_t)s->ev[kernel].size();
+    out->total_ms = tot;
+    out->rays = c.k[kernel].rays;
+    out->nodes = c.k[kernel].nodes;
+    out->tris = c.k[kernel].tris;
+    out->paths = c.k[kernel].paths;
+    out->vertices = c.k[kernel].vertices;
     return IPT_OK;
 }
 

@@ -33,9 +33,16 @@ struct SceneDev {
     float tmin;            // ray epsilon (1e-6 of the scene diagonal)
 };
 
+// Per-kernel work counters (kernel modes 0..2): rays cast, BVH nodes
+// fetched, triangles tested, paths, path vertices.
+struct KStats {
+    unsigned long long rays, nodes, tris, paths, vertices;
+};
+
 struct Counters {
     unsigned long long nonfinite;
     unsigned long long overflow;
+    KStats k[3];
 };
 
 enum Mode { kColor = 0, kGradFwd = 1, kReplay = 2 };
@@ -66,6 +73,7 @@ struct PathArgs {
     Counters* err;
     int* ovf;                      // [kOvfDepth][grid threads]
     int replay_traverse;
+    int count_stats;               // accumulate KStats into err->k[mode]
     // guide (one-sample MIS with BRDF sampling); gmix = 0 disables it
     const void* guide;
     float gmix;

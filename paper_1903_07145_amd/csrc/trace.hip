@@ -95,15 +95,21 @@ __device__ __forceinline__ void load_tri(const SceneDev& sc, int i, V3& p0, V3& 
 // Closest hit (ANY = false) or occlusion test (ANY = true: returns tri >= 0
 // as soon as anything lies in (tmin, tmax)).  skip0/skip1 are leaf indices
 // that are ignored.  Ties in t are resolved toward the smaller original id.
+struct Work {
+    uint32_t rays, nodes, tris, vertices;
+};
+
 template <bool ANY>
 __device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax, int skip0, int skip1,
-                        Stack& st) {
+                        Stack& st, Work& wk) {
     Hit best{-1, tmax, 0.0f, 0.0f};
+    wk.rays++;
     int best_orig = 0x7FFFFFFF;
     st.sp = 0;
     int entry = 0;
     while (true) {
         if (entry >= 0) {
+            wk.nodes++;
             const float4* n = sc.nodes + 4 * (size_t)entry;
             float4 n0 = n[0], n1 = n[1], n2 = n[2], n3 = n[3];
             int c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
@@ -122,6 +128,7 @@ __device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax
         } else {
             int code = ~entry;
             int first = code >> 3, cnt = (code & 7) + 1;
+            wk.tris += cnt;
             for (int i = first; i < first + cnt; ++i) {
                 if (i == skip0 || i == skip1) continue;
                 V3 p0, p1, p2;
@@ -200,7 +207,7 @@ __device__ __forceinline__ void lds_add(float* g, int i, float x) {
 // in kReplay adds w-weighted derivatives into lds.grad.
 // ---------------------------------------------------------------------------
 template <int MODE>
-__device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, uint64_t pid, int64_t q, int s,
+__device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, Work& wk, uint64_t pid, int64_t q, int s,
                        V3 org, V3 dir, V3 wpix, uint64_t& hash, bool& drop_out) {
     const SceneDev& sc = a.sc;
     const float* cdf = lds.lights_in_lds ? lds.cdf : a.cdf;
@@ -233,7 +240,7 @@ __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, uint64_t pi
             ckflags = x;
         } else {
             Ray ray = make_ray(o, d);
-            hit = traverse<false>(sc, ray, sc.tmin, __builtin_inff(), prev_tri, -1, st);
+            hit = traverse<false>(sc, ray, sc.tmin, __builtin_inff(), prev_tri, -1, st, wk);
             if (MODE == kReplay) ckflags = (uint32_t)a.ck_hit[ck].x;
         }
         if (MODE == kReplay) {
@@ -241,6 +248,7 @@ __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, uint64_t pi
             Rn = v3(rr.x, rr.y, rr.z);
         }
         klast = k;
+        wk.vertices++;
         V3 ck_c = v3(0.0f, 0.0f, 0.0f), ck_a = v3(0.0f, 0.0f, 0.0f);
         uint32_t flags = 0;
         if (hit.tri < 0) {
@@ -323,9 +331,10 @@ __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, uint64_t pi
                 load_tri(sc, lrec.x, q0, q1, q2, lorig, lseg, llight);
                 float su = sqrtf(u[1]);
                 float b1 = (1.0f - u[2]) * su, b2 = u[2] * su;
-                V3 y = q0 + (q1 - q0) * b1 + (q2 - q0) * b2;
+                // y - x from vertex differences and edge terms: the light point and
+                // the shading point are never rounded to world coordinates first
+                V3 dl = (q0 - p0) + ((q1 - q0) * b1 + (q2 - q0) * b2 - (e1 * hit.u + e2 * hit.v));
                 V3 lng = normalize(cross(q1 - q0, q2 - q0));
-                V3 dl = y - x;
                 float d2 = dot(dl, dl), dist = sqrtf(d2);
                 V3 wl = dl * (1.0f / dist);
                 float cy = -dot(wl, lng);
@@ -338,7 +347,7 @@ __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, uint64_t pi
                         vis = (ckflags & kCkVis) != 0;
                     } else {
                         Ray sr = make_ray(x, wl);
-                        Hit sh = traverse<true>(sc, sr, sc.tmin, dist * (1.0f - 1e-5f), hit.tri, lrec.x, st);
+                        Hit sh = traverse<true>(sc, sr, sc.tmin, dist * (1.0f - 1e-5f), hit.tri, lrec.x, st, wk);
                         vis = sh.tri < 0;
                     }
                 }
@@ -512,6 +521,8 @@ __global__ __launch_bounds__(kBlock) void path_kernel(PathArgs a) {
     st.sp = 0;
 
     const int64_t npix_img = (int64_t)a.V * a.W * a.H;
+    Work wk{0u, 0u, 0u, 0u};
+    uint32_t npaths = 0;
     while (true) {
         if (tid == 0) tile_sh = atomicAdd(a.work, 1u);
         __syncthreads();
@@ -542,7 +553,8 @@ __global__ __launch_bounds__(kBlock) void path_kernel(PathArgs a) {
             camera_ray(a, view, (float)px + j0, (float)py + j1, o, d);
             uint64_t hsh;
             bool drop;
-            V3 Lp = run_path<MODE>(a, lds, st, pid, q, s, o, d, wpix, hsh, drop);
+            V3 Lp = run_path<MODE>(a, lds, st, wk, pid, q, s, o, d, wpix, hsh, drop);
+            ++npaths;
             if (MODE == kColor) {
                 if (!finite3(Lp)) {
                     atomicAdd(&a.err->nonfinite, 1ull);
@@ -561,6 +573,14 @@ __global__ __launch_bounds__(kBlock) void path_kernel(PathArgs a) {
         }
     }
     if (st.overflow) atomicAdd(&a.err->overflow, 1ull);
+    if (a.count_stats) {
+        KStats* ks = &a.err->k[MODE];
+        atomicAdd(&ks->rays, (unsigned long long)wk.rays);
+        atomicAdd(&ks->nodes, (unsigned long long)wk.nodes);
+        atomicAdd(&ks->tris, (unsigned long long)wk.tris);
+        atomicAdd(&ks->paths, (unsigned long long)npaths);
+        atomicAdd(&ks->vertices, (unsigned long long)wk.vertices);
+    }
     if (MODE == kReplay) {
         __syncthreads();
         float* out = a.grad_part + (size_t)blockIdx.x * a.P;
@@ -607,11 +627,12 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(SceneDev sc, const f
     st.gthreads = gridDim.x * kBlock;
     st.overflow = false;
     st.sp = 0;
+    Work wk{0u, 0u, 0u, 0u};
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
         Ray r = make_ray(v3(o[3 * i], o[3 * i + 1], o[3 * i + 2]), v3(d[3 * i], d[3 * i + 1], d[3 * i + 2]));
         int sk = (skip && skip[i] >= 0 && skip[i] < nt) ? sc.pos_of[skip[i]] : -1;
         Hit h = brute ? brute_closest(sc, nt, r, tmin, sk)
-                      : traverse<false>(sc, r, tmin, __builtin_inff(), sk, -1, st);
+                      : traverse<false>(sc, r, tmin, __builtin_inff(), sk, -1, st, wk);
         int orig = -1;
         if (h.tri >= 0) orig = __float_as_int(sc.tris[3 * h.tri].w);
         out_tri[i] = orig;

@@ -20,7 +20,8 @@ _STATUS = {0: "IPT_OK", 1: "IPT_ERR_INVALID_ARG", 2: "IPT_ERR_BAD_SCENE", 3: "IP
 
 EXPORTS = ["ipt_scene_build", "ipt_scene_free", "ipt_scene_info", "ipt_workspace_query", "ipt_render",
            "ipt_render_grad", "ipt_loss_grad", "ipt_sgd_step", "ipt_trace_rays", "ipt_guide_create",
-           "ipt_guide_free", "ipt_guide_eval", "ipt_guide_train", "ipt_last_error"]
+           "ipt_guide_free", "ipt_guide_eval", "ipt_guide_train", "ipt_profile_enable", "ipt_profile_read",
+           "ipt_profile_reset", "ipt_last_error"]
 
 
 class IPTError(RuntimeError):
@@ -57,6 +58,15 @@ class SceneInfo(ctypes.Structure):
                 ("nonfinite_paths", ctypes.c_uint64), ("stack_overflows", ctypes.c_uint64)]
 
 
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("rays", ctypes.c_uint64),
+                ("nodes", ctypes.c_uint64), ("tris", ctypes.c_uint64), ("paths", ctypes.c_uint64),
+                ("vertices", ctypes.c_uint64)]
+
+
+KERNELS = {0: "colour", 1: "grad_forward", 2: "adjoint_replay"}
+
+
 class GuideOpts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("lr", ctypes.c_float), ("batch", ctypes.c_int32),
                 ("ring_capacity", ctypes.c_int32)]
@@ -88,6 +98,9 @@ def lib():
             "ipt_guide_free": [P],
             "ipt_guide_eval": [P, P, P, I64, P, P],
             "ipt_guide_train": [P, P, P, P, I32, P, SZ, P],
+            "ipt_profile_enable": [P, I32],
+            "ipt_profile_read": [P, I32, P],
+            "ipt_profile_reset": [P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -191,6 +204,17 @@ class Scene:
         inf = SceneInfo()
         _check(lib().ipt_scene_info(self.handle, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in SceneInfo._fields_}
+
+    def profile(self, enable=True):
+        _check(lib().ipt_profile_enable(self.handle, int(bool(enable))))
+
+    def profile_reset(self):
+        _check(lib().ipt_profile_reset(self.handle))
+
+    def profile_read(self, kernel):
+        kp = KernelProfile()
+        _check(lib().ipt_profile_read(self.handle, int(kernel), ctypes.byref(kp)))
+        return {k: getattr(kp, k) for k, _ in KernelProfile._fields_}
 
     def workspace_query(self, dcams, opts):
         mn, full = ctypes.c_size_t(), ctypes.c_size_t()
