@@ -90,6 +90,7 @@ typedef struct {
     float guide_mix;          /* probability of sampling the guide when guide != NULL */
     uint64_t *debug_path_hash;/* DEVICE [pixels*spp] or NULL: FNV-1a of each path's events */
     const uint8_t *path_mask; /* DEVICE [pixels*spp] or NULL: 0 removes the path */
+    float *debug_path_radiance;/* DEVICE [pixels*spp][3] or NULL (ipt_render only) */
 } ipt_render_opts;
 
 typedef struct {

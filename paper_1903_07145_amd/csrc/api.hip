@@ -373,6 +373,7 @@ static PathArgs base_args(const ipt_scene_s* s, const ipt_cameras* cams, const f
     a.jitter = o->jitter;
     a.pixel_list = o->pixel_list;
     a.hash = o->debug_path_hash;
+    a.path_L = o->debug_path_radiance;
     a.mask = o->path_mask;
     a.work = (unsigned*)(ws + pl.off_counters);
     a.err = s->d_err;

@@ -63,6 +63,7 @@ struct PathArgs {
     int64_t pix_begin, pix_count;  // work-pixel chunk
     float* image;                  // colour: [pixels][3]
     uint64_t* hash;                // [pixels*spp] or NULL
+    float* path_L;                 // colour: [pixels*spp][3] per-path radiance or NULL
     const uint8_t* mask;           // [pixels*spp] or NULL
     int4* ck_hit;                  // checkpoint planes, [(k-1)*spp + s][pix_count]
     float4* ck_a;

@@ -115,8 +115,9 @@ __device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax
             int c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
             float t0 = box_entry(r, v3(n0.x, n0.y, n0.z), v3(n0.w, n1.x, n1.y), tmin, best.t);
             float t1 = box_entry(r, v3(n1.z, n1.w, n2.x), v3(n2.y, n2.z, n2.w), tmin, best.t);
-            bool h0 = t0 <= best.t;
-            bool h1 = (c1 != kNone) && t1 <= best.t;
+            // box_entry returns +inf on a miss; best.t may itself be +inf
+            bool h0 = t0 < __builtin_inff();
+            bool h1 = (c1 != kNone) && t1 < __builtin_inff();
             if (h0 && h1) {
                 bool first0 = t0 <= t1;
                 st.push(first0 ? c1 : c0);
@@ -564,6 +565,11 @@ __global__ __launch_bounds__(kBlock) void path_kernel(PathArgs a) {
             }
             if (MODE == kGradFwd && drop) atomicAdd(&a.err->nonfinite, 1ull);
             if (MODE != kReplay && a.hash) a.hash[pidx] = hsh;
+            if (MODE == kColor && a.path_L) {
+                a.path_L[3 * pidx] = Lp.x;
+                a.path_L[3 * pidx + 1] = Lp.y;
+                a.path_L[3 * pidx + 2] = Lp.z;
+            }
         }
         if (MODE == kColor) {
             float inv = 1.0f / (float)a.spp;

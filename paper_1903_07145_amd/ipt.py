@@ -41,7 +41,8 @@ class RenderOpts(ctypes.Structure):
                 ("mis", ctypes.c_int32), ("emission_profile", ctypes.c_int32), ("jitter", ctypes.c_int32),
                 ("replay_traverse", ctypes.c_int32), ("pixel_list", ctypes.c_void_p),
                 ("num_pixels", ctypes.c_int64), ("guide", ctypes.c_void_p), ("guide_mix", ctypes.c_float),
-                ("debug_path_hash", ctypes.c_void_p), ("path_mask", ctypes.c_void_p)]
+                ("debug_path_hash", ctypes.c_void_p), ("path_mask", ctypes.c_void_p),
+                ("debug_path_radiance", ctypes.c_void_p)]
 
 
 class AdamOpts(ctypes.Structure):
@@ -153,7 +154,7 @@ def _cams_struct(dc):
 
 def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=-1, mis=2,
                 emission_profile=0, jitter=1, replay_traverse=0, pixel_list=None, guide=None,
-                guide_mix=0.0, debug_path_hash=None, path_mask=None):
+                guide_mix=0.0, debug_path_hash=None, path_mask=None, debug_path_radiance=None):
     o = RenderOpts()
     o.seed, o.stream_tag, o.iteration = int(seed), int(stream_tag), int(iteration)
     o.spp, o.max_depth, o.rr_depth, o.mis = int(spp), int(max_depth), int(rr_depth), int(mis)
@@ -164,7 +165,8 @@ def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=
     o.guide_mix = float(guide_mix)
     o.debug_path_hash = None if debug_path_hash is None else debug_path_hash.data_ptr()
     o.path_mask = None if path_mask is None else path_mask.data_ptr()
-    o._keep = (pixel_list, debug_path_hash, path_mask)
+    o.debug_path_radiance = None if debug_path_radiance is None else debug_path_radiance.data_ptr()
+    o._keep = (pixel_list, debug_path_hash, path_mask, debug_path_radiance)
     return o
 
 
