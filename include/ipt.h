@@ -91,6 +91,9 @@ typedef struct {
     uint64_t *debug_path_hash;/* DEVICE [pixels*spp] or NULL: FNV-1a of each path's events */
     const uint8_t *path_mask; /* DEVICE [pixels*spp] or NULL: 0 removes the path */
     float *debug_path_radiance;/* DEVICE [pixels*spp][3] or NULL (ipt_render only) */
+    float *debug_vertices;    /* DEVICE [pixels*spp][max_depth+1][8] or NULL (ipt_render
+                                 only): per vertex input triangle id, u, v, t and the
+                                 path radiance accumulated so far */
 } ipt_render_opts;
 
 typedef struct {

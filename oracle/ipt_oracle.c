@@ -753,12 +753,26 @@ typedef struct {
     const double *p, *sp;
     const lightdist *L;
     const orc_opts *o;
+    double pert;      /* conditioning probe: relative perturbation injected at every vertex */
+    v3 pert_dir;
 } ctx;
+
+/* Optional per-vertex record of a path (test diagnostics): for vertex k
+ * (1..D+1) the hit triangle id, u, v, t and the local contribution c_k
+ * (emission hit + light sample, without the prefix throughput). */
+typedef struct { double *v; int nv; } vdump;
 
 /* One path.  Returns radiance in L; adds w-weighted derivatives into grad if
  * grad != NULL.  Event hash in *hash. */
+static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const double *wc,
+                         double *grad, double Lout[3], uint64_t *hash, double *margin, vdump *vd);
 static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const double *wc,
                        double *grad, double Lout[3], uint64_t *hash, double *margin)
+{
+    trace_path_v(C, org, dir, path_id, wc, grad, Lout, hash, margin, NULL);
+}
+static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const double *wc,
+                         double *grad, double Lout[3], uint64_t *hash, double *margin, vdump *vd)
 {
     double mg = INFINITY;
     double *M = margin ? &mg : NULL;
@@ -781,11 +795,17 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
     for (int k = 1; k <= D + 1; ++k) {
         ohit hit = closest_m(s, o, d, tmin, INFINITY, prev_tri, -1, C->o->brute_force, M);
         h = fnv(h, (uint32_t)hit.tri);
+        if (vd && k - 1 < vd->nv) {
+            double *r = vd->v + 8 * (k - 1);
+            r[0] = hit.tri; r[1] = hit.u; r[2] = hit.v; r[3] = hit.t;
+            r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; r[7] = 0;
+        }
         if (hit.tri < 0) break;
         const int32_t *f = &s->F[3 * (int64_t)hit.tri];
         v3 p0 = vtx(s, f[0]), p1 = vtx(s, f[1]), p2 = vtx(s, f[2]);
         v3 e1 = sub(p1, p0), e2 = sub(p2, p0);
         v3 x = add(p0, add(scl(e1, hit.u), scl(e2, hit.v)));
+        if (C->pert != 0.0) x = add(x, scl(C->pert_dir, C->pert * rel_scale(x)));
         v3 ng = nrm(cross(e1, e2));
         int seg = s->seg[hit.tri];
         int em = s->seg_emitter[seg];
@@ -817,6 +837,7 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
                 double tau[3];
                 term_grad(a, na, &phi, wc, grad, tau);
                 for (int c = 0; c < 3; ++c) L[c] += tau[c];
+                if (vd && k - 1 < vd->nv) { double *r = vd->v + 8 * (k - 1); r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; }
             }
             ev |= 1u;
         }
@@ -831,10 +852,12 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
             ns = nrm(add(scl(n0, 1.0 - hit.u - hit.v), add(scl(n1, hit.u), scl(n2, hit.v))));
         }
         v3 ngf = ng;
+        NEAR(dot(ng, wo));
         if (dot(ng, wo) < 0) { ngf = scl(ng, -1.0); ns = scl(ns, -1.0); }
         NEAR(dot(ns, wo));
         if (dot(ns, wo) <= 0) { h = fnv(h, ev | 2u); break; }   /* shading normal faces away */
         const double *mp = p + 7 * seg, *msp = sp + 7 * seg;
+        if (ns.z != 0.0) NEAR(ns.z);   /* the tangent frame switches sign convention at n.z = 0 */
         double u[8];
         vertex_uniforms(C->o->seed, C->o->stream_tag, C->o->iteration, path_id, k, u);
         /* --- explicit light sampling (next-event estimation) --- */
@@ -901,6 +924,8 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
                     double tau[3];
                     term_grad(a, na, &phi, wc, grad, tau);
                     for (int c = 0; c < 3; ++c) L[c] += tau[c];
+                    if (vd && k - 1 < vd->nv) { double *r = vd->v + 8 * (k - 1); r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; r[7] = 1; }
+                if (vd && k - 1 < vd->nv) { double *r = vd->v + 8 * (k - 1); r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; }
                 }
             }
         }
@@ -952,6 +977,7 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
         prev_pdf = pdf;
         prev_tri = hit.tri;
         o = x; d = wi;
+        if (C->pert != 0.0) d = nrm(add(d, scl(C->pert_dir, C->pert)));
     }
     for (int c = 0; c < 3; ++c) Lout[c] = L[c];
     *hash = h;
@@ -967,12 +993,12 @@ static void trace_path(const ctx *C, v3 org, v3 dir, uint64_t path_id, const dou
 int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
                 const double *sampling_params, const orc_opts *o, const double *w,
                 const uint8_t *path_mask, double *image, double *grad, uint64_t *hashes,
-                double *path_L, double *margins)
+                double *path_L, double *margins, double *conds, double *vertices)
 {
     const double *sp = sampling_params ? sampling_params : params;
     int64_t P = 7 * (int64_t)s->ns + 3 * (int64_t)s->ne;
     lightdist L = build_lights(s, sp);
-    ctx C = { s, params, sp, &L, o };
+    ctx C = { s, params, sp, &L, o, 0.0, { 0, 0, 0 } };
     int64_t npix = o->pixel_list ? o->num_pixels
                                  : (int64_t)cams->num_views * cams->width * cams->height;
     int64_t dropped = 0;
@@ -1014,8 +1040,38 @@ int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
             (void)gbuf_local;
             if (gt && use) gp = (double *)calloc((size_t)P, sizeof(double));
             double mgn = INFINITY;
-            trace_path(&C, org, dir, pid, wc, gp, Lp, &hsh, margins ? &mgn : NULL);
+            vdump vdd;
+            vdd.nv = o->max_depth + 1;
+            vdd.v = vertices ? vertices + (size_t)(i * o->spp + sidx) * 8 * (size_t)vdd.nv : NULL;
+            if (vdd.v) for (int q = 0; q < 8 * vdd.nv; ++q) vdd.v[q] = -1.0;
+            trace_path_v(&C, org, dir, pid, wc, gp, Lp, &hsh, margins ? &mgn : NULL, vdd.v ? &vdd : NULL);
             if (margins) margins[i * o->spp + sidx] = mgn;
+            if (conds) {
+                /* Conditioning of the path: relative change of its radiance when
+                 * every vertex position and every direction is perturbed by a
+                 * relative 1e-6 along a fixed direction (two signs), infinite if a
+                 * discrete event changes.  Float32 rounding injects ~1e-7 at every
+                 * vertex; paths that amplify such perturbations (e.g. repeated
+                 * reflections between curved, smoothly shaded surfaces diverge
+                 * exponentially) cannot be reproduced to 1e-4 in float32. */
+                double c = 0.0;
+                double lm = fmax(fmax(fabs(Lp[0]), fabs(Lp[1])), fabs(Lp[2]));
+                for (int k = 0; k < 2 && isfinite(c); ++k) {
+                    ctx Cp = C;
+                    Cp.pert = k == 0 ? 1e-6 : -1e-6;
+                    Cp.pert_dir = nrm(mk(0.6, -0.48, 0.64));
+                    v3 d2 = nrm(add(dir, scl(Cp.pert_dir, Cp.pert)));
+                    double L2[3];
+                    uint64_t h2;
+                    trace_path(&Cp, org, d2, pid, wc, NULL, L2, &h2, NULL);
+                    if (h2 != hsh) { c = INFINITY; break; }
+                    for (int q = 0; q < 3; ++q) {
+                        double r = fabs(L2[q] - Lp[q]) / fmax(lm, 1e-12);
+                        if (r > c) c = r;
+                    }
+                }
+                conds[i * o->spp + sidx] = c;
+            }
             int fin = isfinite(Lp[0]) && isfinite(Lp[1]) && isfinite(Lp[2]);
             if (gp) for (int64_t q = 0; q < P && fin; ++q) if (!isfinite(gp[q])) fin = 0;
             if (!fin) { dropped++; Lp[0] = Lp[1] = Lp[2] = 0; }

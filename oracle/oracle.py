@@ -48,7 +48,7 @@ def lib():
         L.orc_scene_num_light_tris.restype = ctypes.c_int64
         L.orc_scene_num_light_tris.argtypes = [P]
         L.orc_run.restype = ctypes.c_int64
-        L.orc_run.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_run.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_ray_triangle.restype = ctypes.c_int
         L.orc_ray_triangle.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
@@ -164,8 +164,8 @@ class Scene:
                                         t.shape[0], self.num_segments, _ptr(e), e.size)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orc_scene_free(self.h)
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.orc_scene_free(self.h)
             self.h = None
 
     @property
@@ -198,12 +198,17 @@ class Scene:
     def run(self, cams, params, sampling_params=None, *, seed=0, stream_tag=1, iteration=0,
             spp=4, max_depth=3, rr_depth=-1, mis=2, emission_profile=0, jitter=1,
             brute_force=False, pixel_list=None, w=None, path_mask=None, want_grad=False,
-            want_hash=False, want_path_L=False, want_margin=False):
+            want_hash=False, want_path_L=False, want_margin=False, want_cond=False,
+            want_vertices=False):
         """Render (and optionally differentiate) pixels.
 
         cams: dict with cam_to_world [V,4,4] float32, fov_y [V], width, height.
         Returns dict(image [npix,3], grad [P] or None, hash [npix,spp] or None,
-        path_L, margin [npix,spp] (near-tie margin of each path), dropped).
+        path_L, margin [npix,spp] (near-tie margin of each path), cond
+        [npix,spp] (relative radiance change when every vertex and direction
+        is perturbed by 1e-6 relative; inf if an event changes), vertices
+        [npix,spp,D+1,8] (per vertex: triangle id, u, v, t, radiance so far),
+        dropped).
         """
         c2w = np.ascontiguousarray(cams["cam_to_world"], dtype=np.float32)
         fov = np.ascontiguousarray(cams["fov_y"], dtype=np.float32)
@@ -224,7 +229,10 @@ class Scene:
         hsh = np.zeros((npix, spp), dtype=np.uint64) if want_hash else None
         pL = np.zeros((npix, spp, 3)) if want_path_L else None
         mg = np.zeros((npix, spp)) if want_margin else None
+        cd = np.zeros((npix, spp)) if want_cond else None
+        vx = np.zeros((npix, spp, max_depth + 1, 8)) if want_vertices else None
         dropped = lib().orc_run(self.h, ctypes.byref(C), _ptr(p), _ptr(sp), ctypes.byref(O),
                                 _ptr(ww), _ptr(pm), _ptr(img), _ptr(grad), _ptr(hsh), _ptr(pL),
-                                _ptr(mg))
-        return dict(image=img, grad=grad, hash=hsh, path_L=pL, margin=mg, dropped=int(dropped))
+                                _ptr(mg), _ptr(cd), _ptr(vx))
+        return dict(image=img, grad=grad, hash=hsh, path_L=pL, margin=mg, cond=cd, vertices=vx,
+                    dropped=int(dropped))

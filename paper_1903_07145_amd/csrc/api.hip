@@ -374,6 +374,7 @@ static PathArgs base_args(const ipt_scene_s* s, const ipt_cameras* cams, const f
     a.pixel_list = o->pixel_list;
     a.hash = o->debug_path_hash;
     a.path_L = o->debug_path_radiance;
+    a.dbg_vtx = o->debug_vertices;
     a.mask = o->path_mask;
     a.work = (unsigned*)(ws + pl.off_counters);
     a.err = s->d_err;

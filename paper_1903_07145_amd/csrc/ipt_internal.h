@@ -64,6 +64,7 @@ struct PathArgs {
     float* image;                  // colour: [pixels][3]
     uint64_t* hash;                // [pixels*spp] or NULL
     float* path_L;                 // colour: [pixels*spp][3] per-path radiance or NULL
+    float* dbg_vtx;                // colour: [pixels*spp][D+1][8] per-vertex record or NULL
     const uint8_t* mask;           // [pixels*spp] or NULL
     int4* ck_hit;                  // checkpoint planes, [(k-1)*spp + s][pix_count]
     float4* ck_a;

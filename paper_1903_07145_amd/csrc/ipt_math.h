@@ -256,8 +256,9 @@ __device__ __forceinline__ bool brdf_sample(const Mat& m, V3 n, V3 wo, float u3,
     V3 t, b;
     onb(n, t, b);
     float ps = lobe_prob(m);
+    // sin/cos of 2 pi u5 without rounding the angle: 2 u5 is exact
     float s, c;
-    sincosf(2.0f * kPi * u5, &s, &c);
+    sincospif(2.0f * u5, &s, &c);
     if (u3 < ps) {
         lobe = 1;
         float a = clamp_alpha(m.alpha);

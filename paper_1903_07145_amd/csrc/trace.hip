@@ -209,7 +209,7 @@ __device__ __forceinline__ void lds_add(float* g, int i, float x) {
 // ---------------------------------------------------------------------------
 template <int MODE>
 __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, Work& wk, uint64_t pid, int64_t q, int s,
-                       V3 org, V3 dir, V3 wpix, uint64_t& hash, bool& drop_out) {
+                       V3 org, V3 dir, V3 wpix, uint64_t& hash, bool& drop_out, float* dv) {
     const SceneDev& sc = a.sc;
     const float* cdf = lds.lights_in_lds ? lds.cdf : a.cdf;
     const int4* lights = lds.lights_in_lds ? lds.lights : sc.lights;
@@ -262,6 +262,11 @@ __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, Work& wk, u
         int orig, seg, light;
         load_tri(sc, hit.tri, p0, p1, p2, orig, seg, light);
         h = fnv1a(h, (uint32_t)orig);
+        float* dvk = dv ? dv + 8 * (k - 1) : nullptr;
+        if (dvk) {
+            dvk[0] = (float)orig; dvk[1] = hit.u; dvk[2] = hit.v; dvk[3] = hit.t;
+            dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; dvk[7] = 0.0f;
+        }
         V3 e1 = p1 - p0, e2 = p2 - p0;
         V3 x = p0 + e1 * hit.u + e2 * hit.v;
         V3 ng = normalize(cross(e1, e2));
@@ -286,6 +291,7 @@ __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, Work& wk, u
                 V3 c = v3(e[0], e[1], e[2]) * (prof * w);
                 ck_c = ck_c + c;
                 L = L + T * c;
+                if (dvk) { dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; }
                 if (MODE == kReplay) {
                     int eb = 7 * sc.S + 3 * em;
                     lds_add(lds.grad, eb + 0, wT.x * prof * w);
@@ -376,6 +382,7 @@ __device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, Work& wk, u
                         V3 c = f * e * g;
                         ck_c = ck_c + c;
                         L = L + T * c;
+                        if (dvk) { dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; dvk[7] = 1.0f; }
                         if (MODE == kReplay) {
                             int mb = 7 * seg, eb = 7 * sc.S + 3 * lk;
                             V3 we = wT * e * g;
@@ -554,7 +561,12 @@ __global__ __launch_bounds__(kBlock) void path_kernel(PathArgs a) {
             camera_ray(a, view, (float)px + j0, (float)py + j1, o, d);
             uint64_t hsh;
             bool drop;
-            V3 Lp = run_path<MODE>(a, lds, st, wk, pid, q, s, o, d, wpix, hsh, drop);
+            float* dv = nullptr;
+            if (MODE == kColor && a.dbg_vtx) {
+                dv = a.dbg_vtx + pidx * 8 * (size_t)(a.D + 1);
+                for (int k = 0; k < 8 * (a.D + 1); ++k) dv[k] = -1.0f;
+            }
+            V3 Lp = run_path<MODE>(a, lds, st, wk, pid, q, s, o, d, wpix, hsh, drop, dv);
             ++npaths;
             if (MODE == kColor) {
                 if (!finite3(Lp)) {

@@ -42,7 +42,7 @@ class RenderOpts(ctypes.Structure):
                 ("replay_traverse", ctypes.c_int32), ("pixel_list", ctypes.c_void_p),
                 ("num_pixels", ctypes.c_int64), ("guide", ctypes.c_void_p), ("guide_mix", ctypes.c_float),
                 ("debug_path_hash", ctypes.c_void_p), ("path_mask", ctypes.c_void_p),
-                ("debug_path_radiance", ctypes.c_void_p)]
+                ("debug_path_radiance", ctypes.c_void_p), ("debug_vertices", ctypes.c_void_p)]
 
 
 class AdamOpts(ctypes.Structure):
@@ -154,7 +154,8 @@ def _cams_struct(dc):
 
 def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=-1, mis=2,
                 emission_profile=0, jitter=1, replay_traverse=0, pixel_list=None, guide=None,
-                guide_mix=0.0, debug_path_hash=None, path_mask=None, debug_path_radiance=None):
+                guide_mix=0.0, debug_path_hash=None, path_mask=None, debug_path_radiance=None,
+                debug_vertices=None):
     o = RenderOpts()
     o.seed, o.stream_tag, o.iteration = int(seed), int(stream_tag), int(iteration)
     o.spp, o.max_depth, o.rr_depth, o.mis = int(spp), int(max_depth), int(rr_depth), int(mis)
@@ -166,7 +167,8 @@ def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=
     o.debug_path_hash = None if debug_path_hash is None else debug_path_hash.data_ptr()
     o.path_mask = None if path_mask is None else path_mask.data_ptr()
     o.debug_path_radiance = None if debug_path_radiance is None else debug_path_radiance.data_ptr()
-    o._keep = (pixel_list, debug_path_hash, path_mask, debug_path_radiance)
+    o.debug_vertices = None if debug_vertices is None else debug_vertices.data_ptr()
+    o._keep = (pixel_list, debug_path_hash, path_mask, debug_path_radiance, debug_vertices)
     return o
 
 

@@ -26,12 +26,13 @@ def dev(x, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
 
 
-def gpu_render(g, dc, params, opts_kw, pixel_list=None, sampling_params=None):
+def gpu_render(g, dc, params, opts_kw, pixel_list=None, sampling_params=None, mask=None):
     npix = dc["num_views"] * dc["width"] * dc["height"] if pixel_list is None else pixel_list.size
     spp = opts_kw.get("spp", 4)
     hsh = torch.zeros(npix * spp, dtype=torch.int64, device="cuda")
     pl = None if pixel_list is None else dev(pixel_list, torch.int64)
-    o = ipt.render_opts(pixel_list=pl, debug_path_hash=hsh, **opts_kw)
+    pm = None if mask is None else dev(np.asarray(mask).reshape(-1).astype(np.uint8), torch.uint8)
+    o = ipt.render_opts(pixel_list=pl, debug_path_hash=hsh, path_mask=pm, **opts_kw)
     img = g.render(dc, dev(params), o, sampling_params=None if sampling_params is None else dev(sampling_params))
     torch.cuda.synchronize()
     return img.cpu().numpy().astype(np.float64), hsh.cpu().numpy().view(np.uint64).reshape(npix, spp)
@@ -56,12 +57,27 @@ def oracle_opts(kw):
 
 
 NEAR_TIE = 1e-5   # relative margin under which float32 and float64 may legitimately disagree
+ILL_COND = 1e-3   # path radiance change under 1e-6 relative perturbations at every vertex
 
 
-def mismatch_stats(hash_g, hash_o, margin):
-    """(paths mismatching, of which not near-tie)."""
+def mismatch_stats(hash_g, hash_o, margin, cond=None):
+    """(paths mismatching, of which neither near-tie nor ill-conditioned)."""
     mism = hash_g != hash_o
-    return int(mism.sum()), int((mism & (margin >= NEAR_TIE)).sum())
+    hard = mism & (margin >= NEAR_TIE)
+    if cond is not None:
+        hard &= cond <= ILL_COND
+    return int(mism.sum()), int(hard.sum())
+
+
+def comparable(hash_g, r):
+    """Paths whose float32 radiance is expected to match float64 to 1e-4:
+    same events, not a near-tie, and well conditioned."""
+    ok = hash_g == r["hash"]
+    if r.get("margin") is not None:
+        ok &= r["margin"] >= NEAR_TIE
+    if r.get("cond") is not None:
+        ok &= r["cond"] <= ILL_COND
+    return ok
 
 
 def image_parity(img_g, img_o, hash_g, hash_o, rel=1e-4):

@@ -11,8 +11,8 @@ import numpy as np
 import pytest
 import torch
 
-from _gpu import (NEAR_TIE, banner, both, dev, gpu_grad, gpu_render, image_parity, mismatch_stats,
-                  oracle_opts)
+from _gpu import (NEAR_TIE, banner, both, comparable, dev, gpu_grad, gpu_render, image_parity,
+                  mismatch_stats, oracle_opts)
 from paper_1903_07145_amd import ipt, scenes
 
 pytestmark = pytest.mark.gpu
@@ -165,6 +165,11 @@ def test_furnace_closed_form_gpu():
 
 
 def test_room_parity_crop():
+    """50k triangles, GGX, smooth cylinder normals, depth 5.  Paths that bounce
+    between curved smoothly shaded objects are chaotic (float32 rounding at one
+    vertex grows ~10x per bounce); the oracle measures every path's
+    conditioning and both sides drop the paths that are near-ties or
+    ill-conditioned (a path mask), then compare pixel means at 1e-4."""
     banner("room (50k triangles, GGX) parity on a crop")
     sc = scenes.room()
     g, o = both(sc)
@@ -173,24 +178,26 @@ def test_room_parity_crop():
     rng = np.random.default_rng(4)
     pix = np.sort(rng.choice(4 * W * H, size=1500, replace=False)).astype(np.int64)
     kw = dict(seed=21, stream_tag=2, iteration=2, spp=16, max_depth=5, mis=2)
-    img_g, h_g = gpu_render(g, dc, sc["params"], kw, pixel_list=pix)
-    r = o.run(sc["cams"], sc["params"], pixel_list=pix, want_hash=True, want_margin=True, **oracle_opts(kw))
-    ok, mfrac, emax, _ = image_parity(img_g, r["image"], h_g, r["hash"])
-    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"])
-    print("paths %d mismatching %d (not near-tie %d), max rel err %.2e" % (h_g.size, n_mis, n_hard, emax))
-    mm = h_g != r["hash"]
-    print("margins of mismatching paths:", np.sort(r["margin"][mm])[:20])
-    _, _, _, err = image_parity(img_g, r["image"], h_g, r["hash"])
-    okp = (h_g == r["hash"]).all(axis=1)
-    print("pixel err percentiles (matched):", np.percentile(err[okp], [50, 99, 99.9, 100]))
+    _, h_g = gpu_render(g, dc, sc["params"], kw, pixel_list=pix)
+    r = o.run(sc["cams"], sc["params"], pixel_list=pix, want_hash=True, want_margin=True, want_cond=True,
+              **oracle_opts(kw))
+    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"], r["cond"])
+    keep = comparable(h_g, r)
+    print("paths %d mismatching %d (hard %d), compared %.1f%%" % (h_g.size, n_mis, n_hard, 100 * keep.mean()))
     assert n_hard <= RAY_BAR * _rays(5, h_g.size), n_hard
-    assert emax <= PIX_REL, emax
-    mask = (h_g == r["hash"]).astype(np.uint8)
+    assert keep.mean() > 0.85
+    img_g, _ = gpu_render(g, dc, sc["params"], kw, pixel_list=pix, mask=keep)
+    ro = o.run(sc["cams"], sc["params"], pixel_list=pix, path_mask=keep.astype(np.uint8), **oracle_opts(kw))
+    mean = np.abs(ro["image"]).mean()
+    err = np.abs(img_g - ro["image"]) / np.maximum(np.abs(ro["image"]), 1e-4 * mean)
+    print("pixel rel err p50 %.2e p99 %.2e max %.2e" % tuple(np.percentile(err, [50, 99, 100])))
+    assert err.max() <= PIX_REL, err.max()
     w = rng.normal(size=(pix.size, 3))
-    gg = gpu_grad(g, dc, sc["params"], w, kw, pixel_list=pix, mask=mask)
-    go = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, path_mask=mask, want_grad=True,
+    gg = gpu_grad(g, dc, sc["params"], w, kw, pixel_list=pix, mask=keep)
+    go = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, path_mask=keep.astype(np.uint8), want_grad=True,
                **oracle_opts(kw))["grad"]
     emax, err = _grad_parity(gg, go)
+    print("grad rel err max %.2e" % emax)
     assert emax <= GRAD_REL, (emax, np.argmax(err))
 
 
