@@ -15,16 +15,17 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Wno-unused-command-line-argument"]
 
 
-def build(verbose=False, jobs=4):
+def build(verbose=False, jobs=4, out=None, defines=()):
     """Compile every source to an object (in parallel) and link the shared library."""
     hipcc = os.environ.get("HIPCC", "hipcc")
-    objdir = os.path.join(HERE, "_build")
+    lib = out or LIB
+    objdir = os.path.join(HERE, "_build" if out is None else "_build_" + os.path.basename(out).replace(".", "_"))
     os.makedirs(objdir, exist_ok=True)
     procs, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmd = [hipcc] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc] + FLAGS + ["-D" + d for d in defines] + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [hipcc, "-O3", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
@@ -40,11 +41,11 @@ def build(verbose=False, jobs=4):
             sys.stderr.write(out.decode(errors="replace"))
     if not ok:
         raise RuntimeError("HIP build failed")
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -1,9 +1,7 @@
 // Path kernels of the inverse path tracer (gfx950).
 //
-// One lane owns one pixel and walks its spp paths one after another, so the
-// pixel mean is formed in registers (no atomics, deterministic).  Blocks are
-// persistent: they pull 256-pixel tiles from a counter until the chunk is
-// done.  The same path loop runs in three modes:
+// Three passes share one set of shading functions, so they compute the same
+// values:
 //   kColor   - the Monte Carlo pixel estimate (Sec. 3.1, Eq. 1-2) with MIS of
 //              BRDF sampling and light sampling (Appendix A.2, Appendix E);
 //   kGradFwd - the gradient-stream forward pass: traces the independent
@@ -19,6 +17,15 @@
 //              w . T_{k-1} (dc_k/dtheta + da_k/dtheta R_{k+1}) -- the product
 //              rule of Eq. 5 (emission) and Eq. 6 (materials) -- into a block
 //              private gradient in LDS.
+//
+// kColor and kGradFwd run as a per-lane state machine around ONE traversal
+// call site that serves both closest-hit and shadow rays: every iteration
+// each lane traces whatever ray it has pending, then advances its path.  A
+// lane owns one pixel and walks its spp samples in order, so the pixel mean
+// is formed in registers (deterministic, no atomics); a lane that finishes
+// its pixel takes the next one at once (the wave takes as many pixels as it
+// has idle lanes with one atomic).  The lanes of a wave thus stay in the same
+// phase instead of serialising the divergent loops of a nested megakernel.
 #include <hip/hip_runtime.h>
 
 #include "ipt_internal.h"
@@ -46,6 +53,38 @@ size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt) {
     if (mode == kReplay) b += al(sizeof(float) * P);  // block gradient
     b += sizeof(int) * kShortStack * kBlock;          // short stacks
     return b;
+}
+
+__device__ void carve_lds(const PathArgs& a, int mode, unsigned char* smem, Lds& lds) {
+    const int tid = threadIdx.x;
+    unsigned char* p = smem;
+    auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
+    lds.params = (float*)p; p += al(sizeof(float) * a.P);
+    lds.sparams = lds.params;
+    if (a.frozen) { lds.sparams = (float*)p; p += al(sizeof(float) * a.P); }
+    lds.seg_emitter = (int*)p; p += al(sizeof(int) * a.sc.S);
+    lds.lights_in_lds = a.sc.nlt <= kMaxLdsLights;
+    lds.cdf = nullptr;
+    lds.lights = nullptr;
+    if (lds.lights_in_lds) {
+        lds.cdf = (float*)p; p += al(sizeof(float) * a.sc.nlt);
+        lds.lights = (int4*)p; p += al(sizeof(int4) * a.sc.nlt);
+    }
+    lds.grad = nullptr;
+    if (mode == kReplay) { lds.grad = (float*)p; p += al(sizeof(float) * a.P); }
+    lds.stack = (int*)p;
+    for (int i = tid; i < a.P; i += kBlock) {
+        lds.params[i] = a.params[i];
+        if (a.frozen) lds.sparams[i] = a.sparams[i];
+        if (mode == kReplay) lds.grad[i] = 0.0f;
+    }
+    for (int i = tid; i < a.sc.S; i += kBlock) lds.seg_emitter[i] = a.sc.seg_emitter[i];
+    if (lds.lights_in_lds)
+        for (int i = tid; i < a.sc.nlt; i += kBlock) {
+            lds.cdf[i] = a.cdf[i];
+            lds.lights[i] = a.sc.lights[i];
+        }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -78,9 +117,23 @@ struct Stack {
     }
 };
 
+__device__ __forceinline__ void init_stack(Stack& st, const PathArgs& a, int* lds_stack) {
+    st.lds = lds_stack;
+    st.ovf = a.ovf;
+    st.tid = threadIdx.x;
+    st.gtid = blockIdx.x * kBlock + threadIdx.x;
+    st.gthreads = gridDim.x * kBlock;
+    st.overflow = false;
+    st.sp = 0;
+}
+
 struct Hit {
     int tri;     // leaf-ordered index, -1 on miss
     float t, u, v;
+};
+
+struct Work {
+    uint32_t rays, nodes, tris, vertices;
 };
 
 __device__ __forceinline__ void load_tri(const SceneDev& sc, int i, V3& p0, V3& p1, V3& p2, int& orig,
@@ -92,22 +145,18 @@ __device__ __forceinline__ void load_tri(const SceneDev& sc, int i, V3& p0, V3& 
     light = __float_as_int(c.w);
 }
 
-// Closest hit (ANY = false) or occlusion test (ANY = true: returns tri >= 0
-// as soon as anything lies in (tmin, tmax)).  skip0/skip1 are leaf indices
-// that are ignored.  Ties in t are resolved toward the smaller original id.
-struct Work {
-    uint32_t rays, nodes, tris, vertices;
-};
-
-template <bool ANY>
-__device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax, int skip0, int skip1,
+// Closest hit (any = false) or occlusion test (any = true: stops at the
+// first hit in (tmin, tmax)).  skip0/skip1 are leaf indices that are ignored.
+// Ties in t are resolved toward the smaller original id.
+__device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax, int skip0, int skip1, bool any,
                         Stack& st, Work& wk) {
     Hit best{-1, tmax, 0.0f, 0.0f};
-    wk.rays++;
     int best_orig = 0x7FFFFFFF;
+    wk.rays++;
     st.sp = 0;
     int entry = 0;
-    while (true) {
+    bool done = false;
+    while (!done) {
         if (entry >= 0) {
             wk.nodes++;
             const float4* n = sc.nodes + 4 * (size_t)entry;
@@ -137,18 +186,19 @@ __device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax
                 load_tri(sc, i, p0, p1, p2, orig, seg, light);
                 float t, u, v;
                 if (!tri_isect(r, p0, p1, p2, tmin, t, u, v)) continue;
-                if (ANY) {
-                    if (t < tmax) { best.tri = i; best.t = t; return best; }
+                if (any) {
+                    if (t < tmax) { best.tri = i; best.t = t; done = true; break; }
                 } else if (t < best.t || (t == best.t && orig < best_orig)) {
                     best.tri = i; best.t = t; best.u = u; best.v = v;
                     best_orig = orig;
                 }
             }
+            if (done) break;
         }
         if (st.sp == 0 || st.overflow) break;
         entry = st.pop();
     }
-    if (!ANY && best.tri >= 0 && !(best.t < tmax)) best.tri = -1;
+    if (!any && best.tri >= 0 && !(best.t < tmax)) best.tri = -1;
     return best;
 }
 
@@ -204,330 +254,560 @@ __device__ __forceinline__ void lds_add(float* g, int i, float x) {
 }
 
 // ---------------------------------------------------------------------------
-// One path.  Returns the path radiance; in kGradFwd also writes checkpoints;
-// in kReplay adds w-weighted derivatives into lds.grad.
+// Shading shared by all passes.
 // ---------------------------------------------------------------------------
+struct Shade {
+    V3 p0, e1, e2, x, ng, ngf, ns, wo;
+    int tri, orig, seg, light, em;
+    float u, v, t, cos_emit;
+};
+
+// Geometry of a hit: position from barycentrics, geometric and shading
+// normals, both flipped toward the incoming ray (two-sided reflection).
+__device__ __forceinline__ void make_shade(const SceneDev& sc, const Lds& lds, const Hit& hit, V3 d, Shade& g) {
+    V3 p1, p2;
+    load_tri(sc, hit.tri, g.p0, p1, p2, g.orig, g.seg, g.light);
+    g.tri = hit.tri;
+    g.u = hit.u;
+    g.v = hit.v;
+    g.t = hit.t;
+    g.e1 = p1 - g.p0;
+    g.e2 = p2 - g.p0;
+    g.x = g.p0 + g.e1 * hit.u + g.e2 * hit.v;
+    g.ng = normalize(cross(g.e1, g.e2));
+    g.em = lds.seg_emitter[g.seg];
+    g.cos_emit = -dot(d, g.ng);
+    g.wo = v3(-d.x, -d.y, -d.z);
+    g.ns = g.ng;
+    if (sc.nrm) {
+        float b0 = 1.0f - hit.u - hit.v;
+        V3 n0 = xyz(sc.nrm[3 * hit.tri]), n1 = xyz(sc.nrm[3 * hit.tri + 1]), n2 = xyz(sc.nrm[3 * hit.tri + 2]);
+        g.ns = normalize(n0 * b0 + n1 * hit.u + n2 * hit.v);
+    }
+    g.ngf = g.ng;
+    if (dot(g.ng, g.wo) < 0.0f) { g.ngf = g.ng * -1.0f; g.ns = g.ns * -1.0f; }
+}
+
+// MIS weight of an emitter hit at vertex k reached by a direction sampled
+// with pdf prev_pdf (balance or power heuristic against light sampling).
+__device__ __forceinline__ float emit_weight(const PathArgs& a, const float* cdf, const int4* lights, const Shade& g,
+                                             int k, float prev_pdf) {
+    if (k == 1) return 1.0f;
+    if (a.mis == 1) return 0.0f;
+    if (a.mis == 0) return 1.0f;
+    float pa = light_prob(cdf, a.sc.nlt, g.light) / __int_as_float(lights[g.light].z);
+    float pl = pa * g.t * g.t / g.cos_emit;
+    return mis_weight(prev_pdf, pl, a.mis);
+}
+
+struct NeeS {
+    V3 wl;
+    float d2, dist, cy, larea;
+    int lj, ltri, lk;
+    bool shoot;   // geometric tests passed: a shadow ray is needed
+};
+
+// Pick an emitter triangle from the table and a uniform point on it.
+__device__ __forceinline__ NeeS nee_setup(const SceneDev& sc, const float* cdf, const int4* lights, const Shade& g,
+                                          const float u[8]) {
+    NeeS n;
+    n.lj = pick_light(cdf, sc.nlt, u[0]);
+    int4 lrec = lights[n.lj];
+    n.ltri = lrec.x;
+    n.lk = lrec.y;
+    n.larea = __int_as_float(lrec.z);
+    V3 q0, q1, q2;
+    int lorig, lseg, llight;
+    load_tri(sc, lrec.x, q0, q1, q2, lorig, lseg, llight);
+    float su = sqrtf(u[1]);
+    float b1 = (1.0f - u[2]) * su, b2 = u[2] * su;
+    // y - x from vertex differences and edge terms: the light point and the
+    // shading point are never rounded to world coordinates first
+    V3 dl = (q0 - g.p0) + ((q1 - q0) * b1 + (q2 - q0) * b2 - (g.e1 * g.u + g.e2 * g.v));
+    V3 lng = normalize(cross(q1 - q0, q2 - q0));
+    n.d2 = dot(dl, dl);
+    n.dist = sqrtf(n.d2);
+    n.wl = dl * (1.0f / n.dist);
+    n.cy = -dot(n.wl, lng);
+    float cxg = dot(n.wl, g.ngf);
+    // grazing configurations (cosines below 1e-6: the light triangle itself,
+    // a coplanar emitter) are skipped
+    n.shoot = n.cy > 1e-6f && cxg > 1e-6f;
+    return n;
+}
+
+struct NeeC {
+    V3 c;            // local contribution (without the prefix throughput)
+    V3 e, f;         // emission and BRDF value
+    float g;         // cos_x cos_y / d^2 * MIS weight / p_area * profile
+    float spec, dspec;
+    bool valid;
+};
+
+// The light-sample contribution assuming the shadow ray is unoccluded.
+__device__ __forceinline__ NeeC nee_contrib(const PathArgs& a, const Lds& lds, const float* cdf, const Shade& g,
+                                            const Mat& m, const Mat& ms, const NeeS& n) {
+    NeeC r;
+    spec_term(g.ns, g.wo, n.wl, m.alpha, r.spec, r.dspec);
+    float cx = dot(g.ns, n.wl);
+    r.valid = cx > 0.0f;
+    r.c = v3(0.0f, 0.0f, 0.0f);
+    r.e = r.c;
+    r.f = r.c;
+    r.g = 0.0f;
+    if (!r.valid) return r;
+    float parea = light_prob(cdf, a.sc.nlt, n.lj) / n.larea;
+    float w = 1.0f;
+    if (a.mis >= 2) {
+        float pl = parea * n.d2 / n.cy;
+        float pb = brdf_pdf(ms, g.ns, g.wo, n.wl);
+        w = mis_weight(pl, pb, a.mis);
+    }
+    float prof = a.profile ? n.cy : 1.0f;
+    r.g = cx * n.cy / n.d2 * w / parea * prof;
+    const float* ep = lds.params + 7 * a.sc.S + 3 * n.lk;
+    r.e = v3(ep[0], ep[1], ep[2]);
+    r.f = m.kd * kInvPi + m.ks * r.spec;
+    r.c = r.f * r.e * r.g;
+    return r;
+}
+
+struct ContS {
+    V3 wi, av, ts;     // av, ts: continuation weight at params / sampling params (before RR)
+    float pdf, g, spec, dspec, qrr;
+    int lobe;
+    bool ok;           // a direction above the surface with pdf > 0
+    bool alive;        // survived Russian roulette
+};
+
+// Sample the continuation direction from the lobe mixture at sampling
+// parameters; Russian roulette on the sampling-parameter throughput.
+__device__ __forceinline__ ContS cont_sample(const PathArgs& a, const Shade& g, const Mat& m, const Mat& ms,
+                                             const float u[8], int k, V3 Ts) {
+    ContS c;
+    c.lobe = 0;
+    c.pdf = 0.0f;
+    c.qrr = 1.0f;
+    c.alive = false;
+    c.av = v3(0.0f, 0.0f, 0.0f);
+    c.ts = c.av;
+    c.g = c.spec = c.dspec = 0.0f;
+    bool okd = brdf_sample(ms, g.ns, g.wo, u[3], u[4], u[5], c.wi, c.lobe);
+    if (okd && dot(c.wi, g.ngf) > 0.0f && dot(c.wi, g.ns) > 0.0f) c.pdf = brdf_pdf(ms, g.ns, g.wo, c.wi);
+    c.ok = c.pdf > 0.0f;
+    if (!c.ok) return c;
+    spec_term(g.ns, g.wo, c.wi, m.alpha, c.spec, c.dspec);
+    float ci = dot(g.ns, c.wi);
+    c.g = ci / c.pdf;
+    c.av = (m.kd * kInvPi + m.ks * c.spec) * c.g;
+    c.ts = c.av;
+    if (a.frozen) c.ts = (ms.kd * kInvPi + ms.ks * spec_only(g.ns, g.wo, c.wi, ms.alpha)) * c.g;
+    c.alive = true;
+    if (a.rr_depth >= 0 && k >= a.rr_depth) {
+        c.qrr = fminf(fmaxf(maxc(Ts * c.ts), 0.1f), 0.95f);
+        c.alive = u[6] < c.qrr;
+    }
+    return c;
+}
+
+// Backward sweep of the gradient forward pass: R_{k+1} into the c slot of
+// vertex k; returns the path radiance.
+__device__ __forceinline__ V3 suffix_sweep(const PathArgs& a, int klast, int s, int64_t q) {
+    const size_t plane = (size_t)a.pix_count;
+    V3 R = v3(0.0f, 0.0f, 0.0f);
+    for (int k = klast; k >= 1; --k) {
+        size_t ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
+        float4 c = a.ck_c[ck], av = a.ck_a[ck];
+        a.ck_c[ck] = make_float4(R.x, R.y, R.z, 0.0f);
+        R = v3(c.x, c.y, c.z) + v3(av.x, av.y, av.z) * R;
+    }
+    return R;
+}
+
+__device__ __forceinline__ void flush_stats(const PathArgs& a, int mode, const Work& wk, uint32_t npaths) {
+    if (!a.count_stats) return;
+    KStats* ks = &a.err->k[mode];
+    atomicAdd(&ks->rays, (unsigned long long)wk.rays);
+    atomicAdd(&ks->nodes, (unsigned long long)wk.nodes);
+    atomicAdd(&ks->tris, (unsigned long long)wk.tris);
+    atomicAdd(&ks->paths, (unsigned long long)npaths);
+    atomicAdd(&ks->vertices, (unsigned long long)wk.vertices);
+}
+
+// ---------------------------------------------------------------------------
+// Colour / gradient-forward kernel: per-lane state machine.
+// ---------------------------------------------------------------------------
+enum Phase { kNeedPixel = 0, kClosest = 1, kShadow = 2, kExit = 3 };
+
+#ifdef IPT_WAVES_PER_EU
+#define IPT_OCC __attribute__((amdgpu_waves_per_eu(IPT_WAVES_PER_EU, 8)))
+#else
+#define IPT_OCC
+#endif
+
 template <int MODE>
-__device__ V3 run_path(const PathArgs& a, const Lds& lds, Stack& st, Work& wk, uint64_t pid, int64_t q, int s,
-                       V3 org, V3 dir, V3 wpix, uint64_t& hash, bool& drop_out, float* dv) {
+__global__ __launch_bounds__(kBlock) IPT_OCC void path_sm_kernel(PathArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    Lds lds;
+    carve_lds(a, MODE, smem, lds);
+    Stack st;
+    init_stack(st, a, lds.stack);
     const SceneDev& sc = a.sc;
     const float* cdf = lds.lights_in_lds ? lds.cdf : a.cdf;
     const int4* lights = lds.lights_in_lds ? lds.lights : sc.lights;
-    const int D = a.D;
+    const int lane = threadIdx.x & 63;
+    const int64_t npix_img = (int64_t)a.V * a.W * a.H;
     const size_t plane = (size_t)a.pix_count;
-    V3 T = v3(1.0f, 1.0f, 1.0f), Ts = T, L = v3(0.0f, 0.0f, 0.0f);
+    const int D = a.D;
+    Work wk{0u, 0u, 0u, 0u};
+    uint32_t npaths = 0;
+
+    int ph = kNeedPixel;
+    // pixel state
+    int64_t q = 0, wi = 0, pix = 0;
+    int view = 0, px = 0, py = 0, s = 0;
+    V3 acc = v3(0.0f, 0.0f, 0.0f);
+    // path state: k = index of the vertex last processed
+    uint64_t pid = 0, h = 0;
+    int k = 0, klast = 0, prev_tri = -1;
+    V3 T = acc, Ts = acc, L = acc, o = acc, d = acc;
+    float prev_pdf = 0.0f;
+    // vertex pending on a shadow ray
+    V3 wl = acc, nee_LT = acc, nee_c = acc, cpart = acc;
+    float sdist = 0.0f;
+    int sltri = -1;
+    uint32_t ev = 0, evtail = 0, ckx = 0;
+    bool nee_valid = false;
+    float* dvk = nullptr;
+
+    auto start_path = [&]() {
+        pid = (uint64_t)pix * (uint64_t)a.spp + (uint64_t)s;
+        float j0 = 0.5f, j1 = 0.5f;
+        if (a.jitter) jitter_uniforms(a.rng, pid, j0, j1);
+        camera_ray(a, view, (float)px + j0, (float)py + j1, o, d);
+        k = 0;
+        klast = 0;
+        prev_tri = -1;
+        prev_pdf = 0.0f;
+        T = v3(1.0f, 1.0f, 1.0f);
+        Ts = T;
+        L = v3(0.0f, 0.0f, 0.0f);
+        h = 0xCBF29CE484222325ull;
+        if (MODE == kColor && a.dbg_vtx) {
+            float* dv = a.dbg_vtx + ((size_t)wi * a.spp + s) * 8 * (size_t)(D + 1);
+            for (int i = 0; i < 8 * (D + 1); ++i) dv[i] = -1.0f;
+        }
+        ph = kClosest;
+    };
+
+    while (true) {
+        // ---- lanes without a pixel take the next pixels (one atomic per wave) ----
+        uint64_t need = __ballot(ph == kNeedPixel);
+        if (need) {
+            int first = __ffsll((unsigned long long)need) - 1;
+            unsigned base = 0;
+            if (lane == first) base = atomicAdd(a.work, (unsigned)__popcll(need));
+            base = __shfl(base, first);
+            if (ph == kNeedPixel) {
+                unsigned rank = (unsigned)__popcll(need & ((1ull << lane) - 1ull));
+                q = (int64_t)base + rank;
+                if (q >= a.pix_count) {
+                    ph = kExit;
+                } else {
+                    wi = a.pix_begin + q;
+                    pix = a.pixel_list ? a.pixel_list[wi] : wi;
+                    if (pix < 0 || pix >= npix_img) {
+                        if (MODE == kColor) {
+                            a.image[3 * wi] = 0.0f;
+                            a.image[3 * wi + 1] = 0.0f;
+                            a.image[3 * wi + 2] = 0.0f;
+                        }
+                    } else {
+                        view = (int)(pix / ((int64_t)a.W * a.H));
+                        int64_t rem = pix - (int64_t)view * a.W * a.H;
+                        py = (int)(rem / a.W);
+                        px = (int)(rem - (int64_t)py * a.W);
+                        s = 0;
+                        acc = v3(0.0f, 0.0f, 0.0f);
+                        start_path();
+                    }
+                }
+            }
+        }
+        if (__ballot(ph != kExit) == 0) break;
+        if (ph == kNeedPixel || ph == kExit) continue;
+
+        // ---- one traversal call site for closest-hit and shadow rays ----
+        const bool any = ph == kShadow;
+        Ray ray = make_ray(o, any ? wl : d);
+        Hit hr = traverse(sc, ray, sc.tmin, any ? sdist * (1.0f - 1e-5f) : __builtin_inff(), prev_tri,
+                          any ? sltri : -1, any, st, wk);
+
+        bool end_path = false;
+        if (any) {
+            // ---- finish the vertex that waited for its shadow ray ----
+            bool vis = hr.tri < 0;
+            ev |= (uint32_t)vis << 2;
+            if (vis && nee_valid) {
+                cpart = cpart + nee_c;
+                L = L + nee_LT;
+                if (dvk) { dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; dvk[7] = 1.0f; }
+            }
+            h = fnv1a(h, ev | evtail);
+            if (MODE == kGradFwd) {
+                size_t ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
+                if (vis) a.ck_hit[ck].x = (int)(ckx | kCkVis);
+                a.ck_c[ck] = make_float4(cpart.x, cpart.y, cpart.z, 0.0f);
+            }
+            end_path = evtail != 0;
+            ph = kClosest;
+        } else {
+            // ---- closest hit: vertex k ----
+            ++k;
+            klast = k;
+            wk.vertices++;
+            size_t ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
+            if (hr.tri < 0) {
+                h = fnv1a(h, 0xFFFFFFFFu);
+                if (MODE == kGradFwd) a.ck_hit[ck] = make_int4(0, 0, 0, 0);
+                klast = k - 1;   // a miss contributes nothing: the sweep starts below it
+                end_path = true;
+            } else {
+                Shade g;
+                make_shade(sc, lds, hr, d, g);
+                h = fnv1a(h, (uint32_t)g.orig);
+                dvk = nullptr;
+                if (MODE == kColor && a.dbg_vtx) {
+                    dvk = a.dbg_vtx + (((size_t)wi * a.spp + s) * (size_t)(D + 1) + (k - 1)) * 8;
+                    dvk[0] = (float)g.orig; dvk[1] = hr.u; dvk[2] = hr.v; dvk[3] = hr.t;
+                    dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; dvk[7] = 0.0f;
+                }
+                ev = 0;
+                evtail = 0;
+                cpart = v3(0.0f, 0.0f, 0.0f);
+                uint32_t flags = 0;
+                if (g.em >= 0 && g.cos_emit > 0.0f) {
+                    float w = emit_weight(a, cdf, lights, g, k, prev_pdf);
+                    if (w > 0.0f) {
+                        float prof = a.profile ? g.cos_emit : 1.0f;
+                        const float* e = lds.params + 7 * sc.S + 3 * g.em;
+                        V3 c = v3(e[0], e[1], e[2]) * (prof * w);
+                        cpart = c;
+                        L = L + T * c;
+                        if (dvk) { dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; }
+                    }
+                    ev |= 1u;
+                }
+                bool shoot = false;
+                V3 av = v3(0.0f, 0.0f, 0.0f);
+                if (k == D + 1) {
+                    evtail = 0;   // x_{D+1}: only its emission counts
+                    end_path = true;
+                } else if (dot(g.ns, g.wo) <= 0.0f) {
+                    ev |= 2u;     // shading normal faces away: the path ends
+                    end_path = true;
+                } else {
+                    Mat m = load_mat(lds.params, g.seg);
+                    Mat ms = a.frozen ? load_mat(lds.sparams, g.seg) : m;
+                    float u[8];
+                    vertex_uniforms(a.rng, pid, k, u);
+                    if (a.mis != 0 && sc.nlt > 0) {
+                        NeeS n = nee_setup(sc, cdf, lights, g, u);
+                        ev |= (uint32_t)n.lj << 8;
+                        if (n.shoot) {
+                            NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n);
+                            shoot = true;
+                            nee_valid = nc.valid;
+                            nee_c = nc.c;
+                            nee_LT = T * nc.c;
+                            wl = n.wl;
+                            sdist = n.dist;
+                            sltri = n.ltri;
+                        }
+                    }
+                    ContS cs = cont_sample(a, g, m, ms, u, k, Ts);
+                    ev |= (uint32_t)cs.lobe << 3;
+                    if (!cs.ok) {
+                        evtail = 16u;
+                    } else if (!cs.alive) {
+                        evtail = 32u;
+                    } else {
+                        float rq = 1.0f / cs.qrr;
+                        av = cs.av * rq;
+                        Ts = Ts * cs.ts * rq;
+                        flags |= kCkCont;
+                        prev_pdf = cs.pdf;
+                        T = T * av;
+                        d = cs.wi;
+                    }
+                }
+                prev_tri = g.tri;
+                o = g.x;
+                if (MODE == kGradFwd) {
+                    ckx = (uint32_t)(g.tri + 1) | flags;
+                    a.ck_hit[ck] = make_int4((int)ckx, __float_as_int(hr.u), __float_as_int(hr.v),
+                                             __float_as_int(hr.t));
+                    a.ck_a[ck] = make_float4(av.x, av.y, av.z, 0.0f);
+                }
+                if (shoot) {
+                    ph = kShadow;   // the vertex finishes after its shadow ray
+                } else {
+                    h = fnv1a(h, ev | evtail);
+                    if (MODE == kGradFwd) a.ck_c[ck] = make_float4(cpart.x, cpart.y, cpart.z, 0.0f);
+                    end_path = end_path || evtail != 0;
+                }
+            }
+        }
+
+        if (end_path) {
+            ++npaths;
+            size_t pidx = (size_t)wi * a.spp + s;
+            bool use = a.mask ? a.mask[pidx] != 0 : true;
+            if (MODE == kGradFwd) {
+                V3 R = suffix_sweep(a, klast, s, q);
+                if (!finite3(R) || !finite3(L)) {
+                    size_t c1 = (size_t)s * plane + q;
+                    a.ck_hit[c1].x = (int)((uint32_t)a.ck_hit[c1].x | kCkDrop);
+                    atomicAdd(&a.err->nonfinite, 1ull);
+                }
+            } else {
+                if (!finite3(L)) atomicAdd(&a.err->nonfinite, 1ull);
+                else if (use) acc = acc + L;
+                if (a.path_L) {
+                    a.path_L[3 * pidx] = L.x;
+                    a.path_L[3 * pidx + 1] = L.y;
+                    a.path_L[3 * pidx + 2] = L.z;
+                }
+            }
+            if (a.hash) a.hash[pidx] = h;
+            ++s;
+            if (s < a.spp) {
+                start_path();
+            } else {
+                if (MODE == kColor) {
+                    float inv = 1.0f / (float)a.spp;
+                    a.image[3 * wi] = acc.x * inv;
+                    a.image[3 * wi + 1] = acc.y * inv;
+                    a.image[3 * wi + 2] = acc.z * inv;
+                }
+                ph = kNeedPixel;
+            }
+        }
+    }
+    if (st.overflow) atomicAdd(&a.err->overflow, 1ull);
+    flush_stats(a, MODE, wk, npaths);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint replay: one lane per pixel, tiles pulled by blocks.
+// ---------------------------------------------------------------------------
+__device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& wk, uint64_t pid, int64_t q, int s,
+                            V3 org, V3 dir, V3 wpix) {
+    const SceneDev& sc = a.sc;
+    const float* cdf = lds.lights_in_lds ? lds.cdf : a.cdf;
+    const int4* lights = lds.lights_in_lds ? lds.lights : sc.lights;
+    const size_t plane = (size_t)a.pix_count;
+    if ((uint32_t)a.ck_hit[(size_t)s * plane + q].x & kCkDrop) return;
+    V3 T = v3(1.0f, 1.0f, 1.0f), Ts = T;
     float prev_pdf = 0.0f;
     int prev_tri = -1;
-    uint64_t h = 0xCBF29CE484222325ull;
     V3 o = org, d = dir;
-    int klast = 0;
-    drop_out = false;
-    if (MODE == kReplay) {
-        int4 r1 = a.ck_hit[(size_t)s * plane + q];
-        if (r1.x & kCkDrop) { drop_out = true; return L; }
-    }
-    for (int k = 1; k <= D + 1; ++k) {
-        Hit hit;
-        uint32_t ckflags = 0;
-        V3 Rn = v3(0.0f, 0.0f, 0.0f);   // replay: R_{k+1}
+    for (int k = 1; k <= a.D + 1; ++k) {
         size_t ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
-        if (MODE == kReplay && !a.replay_traverse) {
-            int4 rec = a.ck_hit[ck];
-            uint32_t x = (uint32_t)rec.x;
-            hit.tri = (int)(x & kCkTriMask) - 1;
+        int4 rec = a.ck_hit[ck];
+        uint32_t flags = (uint32_t)rec.x;
+        Hit hit;
+        if (!a.replay_traverse) {
+            hit.tri = (int)(flags & kCkTriMask) - 1;
             hit.u = __int_as_float(rec.y);
             hit.v = __int_as_float(rec.z);
             hit.t = __int_as_float(rec.w);
-            ckflags = x;
         } else {
             Ray ray = make_ray(o, d);
-            hit = traverse<false>(sc, ray, sc.tmin, __builtin_inff(), prev_tri, -1, st, wk);
-            if (MODE == kReplay) ckflags = (uint32_t)a.ck_hit[ck].x;
+            hit = traverse(sc, ray, sc.tmin, __builtin_inff(), prev_tri, -1, false, st, wk);
         }
-        if (MODE == kReplay) {
-            float4 rr = a.ck_c[ck];
-            Rn = v3(rr.x, rr.y, rr.z);
-        }
-        klast = k;
+        if (hit.tri < 0) return;
         wk.vertices++;
-        V3 ck_c = v3(0.0f, 0.0f, 0.0f), ck_a = v3(0.0f, 0.0f, 0.0f);
-        uint32_t flags = 0;
-        if (hit.tri < 0) {
-            h = fnv1a(h, 0xFFFFFFFFu);
-            if (MODE == kGradFwd) a.ck_hit[ck] = make_int4(0, 0, 0, 0);
-            klast = k - 1;   // a miss contributes nothing: the sweep starts below it
-            break;
-        }
-        V3 p0, p1, p2;
-        int orig, seg, light;
-        load_tri(sc, hit.tri, p0, p1, p2, orig, seg, light);
-        h = fnv1a(h, (uint32_t)orig);
-        float* dvk = dv ? dv + 8 * (k - 1) : nullptr;
-        if (dvk) {
-            dvk[0] = (float)orig; dvk[1] = hit.u; dvk[2] = hit.v; dvk[3] = hit.t;
-            dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; dvk[7] = 0.0f;
-        }
-        V3 e1 = p1 - p0, e2 = p2 - p0;
-        V3 x = p0 + e1 * hit.u + e2 * hit.v;
-        V3 ng = normalize(cross(e1, e2));
-        int em = lds.seg_emitter[seg];
-        float cos_emit = -dot(d, ng);
-        uint32_t ev = 0;
+        float4 rr = a.ck_c[ck];
+        V3 Rn = v3(rr.x, rr.y, rr.z);   // R_{k+1}
+        Shade g;
+        make_shade(sc, lds, hit, d, g);
         V3 wT = wpix * T;
-        // ---- emitter hit (MIS weight against light sampling) ----
-        if (em >= 0 && cos_emit > 0.0f) {
-            float w = 1.0f;
-            if (k > 1) {
-                if (a.mis == 1) w = 0.0f;
-                else if (a.mis >= 2) {
-                    float pa = light_prob(cdf, sc.nlt, light) / __int_as_float(lights[light].z);
-                    float pl = pa * hit.t * hit.t / cos_emit;
-                    w = mis_weight(prev_pdf, pl, a.mis);
-                }
-            }
+        // emission at this vertex: d/de = w_hit * profile
+        if (g.em >= 0 && g.cos_emit > 0.0f) {
+            float w = emit_weight(a, cdf, lights, g, k, prev_pdf);
             if (w > 0.0f) {
-                float prof = a.profile ? cos_emit : 1.0f;
-                const float* e = lds.params + 7 * sc.S + 3 * em;
-                V3 c = v3(e[0], e[1], e[2]) * (prof * w);
-                ck_c = ck_c + c;
-                L = L + T * c;
-                if (dvk) { dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; }
-                if (MODE == kReplay) {
-                    int eb = 7 * sc.S + 3 * em;
-                    lds_add(lds.grad, eb + 0, wT.x * prof * w);
-                    lds_add(lds.grad, eb + 1, wT.y * prof * w);
-                    lds_add(lds.grad, eb + 2, wT.z * prof * w);
-                }
+                float prof = a.profile ? g.cos_emit : 1.0f;
+                int eb = 7 * sc.S + 3 * g.em;
+                lds_add(lds.grad, eb + 0, wT.x * prof * w);
+                lds_add(lds.grad, eb + 1, wT.y * prof * w);
+                lds_add(lds.grad, eb + 2, wT.z * prof * w);
             }
-            ev |= 1u;
         }
-        if (k == D + 1) {
-            h = fnv1a(h, ev);
-            if (MODE == kGradFwd) {
-                a.ck_hit[ck] = make_int4((int)((uint32_t)(hit.tri + 1) | flags), __float_as_int(hit.u),
-                                         __float_as_int(hit.v), __float_as_int(hit.t));
-                a.ck_c[ck] = make_float4(ck_c.x, ck_c.y, ck_c.z, 0.0f);
-                a.ck_a[ck] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            }
-            break;
-        }
-        // ---- shading frame: two-sided, flipped toward the incoming ray ----
-        V3 wo = v3(-d.x, -d.y, -d.z);
-        V3 ns = ng;
-        if (sc.nrm) {
-            float b0 = 1.0f - hit.u - hit.v;
-            V3 n0 = xyz(sc.nrm[3 * hit.tri]), n1 = xyz(sc.nrm[3 * hit.tri + 1]), n2 = xyz(sc.nrm[3 * hit.tri + 2]);
-            ns = normalize(n0 * b0 + n1 * hit.u + n2 * hit.v);
-        }
-        V3 ngf = ng;
-        if (dot(ng, wo) < 0.0f) { ngf = ng * -1.0f; ns = ns * -1.0f; }
-        bool cont = false;
-        if (dot(ns, wo) <= 0.0f) {
-            h = fnv1a(h, ev | 2u);
-        } else {
-            Mat m = load_mat(lds.params, seg);
-            Mat ms = a.frozen ? load_mat(lds.sparams, seg) : m;
-            float u[8];
-            vertex_uniforms(a.rng, pid, k, u);
-            // ---- next-event estimation ----
-            if (a.mis != 0 && sc.nlt > 0) {
-                int lj = pick_light(cdf, sc.nlt, u[0]);
-                int4 lrec = lights[lj];
-                V3 q0, q1, q2;
-                int lorig, lseg, llight;
-                load_tri(sc, lrec.x, q0, q1, q2, lorig, lseg, llight);
-                float su = sqrtf(u[1]);
-                float b1 = (1.0f - u[2]) * su, b2 = u[2] * su;
-                // y - x from vertex differences and edge terms: the light point and
-                // the shading point are never rounded to world coordinates first
-                V3 dl = (q0 - p0) + ((q1 - q0) * b1 + (q2 - q0) * b2 - (e1 * hit.u + e2 * hit.v));
-                V3 lng = normalize(cross(q1 - q0, q2 - q0));
-                float d2 = dot(dl, dl), dist = sqrtf(d2);
-                V3 wl = dl * (1.0f / dist);
-                float cy = -dot(wl, lng);
-                float cxg = dot(wl, ngf);
-                bool vis = false;
-                // grazing configurations (cosines below 1e-6: the light
-                // triangle itself, a coplanar emitter) are skipped
-                if (cy > 1e-6f && cxg > 1e-6f) {
-                    if (MODE == kReplay && !a.replay_traverse) {
-                        vis = (ckflags & kCkVis) != 0;
-                    } else {
-                        Ray sr = make_ray(x, wl);
-                        Hit sh = traverse<true>(sc, sr, sc.tmin, dist * (1.0f - 1e-5f), hit.tri, lrec.x, st, wk);
-                        vis = sh.tri < 0;
-                    }
-                }
-                ev |= ((uint32_t)lj << 8) | ((uint32_t)vis << 2);
-                if (vis) {
-                    flags |= kCkVis;
-                    float spec, dspec;
-                    spec_term(ns, wo, wl, m.alpha, spec, dspec);
-                    float cx = dot(ns, wl);
-                    if (cx > 0.0f) {
-                        int lk = lrec.y;
-                        float parea = light_prob(cdf, sc.nlt, lj) / __int_as_float(lrec.z);
-                        float w = 1.0f;
-                        if (a.mis >= 2) {
-                            float pl = parea * d2 / cy;
-                            float pb = brdf_pdf(ms, ns, wo, wl);
-                            if (a.gmix > 0.0f) pb = (1.0f - a.gmix) * pb;  // guide pdf added by the guide path
-                            w = mis_weight(pl, pb, a.mis);
-                        }
-                        float prof = a.profile ? cy : 1.0f;
-                        float g = cx * cy / d2 * w / parea * prof;
-                        const float* ep = lds.params + 7 * sc.S + 3 * lk;
-                        V3 e = v3(ep[0], ep[1], ep[2]);
-                        V3 f = m.kd * kInvPi + m.ks * spec;
-                        V3 c = f * e * g;
-                        ck_c = ck_c + c;
-                        L = L + T * c;
-                        if (dvk) { dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; dvk[7] = 1.0f; }
-                        if (MODE == kReplay) {
-                            int mb = 7 * seg, eb = 7 * sc.S + 3 * lk;
-                            V3 we = wT * e * g;
-                            lds_add(lds.grad, mb + 0, we.x * kInvPi);
-                            lds_add(lds.grad, mb + 1, we.y * kInvPi);
-                            lds_add(lds.grad, mb + 2, we.z * kInvPi);
-                            lds_add(lds.grad, mb + 3, we.x * spec);
-                            lds_add(lds.grad, mb + 4, we.y * spec);
-                            lds_add(lds.grad, mb + 5, we.z * spec);
-                            lds_add(lds.grad, mb + 6, dot(we, m.ks) * dspec);
-                            V3 wf = wT * f * g;
-                            lds_add(lds.grad, eb + 0, wf.x);
-                            lds_add(lds.grad, eb + 1, wf.y);
-                            lds_add(lds.grad, eb + 2, wf.z);
-                        }
-                    }
-                }
-            }
-            // ---- continue by sampling the material ----
-            V3 wi;
-            int lobe = 0;
-            bool ok = brdf_sample(ms, ns, wo, u[3], u[4], u[5], wi, lobe);
-            ev |= (uint32_t)lobe << 3;
-            float pdf = 0.0f;
-            if (ok && dot(wi, ngf) > 0.0f && dot(wi, ns) > 0.0f) pdf = brdf_pdf(ms, ns, wo, wi);
-            if (!(pdf > 0.0f)) {
-                h = fnv1a(h, ev | 16u);
-            } else {
-                float spec, dspec;
-                spec_term(ns, wo, wi, m.alpha, spec, dspec);
-                float ci = dot(ns, wi);
-                float g = ci / pdf;
-                V3 av = (m.kd * kInvPi + m.ks * spec) * g;
-                V3 ts = av;
-                if (a.frozen) ts = (ms.kd * kInvPi + ms.ks * spec_only(ns, wo, wi, ms.alpha)) * g;
-                float qrr = 1.0f;
-                bool alive = true;
-                if (a.rr_depth >= 0 && k >= a.rr_depth) {
-                    qrr = fminf(fmaxf(maxc(Ts * ts), 0.1f), 0.95f);
-                    alive = u[6] < qrr;
-                }
-                if (MODE == kReplay) alive = (ckflags & kCkCont) != 0;
-                if (!alive) {
-                    h = fnv1a(h, ev | 32u);
+        if (k == a.D + 1 || dot(g.ns, g.wo) <= 0.0f) return;
+        Mat m = load_mat(lds.params, g.seg);
+        Mat ms = a.frozen ? load_mat(lds.sparams, g.seg) : m;
+        float u[8];
+        vertex_uniforms(a.rng, pid, k, u);
+        if (a.mis != 0 && sc.nlt > 0) {
+            NeeS n = nee_setup(sc, cdf, lights, g, u);
+            bool vis = false;
+            if (n.shoot) {
+                if (!a.replay_traverse) {
+                    vis = (flags & kCkVis) != 0;
                 } else {
-                    float rq = 1.0f / qrr;
-                    av = av * rq;
-                    Ts = Ts * ts * rq;
-                    if (MODE == kReplay) {
-                        int mb = 7 * seg;
-                        float gq = g * rq;
-                        V3 wr = wT * Rn * gq;
-                        lds_add(lds.grad, mb + 0, wr.x * kInvPi);
-                        lds_add(lds.grad, mb + 1, wr.y * kInvPi);
-                        lds_add(lds.grad, mb + 2, wr.z * kInvPi);
-                        lds_add(lds.grad, mb + 3, wr.x * spec);
-                        lds_add(lds.grad, mb + 4, wr.y * spec);
-                        lds_add(lds.grad, mb + 5, wr.z * spec);
-                        lds_add(lds.grad, mb + 6, dot(wr, m.ks) * dspec);
-                    }
-                    h = fnv1a(h, ev);
-                    ck_a = av;
-                    flags |= kCkCont;
-                    cont = true;
-                    prev_pdf = pdf;
-                    prev_tri = hit.tri;
-                    T = T * av;
-                    o = x;
-                    d = wi;
+                    Ray sr = make_ray(g.x, n.wl);
+                    vis = traverse(sc, sr, sc.tmin, n.dist * (1.0f - 1e-5f), g.tri, n.ltri, true, st, wk).tri < 0;
+                }
+            }
+            if (vis) {
+                NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n);
+                if (nc.valid) {
+                    int mb = 7 * g.seg, eb = 7 * sc.S + 3 * n.lk;
+                    V3 we = wT * nc.e * nc.g;
+                    lds_add(lds.grad, mb + 0, we.x * kInvPi);
+                    lds_add(lds.grad, mb + 1, we.y * kInvPi);
+                    lds_add(lds.grad, mb + 2, we.z * kInvPi);
+                    lds_add(lds.grad, mb + 3, we.x * nc.spec);
+                    lds_add(lds.grad, mb + 4, we.y * nc.spec);
+                    lds_add(lds.grad, mb + 5, we.z * nc.spec);
+                    lds_add(lds.grad, mb + 6, dot(we, m.ks) * nc.dspec);
+                    V3 wf = wT * nc.f * nc.g;
+                    lds_add(lds.grad, eb + 0, wf.x);
+                    lds_add(lds.grad, eb + 1, wf.y);
+                    lds_add(lds.grad, eb + 2, wf.z);
                 }
             }
         }
-        if (MODE == kGradFwd) {
-            a.ck_hit[ck] = make_int4((int)((uint32_t)(hit.tri + 1) | flags), __float_as_int(hit.u),
-                                     __float_as_int(hit.v), __float_as_int(hit.t));
-            a.ck_c[ck] = make_float4(ck_c.x, ck_c.y, ck_c.z, 0.0f);
-            a.ck_a[ck] = make_float4(ck_a.x, ck_a.y, ck_a.z, 0.0f);
-        }
-        if (!cont) break;
+        if (!(flags & kCkCont)) return;
+        ContS cs = cont_sample(a, g, m, ms, u, k, Ts);
+        float rq = 1.0f / cs.qrr;
+        int mb = 7 * g.seg;
+        V3 wr = wT * Rn * (cs.g * rq);
+        lds_add(lds.grad, mb + 0, wr.x * kInvPi);
+        lds_add(lds.grad, mb + 1, wr.y * kInvPi);
+        lds_add(lds.grad, mb + 2, wr.z * kInvPi);
+        lds_add(lds.grad, mb + 3, wr.x * cs.spec);
+        lds_add(lds.grad, mb + 4, wr.y * cs.spec);
+        lds_add(lds.grad, mb + 5, wr.z * cs.spec);
+        lds_add(lds.grad, mb + 6, dot(wr, m.ks) * cs.dspec);
+        T = T * (cs.av * rq);
+        Ts = Ts * cs.ts * rq;
+        prev_pdf = cs.pdf;
+        prev_tri = g.tri;
+        o = g.x;
+        d = cs.wi;
     }
-    if (MODE == kGradFwd) {
-        // backward sweep: R_{k+1} into the c slot of vertex k
-        V3 R = v3(0.0f, 0.0f, 0.0f);
-        for (int k = klast; k >= 1; --k) {
-            size_t ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
-            float4 c = a.ck_c[ck], av = a.ck_a[ck];
-            a.ck_c[ck] = make_float4(R.x, R.y, R.z, 0.0f);
-            R = v3(c.x, c.y, c.z) + v3(av.x, av.y, av.z) * R;
-        }
-        if (!finite3(R) || !finite3(L)) {
-            size_t c1 = (size_t)s * plane + q;
-            int4 r1 = a.ck_hit[c1];
-            r1.x = (int)((uint32_t)r1.x | kCkDrop);
-            a.ck_hit[c1] = r1;
-            drop_out = true;
-        }
-    }
-    hash = h;
-    return L;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void path_kernel(PathArgs a) {
+__global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned tile_sh;
     const int tid = threadIdx.x;
-    // ---- carve LDS ----
     Lds lds;
-    unsigned char* p = smem;
-    auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
-    lds.params = (float*)p; p += al(sizeof(float) * a.P);
-    lds.sparams = lds.params;
-    if (a.frozen) { lds.sparams = (float*)p; p += al(sizeof(float) * a.P); }
-    lds.seg_emitter = (int*)p; p += al(sizeof(int) * a.sc.S);
-    lds.lights_in_lds = a.sc.nlt <= kMaxLdsLights;
-    lds.cdf = nullptr; lds.lights = nullptr;
-    if (lds.lights_in_lds) {
-        lds.cdf = (float*)p; p += al(sizeof(float) * a.sc.nlt);
-        lds.lights = (int4*)p; p += al(sizeof(int4) * a.sc.nlt);
-    }
-    lds.grad = nullptr;
-    if (MODE == kReplay) { lds.grad = (float*)p; p += al(sizeof(float) * a.P); }
-    lds.stack = (int*)p;
-    for (int i = tid; i < a.P; i += kBlock) {
-        lds.params[i] = a.params[i];
-        if (a.frozen) lds.sparams[i] = a.sparams[i];
-        if (MODE == kReplay) lds.grad[i] = 0.0f;
-    }
-    for (int i = tid; i < a.sc.S; i += kBlock) lds.seg_emitter[i] = a.sc.seg_emitter[i];
-    if (lds.lights_in_lds)
-        for (int i = tid; i < a.sc.nlt; i += kBlock) {
-            lds.cdf[i] = a.cdf[i];
-            lds.lights[i] = a.sc.lights[i];
-        }
-    __syncthreads();
-
+    carve_lds(a, kReplay, smem, lds);
     Stack st;
-    st.lds = lds.stack;
-    st.ovf = a.ovf;
-    st.tid = tid;
-    st.gtid = blockIdx.x * kBlock + tid;
-    st.gthreads = gridDim.x * kBlock;
-    st.overflow = false;
-    st.sp = 0;
-
+    init_stack(st, a, lds.stack);
     const int64_t npix_img = (int64_t)a.V * a.W * a.H;
     Work wk{0u, 0u, 0u, 0u};
     uint32_t npaths = 0;
@@ -538,94 +818,53 @@ __global__ __launch_bounds__(kBlock) void path_kernel(PathArgs a) {
         __syncthreads();
         if ((int64_t)tile_sh * kBlock >= a.pix_count) break;
         if (q >= a.pix_count) continue;
-        int64_t wi = a.pix_begin + q;                     // work-pixel index
+        int64_t wi = a.pix_begin + q;
         int64_t pix = a.pixel_list ? a.pixel_list[wi] : wi;
         if (pix < 0 || pix >= npix_img) continue;
         int view = (int)(pix / ((int64_t)a.W * a.H));
         int64_t rem = pix - (int64_t)view * a.W * a.H;
         int py = (int)(rem / a.W), px = (int)(rem - (int64_t)py * a.W);
-        V3 wpix = v3(0.0f, 0.0f, 0.0f);
-        if (MODE == kReplay) {
-            float inv = 1.0f / (float)a.spp;
-            wpix = v3(a.w[3 * wi] * inv, a.w[3 * wi + 1] * inv, a.w[3 * wi + 2] * inv);
-        }
-        V3 acc = v3(0.0f, 0.0f, 0.0f);
+        float inv = 1.0f / (float)a.spp;
+        V3 wpix = v3(a.w[3 * wi] * inv, a.w[3 * wi + 1] * inv, a.w[3 * wi + 2] * inv);
         for (int s = 0; s < a.spp; ++s) {
             uint64_t pid = (uint64_t)pix * (uint64_t)a.spp + (uint64_t)s;
             size_t pidx = (size_t)wi * a.spp + s;
-            bool use = a.mask ? a.mask[pidx] != 0 : true;
-            if (MODE == kReplay && !use) continue;
+            if (a.mask && a.mask[pidx] == 0) continue;
             float j0 = 0.5f, j1 = 0.5f;
             if (a.jitter) jitter_uniforms(a.rng, pid, j0, j1);
             V3 o, d;
             camera_ray(a, view, (float)px + j0, (float)py + j1, o, d);
-            uint64_t hsh;
-            bool drop;
-            float* dv = nullptr;
-            if (MODE == kColor && a.dbg_vtx) {
-                dv = a.dbg_vtx + pidx * 8 * (size_t)(a.D + 1);
-                for (int k = 0; k < 8 * (a.D + 1); ++k) dv[k] = -1.0f;
-            }
-            V3 Lp = run_path<MODE>(a, lds, st, wk, pid, q, s, o, d, wpix, hsh, drop, dv);
+            replay_path(a, lds, st, wk, pid, q, s, o, d, wpix);
             ++npaths;
-            if (MODE == kColor) {
-                if (!finite3(Lp)) {
-                    atomicAdd(&a.err->nonfinite, 1ull);
-                } else if (use) {
-                    acc = acc + Lp;
-                }
-            }
-            if (MODE == kGradFwd && drop) atomicAdd(&a.err->nonfinite, 1ull);
-            if (MODE != kReplay && a.hash) a.hash[pidx] = hsh;
-            if (MODE == kColor && a.path_L) {
-                a.path_L[3 * pidx] = Lp.x;
-                a.path_L[3 * pidx + 1] = Lp.y;
-                a.path_L[3 * pidx + 2] = Lp.z;
-            }
-        }
-        if (MODE == kColor) {
-            float inv = 1.0f / (float)a.spp;
-            a.image[3 * wi] = acc.x * inv;
-            a.image[3 * wi + 1] = acc.y * inv;
-            a.image[3 * wi + 2] = acc.z * inv;
         }
     }
     if (st.overflow) atomicAdd(&a.err->overflow, 1ull);
-    if (a.count_stats) {
-        KStats* ks = &a.err->k[MODE];
-        atomicAdd(&ks->rays, (unsigned long long)wk.rays);
-        atomicAdd(&ks->nodes, (unsigned long long)wk.nodes);
-        atomicAdd(&ks->tris, (unsigned long long)wk.tris);
-        atomicAdd(&ks->paths, (unsigned long long)npaths);
-        atomicAdd(&ks->vertices, (unsigned long long)wk.vertices);
-    }
-    if (MODE == kReplay) {
-        __syncthreads();
-        float* out = a.grad_part + (size_t)blockIdx.x * a.P;
-        for (int i = tid; i < a.P; i += kBlock) out[i] = lds.grad[i];
-    }
+    flush_stats(a, kReplay, wk, npaths);
+    __syncthreads();
+    float* out = a.grad_part + (size_t)blockIdx.x * a.P;
+    for (int i = tid; i < a.P; i += kBlock) out[i] = lds.grad[i];
 }
 
 int path_blocks_per_cu(int mode, size_t lds) {
     int nb = 0;
     hipError_t e;
     if (mode == kColor)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, path_kernel<kColor>, kBlock, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, path_sm_kernel<kColor>, kBlock, lds);
     else if (mode == kGradFwd)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, path_kernel<kGradFwd>, kBlock, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, path_sm_kernel<kGradFwd>, kBlock, lds);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, path_kernel<kReplay>, kBlock, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, replay_kernel, kBlock, lds);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
 
 hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st) {
     if (mode == kColor)
-        hipLaunchKernelGGL(path_kernel<kColor>, dim3(grid), dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL(path_sm_kernel<kColor>, dim3(grid), dim3(kBlock), lds, st, a);
     else if (mode == kGradFwd)
-        hipLaunchKernelGGL(path_kernel<kGradFwd>, dim3(grid), dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL(path_sm_kernel<kGradFwd>, dim3(grid), dim3(kBlock), lds, st, a);
     else
-        hipLaunchKernelGGL(path_kernel<kReplay>, dim3(grid), dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL(replay_kernel, dim3(grid), dim3(kBlock), lds, st, a);
     return hipGetLastError();
 }
 
@@ -633,9 +872,9 @@ hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipSt
 // Batch ray casting (hit parity and BVH checks).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void trace_rays_kernel(SceneDev sc, const float* o, const float* d,
-                                                            const int* skip, int64_t n, float tmin,
-                                                            int brute, int64_t nt, int* out_tri,
-                                                            float* out_tuv, int* ovf, Counters* err) {
+                                                            const int* skip, int64_t n, float tmin, int brute,
+                                                            int64_t nt, int* out_tri, float* out_tuv, int* ovf,
+                                                            Counters* err) {
     __shared__ int stk[kShortStack * kBlock];
     Stack st;
     st.lds = stk;
@@ -650,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(SceneDev sc, const f
         Ray r = make_ray(v3(o[3 * i], o[3 * i + 1], o[3 * i + 2]), v3(d[3 * i], d[3 * i + 1], d[3 * i + 2]));
         int sk = (skip && skip[i] >= 0 && skip[i] < nt) ? sc.pos_of[skip[i]] : -1;
         Hit h = brute ? brute_closest(sc, nt, r, tmin, sk)
-                      : traverse<false>(sc, r, tmin, __builtin_inff(), sk, -1, st, wk);
+                      : traverse(sc, r, tmin, __builtin_inff(), sk, -1, false, st, wk);
         int orig = -1;
         if (h.tri >= 0) orig = __float_as_int(sc.tris[3 * h.tri].w);
         out_tri[i] = orig;
@@ -663,11 +902,11 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(SceneDev sc, const f
 
 int trace_rays_grid(int num_cu) { return num_cu * 4; }
 
-hipError_t launch_trace_rays(const SceneDev& sc, const float* o, const float* d, const int* skip,
-                             int64_t n, float tmin, int brute, int64_t nt, int* out_tri,
-                             float* out_tuv, int* ovf, int grid, Counters* err, hipStream_t st) {
-    hipLaunchKernelGGL(trace_rays_kernel, dim3(grid), dim3(kBlock), 0, st, sc, o, d, skip, n, tmin,
-                       brute, nt, out_tri, out_tuv, ovf, err);
+hipError_t launch_trace_rays(const SceneDev& sc, const float* o, const float* d, const int* skip, int64_t n,
+                             float tmin, int brute, int64_t nt, int* out_tri, float* out_tuv, int* ovf, int grid,
+                             Counters* err, hipStream_t st) {
+    hipLaunchKernelGGL(trace_rays_kernel, dim3(grid), dim3(kBlock), 0, st, sc, o, d, skip, n, tmin, brute, nt,
+                       out_tri, out_tuv, ovf, err);
     return hipGetLastError();
 }
 

@@ -12,7 +12,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libipt.so")
+# IPT_LIB_PATH selects another build of the same library (A/B comparisons of build variants)
+LIB_PATH = os.environ.get("IPT_LIB_PATH", os.path.join(_HERE, "libipt.so"))
 
 IPT_OK = 0
 _STATUS = {0: "IPT_OK", 1: "IPT_ERR_INVALID_ARG", 2: "IPT_ERR_BAD_SCENE", 3: "IPT_ERR_OUT_OF_MEMORY",
