@@ -88,6 +88,8 @@ typedef struct {
     int64_t num_pixels;
     ipt_guide_t guide;        /* NULL = BRDF sampling only */
     float guide_mix;          /* probability of sampling the guide when guide != NULL */
+    int32_t guide_fp32;       /* 1: evaluate the guide in float32 on VALU (reference
+                                 mode) instead of bfloat16 MFMA */
     uint64_t *debug_path_hash;/* DEVICE [pixels*spp] or NULL: FNV-1a of each path's events */
     const uint8_t *path_mask; /* DEVICE [pixels*spp] or NULL: 0 removes the path */
     float *debug_path_radiance;/* DEVICE [pixels*spp][3] or NULL (ipt_render only) */
@@ -182,30 +184,47 @@ ipt_status ipt_trace_rays(ipt_scene_t scene, const float *origins, const float *
                           const int32_t *skip_tri, int64_t n, float tmin, int32_t brute_force,
                           int32_t *out_tri, float *out_tuv, void *hip_stream);
 
-/* Learned path-guiding proposal (an MLP mapping position, normal and
- * outgoing direction plus a per-segment embedding to an 8-lobe von
- * Mises-Fisher mixture).  It only changes how directions are sampled: it is
- * mixed with BRDF sampling by one-sample MIS, so estimates stay unbiased. */
+/* Learned path-guiding proposal: an MLP (bfloat16 MFMA inference and
+ * training, float32 accumulation and master weights) that maps a path
+ * vertex -- position normalised to the scene box, shading normal, outgoing
+ * direction -- and a learned 16-d embedding of its segment to an 8-lobe von
+ * Mises-Fisher mixture over incident directions.  Attached to
+ * ipt_render_opts.guide with guide_mix = c > 0, every continuation direction
+ * is drawn from the mixture with probability c and from the BRDF otherwise,
+ * and weighted by the combined density c q + (1 - c) p_brdf (one-sample MIS),
+ * so every estimate stays unbiased; c = 0 samples the BRDF only.  A guide
+ * attached to the gradient pass (ipt_render_grad / ipt_loss_grad) also makes
+ * that pass write training records (vertex features, sampled direction, its
+ * density, incident-radiance estimate) for every record_stride-th path into
+ * the guide's ring.  The guide does not depend on the unknowns and is not
+ * differentiated.  Not part of the paper's method (Sec. 3.1 uses BRDF and
+ * light sampling); the estimator it feeds is the paper's. */
 typedef struct {
-    uint64_t seed;
-    float lr;               /* Adam learning rate of the network */
-    int32_t batch;          /* training records per step */
+    uint64_t seed;          /* initial weights */
+    float lr;               /* Adam learning rate of the network and embedding */
+    int32_t batch;          /* training records per step (multiple of 64) */
     int32_t ring_capacity;  /* training records kept */
+    int32_t record_stride;  /* record every record_stride-th gradient path */
 } ipt_guide_opts;
 
+/* Allocates the network, its Adam state and the record ring (the library
+ * owns them).  The scene fixes the segment count and the box. */
 ipt_status ipt_guide_create(ipt_scene_t scene, const ipt_guide_opts *opts, void *hip_stream,
                             ipt_guide_t *out);
 ipt_status ipt_guide_free(ipt_guide_t guide);
-/* Evaluate the mixture for n queries: feat [n][9] (position in scene-box
- * units [-1,1]^3, normal, outgoing direction), seg [n]; out [n][40]
- * (per lobe: mu xyz, kappa, weight) after normalisation. */
+/* Mixture for n queries: feat [n][9] (DEVICE: normalised position, normal,
+ * outgoing direction), seg [n] (DEVICE); out [n][40] (DEVICE) = per lobe
+ * (mu xyz, kappa, weight).  mode 0: bfloat16 MFMA, 1: float32 VALU. */
 ipt_status ipt_guide_eval(ipt_guide_t guide, const float *feat, const int32_t *seg, int64_t n,
-                          float *out, void *hip_stream);
-/* Render `paths` guide-training samples with opts (stream tag 3) into the
- * record ring, then take `steps` Adam steps on minibatches of it. */
-ipt_status ipt_guide_train(ipt_guide_t guide, const ipt_cameras *cams, const float *params,
-                           const ipt_render_opts *opts, int32_t steps, void *workspace,
-                           size_t workspace_bytes, void *hip_stream);
+                          int32_t mode, float *out, void *hip_stream);
+/* steps Adam steps on minibatches drawn from the ring; *loss_out (HOST,
+ * nullable) receives the last batch's loss (synchronises when given). */
+ipt_status ipt_guide_train(ipt_guide_t guide, int32_t steps, float *loss_out, void *hip_stream);
+/* Copy the float32 parameters (16744 network values then 16 per segment)
+ * to (get = 1) or from (get = 0) the HOST array w; synchronises. */
+ipt_status ipt_guide_weights(ipt_guide_t guide, float *w, int32_t get, int64_t count);
+/* Number of records written so far (the ring keeps the last capacity). */
+ipt_status ipt_guide_records(ipt_guide_t guide, int64_t *count);
 
 /* Kernel timing and work counters of the path kernels of one scene (kernel
  * 0: colour pass, 1: gradient forward pass, 2: adjoint replay).  While

@@ -673,6 +673,7 @@ static double light_prob(const lightdist *L, int64_t j)
     return (L->cdf[j] - prev) / L->total;
 }
 
+
 /* ------------------------------------------------------------------------- */
 /* Path tracing with per-factor derivative bookkeeping.                       */
 /* ------------------------------------------------------------------------- */
@@ -691,9 +692,145 @@ typedef struct {
     uint64_t seed; uint32_t stream_tag, iteration;
     int32_t spp, max_depth, rr_depth, mis, emission_profile, jitter, brute_force;
     const int64_t *pixel_list; int64_t num_pixels;
+    /* learned proposal: float32 network weights (16744 + 16 S values), the
+     * probability of sampling it, and the scene box used for its features */
+    const float *guide_w; double guide_mix; double bb_lo[3], bb_inv[3];
 } orc_opts;
 
 typedef struct { int32_t num_views, width, height; const float *cam_to_world; const float *fov_y; } orc_cams;
+/* ------------------------------------------------------------------------- */
+/* Learned proposal (not part of the paper's method): an MLP 25 -> 64 x 4 ->  */
+/* 40 with ReLU maps (normalised position, shading normal, outgoing           */
+/* direction, 16-d segment embedding) to 8 von Mises-Fisher lobes (mu =        */
+/* normalised y[0..2], kappa = softplus(y[3]) + 0.01 capped at 1e4, weight =   */
+/* softmax of y[4]); combined with BRDF sampling by one-sample MIS.            */
+/* Parameter block (float32): W1 [25][64], b1, W2..W4 [64][64], b2..b4,         */
+/* W5 [64][40], b5, then the embedding [S][16].                                */
+/* ------------------------------------------------------------------------- */
+#define G_IN 25
+#define G_HID 64
+#define G_OUT 40
+#define G_LOBES 8
+
+static void guide_mlp(const float *w, const double x[G_IN], double y[G_OUT])
+{
+    const float *W1 = w, *b1 = W1 + G_IN * G_HID, *W2 = b1 + G_HID, *b2 = W2 + G_HID * G_HID;
+    const float *W3 = b2 + G_HID, *b3 = W3 + G_HID * G_HID, *W4 = b3 + G_HID, *b4 = W4 + G_HID * G_HID;
+    const float *W5 = b4 + G_HID, *b5 = W5 + G_HID * G_OUT;
+    double h[G_HID], g[G_HID];
+    for (int n = 0; n < G_HID; ++n) {
+        double s = b1[n];
+        for (int k = 0; k < G_IN; ++k) s += x[k] * (double)W1[k * G_HID + n];
+        h[n] = s > 0 ? s : 0;
+    }
+    const float *Ws[3] = { W2, W3, W4 }, *bs[3] = { b2, b3, b4 };
+    for (int l = 0; l < 3; ++l) {
+        for (int n = 0; n < G_HID; ++n) {
+            double s = bs[l][n];
+            for (int k = 0; k < G_HID; ++k) s += h[k] * (double)Ws[l][k * G_HID + n];
+            g[n] = s > 0 ? s : 0;
+        }
+        for (int n = 0; n < G_HID; ++n) h[n] = g[n];
+    }
+    for (int n = 0; n < G_OUT; ++n) {
+        double s = b5[n];
+        for (int k = 0; k < G_HID; ++k) s += h[k] * (double)W5[k * G_OUT + n];
+        y[n] = s;
+    }
+}
+
+static double softplus_d(double x) { return x > 30 ? x : log1p(exp(x)); }
+
+/* raw outputs -> per lobe (mu xyz, kappa, weight) */
+static void guide_mixture(double y[G_OUT])
+{
+    double mx = -INFINITY, z = 0;
+    for (int j = 0; j < G_LOBES; ++j) if (y[5 * j + 4] > mx) mx = y[5 * j + 4];
+    for (int j = 0; j < G_LOBES; ++j) {
+        double *l = y + 5 * j;
+        double n2 = l[0] * l[0] + l[1] * l[1] + l[2] * l[2];
+        if (n2 > 0) { double r = 1.0 / sqrt(n2); l[0] *= r; l[1] *= r; l[2] *= r; }
+        else { l[0] = 0; l[1] = 0; l[2] = 1; }
+        l[3] = fmin(softplus_d(l[3]) + 0.01, 1e4);
+        l[4] = exp(l[4] - mx);
+        z += l[4];
+    }
+    for (int j = 0; j < G_LOBES; ++j) y[5 * j + 4] /= z;
+}
+
+static double vmf_pdf_d(double kappa, double c)
+{
+    return kappa / (2.0 * ORC_PI * -expm1(-2.0 * kappa)) * exp(kappa * (c - 1.0));
+}
+
+static double mixture_pdf_d(const double *mix, v3 w)
+{
+    double q = 0;
+    for (int j = 0; j < G_LOBES; ++j) {
+        const double *l = mix + 5 * j;
+        q += l[4] * vmf_pdf_d(l[3], l[0] * w.x + l[1] * w.y + l[2] * w.z);
+    }
+    return q;
+}
+
+/* lobe by u3 (margins recorded), then w = 1 + log(u4 + (1-u4) e^{-2 kappa}) / kappa */
+static v3 mixture_sample_d(const double *mix, double u3, double u4, double u5, double *margin)
+{
+    int j = G_LOBES - 1;
+    double acc = 0;
+    for (int i = 0; i < G_LOBES; ++i) {
+        acc += mix[5 * i + 4];
+        if (margin && fabs(u3 - acc) < *margin) *margin = fabs(u3 - acc);
+        if (u3 < acc) { j = i; break; }
+    }
+    const double *l = mix + 5 * j;
+    v3 mu = mk(l[0], l[1], l[2]);
+    double kappa = l[3];
+    double w = 1.0 + log1p(-(1.0 - u4) * -expm1(-2.0 * kappa)) / kappa;
+    if (w > 1) w = 1;
+    if (w < -1) w = -1;
+    double sw = sqrt(fmax(0.0, 1.0 - w * w));
+    v3 t, b;
+    onb(mu, &t, &b);
+    double phi = 2.0 * ORC_PI * u5;
+    return add(add(scl(t, sw * cos(phi)), scl(b, sw * sin(phi))), scl(mu, w));
+}
+
+static void guide_eval_vertex(const orc_opts *o, int nseg, int seg, v3 x, v3 n, v3 wo, double mix[G_OUT])
+{
+    double f[G_IN];
+    f[0] = 2.0 * (x.x - o->bb_lo[0]) * o->bb_inv[0] - 1.0;
+    f[1] = 2.0 * (x.y - o->bb_lo[1]) * o->bb_inv[1] - 1.0;
+    f[2] = 2.0 * (x.z - o->bb_lo[2]) * o->bb_inv[2] - 1.0;
+    f[3] = n.x; f[4] = n.y; f[5] = n.z;
+    f[6] = wo.x; f[7] = wo.y; f[8] = wo.z;
+    const float *emb = o->guide_w + 16744;
+    (void)nseg;
+    for (int i = 0; i < 16; ++i) f[9 + i] = emb[16 * seg + i];
+    guide_mlp(o->guide_w, f, mix);
+    guide_mixture(mix);
+}
+
+/* Exported for tests: mixture parameters for n feature rows [n][9] + segments. */
+void orc_guide_eval(const float *w, const double *feat, const int32_t *seg, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double f[G_IN];
+        for (int j = 0; j < 9; ++j) f[j] = feat[9 * i + j];
+        for (int j = 0; j < 16; ++j) f[9 + j] = w[16744 + 16 * seg[i] + j];
+        guide_mlp(w, f, out + G_OUT * i);
+        guide_mixture(out + G_OUT * i);
+    }
+}
+
+double orc_mixture_pdf(const double *mix, const double w[3]) { return mixture_pdf_d(mix, mk(w[0], w[1], w[2])); }
+
+void orc_mixture_sample(const double *mix, double u3, double u4, double u5, double out[3])
+{
+    v3 r = mixture_sample_d(mix, u3, u4, u5, NULL);
+    out[0] = r.x; out[1] = r.y; out[2] = r.z;
+}
+
 
 static void fadd(factor *f, int32_t idx, double d0, double d1, double d2)
 {
@@ -860,6 +997,11 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
         if (ns.z != 0.0) NEAR(ns.z);   /* the tangent frame switches sign convention at n.z = 0 */
         double u[8];
         vertex_uniforms(C->o->seed, C->o->stream_tag, C->o->iteration, path_id, k, u);
+        /* --- learned proposal for this vertex (one-sample MIS with the BRDF) --- */
+        double gmix[G_OUT];
+        const int guided = C->o->guide_w && C->o->guide_mix > 0;
+        if (guided) guide_eval_vertex(C->o, s->ns, seg, x, ns, wo, gmix);
+        const double cg = guided ? C->o->guide_mix : 0.0;
         /* --- explicit light sampling (next-event estimation) --- */
         if (mis != 0 && s->nlt > 0) {
             int64_t lj = pick_light(C->L, s->nlt, u[0]);
@@ -932,16 +1074,27 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
         /* --- continue the path by sampling the BRDF --- */
         v3 wi;
         int lobe = 0;
-        int ok = brdf_sample(msp, ns, wo, u[3], u[4], u[5], &wi, &lobe);
+        int ok;
+        int use_guide = guided && u[7] < cg;
+        if (guided) NEAR(u[7] - cg);
+        if (use_guide) {
+            wi = mixture_sample_d(gmix, u[3], u[4], u[5], M ? &mg : NULL);
+            ok = 1;
+            ev |= 64u;
+        } else {
+            ok = brdf_sample(msp, ns, wo, u[3], u[4], u[5], &wi, &lobe);
+        }
         ev |= (uint32_t)lobe << 3;
-        {
+        if (!use_guide) {
             double ps = lobe_prob(msp);
             if (ps > 0 && ps < 1) NEAR(u[3] - ps);
             if (ok) { NEAR(dot(wi, ngf)); NEAR(dot(wi, ns)); }
             if (lobe == 1) { v3 hh = nrm(add(wo, ok ? wi : wo)); NEAR(dot(wo, hh)); }
         }
+        if (use_guide && ok) { NEAR(dot(wi, ngf)); NEAR(dot(wi, ns)); }
         if (!ok || dot(wi, ngf) <= 0 || dot(wi, ns) <= 0) { h = fnv(h, ev | 16u); break; }
         double pdf = brdf_pdf(msp, ns, wo, wi);
+        if (guided) pdf = cg * mixture_pdf_d(gmix, wi) + (1.0 - cg) * pdf;
         if (!(pdf > 0)) { h = fnv(h, ev | 16u); break; }
         double spec, dspec, specs, dspecs;
         spec_term(ns, wo, wi, mp[6], &spec, &dspec);

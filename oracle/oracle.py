@@ -66,6 +66,10 @@ def lib():
         L.orc_loss_adjoint.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P]
         L.orc_adam.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                                ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P, P, P]
+        L.orc_guide_eval.argtypes = [P, P, P, ctypes.c_int64, P]
+        L.orc_mixture_pdf.restype = ctypes.c_double
+        L.orc_mixture_pdf.argtypes = [P, P]
+        L.orc_mixture_sample.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
         _lib = L
     return _lib
 
@@ -80,7 +84,9 @@ class _Opts(ctypes.Structure):
                 ("max_depth", ctypes.c_int32), ("rr_depth", ctypes.c_int32),
                 ("mis", ctypes.c_int32), ("emission_profile", ctypes.c_int32),
                 ("jitter", ctypes.c_int32), ("brute_force", ctypes.c_int32),
-                ("pixel_list", ctypes.c_void_p), ("num_pixels", ctypes.c_int64)]
+                ("pixel_list", ctypes.c_void_p), ("num_pixels", ctypes.c_int64),
+                ("guide_w", ctypes.c_void_p), ("guide_mix", ctypes.c_double),
+                ("bb_lo", ctypes.c_double * 3), ("bb_inv", ctypes.c_double * 3)]
 
 
 class _Cams(ctypes.Structure):
@@ -125,6 +131,29 @@ def brdf_sample(mp, n, wo, u3, u4, u5):
     lobe = lib().orc_brdf_sample(*[_ptr(x) for x in arr], float(u3), float(u4), float(u5),
                                  _ptr(out))
     return lobe, out
+
+
+def guide_eval(weights, feat, seg):
+    """Mixture parameters [n, 40] (per lobe mu xyz, kappa, weight) of the
+    guide network with float32 weights, evaluated in float64."""
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    f = np.ascontiguousarray(feat, dtype=np.float64).reshape(-1, 9)
+    sg = np.ascontiguousarray(seg, dtype=np.int32)
+    out = np.zeros((f.shape[0], 40))
+    lib().orc_guide_eval(_ptr(w), _ptr(f), _ptr(sg), f.shape[0], _ptr(out))
+    return out
+
+
+def mixture_pdf(mix, w):
+    m = np.ascontiguousarray(mix, dtype=np.float64)
+    return lib().orc_mixture_pdf(_ptr(m), _ptr(np.ascontiguousarray(w, dtype=np.float64)))
+
+
+def mixture_sample(mix, u3, u4, u5):
+    m = np.ascontiguousarray(mix, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_mixture_sample(_ptr(m), float(u3), float(u4), float(u5), _ptr(out))
+    return out
 
 
 def loss_adjoint(img, target, kind=0):
@@ -199,7 +228,7 @@ class Scene:
             spp=4, max_depth=3, rr_depth=-1, mis=2, emission_profile=0, jitter=1,
             brute_force=False, pixel_list=None, w=None, path_mask=None, want_grad=False,
             want_hash=False, want_path_L=False, want_margin=False, want_cond=False,
-            want_vertices=False):
+            want_vertices=False, guide_w=None, guide_mix=0.0, bb_lo=None, bb_inv=None):
         """Render (and optionally differentiate) pixels.
 
         cams: dict with cam_to_world [V,4,4] float32, fov_y [V], width, height.
@@ -217,8 +246,11 @@ class Scene:
         pl = None if pixel_list is None else np.ascontiguousarray(pixel_list, dtype=np.int64)
         npix = V * W * H if pl is None else pl.size
         C = _Cams(V, W, H, _ptr(c2w), _ptr(fov))
+        gw = None if guide_w is None else np.ascontiguousarray(guide_w, dtype=np.float32)
         O = _Opts(seed, stream_tag, iteration, spp, max_depth, rr_depth, mis, emission_profile,
-                  jitter, int(brute_force), _ptr(pl), 0 if pl is None else pl.size)
+                  jitter, int(brute_force), _ptr(pl), 0 if pl is None else pl.size, _ptr(gw),
+                  float(guide_mix), (ctypes.c_double * 3)(*(bb_lo if bb_lo is not None else (0, 0, 0))),
+                  (ctypes.c_double * 3)(*(bb_inv if bb_inv is not None else (1, 1, 1))))
         p = np.ascontiguousarray(params, dtype=np.float64)
         sp = None if sampling_params is None else np.ascontiguousarray(sampling_params,
                                                                          dtype=np.float64)

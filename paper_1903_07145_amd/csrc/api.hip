@@ -38,6 +38,14 @@ static ipt_status fail(ipt_status s, const char* fmt, ...) {
 
 extern "C" const char* ipt_last_error(void) { return g_err.c_str(); }
 
+// guide internals (guide.hip)
+GuideDev guide_dev(const ipt_guide_s* g);
+float* guide_records(ipt_guide_s* g);
+unsigned* guide_record_count(ipt_guide_s* g);
+int guide_capacity(const ipt_guide_s* g);
+int guide_record_stride(const ipt_guide_s* g);
+ipt_status ipt_fail(ipt_status s, const char* msg) { return fail(s, "%s", msg); }
+
 struct ipt_scene_s {
     int device = 0;
     int num_cu = 0;
@@ -283,7 +291,10 @@ static ipt_status check_opts(const ipt_scene_s* s, const ipt_cameras* cams, cons
     if (o->max_depth < 1 || o->max_depth > kMaxDepth) return fail(IPT_ERR_INVALID_ARG, "max_depth must be in [1, %d]", kMaxDepth);
     if (o->mis < 0 || o->mis > 3) return fail(IPT_ERR_INVALID_ARG, "mis must be 0..3");
     if (o->emission_profile < 0 || o->emission_profile > 1) return fail(IPT_ERR_INVALID_ARG, "emission_profile must be 0/1");
-    if (o->guide) return fail(IPT_ERR_NOT_SUPPORTED, "guided sampling is not available in this call");
+    if (o->guide && o->replay_traverse)
+        return fail(IPT_ERR_NOT_SUPPORTED, "a guided gradient replays from vertex checkpoints only");
+    if (!(o->guide_mix >= 0.0f && o->guide_mix < 1.0f)) return fail(IPT_ERR_INVALID_ARG, "guide_mix must be in [0, 1)");
+    if (o->guide_mix > 0.0f && !o->guide) return fail(IPT_ERR_INVALID_ARG, "guide_mix > 0 needs a guide");
     int64_t all = (int64_t)cams->num_views * cams->width * cams->height;
     if (o->pixel_list) {
         if (o->num_pixels < 1) return fail(IPT_ERR_INVALID_ARG, "num_pixels must be >= 1 with a pixel list");
@@ -305,9 +316,9 @@ struct Plan {
     size_t ck_per_pixel = 0;   // checkpoint bytes per work pixel
 };
 
-static int path_grid(const ipt_scene_s* s, int P, int frozen) {
-    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt));
-    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt)));
+static int path_grid(const ipt_scene_s* s, int P, int frozen, int guided) {
+    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, guided), guided);
+    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, guided), guided));
     occ = std::min(occ, path_blocks_per_cu(kReplay, path_lds_bytes(kReplay, P, frozen, s->S, s->nlt)));
     occ = std::max(1, std::min(occ, 8));
     return s->num_cu * occ;
@@ -315,7 +326,8 @@ static int path_grid(const ipt_scene_s* s, int P, int frozen) {
 
 static void make_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t npix, bool with_loss, Plan& pl) {
     int P = 7 * s->S + 3 * s->E;
-    pl.grid = path_grid(s, P, 1);
+    const int guided = o->guide != nullptr;
+    pl.grid = path_grid(s, P, 1, guided && o->guide_mix > 0.0f);
     size_t off = 0;
     pl.off_counters = off; off = al256(off + 64 * sizeof(unsigned));
     pl.off_cdf = off; off = al256(off + sizeof(float) * std::max(1, s->nlt));
@@ -326,14 +338,14 @@ static void make_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t np
     pl.off_ovf = off; off = al256(off + sizeof(int) * (size_t)kOvfDepth * pl.grid * kBlock);
     pl.off_ck = off;
     pl.end_fixed = off;
-    pl.ck_per_pixel = (size_t)(o->max_depth + 1) * o->spp * (sizeof(int4) + 2 * sizeof(float4));
+    pl.ck_per_pixel = (size_t)(o->max_depth + 1) * o->spp * (sizeof(int4) + (guided ? 3 : 2) * sizeof(float4));
 }
 
 static size_t plan_min(const Plan& pl, int64_t npix) {
     int64_t c = std::min<int64_t>(npix, kBlock);
-    return pl.end_fixed + 3 * 256 + (size_t)c * pl.ck_per_pixel;
+    return pl.end_fixed + 4 * 256 + (size_t)c * pl.ck_per_pixel;
 }
-static size_t plan_full(const Plan& pl, int64_t npix) { return pl.end_fixed + 3 * 256 + (size_t)npix * pl.ck_per_pixel; }
+static size_t plan_full(const Plan& pl, int64_t npix) { return pl.end_fixed + 4 * 256 + (size_t)npix * pl.ck_per_pixel; }
 
 extern "C" ipt_status ipt_workspace_query(ipt_scene_t s, const ipt_cameras* cams, const ipt_render_opts* o,
                                           size_t* min_bytes, size_t* full_bytes) {
@@ -381,7 +393,10 @@ static PathArgs base_args(const ipt_scene_s* s, const ipt_cameras* cams, const f
     a.ovf = (int*)(ws + pl.off_ovf);
     a.grad_part = (float*)(ws + pl.off_gpart);
     a.replay_traverse = o->replay_traverse;
-    a.gmix = 0.0f;
+    a.guided = o->guide != nullptr;
+    a.gmix = a.guided ? o->guide_mix : 0.0f;
+    a.guide_fp32 = o->guide_fp32;
+    if (a.guided) a.gd = guide_dev(o->guide);
     return a;
 }
 
@@ -394,7 +409,7 @@ static ipt_status do_render(ipt_scene_t s, const ipt_cameras* cams, const float*
     a.pix_count = npix;
     HIP_OK(launch_light_cdf(s->dev, a.sparams, (float*)(ws + pl.off_cdf), st));
     HIP_OK(launch_zero_u32(a.work, 1, st));
-    size_t lds = path_lds_bytes(kColor, a.P, a.frozen, s->S, s->nlt);
+    size_t lds = path_lds_bytes(kColor, a.P, a.frozen, s->S, s->nlt, a.guided && a.gmix > 0.0f);
     int grid = std::min<int64_t>(pl.grid, (npix + kBlock - 1) / kBlock);
     HIP_OK(timed_launch(s, kColor, a, std::max(1, grid), lds, st));
     return IPT_OK;
@@ -406,7 +421,7 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
     PathArgs a = base_args(s, cams, params, sp, o, ws, pl);
     a.w = w;
     // chunk size from the space left for checkpoints
-    size_t avail = ws_bytes > pl.end_fixed + 3 * 256 ? ws_bytes - pl.end_fixed - 3 * 256 : 0;
+    size_t avail = ws_bytes > pl.end_fixed + 4 * 256 ? ws_bytes - pl.end_fixed - 4 * 256 : 0;
     int64_t chunk = (int64_t)(avail / pl.ck_per_pixel);
     if (chunk < npix) chunk = (chunk / kBlock) * kBlock;
     chunk = std::min<int64_t>(chunk, npix);
@@ -416,8 +431,15 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
     a.ck_hit = (int4*)ck;
     a.ck_a = (float4*)(ck + al256(rec * sizeof(int4)));
     a.ck_c = (float4*)(ck + al256(rec * sizeof(int4)) + al256(rec * sizeof(float4)));
+    a.ck_d = a.guided ? (float4*)(ck + al256(rec * sizeof(int4)) + 2 * al256(rec * sizeof(float4))) : nullptr;
+    if (a.guided) {
+        a.grec = guide_records(o->guide);
+        a.grec_count = guide_record_count(o->guide);
+        a.grec_cap = guide_capacity(o->guide);
+        a.grec_stride = guide_record_stride(o->guide);
+    }
     HIP_OK(launch_light_cdf(s->dev, a.sparams, (float*)(ws + pl.off_cdf), st));
-    size_t lds_f = path_lds_bytes(kGradFwd, a.P, a.frozen, s->S, s->nlt);
+    size_t lds_f = path_lds_bytes(kGradFwd, a.P, a.frozen, s->S, s->nlt, a.guided && a.gmix > 0.0f);
     size_t lds_r = path_lds_bytes(kReplay, a.P, a.frozen, s->S, s->nlt);
     for (int64_t b = 0; b < npix; b += chunk) {
         a.pix_begin = b;
@@ -425,6 +447,7 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
         int grid = (int)std::max<int64_t>(1, std::min<int64_t>(pl.grid, (a.pix_count + kBlock - 1) / kBlock));
         HIP_OK(launch_zero_u32(a.work, 1, st));
         HIP_OK(timed_launch(s, kGradFwd, a, grid, lds_f, st));
+        if (a.guided) HIP_OK(launch_guide_records(a, st));
         HIP_OK(launch_zero_u32(a.work, 1, st));
         HIP_OK(timed_launch(s, kReplay, a, grid, lds_r, st));
         HIP_OK(launch_grad_reduce(a.grad_part, grid, a.P, grad, b > 0 ? 1 : 0, st));
@@ -548,16 +571,13 @@ extern "C" ipt_status ipt_profile_read(ipt_scene_t s, int32_t kernel, ipt_kernel
     return IPT_OK;
 }
 
-// Guide entry points (not yet available).
-extern "C" ipt_status ipt_guide_create(ipt_scene_t, const ipt_guide_opts*, void*, ipt_guide_t* out) {
-    if (out) *out = nullptr;
-    return fail(IPT_ERR_NOT_SUPPORTED, "guide not available");
-}
-extern "C" ipt_status ipt_guide_free(ipt_guide_t) { return IPT_OK; }
-extern "C" ipt_status ipt_guide_eval(ipt_guide_t, const float*, const int32_t*, int64_t, float*, void*) {
-    return fail(IPT_ERR_NOT_SUPPORTED, "guide not available");
-}
-extern "C" ipt_status ipt_guide_train(ipt_guide_t, const ipt_cameras*, const float*, const ipt_render_opts*,
-                                      int32_t, void*, size_t, void*) {
-    return fail(IPT_ERR_NOT_SUPPORTED, "guide not available");
+ipt_status guide_create_impl(int S, const float lo[3], const float hi[3], const ipt_guide_opts* o, void* stream,
+                             ipt_guide_t* out);
+
+extern "C" ipt_status ipt_guide_create(ipt_scene_t s, const ipt_guide_opts* o, void* stream, ipt_guide_t* out) {
+    if (!s || !o || !out) return fail(IPT_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (o->batch < 64 || o->batch % 64 || o->ring_capacity < 64 || !(o->lr > 0.0f) || o->record_stride < 1)
+        return fail(IPT_ERR_INVALID_ARG, "guide options: batch multiple of 64, ring >= 64, lr > 0, stride >= 1");
+    return guide_create_impl(s->S, s->bb_lo, s->bb_hi, o, stream, out);
 }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "guide_dev.h"
 #include "ipt_math.h"
 
 namespace ipt {
@@ -76,18 +77,23 @@ struct PathArgs {
     int* ovf;                      // [kOvfDepth][grid threads]
     int replay_traverse;
     int count_stats;               // accumulate KStats into err->k[mode]
-    // guide (one-sample MIS with BRDF sampling); gmix = 0 disables it
-    const void* guide;
-    float gmix;
-    float* guide_rec;              // training records or NULL
-    unsigned* guide_rec_count;
-    int guide_rec_cap;
-    float3 bb_lo, bb_inv;          // scene box for guide features
+    // learned proposal (one-sample MIS with BRDF sampling)
+    GuideDev gd;
+    int guided;                    // a guide is attached (checkpoint plane ck_d is written)
+    int guide_fp32;                // evaluate it in float32 on VALU
+    float gmix;                    // probability of sampling the guide
+    float4* ck_d;                  // guided: [(k-1)*spp + s][pix_count] (sampled direction, NEE density)
+    float* grec;                   // training-record ring [cap][16] or NULL
+    unsigned* grec_count;
+    int grec_cap, grec_stride;
 };
 
-size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt);
-int path_blocks_per_cu(int mode, size_t lds);
+size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guided = 0);
+int path_blocks_per_cu(int mode, size_t lds, int guided = 0);
+hipError_t launch_guide_records(const PathArgs& a, hipStream_t st);
 hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st);
+// guide handle internals (guide.hip)
+struct GuideHandle;
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 hipError_t launch_light_cdf(const SceneDev& sc, const float* sparams, float* cdf, hipStream_t st);
 hipError_t launch_loss_adjoint(const float* img, const float* target, int64_t n3, int kind,

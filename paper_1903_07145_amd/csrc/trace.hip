@@ -33,6 +33,7 @@
 namespace ipt {
 
 struct Lds {
+    __bf16* gact;       // this wave's guide activation rows (guided kernels)
     float* params;
     float* sparams;
     int* seg_emitter;
@@ -43,7 +44,10 @@ struct Lds {
     bool lights_in_lds;
 };
 
-size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt) {
+// per-wave guide activation rows (64 x kGRowStride bf16), 4 waves per block
+constexpr size_t kGuideLds = 4 * 64 * kGRowStride * sizeof(__bf16);
+
+size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guided) {
     size_t b = 0;
     auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
     b += al(sizeof(float) * P);                       // params
@@ -52,6 +56,7 @@ size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt) {
     if (nlt <= kMaxLdsLights) b += al(sizeof(float) * nlt) + al(sizeof(int4) * nlt);
     if (mode == kReplay) b += al(sizeof(float) * P);  // block gradient
     b += sizeof(int) * kShortStack * kBlock;          // short stacks
+    if (guided && mode != kReplay) b += kGuideLds;     // guide activations
     return b;
 }
 
@@ -73,6 +78,8 @@ __device__ void carve_lds(const PathArgs& a, int mode, unsigned char* smem, Lds&
     lds.grad = nullptr;
     if (mode == kReplay) { lds.grad = (float*)p; p += al(sizeof(float) * a.P); }
     lds.stack = (int*)p;
+    p += sizeof(int) * kShortStack * kBlock;
+    lds.gact = (__bf16*)p + (threadIdx.x >> 6) * 64 * kGRowStride;
     for (int i = tid; i < a.P; i += kBlock) {
         lds.params[i] = a.params[i];
         if (a.frozen) lds.sparams[i] = a.sparams[i];
@@ -345,8 +352,10 @@ struct NeeC {
 };
 
 // The light-sample contribution assuming the shadow ray is unoccluded.
+// pb >= 0 overrides the BRDF-sampling density of the light direction (the
+// combined density when a guide is used).
 __device__ __forceinline__ NeeC nee_contrib(const PathArgs& a, const Lds& lds, const float* cdf, const Shade& g,
-                                            const Mat& m, const Mat& ms, const NeeS& n) {
+                                            const Mat& m, const Mat& ms, const NeeS& n, float pb_in = -1.0f) {
     NeeC r;
     spec_term(g.ns, g.wo, n.wl, m.alpha, r.spec, r.dspec);
     float cx = dot(g.ns, n.wl);
@@ -360,7 +369,7 @@ __device__ __forceinline__ NeeC nee_contrib(const PathArgs& a, const Lds& lds, c
     float w = 1.0f;
     if (a.mis >= 2) {
         float pl = parea * n.d2 / n.cy;
-        float pb = brdf_pdf(ms, g.ns, g.wo, n.wl);
+        float pb = pb_in >= 0.0f ? pb_in : brdf_pdf(ms, g.ns, g.wo, n.wl);
         w = mis_weight(pl, pb, a.mis);
     }
     float prof = a.profile ? n.cy : 1.0f;
@@ -380,34 +389,59 @@ struct ContS {
     bool alive;        // survived Russian roulette
 };
 
-// Sample the continuation direction from the lobe mixture at sampling
-// parameters; Russian roulette on the sampling-parameter throughput.
-__device__ __forceinline__ ContS cont_sample(const PathArgs& a, const Shade& g, const Mat& m, const Mat& ms,
-                                             const float u[8], int k, V3 Ts) {
+// Continuation weight of a sampled direction wi with sampling density pdf:
+// validity (above both the geometric and the shading surface, pdf > 0),
+// a = f cos / pdf at params, the same at sampling params (for Russian
+// roulette), and the roulette decision.
+__device__ __forceinline__ ContS cont_eval(const PathArgs& a, const Shade& g, const Mat& m, const Mat& ms, V3 wi,
+                                           float pdf, int lobe, const float u[8], int k, V3 Ts) {
     ContS c;
-    c.lobe = 0;
-    c.pdf = 0.0f;
+    c.wi = wi;
+    c.lobe = lobe;
+    c.pdf = pdf;
     c.qrr = 1.0f;
     c.alive = false;
     c.av = v3(0.0f, 0.0f, 0.0f);
     c.ts = c.av;
     c.g = c.spec = c.dspec = 0.0f;
-    bool okd = brdf_sample(ms, g.ns, g.wo, u[3], u[4], u[5], c.wi, c.lobe);
-    if (okd && dot(c.wi, g.ngf) > 0.0f && dot(c.wi, g.ns) > 0.0f) c.pdf = brdf_pdf(ms, g.ns, g.wo, c.wi);
-    c.ok = c.pdf > 0.0f;
+    c.ok = pdf > 0.0f && dot(wi, g.ngf) > 0.0f && dot(wi, g.ns) > 0.0f;
     if (!c.ok) return c;
-    spec_term(g.ns, g.wo, c.wi, m.alpha, c.spec, c.dspec);
-    float ci = dot(g.ns, c.wi);
-    c.g = ci / c.pdf;
+    spec_term(g.ns, g.wo, wi, m.alpha, c.spec, c.dspec);
+    float ci = dot(g.ns, wi);
+    c.g = ci / pdf;
     c.av = (m.kd * kInvPi + m.ks * c.spec) * c.g;
     c.ts = c.av;
-    if (a.frozen) c.ts = (ms.kd * kInvPi + ms.ks * spec_only(g.ns, g.wo, c.wi, ms.alpha)) * c.g;
+    if (a.frozen) c.ts = (ms.kd * kInvPi + ms.ks * spec_only(g.ns, g.wo, wi, ms.alpha)) * c.g;
     c.alive = true;
     if (a.rr_depth >= 0 && k >= a.rr_depth) {
         c.qrr = fminf(fmaxf(maxc(Ts * c.ts), 0.1f), 0.95f);
         c.alive = u[6] < c.qrr;
     }
     return c;
+}
+
+// Sample the continuation direction.  Without a guide (mix == NULL): the
+// lobe mixture at sampling parameters.  With a guide: the technique is the
+// guide with probability gmix (u[7]), the BRDF otherwise, and the density is
+// the combined gmix q + (1 - gmix) p_brdf (one-sample MIS).
+__device__ __forceinline__ ContS cont_sample(const PathArgs& a, const Shade& g, const Mat& m, const Mat& ms,
+                                             const float u[8], int k, V3 Ts, const float* mix, bool& used_guide) {
+    V3 wi = v3(0.0f, 0.0f, 1.0f);
+    int lobe = 0;
+    used_guide = false;
+    float pdf = 0.0f;
+    if (mix && u[7] < a.gmix) {
+        used_guide = true;
+        wi = mixture_sample(mix, u[3], u[4], u[5]);
+        pdf = a.gmix * mixture_pdf(mix, wi) + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, wi);
+    } else {
+        bool okd = brdf_sample(ms, g.ns, g.wo, u[3], u[4], u[5], wi, lobe);
+        if (okd && dot(wi, g.ngf) > 0.0f && dot(wi, g.ns) > 0.0f) {
+            pdf = brdf_pdf(ms, g.ns, g.wo, wi);
+            if (mix) pdf = a.gmix * mixture_pdf(mix, wi) + (1.0f - a.gmix) * pdf;
+        }
+    }
+    return cont_eval(a, g, m, ms, wi, pdf, lobe, u, k, Ts);
 }
 
 // Backward sweep of the gradient forward pass: R_{k+1} into the c slot of
@@ -445,7 +479,8 @@ enum Phase { kNeedPixel = 0, kClosest = 1, kShadow = 2, kExit = 3 };
 #define IPT_OCC
 #endif
 
-template <int MODE>
+// GUIDE: 0 none, 1 bfloat16 MFMA evaluation, 2 float32 VALU evaluation
+template <int MODE, int GUIDE>
 __global__ __launch_bounds__(kBlock) IPT_OCC void path_sm_kernel(PathArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     Lds lds;
@@ -535,127 +570,170 @@ __global__ __launch_bounds__(kBlock) IPT_OCC void path_sm_kernel(PathArgs a) {
             }
         }
         if (__ballot(ph != kExit) == 0) break;
-        if (ph == kNeedPixel || ph == kExit) continue;
-
-        // ---- one traversal call site for closest-hit and shadow rays ----
-        const bool any = ph == kShadow;
-        Ray ray = make_ray(o, any ? wl : d);
-        Hit hr = traverse(sc, ray, sc.tmin, any ? sdist * (1.0f - 1e-5f) : __builtin_inff(), prev_tri,
-                          any ? sltri : -1, any, st, wk);
 
         bool end_path = false;
-        if (any) {
-            // ---- finish the vertex that waited for its shadow ray ----
-            bool vis = hr.tri < 0;
-            ev |= (uint32_t)vis << 2;
-            if (vis && nee_valid) {
-                cpart = cpart + nee_c;
-                L = L + nee_LT;
-                if (dvk) { dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; dvk[7] = 1.0f; }
-            }
-            h = fnv1a(h, ev | evtail);
-            if (MODE == kGradFwd) {
-                size_t ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
-                if (vis) a.ck_hit[ck].x = (int)(ckx | kCkVis);
-                a.ck_c[ck] = make_float4(cpart.x, cpart.y, cpart.z, 0.0f);
-            }
-            end_path = evtail != 0;
-            ph = kClosest;
-        } else {
-            // ---- closest hit: vertex k ----
-            ++k;
-            klast = k;
-            wk.vertices++;
-            size_t ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
-            if (hr.tri < 0) {
-                h = fnv1a(h, 0xFFFFFFFFu);
-                if (MODE == kGradFwd) a.ck_hit[ck] = make_int4(0, 0, 0, 0);
-                klast = k - 1;   // a miss contributes nothing: the sweep starts below it
-                end_path = true;
-            } else {
-                Shade g;
-                make_shade(sc, lds, hr, d, g);
-                h = fnv1a(h, (uint32_t)g.orig);
-                dvk = nullptr;
-                if (MODE == kColor && a.dbg_vtx) {
-                    dvk = a.dbg_vtx + (((size_t)wi * a.spp + s) * (size_t)(D + 1) + (k - 1)) * 8;
-                    dvk[0] = (float)g.orig; dvk[1] = hr.u; dvk[2] = hr.v; dvk[3] = hr.t;
-                    dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; dvk[7] = 0.0f;
+        bool shade = false;      // vertex k still needs light sampling and a continuation
+        Shade g;
+        Hit hr;
+        hr.tri = -1;
+        hr.t = hr.u = hr.v = 0.0f;
+        size_t ck = 0;
+        if (ph == kClosest || ph == kShadow) {
+            // ---- one traversal call site for closest-hit and shadow rays ----
+            const bool any = ph == kShadow;
+            Ray ray = make_ray(o, any ? wl : d);
+            hr = traverse(sc, ray, sc.tmin, any ? sdist * (1.0f - 1e-5f) : __builtin_inff(), prev_tri,
+                          any ? sltri : -1, any, st, wk);
+            if (any) {
+                // ---- finish the vertex that waited for its shadow ray ----
+                bool vis = hr.tri < 0;
+                ev |= (uint32_t)vis << 2;
+                if (vis && nee_valid) {
+                    cpart = cpart + nee_c;
+                    L = L + nee_LT;
+                    if (dvk) { dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; dvk[7] = 1.0f; }
                 }
-                ev = 0;
-                evtail = 0;
-                cpart = v3(0.0f, 0.0f, 0.0f);
-                uint32_t flags = 0;
-                if (g.em >= 0 && g.cos_emit > 0.0f) {
-                    float w = emit_weight(a, cdf, lights, g, k, prev_pdf);
-                    if (w > 0.0f) {
-                        float prof = a.profile ? g.cos_emit : 1.0f;
-                        const float* e = lds.params + 7 * sc.S + 3 * g.em;
-                        V3 c = v3(e[0], e[1], e[2]) * (prof * w);
-                        cpart = c;
-                        L = L + T * c;
-                        if (dvk) { dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; }
-                    }
-                    ev |= 1u;
-                }
-                bool shoot = false;
-                V3 av = v3(0.0f, 0.0f, 0.0f);
-                if (k == D + 1) {
-                    evtail = 0;   // x_{D+1}: only its emission counts
-                    end_path = true;
-                } else if (dot(g.ns, g.wo) <= 0.0f) {
-                    ev |= 2u;     // shading normal faces away: the path ends
-                    end_path = true;
-                } else {
-                    Mat m = load_mat(lds.params, g.seg);
-                    Mat ms = a.frozen ? load_mat(lds.sparams, g.seg) : m;
-                    float u[8];
-                    vertex_uniforms(a.rng, pid, k, u);
-                    if (a.mis != 0 && sc.nlt > 0) {
-                        NeeS n = nee_setup(sc, cdf, lights, g, u);
-                        ev |= (uint32_t)n.lj << 8;
-                        if (n.shoot) {
-                            NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n);
-                            shoot = true;
-                            nee_valid = nc.valid;
-                            nee_c = nc.c;
-                            nee_LT = T * nc.c;
-                            wl = n.wl;
-                            sdist = n.dist;
-                            sltri = n.ltri;
-                        }
-                    }
-                    ContS cs = cont_sample(a, g, m, ms, u, k, Ts);
-                    ev |= (uint32_t)cs.lobe << 3;
-                    if (!cs.ok) {
-                        evtail = 16u;
-                    } else if (!cs.alive) {
-                        evtail = 32u;
-                    } else {
-                        float rq = 1.0f / cs.qrr;
-                        av = cs.av * rq;
-                        Ts = Ts * cs.ts * rq;
-                        flags |= kCkCont;
-                        prev_pdf = cs.pdf;
-                        T = T * av;
-                        d = cs.wi;
-                    }
-                }
-                prev_tri = g.tri;
-                o = g.x;
+                h = fnv1a(h, ev | evtail);
                 if (MODE == kGradFwd) {
-                    ckx = (uint32_t)(g.tri + 1) | flags;
-                    a.ck_hit[ck] = make_int4((int)ckx, __float_as_int(hr.u), __float_as_int(hr.v),
-                                             __float_as_int(hr.t));
-                    a.ck_a[ck] = make_float4(av.x, av.y, av.z, 0.0f);
+                    ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
+                    if (vis) a.ck_hit[ck].x = (int)(ckx | kCkVis);
+                    a.ck_c[ck] = make_float4(cpart.x, cpart.y, cpart.z, 0.0f);
                 }
-                if (shoot) {
-                    ph = kShadow;   // the vertex finishes after its shadow ray
+                end_path = evtail != 0;
+                ph = kClosest;
+            } else {
+                // ---- closest hit: vertex k ----
+                ++k;
+                klast = k;
+                wk.vertices++;
+                ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
+                if (hr.tri < 0) {
+                    h = fnv1a(h, 0xFFFFFFFFu);
+                    if (MODE == kGradFwd) a.ck_hit[ck] = make_int4(0, 0, 0, 0);
+                    klast = k - 1;   // a miss contributes nothing: the sweep starts below it
+                    end_path = true;
                 } else {
-                    h = fnv1a(h, ev | evtail);
-                    if (MODE == kGradFwd) a.ck_c[ck] = make_float4(cpart.x, cpart.y, cpart.z, 0.0f);
-                    end_path = end_path || evtail != 0;
+                    make_shade(sc, lds, hr, d, g);
+                    h = fnv1a(h, (uint32_t)g.orig);
+                    dvk = nullptr;
+                    if (MODE == kColor && a.dbg_vtx) {
+                        dvk = a.dbg_vtx + (((size_t)wi * a.spp + s) * (size_t)(D + 1) + (k - 1)) * 8;
+                        dvk[0] = (float)g.orig; dvk[1] = hr.u; dvk[2] = hr.v; dvk[3] = hr.t;
+                        dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; dvk[7] = 0.0f;
+                    }
+                    ev = 0;
+                    evtail = 0;
+                    cpart = v3(0.0f, 0.0f, 0.0f);
+                    if (g.em >= 0 && g.cos_emit > 0.0f) {
+                        float w = emit_weight(a, cdf, lights, g, k, prev_pdf);
+                        if (w > 0.0f) {
+                            float prof = a.profile ? g.cos_emit : 1.0f;
+                            const float* e = lds.params + 7 * sc.S + 3 * g.em;
+                            V3 c = v3(e[0], e[1], e[2]) * (prof * w);
+                            cpart = c;
+                            L = L + T * c;
+                            if (dvk) { dvk[4] = L.x; dvk[5] = L.y; dvk[6] = L.z; }
+                        }
+                        ev |= 1u;
+                    }
+                    if (k == D + 1 || dot(g.ns, g.wo) <= 0.0f) {
+                        // x_{D+1} only counts its emission; a shading normal facing
+                        // away ends the path
+                        if (k != D + 1) ev |= 2u;
+                        end_path = true;
+                        h = fnv1a(h, ev);
+                        prev_tri = g.tri;
+                        if (MODE == kGradFwd) {
+                            a.ck_hit[ck] = make_int4(g.tri + 1, __float_as_int(hr.u), __float_as_int(hr.v),
+                                                     __float_as_int(hr.t));
+                            a.ck_a[ck] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                            a.ck_c[ck] = make_float4(cpart.x, cpart.y, cpart.z, 0.0f);
+                        }
+                    } else {
+                        shade = true;
+                    }
                 }
+            }
+        }
+
+        // ---- guide evaluation for the lanes about to sample (all lanes active here) ----
+        float* mix = nullptr;
+        if (GUIDE) {
+            float* row = (float*)(lds.gact + lane * kGRowStride);
+            if (GUIDE == 1) {
+                if (shade) {
+                    float f[9];
+                    guide_features(a.gd, g.x, g.ns, g.wo, f);
+                    guide_put_inputs(a.gd, lds.gact, f, g.seg);
+                }
+                if (__ballot(shade)) guide_mlp_wave(a.gd, lds.gact);
+            } else if (shade) {
+                float f[9];
+                guide_features(a.gd, g.x, g.ns, g.wo, f);
+                guide_mlp_fp32(a.gd, f, g.seg, row);
+            }
+            if (shade) {
+                mixture_from_raw(row);
+                mix = row;
+            }
+        }
+
+        if (shade) {
+            // ---- light sample and continuation of vertex k ----
+            uint32_t flags = 0;
+            bool shoot = false;
+            V3 av = v3(0.0f, 0.0f, 0.0f);
+            Mat m = load_mat(lds.params, g.seg);
+            Mat ms = a.frozen ? load_mat(lds.sparams, g.seg) : m;
+            float u[8];
+            vertex_uniforms(a.rng, pid, k, u);
+            float pb_nee = -1.0f;
+            if (a.mis != 0 && sc.nlt > 0) {
+                NeeS n = nee_setup(sc, cdf, lights, g, u);
+                ev |= (uint32_t)n.lj << 8;
+                if (n.shoot) {
+                    if (mix) pb_nee = a.gmix * mixture_pdf(mix, n.wl) + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, n.wl);
+                    NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n, pb_nee);
+                    shoot = true;
+                    nee_valid = nc.valid;
+                    nee_c = nc.c;
+                    nee_LT = T * nc.c;
+                    wl = n.wl;
+                    sdist = n.dist;
+                    sltri = n.ltri;
+                }
+            }
+            bool used_guide = false;
+            ContS cs = cont_sample(a, g, m, ms, u, k, Ts, mix, used_guide);
+            ev |= (uint32_t)cs.lobe << 3;
+            if (used_guide) ev |= 64u;
+            if (!cs.ok) {
+                evtail = 16u;
+            } else if (!cs.alive) {
+                evtail = 32u;
+            } else {
+                float rq = 1.0f / cs.qrr;
+                av = cs.av * rq;
+                Ts = Ts * cs.ts * rq;
+                flags |= kCkCont;
+                prev_pdf = cs.pdf;
+                T = T * av;
+                d = cs.wi;
+            }
+            prev_tri = g.tri;
+            o = g.x;
+            if (MODE == kGradFwd) {
+                ckx = (uint32_t)(g.tri + 1) | flags;
+                a.ck_hit[ck] = make_int4((int)ckx, __float_as_int(hr.u), __float_as_int(hr.v), __float_as_int(hr.t));
+                a.ck_a[ck] = make_float4(av.x, av.y, av.z, cs.pdf);
+                if (a.guided) a.ck_d[ck] = make_float4(cs.wi.x, cs.wi.y, cs.wi.z, pb_nee);
+            }
+            if (shoot) {
+                ph = kShadow;   // the vertex finishes after its shadow ray
+            } else {
+                h = fnv1a(h, ev | evtail);
+                if (MODE == kGradFwd) a.ck_c[ck] = make_float4(cpart.x, cpart.y, cpart.z, 0.0f);
+                end_path = evtail != 0;
             }
         }
 
@@ -749,6 +827,7 @@ __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& 
         Mat ms = a.frozen ? load_mat(lds.sparams, g.seg) : m;
         float u[8];
         vertex_uniforms(a.rng, pid, k, u);
+        float4 dk = a.guided ? a.ck_d[ck] : make_float4(0.0f, 0.0f, 0.0f, -1.0f);
         if (a.mis != 0 && sc.nlt > 0) {
             NeeS n = nee_setup(sc, cdf, lights, g, u);
             bool vis = false;
@@ -761,7 +840,8 @@ __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& 
                 }
             }
             if (vis) {
-                NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n);
+                // with a guide the forward pass stored the combined density of wl
+                NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n, dk.w);
                 if (nc.valid) {
                     int mb = 7 * g.seg, eb = 7 * sc.S + 3 * n.lk;
                     V3 we = wT * nc.e * nc.g;
@@ -780,7 +860,14 @@ __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& 
             }
         }
         if (!(flags & kCkCont)) return;
-        ContS cs = cont_sample(a, g, m, ms, u, k, Ts);
+        ContS cs;
+        if (a.guided) {
+            // the sampled direction and its density come from the checkpoint
+            cs = cont_eval(a, g, m, ms, v3(dk.x, dk.y, dk.z), a.ck_a[ck].w, 0, u, k, Ts);
+        } else {
+            bool ug;
+            cs = cont_sample(a, g, m, ms, u, k, Ts, nullptr, ug);
+        }
         float rq = 1.0f / cs.qrr;
         int mb = 7 * g.seg;
         V3 wr = wT * Rn * (cs.g * rq);
@@ -845,26 +932,108 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     for (int i = tid; i < a.P; i += kBlock) out[i] = lds.grad[i];
 }
 
-int path_blocks_per_cu(int mode, size_t lds) {
-    int nb = 0;
-    hipError_t e;
-    if (mode == kColor)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, path_sm_kernel<kColor>, kBlock, lds);
-    else if (mode == kGradFwd)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, path_sm_kernel<kGradFwd>, kBlock, lds);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, replay_kernel, kBlock, lds);
-    if (e != hipSuccess || nb < 1) nb = 1;
-    return nb;
+// ---------------------------------------------------------------------------
+// Guide training records from the gradient pass: after the forward pass and
+// its backward sweep, vertex k of a path holds its hit, the sampled
+// continuation direction w_i and density p_i, and R_{k+1}, the radiance
+// arriving along w_i.  Every record_stride-th path contributes one record per
+// continued vertex: (normalised position, shading normal, outgoing
+// direction, segment, w_i, weight = luminance(R_{k+1}) / p_i).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void guide_records_kernel(PathArgs a) {
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.pix_count * a.spp) return;
+    int64_t q = p / a.spp;
+    int s = (int)(p - q * a.spp);
+    int64_t wi = a.pix_begin + q;
+    int64_t gpath = wi * a.spp + s;
+    if (gpath % a.grec_stride != 0) return;
+    if (a.mask && a.mask[gpath] == 0) return;
+    const size_t plane = (size_t)a.pix_count;
+    if ((uint32_t)a.ck_hit[(size_t)s * plane + q].x & kCkDrop) return;
+    int64_t pix = a.pixel_list ? a.pixel_list[wi] : wi;
+    int64_t npix_img = (int64_t)a.V * a.W * a.H;
+    if (pix < 0 || pix >= npix_img) return;
+    int view = (int)(pix / ((int64_t)a.W * a.H));
+    int64_t rem = pix - (int64_t)view * a.W * a.H;
+    int py = (int)(rem / a.W), px = (int)(rem - (int64_t)py * a.W);
+    uint64_t pid = (uint64_t)pix * (uint64_t)a.spp + (uint64_t)s;
+    float j0 = 0.5f, j1 = 0.5f;
+    if (a.jitter) jitter_uniforms(a.rng, pid, j0, j1);
+    V3 o, d;
+    camera_ray(a, view, (float)px + j0, (float)py + j1, o, d);
+    for (int k = 1; k <= a.D; ++k) {
+        size_t ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
+        int4 rec = a.ck_hit[ck];
+        uint32_t fl = (uint32_t)rec.x;
+        int tri = (int)(fl & kCkTriMask) - 1;
+        if (tri < 0 || !(fl & kCkCont)) break;
+        V3 p0, p1, p2;
+        int orig, seg, light;
+        load_tri(a.sc, tri, p0, p1, p2, orig, seg, light);
+        float u = __int_as_float(rec.y), v = __int_as_float(rec.z);
+        V3 e1 = p1 - p0, e2 = p2 - p0;
+        V3 x = p0 + e1 * u + e2 * v;
+        V3 ng = normalize(cross(e1, e2));
+        V3 wo = v3(-d.x, -d.y, -d.z);
+        V3 ns = ng;
+        if (a.sc.nrm) {
+            float b0 = 1.0f - u - v;
+            ns = normalize(xyz(a.sc.nrm[3 * tri]) * b0 + xyz(a.sc.nrm[3 * tri + 1]) * u + xyz(a.sc.nrm[3 * tri + 2]) * v);
+        }
+        if (dot(ng, wo) < 0.0f) ns = ns * -1.0f;
+        float4 dk = a.ck_d[ck];
+        float pdf = a.ck_a[ck].w;
+        float4 R = a.ck_c[ck];   // R_{k+1} after the sweep
+        float w = lum(v3(R.x, R.y, R.z)) / pdf;
+        if (w > 0.0f && isfinite(w)) {
+            unsigned slot = atomicAdd(a.grec_count, 1u) % (unsigned)a.grec_cap;
+            float f[9];
+            guide_features(a.gd, x, ns, wo, f);
+            float4* r = (float4*)(a.grec + 16 * (size_t)slot);
+            r[0] = make_float4(f[0], f[1], f[2], __int_as_float(seg));
+            r[1] = make_float4(f[3], f[4], f[5], w);
+            r[2] = make_float4(f[6], f[7], f[8], 0.0f);
+            r[3] = make_float4(dk.x, dk.y, dk.z, 0.0f);
+        }
+        d = v3(dk.x, dk.y, dk.z);
+    }
 }
 
+hipError_t launch_guide_records(const PathArgs& a, hipStream_t st) {
+    int64_t n = a.pix_count * a.spp;
+    hipLaunchKernelGGL(guide_records_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename K>
+static int occ(K kern, size_t lds) {
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, lds);
+    return (e != hipSuccess || nb < 1) ? 1 : nb;
+}
+
+int path_blocks_per_cu(int mode, size_t lds, int guided) {
+    if (mode == kColor) return guided ? occ(path_sm_kernel<kColor, 1>, lds) : occ(path_sm_kernel<kColor, 0>, lds);
+    if (mode == kGradFwd)
+        return guided ? occ(path_sm_kernel<kGradFwd, 1>, lds) : occ(path_sm_kernel<kGradFwd, 0>, lds);
+    return occ(replay_kernel, lds);
+}
+
+// The guide evaluation is compiled in only when the guide is sampled (guide_mix > 0).
 hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st) {
-    if (mode == kColor)
-        hipLaunchKernelGGL(path_sm_kernel<kColor>, dim3(grid), dim3(kBlock), lds, st, a);
-    else if (mode == kGradFwd)
-        hipLaunchKernelGGL(path_sm_kernel<kGradFwd>, dim3(grid), dim3(kBlock), lds, st, a);
-    else
+    int gk = (a.guided && a.gmix > 0.0f) ? (a.guide_fp32 ? 2 : 1) : 0;
+    if (mode == kColor) {
+        if (gk == 1) hipLaunchKernelGGL((path_sm_kernel<kColor, 1>), dim3(grid), dim3(kBlock), lds, st, a);
+        else if (gk == 2) hipLaunchKernelGGL((path_sm_kernel<kColor, 2>), dim3(grid), dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((path_sm_kernel<kColor, 0>), dim3(grid), dim3(kBlock), lds, st, a);
+    } else if (mode == kGradFwd) {
+        if (gk == 1) hipLaunchKernelGGL((path_sm_kernel<kGradFwd, 1>), dim3(grid), dim3(kBlock), lds, st, a);
+        else if (gk == 2) hipLaunchKernelGGL((path_sm_kernel<kGradFwd, 2>), dim3(grid), dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((path_sm_kernel<kGradFwd, 0>), dim3(grid), dim3(kBlock), lds, st, a);
+    } else {
         hipLaunchKernelGGL(replay_kernel, dim3(grid), dim3(kBlock), lds, st, a);
+    }
     return hipGetLastError();
 }
 

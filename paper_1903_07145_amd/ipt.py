@@ -21,7 +21,8 @@ _STATUS = {0: "IPT_OK", 1: "IPT_ERR_INVALID_ARG", 2: "IPT_ERR_BAD_SCENE", 3: "IP
 
 EXPORTS = ["ipt_scene_build", "ipt_scene_free", "ipt_scene_info", "ipt_workspace_query", "ipt_render",
            "ipt_render_grad", "ipt_loss_grad", "ipt_sgd_step", "ipt_trace_rays", "ipt_guide_create",
-           "ipt_guide_free", "ipt_guide_eval", "ipt_guide_train", "ipt_profile_enable", "ipt_profile_read",
+           "ipt_guide_free", "ipt_guide_eval", "ipt_guide_train", "ipt_guide_weights", "ipt_guide_records",
+           "ipt_profile_enable", "ipt_profile_read",
            "ipt_profile_reset", "ipt_last_error"]
 
 
@@ -42,7 +43,7 @@ class RenderOpts(ctypes.Structure):
                 ("mis", ctypes.c_int32), ("emission_profile", ctypes.c_int32), ("jitter", ctypes.c_int32),
                 ("replay_traverse", ctypes.c_int32), ("pixel_list", ctypes.c_void_p),
                 ("num_pixels", ctypes.c_int64), ("guide", ctypes.c_void_p), ("guide_mix", ctypes.c_float),
-                ("debug_path_hash", ctypes.c_void_p), ("path_mask", ctypes.c_void_p),
+                ("guide_fp32", ctypes.c_int32), ("debug_path_hash", ctypes.c_void_p), ("path_mask", ctypes.c_void_p),
                 ("debug_path_radiance", ctypes.c_void_p), ("debug_vertices", ctypes.c_void_p)]
 
 
@@ -71,7 +72,7 @@ KERNELS = {0: "colour", 1: "grad_forward", 2: "adjoint_replay"}
 
 class GuideOpts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("lr", ctypes.c_float), ("batch", ctypes.c_int32),
-                ("ring_capacity", ctypes.c_int32)]
+                ("ring_capacity", ctypes.c_int32), ("record_stride", ctypes.c_int32)]
 
 
 _lib = None
@@ -98,8 +99,10 @@ def lib():
             "ipt_trace_rays": [P, P, P, P, I64, ctypes.c_float, I32, P, P, P],
             "ipt_guide_create": [P, P, P, P],
             "ipt_guide_free": [P],
-            "ipt_guide_eval": [P, P, P, I64, P, P],
-            "ipt_guide_train": [P, P, P, P, I32, P, SZ, P],
+            "ipt_guide_eval": [P, P, P, I64, I32, P, P],
+            "ipt_guide_train": [P, I32, P, P],
+            "ipt_guide_weights": [P, P, I32, I64],
+            "ipt_guide_records": [P, P],
             "ipt_profile_enable": [P, I32],
             "ipt_profile_read": [P, I32, P],
             "ipt_profile_reset": [P],
@@ -155,8 +158,8 @@ def _cams_struct(dc):
 
 def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=-1, mis=2,
                 emission_profile=0, jitter=1, replay_traverse=0, pixel_list=None, guide=None,
-                guide_mix=0.0, debug_path_hash=None, path_mask=None, debug_path_radiance=None,
-                debug_vertices=None):
+                guide_mix=0.0, guide_fp32=0, debug_path_hash=None, path_mask=None,
+                debug_path_radiance=None, debug_vertices=None):
     o = RenderOpts()
     o.seed, o.stream_tag, o.iteration = int(seed), int(stream_tag), int(iteration)
     o.spp, o.max_depth, o.rr_depth, o.mis = int(spp), int(max_depth), int(rr_depth), int(mis)
@@ -165,6 +168,7 @@ def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=
     o.num_pixels = 0 if pixel_list is None else int(pixel_list.numel())
     o.guide = None if guide is None else guide.handle
     o.guide_mix = float(guide_mix)
+    o.guide_fp32 = int(guide_fp32)
     o.debug_path_hash = None if debug_path_hash is None else debug_path_hash.data_ptr()
     o.path_mask = None if path_mask is None else path_mask.data_ptr()
     o.debug_path_radiance = None if debug_path_radiance is None else debug_path_radiance.data_ptr()
@@ -281,3 +285,55 @@ def sgd_step(params, grad, m, v, step, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8
     a = AdamOpts(lr, beta1, beta2, eps)
     _check(lib().ipt_sgd_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(step),
                               ctypes.byref(a), _ptr(scale), _ptr(lo), _ptr(hi), _ptr(trainable), _stream()))
+
+
+class Guide:
+    """A learned path-guiding proposal attached to a scene (ipt_guide_create)."""
+
+    NUM_NET = 16744
+    NUM_EMB = 16
+
+    def __init__(self, scene, seed=1, lr=2e-3, batch=4096, ring_capacity=1 << 20, record_stride=1):
+        o = GuideOpts(int(seed), float(lr), int(batch), int(ring_capacity), int(record_stride))
+        h = ctypes.c_void_p()
+        _check(lib().ipt_guide_create(scene.handle, ctypes.byref(o), _stream(), ctypes.byref(h)))
+        self.handle = h
+        self.scene = scene
+        self.num_params = self.NUM_NET + self.NUM_EMB * scene.num_segments
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ipt_guide_free(h)
+            self.handle = None
+
+    def eval(self, feat, seg, mode=0):
+        """Mixture parameters [n, 40] of feature rows feat [n, 9] (device) and segments seg [n]."""
+        feat = _dev(feat, torch.float32)
+        seg = _dev(seg, torch.int32)
+        n = int(seg.numel())
+        out = torch.empty((n, 40), dtype=torch.float32, device="cuda")
+        _check(lib().ipt_guide_eval(self.handle, _ptr(feat), _ptr(seg), n, int(mode), _ptr(out), _stream()))
+        return out
+
+    def train(self, steps=1, want_loss=True):
+        loss = ctypes.c_float(0.0)
+        _check(lib().ipt_guide_train(self.handle, int(steps), ctypes.byref(loss) if want_loss else None,
+                                     _stream()))
+        return float(loss.value) if want_loss else None
+
+    def get_weights(self):
+        w = np.zeros(self.num_params, np.float32)
+        _check(lib().ipt_guide_weights(self.handle, w.ctypes.data_as(ctypes.c_void_p), 1, w.size))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        if w.size != self.num_params:
+            raise ValueError("expected %d parameters" % self.num_params)
+        _check(lib().ipt_guide_weights(self.handle, w.ctypes.data_as(ctypes.c_void_p), 0, w.size))
+
+    def records(self):
+        c = ctypes.c_int64(0)
+        _check(lib().ipt_guide_records(self.handle, ctypes.byref(c)))
+        return int(c.value)
