@@ -223,8 +223,28 @@ ipt_status ipt_guide_train(ipt_guide_t guide, int32_t steps, float *loss_out, vo
 /* Copy the float32 parameters (16744 network values then 16 per segment)
  * to (get = 1) or from (get = 0) the HOST array w; synchronises. */
 ipt_status ipt_guide_weights(ipt_guide_t guide, float *w, int32_t get, int64_t count);
-/* Number of records written so far (the ring keeps the last capacity). */
+/* Number of records written so far (the ring keeps the last capacity; the
+ * count is 32-bit and wraps after 2^32 records). */
 ipt_status ipt_guide_records(ipt_guide_t guide, int64_t *count);
+/* Training record, 16 float32 (the ring's layout):
+ *   [0..2]  position normalised to the scene box, [3] segment (int32 bits),
+ *   [4..6]  shading normal (facing the outgoing side), [7] weight L/p,
+ *   [8..10] outgoing direction, [11] path index (int32 bits),
+ *   [12..14] sampled incident direction, [15] vertex index k >= 1 (int32 bits).
+ * L is the luminance of the radiance estimate arriving along the sampled
+ * direction and p the combined density it was sampled with. */
+/* Loss -sum_i w_i log q_i / sum_i w_i of n records rec [n][16] (DEVICE), and
+ * its gradient grad [16744 + 16 S] (DEVICE) with respect to the float32
+ * parameters, through the bfloat16 forward pass; *loss is DEVICE.  Does not
+ * change the guide.  1 <= n <= 2^24. */
+ipt_status ipt_guide_loss_grad(ipt_guide_t guide, const float *rec, int64_t n, float *loss, float *grad,
+                               void *hip_stream);
+/* Appends n records rec [n][16] (DEVICE) to the ring (0 <= n <= capacity). */
+ipt_status ipt_guide_add_records(ipt_guide_t guide, const float *rec, int64_t n, void *hip_stream);
+/* Copies ring slots [0, n) to out [n][16] (DEVICE); 0 <= n <= capacity.
+ * Slot i holds record i mod capacity of the order in which records arrived
+ * (for records from a gradient pass that order is not deterministic). */
+ipt_status ipt_guide_read_records(ipt_guide_t guide, float *out, int64_t n, void *hip_stream);
 
 /* Kernel timing and work counters of the path kernels of one scene (kernel
  * 0: colour pass, 1: gradient forward pass, 2: adjoint replay).  While

@@ -897,6 +897,12 @@ typedef struct {
 /* Optional per-vertex record of a path (test diagnostics): for vertex k
  * (1..D+1) the hit triangle id, u, v, t and the local contribution c_k
  * (emission hit + light sample, without the prefix throughput). */
+/* Per-vertex debug record: triangle, u, v, t, radiance so far (after the
+ * vertex's emission and light sample), light-sample flag, then for a vertex
+ * that continues: the product of the continuation weights up to and
+ * including this vertex (RGB), the density of the sampled direction, the
+ * direction, and 1. */
+#define VREC 16
 typedef struct { double *v; int nv; } vdump;
 
 /* One path.  Returns radiance in L; adds w-weighted derivatives into grad if
@@ -923,6 +929,7 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
     int na = 0;
     double Ts[3] = { 1, 1, 1 };     /* throughput at sampling params (for RR) */
     double L[3] = { 0, 0, 0 };
+    double Tc[3] = { 1, 1, 1 };
     uint64_t h = 0xCBF29CE484222325ull;
     int32_t prev_tri = -1;
     double prev_pdf = 0;            /* pdf of the direction that produced this ray */
@@ -933,9 +940,10 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
         ohit hit = closest_m(s, o, d, tmin, INFINITY, prev_tri, -1, C->o->brute_force, M);
         h = fnv(h, (uint32_t)hit.tri);
         if (vd && k - 1 < vd->nv) {
-            double *r = vd->v + 8 * (k - 1);
+            double *r = vd->v + VREC * (k - 1);
             r[0] = hit.tri; r[1] = hit.u; r[2] = hit.v; r[3] = hit.t;
             r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; r[7] = 0;
+            for (int q = 8; q < VREC; ++q) r[q] = 0;
         }
         if (hit.tri < 0) break;
         const int32_t *f = &s->F[3 * (int64_t)hit.tri];
@@ -974,7 +982,7 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
                 double tau[3];
                 term_grad(a, na, &phi, wc, grad, tau);
                 for (int c = 0; c < 3; ++c) L[c] += tau[c];
-                if (vd && k - 1 < vd->nv) { double *r = vd->v + 8 * (k - 1); r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; }
+                if (vd && k - 1 < vd->nv) { double *r = vd->v + VREC * (k - 1); r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; }
             }
             ev |= 1u;
         }
@@ -1043,6 +1051,7 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
                     if (mis >= 2) {
                         double pl = parea * d2 / cy;
                         double pb = brdf_pdf(msp, ns, wo, wl);
+                        if (guided) pb = cg * mixture_pdf_d(gmix, wl) + (1.0 - cg) * pb;
                         w = mis_w(pl, pb, mis);
                     }
                     double prof = C->o->emission_profile ? cy : 1.0;
@@ -1066,8 +1075,8 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
                     double tau[3];
                     term_grad(a, na, &phi, wc, grad, tau);
                     for (int c = 0; c < 3; ++c) L[c] += tau[c];
-                    if (vd && k - 1 < vd->nv) { double *r = vd->v + 8 * (k - 1); r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; r[7] = 1; }
-                if (vd && k - 1 < vd->nv) { double *r = vd->v + 8 * (k - 1); r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; }
+                    if (vd && k - 1 < vd->nv) { double *r = vd->v + VREC * (k - 1); r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; r[7] = 1; }
+                if (vd && k - 1 < vd->nv) { double *r = vd->v + VREC * (k - 1); r[4] = L[0]; r[5] = L[1]; r[6] = L[2]; }
                 }
             }
         }
@@ -1116,7 +1125,12 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
             if (!(u[6] < q)) { h = fnv(h, ev | 32u); break; }
         }
         g /= q;
-        for (int c = 0; c < 3; ++c) { ak->v[c] /= q; Ts[c] *= ts[c] / q; }
+        for (int c = 0; c < 3; ++c) { ak->v[c] /= q; Ts[c] *= ts[c] / q; Tc[c] *= ak->v[c]; }
+        if (vd && k - 1 < vd->nv) {
+            double *r = vd->v + VREC * (k - 1);
+            r[8] = Tc[0]; r[9] = Tc[1]; r[10] = Tc[2]; r[11] = pdf;
+            r[12] = wi.x; r[13] = wi.y; r[14] = wi.z; r[15] = 1;
+        }
         int mb = 7 * seg;
         fadd(ak, mb + 0, g / ORC_PI, 0, 0);
         fadd(ak, mb + 1, 0, g / ORC_PI, 0);
@@ -1195,8 +1209,8 @@ int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
             double mgn = INFINITY;
             vdump vdd;
             vdd.nv = o->max_depth + 1;
-            vdd.v = vertices ? vertices + (size_t)(i * o->spp + sidx) * 8 * (size_t)vdd.nv : NULL;
-            if (vdd.v) for (int q = 0; q < 8 * vdd.nv; ++q) vdd.v[q] = -1.0;
+            vdd.v = vertices ? vertices + (size_t)(i * o->spp + sidx) * VREC * (size_t)vdd.nv : NULL;
+            if (vdd.v) for (int q = 0; q < VREC * vdd.nv; ++q) vdd.v[q] = -1.0;
             trace_path_v(&C, org, dir, pid, wc, gp, Lp, &hsh, margins ? &mgn : NULL, vdd.v ? &vdd : NULL);
             if (margins) margins[i * o->spp + sidx] = mgn;
             if (conds) {

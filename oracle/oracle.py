@@ -236,7 +236,10 @@ class Scene:
         path_L, margin [npix,spp] (near-tie margin of each path), cond
         [npix,spp] (relative radiance change when every vertex and direction
         is perturbed by 1e-6 relative; inf if an event changes), vertices
-        [npix,spp,D+1,8] (per vertex: triangle id, u, v, t, radiance so far),
+        [npix,spp,D+1,16] (per vertex: triangle id, u, v, t, radiance so far
+        after its emission and light sample, light flag; for a vertex that
+        continues: product of continuation weights up to it (RGB), density
+        of the sampled direction, the direction, 1),
         dropped).
         """
         c2w = np.ascontiguousarray(cams["cam_to_world"], dtype=np.float32)
@@ -262,7 +265,7 @@ class Scene:
         pL = np.zeros((npix, spp, 3)) if want_path_L else None
         mg = np.zeros((npix, spp)) if want_margin else None
         cd = np.zeros((npix, spp)) if want_cond else None
-        vx = np.zeros((npix, spp, max_depth + 1, 8)) if want_vertices else None
+        vx = np.zeros((npix, spp, max_depth + 1, 16)) if want_vertices else None
         dropped = lib().orc_run(self.h, ctypes.byref(C), _ptr(p), _ptr(sp), ctypes.byref(O),
                                 _ptr(ww), _ptr(pm), _ptr(img), _ptr(grad), _ptr(hsh), _ptr(pL),
                                 _ptr(mg), _ptr(cd), _ptr(vx))

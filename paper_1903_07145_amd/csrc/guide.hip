@@ -100,6 +100,7 @@ struct TrainArgs {
     int64_t nrec;            // valid records
     int batch;
     uint32_t key0, key1, step;
+    int direct;              // 1: record b of the batch is record b (no sampling)
     float* wsum;             // [1] sum of record weights in the batch
     float* lsum;             // [1] sum of w log q
     float* gw;               // [kGParams] gradient
@@ -107,6 +108,7 @@ struct TrainArgs {
 };
 
 __device__ __forceinline__ int64_t batch_index(const TrainArgs& t, int b) {
+    if (t.direct) return b;
     uint4 r = philox(make_uint4((uint32_t)b, 0u, 7u, t.step), t.key0, t.key1);
     uint64_t x = ((uint64_t)r.x << 32) | r.y;
     return (int64_t)(x % (uint64_t)t.nrec);
@@ -339,6 +341,20 @@ __global__ void guide_adam_kernel(float* p, const float* g, float* m, float* v, 
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
 }
 
+__global__ void neg_copy_kernel(const float* src, float* dst) { dst[0] = -src[0]; }
+
+// Appends n caller records at the ring position the counter holds (read
+// only here; a second launch advances it).
+__global__ void guide_append_kernel(const float* src, int64_t n, float* ring, const unsigned* count, int cap) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * kRecF) return;
+    int64_t r = i / kRecF;
+    uint64_t slot = ((uint64_t)*count + (uint64_t)r) % (uint64_t)cap;
+    ring[slot * kRecF + (i - r * kRecF)] = src[i];
+}
+
+__global__ void guide_count_add_kernel(unsigned* count, unsigned n) { *count += n; }
+
 __global__ void zero_f32_kernel(float* p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0f;
@@ -496,6 +512,62 @@ extern "C" ipt_status ipt_guide_eval(ipt_guide_t g, const float* feat, const int
     return e == hipSuccess ? IPT_OK : ipt_fail(IPT_ERR_HIP, hipGetErrorString(e));
 }
 
+// Loss and gradient of one batch into grad [np]; scal[0] = sum of weights,
+// scal[1] = sum_b (w_b / sum w) log q_b.
+static void launch_loss_grad(ipt_guide_s* g, const float* rec, int64_t nrec, int batch, int direct, float* grad,
+                             hipStream_t st) {
+    size_t np = kGParams + (size_t)g->S * kGEmb;
+    TrainArgs t;
+    t.gd = guide_dev(g);
+    t.rec = rec;
+    t.nrec = nrec;
+    t.batch = batch;
+    t.key0 = (uint32_t)g->seed ^ 0xA5A5A5A5u;
+    t.key1 = (uint32_t)(g->seed >> 32);
+    t.step = (uint32_t)g->step;
+    t.direct = direct;
+    t.wsum = g->scal;
+    t.lsum = g->scal + 1;
+    t.gw = grad;
+    t.gemb = grad + kGParams;
+    hipLaunchKernelGGL(zero_f32_kernel, dim3((int)((np + 255) / 256)), dim3(256), 0, st, grad, (int)np);
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, st, g->scal, 2);
+    hipLaunchKernelGGL(guide_wsum_kernel, dim3(64), dim3(256), 0, st, t);
+    hipLaunchKernelGGL(guide_train_kernel, dim3((t.batch + 63) / 64), dim3(64), 0, st, t);
+}
+
+extern "C" ipt_status ipt_guide_loss_grad(ipt_guide_t g, const float* rec, int64_t n, float* loss, float* grad,
+                                          void* stream) {
+    if (!g || !rec || !loss || !grad || n < 1 || n > (1 << 24))
+        return ipt_fail(IPT_ERR_INVALID_ARG, "bad guide loss_grad arguments (1 <= n <= 2^24)");
+    hipStream_t st = (hipStream_t)stream;
+    launch_loss_grad(g, rec, n, (int)n, 1, grad, st);
+    hipLaunchKernelGGL(neg_copy_kernel, dim3(1), dim3(1), 0, st, g->scal + 1, loss);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? IPT_OK : ipt_fail(IPT_ERR_HIP, hipGetErrorString(e));
+}
+
+extern "C" ipt_status ipt_guide_add_records(ipt_guide_t g, const float* rec, int64_t n, void* stream) {
+    if (!g || (!rec && n > 0) || n < 0 || n > g->cap)
+        return ipt_fail(IPT_ERR_INVALID_ARG, "bad record count (0 <= n <= ring capacity)");
+    if (n == 0) return IPT_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int64_t tot = n * kRecF;
+    hipLaunchKernelGGL(guide_append_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, rec, n, g->rec,
+                       g->rec_count, g->cap);
+    hipLaunchKernelGGL(guide_count_add_kernel, dim3(1), dim3(1), 0, st, g->rec_count, (unsigned)n);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? IPT_OK : ipt_fail(IPT_ERR_HIP, hipGetErrorString(e));
+}
+
+extern "C" ipt_status ipt_guide_read_records(ipt_guide_t g, float* out, int64_t n, void* stream) {
+    if (!g || (!out && n > 0) || n < 0 || n > g->cap)
+        return ipt_fail(IPT_ERR_INVALID_ARG, "bad record count (0 <= n <= ring capacity)");
+    if (n == 0) return IPT_OK;
+    hipError_t e = hipMemcpyAsync(out, g->rec, (size_t)n * kRecF * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? IPT_OK : ipt_fail(IPT_ERR_HIP, hipGetErrorString(e));
+}
+
 extern "C" ipt_status ipt_guide_train(ipt_guide_t g, int32_t steps, float* loss_out, void* stream) {
     if (!g || steps < 0) return ipt_fail(IPT_ERR_INVALID_ARG, "bad guide train arguments");
     hipStream_t st = (hipStream_t)stream;
@@ -507,22 +579,7 @@ extern "C" ipt_status ipt_guide_train(ipt_guide_t g, int32_t steps, float* loss_
     size_t np = kGParams + (size_t)g->S * kGEmb;
     float lsum_tot = 0.0f;
     for (int s = 0; s < steps; ++s) {
-        TrainArgs t;
-        t.gd = guide_dev(g);
-        t.rec = g->rec;
-        t.nrec = nrec;
-        t.batch = g->batch;
-        t.key0 = (uint32_t)g->seed ^ 0xA5A5A5A5u;
-        t.key1 = (uint32_t)(g->seed >> 32);
-        t.step = (uint32_t)g->step;
-        t.wsum = g->scal;
-        t.lsum = g->scal + 1;
-        t.gw = g->g;
-        t.gemb = g->g + kGParams;
-        hipLaunchKernelGGL(zero_f32_kernel, dim3((int)((np + 255) / 256)), dim3(256), 0, st, g->g, (int)np);
-        hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, st, g->scal, 2);
-        hipLaunchKernelGGL(guide_wsum_kernel, dim3(64), dim3(256), 0, st, t);
-        hipLaunchKernelGGL(guide_train_kernel, dim3((t.batch + 63) / 64), dim3(64), 0, st, t);
+        launch_loss_grad(g, g->rec, nrec, g->batch, 0, g->g, st);
         g->step++;
         float c1 = (float)(1.0 - std::pow(0.9, g->step)), c2 = (float)(1.0 - std::pow(0.999, g->step));
         hipLaunchKernelGGL(guide_adam_kernel, dim3((int)((np + 255) / 256)), dim3(256), 0, st, g->w, g->g, g->m,

@@ -993,8 +993,8 @@ __global__ __launch_bounds__(256) void guide_records_kernel(PathArgs a) {
             float4* r = (float4*)(a.grec + 16 * (size_t)slot);
             r[0] = make_float4(f[0], f[1], f[2], __int_as_float(seg));
             r[1] = make_float4(f[3], f[4], f[5], w);
-            r[2] = make_float4(f[6], f[7], f[8], 0.0f);
-            r[3] = make_float4(dk.x, dk.y, dk.z, 0.0f);
+            r[2] = make_float4(f[6], f[7], f[8], __int_as_float((int)gpath));
+            r[3] = make_float4(dk.x, dk.y, dk.z, __int_as_float(k));
         }
         d = v3(dk.x, dk.y, dk.z);
     }

@@ -22,6 +22,7 @@ _STATUS = {0: "IPT_OK", 1: "IPT_ERR_INVALID_ARG", 2: "IPT_ERR_BAD_SCENE", 3: "IP
 EXPORTS = ["ipt_scene_build", "ipt_scene_free", "ipt_scene_info", "ipt_workspace_query", "ipt_render",
            "ipt_render_grad", "ipt_loss_grad", "ipt_sgd_step", "ipt_trace_rays", "ipt_guide_create",
            "ipt_guide_free", "ipt_guide_eval", "ipt_guide_train", "ipt_guide_weights", "ipt_guide_records",
+           "ipt_guide_loss_grad", "ipt_guide_add_records", "ipt_guide_read_records",
            "ipt_profile_enable", "ipt_profile_read",
            "ipt_profile_reset", "ipt_last_error"]
 
@@ -103,6 +104,9 @@ def lib():
             "ipt_guide_train": [P, I32, P, P],
             "ipt_guide_weights": [P, P, I32, I64],
             "ipt_guide_records": [P, P],
+            "ipt_guide_loss_grad": [P, P, I64, P, P, P],
+            "ipt_guide_add_records": [P, P, I64, P],
+            "ipt_guide_read_records": [P, P, I64, P],
             "ipt_profile_enable": [P, I32],
             "ipt_profile_read": [P, I32, P],
             "ipt_profile_reset": [P],
@@ -299,6 +303,7 @@ class Guide:
         _check(lib().ipt_guide_create(scene.handle, ctypes.byref(o), _stream(), ctypes.byref(h)))
         self.handle = h
         self.scene = scene
+        self.capacity = int(ring_capacity)
         self.num_params = self.NUM_NET + self.NUM_EMB * scene.num_segments
 
     def __del__(self):
@@ -332,6 +337,27 @@ class Guide:
         if w.size != self.num_params:
             raise ValueError("expected %d parameters" % self.num_params)
         _check(lib().ipt_guide_weights(self.handle, w.ctypes.data_as(ctypes.c_void_p), 0, w.size))
+
+    def loss_grad(self, rec):
+        """(loss, grad) of records rec [n, 16] (float32, ring layout) without training."""
+        rec = _dev(rec, torch.float32)
+        n = int(rec.shape[0])
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        grad = torch.zeros(self.num_params, dtype=torch.float32, device="cuda")
+        _check(lib().ipt_guide_loss_grad(self.handle, _ptr(rec), n, _ptr(loss), _ptr(grad), _stream()))
+        return loss, grad
+
+    def add_records(self, rec):
+        rec = _dev(rec, torch.float32)
+        _check(lib().ipt_guide_add_records(self.handle, _ptr(rec), int(rec.shape[0]), _stream()))
+
+    def read_records(self, n=None):
+        """Ring slots [0, n) as a device tensor [n, 16] (default: the filled part)."""
+        if n is None:
+            n = min(self.records(), self.capacity)
+        out = torch.zeros((int(n), 16), dtype=torch.float32, device="cuda")
+        _check(lib().ipt_guide_read_records(self.handle, _ptr(out), int(n), _stream()))
+        return out
 
     def records(self):
         c = ctypes.c_int64(0)

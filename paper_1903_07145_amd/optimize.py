@@ -1,0 +1,144 @@
+"""Nested SGD of inverse path tracing (Sec. 3, Eq. 3-4): every iteration
+renders an independent colour estimate (stream A), forms the L2 adjoint image
+against the target, estimates the parameter gradient from an independent set
+of paths (stream B) and takes a projected Adam step on the normalised
+parameters.  With ``guide=True`` both estimates sample directions from the
+learned proposal combined with BRDF sampling (one-sample MIS), the gradient
+pass writes training records, and the proposal is trained online between
+iterations (mixing weight 0 during the warm-up, ``guide_mix`` after).
+
+Every step runs in the HIP library; this module only sequences the calls.
+
+    python -m paper_1903_07145_amd.optimize --workload apartment --iters 200 --guide
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import ipt, scenes
+
+TAG_TARGET, TAG_A, TAG_B = 0, 1, 2
+
+
+def render_target(g, dc, p_true, spp_total, D, rr, seed=1, chunk=16):
+    """Target images: the true parameters at spp_total samples (stream tag 0)."""
+    npix = dc["num_views"] * dc["width"] * dc["height"]
+    target = torch.zeros((npix, 3), dtype=torch.float32, device="cuda")
+    npass = max(1, spp_total // chunk)
+    for i in range(npass):
+        o = ipt.render_opts(seed=seed, stream_tag=TAG_TARGET, iteration=i, spp=min(chunk, spp_total),
+                            max_depth=D, rr_depth=rr, mis=2)
+        target += g.render(dc, p_true, o)
+    target /= npass
+    return target
+
+
+def param_rmse(params, p_true, scale, trainable):
+    """RMSE of the normalised trainable parameters."""
+    m = trainable.bool()
+    d = (params[m] - p_true[m]) / scale[m]
+    return float(torch.sqrt(torch.mean(d * d)))
+
+
+def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guide_steps=10, guide_lr=2e-3,
+             guide_batch=16384, record_stride=None, target_rmse=1e-2, stop_at_target=False, target=None,
+             g=None, log=None, spp=None):
+    """Runs the optimisation; returns a dict with the RMSE/loss history and timings.
+
+    Wall-clock time counts from the first iteration (scene build and target
+    render excluded) and includes guide training in the guided arm."""
+    cfg = sc["render"]
+    iters = iters or cfg["iters"]
+    spp = spp or cfg["spp"]
+    D, rr, lr = cfg["max_depth"], cfg["rr_depth"], cfg["lr"]
+    g = g or ipt.Scene.from_dict(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    npix = dc["num_views"] * dc["width"] * dc["height"]
+    p_true = torch.as_tensor(sc["params"], device="cuda")
+    if target is None:
+        target = render_target(g, dc, p_true, cfg["target_spp"], D, rr)
+    params = torch.as_tensor(scenes.init_theta(sc, cfg["init"], seed=seed), device="cuda")
+    scale = torch.as_tensor(sc["scale"], device="cuda")
+    lo = torch.as_tensor(sc["lo"], device="cuda")
+    hi = torch.as_tensor(sc["hi"], device="cuda")
+    tr = torch.as_tensor(sc["trainable"], device="cuda")
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    grad = torch.zeros_like(params)
+    gd = None
+    if guide:
+        # about one million training records per iteration
+        stride = record_stride or max(1, (npix * spp * 3) // (1 << 20))
+        gd = ipt.Guide(g, seed=seed, lr=guide_lr, batch=guide_batch, ring_capacity=1 << 21, record_stride=stride)
+    g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr, guide=gd, guide_mix=guide_mix if gd else 0.0))
+    hist = dict(it=[], t=[], rmse=[], loss=[], guide_loss=[])
+    torch.cuda.synchronize()
+    t0 = time.time()
+    t_hit = None
+    for it in range(iters):
+        mix = guide_mix if (gd is not None and it >= warmup) else 0.0
+        kw = dict(seed=1000 * seed + 11, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2)
+        co = ipt.render_opts(stream_tag=TAG_A, guide=gd if mix > 0 else None, guide_mix=mix, **kw)
+        go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, **kw)
+        g.loss_grad(dc, params, target, co, go, 0, loss=loss, grad=grad)
+        ipt.sgd_step(params, grad, m, v, it + 1, lr=lr, scale=scale, lo=lo, hi=hi, trainable=tr)
+        gl = None
+        if gd is not None and gd.records() >= guide_batch:
+            gl = gd.train(guide_steps, want_loss=(it % 10 == 0))
+        r = param_rmse(params, p_true, scale, tr)   # synchronises
+        t = time.time() - t0
+        hist["it"].append(it)
+        hist["t"].append(t)
+        hist["rmse"].append(r)
+        hist["loss"].append(float(loss.cpu()))
+        hist["guide_loss"].append(gl)
+        if t_hit is None and r <= target_rmse:
+            t_hit = t
+            if stop_at_target:
+                break
+        if log and (it % 10 == 0 or it == iters - 1):
+            log("it %4d  t %7.2fs  loss %.5f  rmse %.4f%s" % (it, t, hist["loss"][-1], r,
+                                                           "" if gl is None else "  guide loss %.4f" % gl))
+    return dict(history=hist, time_to_target=t_hit, final_rmse=hist["rmse"][-1], seconds=hist["t"][-1],
+                iters=len(hist["it"]), guide=guide, seed=seed)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="apartment", choices=sorted(scenes.WORKLOADS))
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--seeds", type=int, nargs="+", default=[7])
+    ap.add_argument("--guide", action="store_true")
+    ap.add_argument("--guide-mix", type=float, default=0.5)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--guide-steps", type=int, default=10)
+    ap.add_argument("--target-rmse", type=float, default=1e-2)
+    ap.add_argument("--out", default=None, help="JSON lines file for the histories")
+    a = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    sc = scenes.WORKLOADS[a.workload]()
+    g = ipt.Scene.from_dict(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    cfg = sc["render"]
+    target = render_target(g, dc, torch.as_tensor(sc["params"], device="cuda"), cfg["target_spp"],
+                           cfg["max_depth"], cfg["rr_depth"])
+    log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
+    for seed in a.seeds:
+        log("workload %s seed %d guide %s" % (a.workload, seed, a.guide))
+        res = optimize(sc, iters=a.iters, seed=seed, guide=a.guide, guide_mix=a.guide_mix, warmup=a.warmup,
+                       guide_steps=a.guide_steps, target_rmse=a.target_rmse, target=target, g=g, log=log)
+        line = json.dumps(dict(workload=a.workload, **res))
+        if a.out:
+            with open(a.out, "a") as f:
+                f.write(line + "\n")
+        log("seed %d: final rmse %.4f after %d iters in %.1fs; time to %.0e: %s" % (
+            seed, res["final_rmse"], res["iters"], res["seconds"], a.target_rmse, res["time_to_target"]))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,267 @@
+"""The learned proposal on the GPU, through the C ABI, against the oracle.
+
+* Network: float32 VALU evaluation against the float64 oracle network (same
+  float32 weights) at 1e-4; bfloat16 MFMA evaluation against the oracle's
+  bfloat16-emulating network at 1e-2 (mixture density).
+* Training: loss and parameter gradient of the MFMA training kernel against
+  the oracle's reverse-mode gradient of the same loss at 1e-2.
+* Guided estimator with a frozen guide evaluated in float32: images at 1e-4
+  and gradients at 1e-3 against the oracle's guided estimator, with the
+  same path masks as the unguided parity tests.
+* Training records written by the gradient pass, matched to oracle paths.
+* Unbiasedness of the MFMA-guided estimator, and what a guide trained on
+  the tracer's own records gains over BRDF sampling (variance).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import _guide
+from _gpu import (ILL_COND, NEAR_TIE, banner, both, comparable, dev, gpu_grad, gpu_render, mismatch_stats,
+                  oracle_opts)
+from oracle import guide_ref, oracle
+from paper_1903_07145_amd import ipt, scenes
+
+pytestmark = pytest.mark.gpu
+
+PIX_REL = 1e-4
+GRAD_REL = 1e-3
+BF16_REL = 1e-2
+
+
+@pytest.fixture(scope="module")
+def cornell():
+    sc = scenes.cornell()
+    g, o = both(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    lo, inv = _guide.box(sc["verts"])
+    return sc, g, o, dc, lo, inv
+
+
+def _guide_with(g, w, **kw):
+    gd = ipt.Guide(g, **kw)
+    gd.set_weights(w)
+    return gd
+
+
+def _queries(S, n, seed):
+    rng = np.random.default_rng(seed)
+    feat = np.concatenate([rng.uniform(-1, 1, (n, 3)), _guide.random_unit(rng, n), _guide.random_unit(rng, n)],
+                          1).astype(np.float32)
+    seg = rng.integers(0, S, n).astype(np.int32)
+    return feat, seg
+
+
+def test_guide_eval_fp32_and_mfma(cornell):
+    banner("guide network: float32 VALU vs float64 oracle, bf16 MFMA vs bf16-emulating oracle")
+    sc, g, o, dc, lo, inv = cornell
+    S = sc["num_segments"]
+    w = _guide.random_weights(S, seed=11, out_gain=3.0, kappa_bias=1.0)
+    gd = _guide_with(g, w)
+    assert np.array_equal(gd.get_weights(), w)
+    n = 1000   # ragged against the 64-query wave tiles
+    feat, seg = _queries(S, n, 1)
+    ref = oracle.guide_eval(w, feat.astype(np.float64), seg)
+    out32 = gd.eval(feat, seg, mode=1).cpu().numpy().astype(np.float64)
+    err32 = np.abs(out32 - ref) / np.maximum(np.abs(ref), 1.0)
+    print("fp32 mixture max err %.2e" % err32.max())
+    assert err32.max() <= PIX_REL
+    # bf16 MFMA: density of the mixture at random directions
+    out16 = gd.eval(feat, seg, mode=0).cpu().numpy().astype(np.float64)
+    ref16 = guide_ref.mixture_flat(guide_ref.network(w, feat, seg, bf16=True)).numpy()
+    rng = np.random.default_rng(2)
+    dirs = torch.as_tensor(_guide.random_unit(rng, n))
+
+    def q(m):
+        m = torch.as_tensor(m).reshape(n, 8, 5)
+        return torch.exp(guide_ref.log_q(m[..., :3], m[..., 3], m[..., 4], dirs)).numpy()
+
+    e16 = np.abs(q(out16) - q(ref16)) / q(ref16)
+    print("bf16 density rel err p50 %.2e max %.2e" % (np.median(e16), e16.max()))
+    assert e16.max() <= BF16_REL
+    # n = 0 is a no-op, n = 1 a single ragged wave
+    f1, s1 = feat[:1], seg[:1]
+    assert np.allclose(gd.eval(f1, s1, mode=0).cpu().numpy(), out16[:1], rtol=1e-6, atol=1e-7)
+
+
+def test_guide_loss_grad_vs_oracle(cornell):
+    banner("guide training kernel: loss and gradient vs oracle")
+    sc, g, o, dc, lo, inv = cornell
+    S = sc["num_segments"]
+    w = _guide.random_weights(S, seed=12, out_gain=2.0)
+    gd = _guide_with(g, w)
+    for n in (4096, 1000):
+        rec = _guide.random_records(n, S, seed=n)
+        loss, grad = gd.loss_grad(rec)
+        torch.cuda.synchronize()
+        loss, grad = float(loss.cpu()), grad.cpu().numpy().astype(np.float64)
+        L_ref, g_ref = guide_ref.loss_grad(w, rec, bf16=True)
+        print("n %d loss gpu %.6f oracle %.6f" % (n, loss, L_ref))
+        assert abs(loss - L_ref) <= BF16_REL * abs(L_ref)
+        # per parameter block: W1 b1 ... W5 b5 embedding
+        sizes = [25 * 64, 64, 64 * 64, 64, 64 * 64, 64, 64 * 64, 64, 64 * 40, 40, 16 * S]
+        off = 0
+        for i, sz in enumerate(sizes):
+            a, b = grad[off:off + sz], g_ref[off:off + sz]
+            rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
+            print("  block %d |g| %.3e rel %.2e" % (i, np.linalg.norm(b), rel))
+            assert rel <= BF16_REL, (i, rel)
+            off += sz
+
+
+def _guided_kw(kw, gd, fp32=1, mix=0.5):
+    return dict(kw, guide=gd, guide_mix=mix, guide_fp32=fp32)
+
+
+def _oracle_guided(lo, inv, w, mix=0.5):
+    return dict(guide_w=w, guide_mix=mix, bb_lo=lo, bb_inv=inv)
+
+
+@pytest.mark.parametrize("mis", [0, 2])
+def test_guided_render_and_grad_parity_fp32(cornell, mis):
+    banner("guided estimator parity (frozen guide, float32) mis=%d" % mis)
+    sc, g, o, dc, lo, inv = cornell
+    S = sc["num_segments"]
+    w = _guide.random_weights(S, seed=13, out_gain=3.0, kappa_bias=1.0)
+    gd = _guide_with(g, w)
+    kw = dict(seed=31, stream_tag=1, iteration=4, spp=4, max_depth=3, mis=mis)
+    _, h_g = gpu_render(g, dc, sc["params"], _guided_kw(kw, gd))
+    r = o.run(sc["cams"], sc["params"], want_hash=True, want_margin=True, want_cond=True, **oracle_opts(kw),
+              **_oracle_guided(lo, inv, w))
+    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"], r["cond"])
+    keep = comparable(h_g, r)
+    print("paths %d mismatching %d (hard %d), compared %.1f%%" % (h_g.size, n_mis, n_hard, 100 * keep.mean()))
+    assert n_hard <= 1e-5 * 3 * h_g.size
+    assert keep.mean() > 0.95
+    img_g, _ = gpu_render(g, dc, sc["params"], _guided_kw(kw, gd), mask=keep)
+    ro = o.run(sc["cams"], sc["params"], path_mask=keep.astype(np.uint8), **oracle_opts(kw),
+               **_oracle_guided(lo, inv, w))
+    mean = np.abs(ro["image"]).mean()
+    err = np.abs(img_g - ro["image"]) / np.maximum(np.abs(ro["image"]), 1e-4 * mean)
+    print("pixel rel err p50 %.2e max %.2e" % (np.median(err), err.max()))
+    assert err.max() <= PIX_REL
+    rng = np.random.default_rng(5)
+    wimg = rng.normal(size=(64 * 64, 3))
+    gg = gpu_grad(g, dc, sc["params"], wimg, _guided_kw(dict(kw, stream_tag=1), gd), mask=keep)
+    go = o.run(sc["cams"], sc["params"], w=wimg, path_mask=keep.astype(np.uint8), want_grad=True,
+               **oracle_opts(kw), **_oracle_guided(lo, inv, w))["grad"]
+    rms = math.sqrt(np.mean(go ** 2))
+    gerr = np.abs(gg - go) / np.maximum(np.abs(go), 1e-2 * rms)
+    print("grad rel err max %.2e" % gerr.max())
+    assert gerr.max() <= GRAD_REL
+
+
+def test_training_records_match_oracle_paths(cornell):
+    banner("training records of the gradient pass vs oracle vertices")
+    sc, g, o, dc, lo, inv = cornell
+    S = sc["num_segments"]
+    w = _guide.random_weights(S, seed=14, out_gain=2.0, kappa_bias=1.0)
+    gd = _guide_with(g, w, ring_capacity=1 << 16, record_stride=1)
+    rng = np.random.default_rng(6)
+    pix = np.sort(rng.choice(64 * 64, 700, replace=False)).astype(np.int64)
+    spp, D = 4, 3
+    kw = dict(seed=41, stream_tag=2, iteration=1, spp=spp, max_depth=D, mis=2)
+    _, h_g = gpu_render(g, dc, sc["params"], _guided_kw(kw, gd), pixel_list=pix)
+    r = o.run(sc["cams"], sc["params"], pixel_list=pix, want_hash=True, want_margin=True, want_cond=True,
+              want_vertices=True, want_path_L=True, **oracle_opts(kw), **_oracle_guided(lo, inv, w))
+    keep = comparable(h_g, r)
+    gpu_grad(g, dc, sc["params"], np.ones((pix.size, 3)), _guided_kw(kw, gd), pixel_list=pix)
+    nrec = gd.records()
+    rec = gd.read_records(nrec).cpu().numpy()
+    path = rec[:, 11].view(np.int32)
+    kk = rec[:, 15].view(np.int32)
+    assert path.min() >= 0 and path.max() < pix.size * spp and kk.min() >= 1 and kk.max() <= D
+    # the oracle's continuing vertices with incident radiance > 0
+    V = r["vertices"]
+    Lf = r["path_L"]
+    expect = {}
+    verts = np.asarray(sc["verts"], np.float64)
+    tris = np.asarray(sc["tris"])
+    eye = np.asarray(sc["cams"]["cam_to_world"], np.float64)[0][:3, 3]
+    for pi in range(pix.size):
+        for s in range(spp):
+            prev_d = None
+            for k in range(1, D + 1):
+                v = V[pi, s, k - 1]
+                if v[0] < 0 or v[15] != 1:
+                    break
+                R = (Lf[pi, s] - v[4:7]) / v[8:11]
+                t = tris[int(v[0])]
+                x = verts[t[0]] + v[1] * (verts[t[1]] - verts[t[0]]) + v[2] * (verts[t[2]] - verts[t[0]])
+                wo = -prev_d if prev_d is not None else (eye - x) / np.linalg.norm(eye - x)
+                if R.mean() > 0:
+                    expect[(pi * spp + s, k)] = (x, wo, v[12:15], R.mean() / v[11])
+                prev_d = v[12:15]
+    ok_paths = keep.reshape(-1)
+    got = {(int(p), int(k)): i for i, (p, k) in enumerate(zip(path, kk))}
+    compared = 0
+    for key, (x, wo, wi, wt) in expect.items():
+        if not ok_paths[key[0]]:
+            continue
+        assert key in got, key
+        rr = rec[got[key]]
+        assert np.allclose(rr[0:3], 2 * (x - lo) * inv - 1, atol=1e-4)
+        assert np.allclose(rr[8:11], wo, atol=1e-4)
+        assert np.allclose(rr[12:15], wi, atol=1e-4)
+        assert abs(rr[7] - wt) <= 1e-3 * wt
+        compared += 1
+    n_ok = sum(1 for key in got if ok_paths[key[0]])
+    print("records %d, compared %d" % (nrec, compared))
+    assert compared > 1000 and n_ok == compared
+
+
+def _path_radiance(g, dc, params, kw, npix):
+    L = torch.zeros(npix * kw["spp"] * 3, dtype=torch.float32, device="cuda")
+    o = ipt.render_opts(debug_path_radiance=L, **kw)
+    g.render(dc, dev(params), o)
+    torch.cuda.synchronize()
+    return L.cpu().numpy().astype(np.float64).reshape(npix, kw["spp"], 3)
+
+
+def test_mfma_guided_estimator_unbiased(cornell):
+    banner("MFMA-guided estimator: same mean as BRDF sampling")
+    sc, g, o, dc, lo, inv = cornell
+    w = _guide.random_weights(sc["num_segments"], seed=15, out_gain=3.0, kappa_bias=1.5)
+    gd = _guide_with(g, w)
+    for mis in (0, 2):
+        kw = dict(seed=51, stream_tag=1, iteration=0, spp=64, max_depth=3, mis=mis)
+        a = _path_radiance(g, dc, sc["params"], kw, 4096).reshape(-1, 3)
+        b = _path_radiance(g, dc, sc["params"], dict(_guided_kw(kw, gd, fp32=0), seed=52), 4096).reshape(-1, 3)
+        se = np.sqrt(a.var(0) / a.shape[0] + b.var(0) / b.shape[0])
+        print("mis %d mean brdf %s guided %s se %s" % (mis, a.mean(0), b.mean(0), se))
+        assert np.all(np.abs(a.mean(0) - b.mean(0)) < 5 * se)
+
+
+def test_trained_guide_reduces_variance(cornell):
+    """Online training on the tracer's own records (BRDF-only light transport,
+    the case a proposal can change most): the trained guide's pixel variance
+    is well below plain BRDF sampling's, and its training loss has dropped."""
+    banner("online training: variance against BRDF sampling")
+    sc, g, o, dc, lo, inv = cornell
+    gd = ipt.Guide(g, seed=5, lr=5e-3, batch=4096, ring_capacity=1 << 18, record_stride=1)
+    rng = np.random.default_rng(7)
+    wimg = np.ones((64 * 64, 3))
+    base = dict(stream_tag=3, spp=4, max_depth=3, mis=0)
+    held = None
+    losses = []
+    for it in range(30):
+        mix = 0.0 if it < 5 else 0.5
+        gpu_grad(g, dc, sc["params"], wimg, _guided_kw(dict(base, seed=100 + it, iteration=it), gd, fp32=0, mix=mix))
+        if held is None:
+            held = gd.read_records(min(gd.records(), 8192)).clone()
+            l0 = float(gd.loss_grad(held)[0].cpu())
+        losses.append(gd.train(10))
+    l1 = float(gd.loss_grad(held)[0].cpu())
+    print("held-out loss %.4f -> %.4f; last batch losses %s" % (l0, l1, np.round(losses[-3:], 4)))
+    assert l1 < l0 - 0.2
+    kw = dict(seed=77, stream_tag=1, iteration=0, spp=64, max_depth=3, mis=0)
+    a = _path_radiance(g, dc, sc["params"], kw, 4096)
+    b = _path_radiance(g, dc, sc["params"], _guided_kw(kw, gd, fp32=0), 4096)
+    va = a.var(axis=1).mean()
+    vb = b.var(axis=1).mean()
+    print("mean per-pixel path variance: BRDF %.4g guided %.4g (ratio %.2f)" % (va, vb, va / vb))
+    assert np.all(np.abs(a.mean((0, 1)) - b.mean((0, 1))) < 5 * np.sqrt(a.var((0, 1)) / a[..., 0].size +
+                                                                       b.var((0, 1)) / b[..., 0].size))
+    assert va / vb > 1.5
