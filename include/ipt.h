@@ -188,15 +188,16 @@ ipt_status ipt_trace_rays(ipt_scene_t scene, const float *origins, const float *
  * training, float32 accumulation and master weights) that maps a path
  * vertex -- position normalised to the scene box, shading normal, outgoing
  * direction -- and a learned 16-d embedding of its segment to an 8-lobe von
- * Mises-Fisher mixture over incident directions.  Attached to
+ * Mises-Fisher mixture over incident directions, trained towards the
+ * product of BRDF, cosine and incident radiance.  Attached to
  * ipt_render_opts.guide with guide_mix = c > 0, every continuation direction
  * is drawn from the mixture with probability c and from the BRDF otherwise,
  * and weighted by the combined density c q + (1 - c) p_brdf (one-sample MIS),
  * so every estimate stays unbiased; c = 0 samples the BRDF only.  A guide
  * attached to the gradient pass (ipt_render_grad / ipt_loss_grad) also makes
- * that pass write training records (vertex features, sampled direction, its
- * density, incident-radiance estimate) for every record_stride-th path into
- * the guide's ring.  The guide does not depend on the unknowns and is not
+ * that pass write training records (vertex features, sampled direction,
+ * estimate of BRDF x cosine x incident radiance over the sampling density)
+ * for every record_stride-th path into the guide's ring.  The guide does not depend on the unknowns and is not
  * differentiated.  Not part of the paper's method (Sec. 3.1 uses BRDF and
  * light sampling); the estimator it feeds is the paper's. */
 typedef struct {
@@ -231,8 +232,10 @@ ipt_status ipt_guide_records(ipt_guide_t guide, int64_t *count);
  *   [4..6]  shading normal (facing the outgoing side), [7] weight L/p,
  *   [8..10] outgoing direction, [11] path index (int32 bits),
  *   [12..14] sampled incident direction, [15] vertex index k >= 1 (int32 bits).
- * L is the luminance of the radiance estimate arriving along the sampled
- * direction and p the combined density it was sampled with. */
+ * The weight is the luminance of f cos L_i / p: the BRDF times the cosine
+ * times the radiance estimate arriving along the sampled direction, over
+ * the combined density it was sampled with (the training target is the
+ * product f cos L_i, which vanishes below the surface). */
 /* Loss -sum_i w_i log q_i / sum_i w_i of n records rec [n][16] (DEVICE), and
  * its gradient grad [16744 + 16 S] (DEVICE) with respect to the float32
  * parameters, through the bfloat16 forward pass; *loss is DEVICE.  Does not

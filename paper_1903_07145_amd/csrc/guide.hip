@@ -3,11 +3,12 @@
 //
 // Training follows the neural-importance-sampling objective (Mueller et al.,
 // "Neural Importance Sampling", 2019): for records (vertex features, sampled
-// direction w_i, its sampling density p_i, incident-radiance estimate L_i)
-// the loss  -sum_i (L_i / p_i) log q(w_i) / sum_i (L_i / p_i)  is a Monte
-// Carlo estimate (up to a constant) of the KL divergence from the normalised
-// incident radiance to the mixture q.  Records come from the gradient pass
-// of the tracer itself (see ipt_render_grad).
+// direction w_i, weight r_i = target(w_i) / p_i with p_i the density it was
+// sampled with) the loss  -sum_i r_i log q(w_i) / sum_i r_i  is a Monte Carlo
+// estimate (up to a constant) of the KL divergence from the normalised target
+// to the mixture q.  The target is the product BRDF x cosine x incident
+// radiance; records come from the gradient pass of the tracer itself (see
+// ipt_render_grad).
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -983,9 +983,10 @@ __global__ __launch_bounds__(256) void guide_records_kernel(PathArgs a) {
         }
         if (dot(ng, wo) < 0.0f) ns = ns * -1.0f;
         float4 dk = a.ck_d[ck];
-        float pdf = a.ck_a[ck].w;
+        float4 av = a.ck_a[ck];  // continuation factor f cos / p (and 1 / q_rr)
         float4 R = a.ck_c[ck];   // R_{k+1} after the sweep
-        float w = lum(v3(R.x, R.y, R.z)) / pdf;
+        // product target f cos L_i: its ratio to the sampling density is a_k R_{k+1}
+        float w = lum(v3(av.x * R.x, av.y * R.y, av.z * R.z));
         if (w > 0.0f && isfinite(w)) {
             unsigned slot = atomicAdd(a.grec_count, 1u) % (unsigned)a.grec_cap;
             float f[9];

@@ -44,9 +44,19 @@ def param_rmse(params, p_true, scale, trainable):
     return float(torch.sqrt(torch.mean(d * d)))
 
 
+def group_rmse(params, p_true, scale, trainable, S):
+    """RMSE per parameter group (diffuse, specular, roughness, emission)."""
+    d = ((params - p_true) / scale).cpu().numpy()
+    t = trainable.cpu().numpy().astype(bool)
+    idx = np.arange(d.size)
+    groups = dict(kd=(idx < 7 * S) & (idx % 7 < 3), ks=(idx < 7 * S) & (idx % 7 >= 3) & (idx % 7 < 6),
+                  alpha=(idx < 7 * S) & (idx % 7 == 6), e=idx >= 7 * S)
+    return {k: float(np.sqrt(np.mean(d[m & t] ** 2))) for k, m in groups.items() if (m & t).any()}
+
+
 def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guide_steps=10, guide_lr=2e-3,
              guide_batch=16384, record_stride=None, target_rmse=1e-2, stop_at_target=False, target=None,
-             g=None, log=None, spp=None):
+             g=None, log=None, spp=None, lr=None, lr_schedule="const"):
     """Runs the optimisation; returns a dict with the RMSE/loss history and timings.
 
     Wall-clock time counts from the first iteration (scene build and target
@@ -54,7 +64,8 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
     cfg = sc["render"]
     iters = iters or cfg["iters"]
     spp = spp or cfg["spp"]
-    D, rr, lr = cfg["max_depth"], cfg["rr_depth"], cfg["lr"]
+    D, rr = cfg["max_depth"], cfg["rr_depth"]
+    lr0 = lr or cfg["lr"]
     g = g or ipt.Scene.from_dict(sc)
     dc = ipt.make_cameras(sc["cams"])
     npix = dc["num_views"] * dc["width"] * dc["height"]
@@ -76,7 +87,7 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         stride = record_stride or max(1, (npix * spp * 3) // (1 << 20))
         gd = ipt.Guide(g, seed=seed, lr=guide_lr, batch=guide_batch, ring_capacity=1 << 21, record_stride=stride)
     g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr, guide=gd, guide_mix=guide_mix if gd else 0.0))
-    hist = dict(it=[], t=[], rmse=[], loss=[], guide_loss=[])
+    hist = dict(it=[], t=[], rmse=[], loss=[], guide_loss=[], groups=[])
     torch.cuda.synchronize()
     t0 = time.time()
     t_hit = None
@@ -86,7 +97,9 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         co = ipt.render_opts(stream_tag=TAG_A, guide=gd if mix > 0 else None, guide_mix=mix, **kw)
         go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, **kw)
         g.loss_grad(dc, params, target, co, go, 0, loss=loss, grad=grad)
-        ipt.sgd_step(params, grad, m, v, it + 1, lr=lr, scale=scale, lo=lo, hi=hi, trainable=tr)
+        # constant, or cosine decay to lr/20 over the run
+        lr_it = lr0 if lr_schedule == "const" else lr0 * (0.05 + 0.95 * 0.5 * (1 + np.cos(np.pi * it / iters)))
+        ipt.sgd_step(params, grad, m, v, it + 1, lr=lr_it, scale=scale, lo=lo, hi=hi, trainable=tr)
         gl = None
         if gd is not None and gd.records() >= guide_batch:
             gl = gd.train(guide_steps, want_loss=(it % 10 == 0))
@@ -97,13 +110,16 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         hist["rmse"].append(r)
         hist["loss"].append(float(loss.cpu()))
         hist["guide_loss"].append(gl)
+        hist["groups"].append(group_rmse(params, p_true, scale, tr, sc["num_segments"])
+                              if (it % 10 == 0 or it == iters - 1) else None)
         if t_hit is None and r <= target_rmse:
             t_hit = t
             if stop_at_target:
                 break
         if log and (it % 10 == 0 or it == iters - 1):
-            log("it %4d  t %7.2fs  loss %.5f  rmse %.4f%s" % (it, t, hist["loss"][-1], r,
-                                                           "" if gl is None else "  guide loss %.4f" % gl))
+            gr = " ".join("%s %.3f" % kv for kv in hist["groups"][-1].items())
+            log("it %4d  t %7.2fs  loss %.5f  rmse %.4f (%s)%s" % (it, t, hist["loss"][-1], r, gr,
+                                                                "" if gl is None else "  guide loss %.4f" % gl))
     return dict(history=hist, time_to_target=t_hit, final_rmse=hist["rmse"][-1], seconds=hist["t"][-1],
                 iters=len(hist["it"]), guide=guide, seed=seed)
 
@@ -118,6 +134,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--guide-steps", type=int, default=10)
     ap.add_argument("--target-rmse", type=float, default=1e-2)
+    ap.add_argument("--lr", type=float, default=None)
+    ap.add_argument("--lr-schedule", default="const", choices=["const", "cos"])
     ap.add_argument("--out", default=None, help="JSON lines file for the histories")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
@@ -131,7 +149,8 @@ def main(argv=None):
     for seed in a.seeds:
         log("workload %s seed %d guide %s" % (a.workload, seed, a.guide))
         res = optimize(sc, iters=a.iters, seed=seed, guide=a.guide, guide_mix=a.guide_mix, warmup=a.warmup,
-                       guide_steps=a.guide_steps, target_rmse=a.target_rmse, target=target, g=g, log=log)
+                       guide_steps=a.guide_steps, target_rmse=a.target_rmse, target=target, g=g, log=log,
+                       lr=a.lr, lr_schedule=a.lr_schedule)
         line = json.dumps(dict(workload=a.workload, **res))
         if a.out:
             with open(a.out, "a") as f:

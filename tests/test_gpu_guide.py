@@ -187,12 +187,15 @@ def test_training_records_match_oracle_paths(cornell):
                 v = V[pi, s, k - 1]
                 if v[0] < 0 or v[15] != 1:
                     break
-                R = (Lf[pi, s] - v[4:7]) / v[8:11]
+                # a_k R_{k+1} = (L - L_k) / T_{k-1}: the part of the path radiance
+                # gathered after vertex k, over the throughput before vertex k
+                T_prev = V[pi, s, k - 2, 8:11] if k > 1 else np.ones(3)
+                aR = (Lf[pi, s] - v[4:7]) / T_prev
                 t = tris[int(v[0])]
                 x = verts[t[0]] + v[1] * (verts[t[1]] - verts[t[0]]) + v[2] * (verts[t[2]] - verts[t[0]])
                 wo = -prev_d if prev_d is not None else (eye - x) / np.linalg.norm(eye - x)
-                if R.mean() > 0:
-                    expect[(pi * spp + s, k)] = (x, wo, v[12:15], R.mean() / v[11])
+                if aR.mean() > 0:
+                    expect[(pi * spp + s, k)] = (x, wo, v[12:15], aR.mean())
                 prev_d = v[12:15]
     ok_paths = keep.reshape(-1)
     got = {(int(p), int(k)): i for i, (p, k) in enumerate(zip(path, kk))}
