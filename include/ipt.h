@@ -110,21 +110,39 @@ typedef struct {
     float scene_diag;
     uint64_t nonfinite_paths; /* paths dropped for a non-finite contribution */
     uint64_t stack_overflows; /* traversals that ran out of stack */
+    int32_t bvh_builder;      /* the ipt_bvh_builder that built the BVH */
 } ipt_scene_info_t;
 
-/* Build a scene: upload geometry, build the BVH (binned SAH, leaves of at
- * most 4 triangles), the leaf-ordered triangle layout and the emitter table.
+/* Where the BVH is built.  Both builders apply the same rule (binned SAH,
+ * 32 slabs per axis, C_trav = C_isect = 1, leaves of at most 4 triangles)
+ * and give the same tree; the host builder is kept as a reference. */
+typedef enum { IPT_BVH_GPU = 0, IPT_BVH_HOST = 1 } ipt_bvh_builder;
+typedef struct {
+    int32_t bvh_builder;      /* an ipt_bvh_builder */
+} ipt_build_opts;
+
+/* Build a scene: upload geometry, build the BVH on the GPU (binned SAH,
+ * leaves of at most 4 triangles), the leaf-ordered triangle layout and the
+ * emitter table, all on hip_stream (the call synchronises it).
  * Inputs are HOST arrays: verts [nv][3], normals [nv][3] or NULL (flat
  * shading), tris [nt][3] vertex indices, tri_seg [nt] segment ids in
  * [0, num_segments), emitter_seg [num_emitters] distinct segment ids.  The
  * triangles of an emitter segment emit; every segment reflects.
  * Sec. 4.2 (per-vertex normals, per-object constant parameters).
  * Errors: IPT_ERR_INVALID_ARG (NULL/size), IPT_ERR_BAD_SCENE (index out of
- * range, non-finite vertex, degenerate emitter triangle, duplicate emitter). */
+ * range, non-finite vertex, degenerate emitter triangle, duplicate emitter),
+ * IPT_ERR_NOT_SUPPORTED (more than 2^27 triangles, or a BVH deeper than the
+ * traversal stack), IPT_ERR_OUT_OF_MEMORY / IPT_ERR_HIP (device). */
 ipt_status ipt_scene_build(const float *verts, int64_t nv, const float *normals,
                            const int32_t *tris, const int32_t *tri_seg, int64_t nt,
                            int32_t num_segments, const int32_t *emitter_seg,
                            int32_t num_emitters, void *hip_stream, ipt_scene_t *out);
+/* ipt_scene_build with build options (NULL = defaults: GPU builder). */
+ipt_status ipt_scene_build_ex(const float *verts, int64_t nv, const float *normals,
+                              const int32_t *tris, const int32_t *tri_seg, int64_t nt,
+                              int32_t num_segments, const int32_t *emitter_seg,
+                              int32_t num_emitters, const ipt_build_opts *opts,
+                              void *hip_stream, ipt_scene_t *out);
 ipt_status ipt_scene_free(ipt_scene_t scene);
 /* Sizes, BVH statistics and device error counters (synchronises). */
 ipt_status ipt_scene_info(ipt_scene_t scene, ipt_scene_info_t *out);

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/ipt.h"
+#include "bvh_gpu.h"
 #include "bvh_host.h"
 #include "ipt_internal.h"
 
@@ -59,7 +60,7 @@ struct ipt_scene_s {
     Counters* d_err = nullptr;
     int* d_ovf_rays = nullptr;   // overflow stacks of ipt_trace_rays
     int64_t nt = 0, nv = 0, nnodes = 0;
-    int S = 0, E = 0, nlt = 0, depth = 0, has_normals = 0;
+    int S = 0, E = 0, nlt = 0, depth = 0, has_normals = 0, bvh_builder = 0;
     double sah = 0.0, build_ms = 0.0;
     float diag = 0.0f;
     float bb_lo[3] = {0, 0, 0}, bb_hi[3] = {0, 0, 0};
@@ -111,11 +112,14 @@ extern "C" ipt_status ipt_scene_free(ipt_scene_t s) {
     return IPT_OK;
 }
 
-extern "C" ipt_status ipt_scene_build(const float* verts, int64_t nv, const float* normals,
-                                      const int32_t* tris, const int32_t* tri_seg, int64_t nt,
-                                      int32_t num_segments, const int32_t* emitter_seg,
-                                      int32_t num_emitters, void* hip_stream, ipt_scene_t* out) {
-    (void)hip_stream;
+extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const float* normals,
+                                         const int32_t* tris, const int32_t* tri_seg, int64_t nt,
+                                         int32_t num_segments, const int32_t* emitter_seg,
+                                         int32_t num_emitters, const ipt_build_opts* bopts, void* hip_stream,
+                                         ipt_scene_t* out) {
+    const int builder = bopts ? bopts->bvh_builder : IPT_BVH_GPU;
+    if (builder != IPT_BVH_GPU && builder != IPT_BVH_HOST) return fail(IPT_ERR_INVALID_ARG, "unknown bvh_builder %d", builder);
+    hipStream_t st = (hipStream_t)hip_stream;
     if (!out) return fail(IPT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!verts || !tris || !tri_seg) return fail(IPT_ERR_INVALID_ARG, "verts/tris/tri_seg is NULL");
@@ -150,16 +154,8 @@ extern "C" ipt_status ipt_scene_build(const float* verts, int64_t nv, const floa
     int64_t P = 7 * (int64_t)num_segments + 3 * (int64_t)num_emitters;
     if (P > 8192) return fail(IPT_ERR_NOT_SUPPORTED, "parameter vector too long (%lld > 8192)", (long long)P);
 
-    auto t0 = std::chrono::steady_clock::now();
-    BvhOut bvh;
-    if (!build_bvh_host(verts, tris, nt, bvh)) return fail(IPT_ERR_BAD_SCENE, "BVH build failed");
-    if (bvh.depth > kShortStack + kOvfDepth)
-        return fail(IPT_ERR_NOT_SUPPORTED, "BVH depth %d exceeds the traversal stack", bvh.depth);
-    auto t1 = std::chrono::steady_clock::now();
 
-    // leaf-ordered triangle records; light table in ascending input-id order
-    std::vector<int> pos_of(nt);
-    for (int64_t p = 0; p < nt; ++p) pos_of[bvh.leaf_order[p]] = (int)p;
+    // emitter table in ascending input-id order (leaf positions filled in on the device)
     std::vector<int4> lights;
     std::vector<int> light_of_tri(nt, -1);
     for (int64_t t = 0; t < nt; ++t) {
@@ -175,29 +171,12 @@ extern "C" ipt_status ipt_scene_build(const float* verts, int64_t nv, const floa
         float area = (float)(0.5 * std::sqrt(cx * cx + cy * cy + cz * cz));
         if (!(area > 0.0f)) return fail(IPT_ERR_BAD_SCENE, "emitter triangle %lld has zero area", (long long)t);
         int4 L;
-        L.x = pos_of[t];
+        L.x = -1;
         L.y = k;
         std::memcpy(&L.z, &area, 4);
         L.w = (int)t;
         light_of_tri[t] = (int)lights.size();
         lights.push_back(L);
-    }
-    std::vector<float4> trec(3 * nt);
-    std::vector<float4> nrec;
-    if (normals) nrec.resize(3 * nt);
-    for (int64_t p = 0; p < nt; ++p) {
-        int t = bvh.leaf_order[p];
-        for (int j = 0; j < 3; ++j) {
-            const float* v = verts + 3 * (int64_t)tris[3 * (int64_t)t + j];
-            int tag = j == 0 ? t : (j == 1 ? tri_seg[t] : light_of_tri[t]);
-            float tf;
-            std::memcpy(&tf, &tag, 4);
-            trec[3 * p + j] = make_float4(v[0], v[1], v[2], tf);
-            if (normals) {
-                const float* n = normals + 3 * (int64_t)tris[3 * (int64_t)t + j];
-                nrec[3 * p + j] = make_float4(n[0], n[1], n[2], 0.0f);
-            }
-        }
     }
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = 0; i < nv; ++i)
@@ -208,39 +187,105 @@ extern "C" ipt_status ipt_scene_build(const float* verts, int64_t nv, const floa
     ipt_scene_t s = new ipt_scene_s();
     HIP_OK(hipGetDevice(&s->device));
     HIP_OK(hipDeviceGetAttribute(&s->num_cu, hipDeviceAttributeMultiprocessorCount, s->device));
-    auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    // inputs on the device for the build (freed before returning)
+    struct Tmp {
+        std::vector<void*> p;
+        ~Tmp() { for (void* q : p) (void)hipFree(q); }
+    } tmp;
+    auto up = [&](void** dst, const void* src, size_t bytes, bool temporary) -> hipError_t {
         hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
         if (e != hipSuccess) return e;
-        if (bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        if (temporary) tmp.p.push_back(*dst);
+        if (bytes) e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, st);
         return e;
     };
+    float* d_verts = nullptr;
+    float* d_vnrm = nullptr;
+    int *d_tris = nullptr, *d_seg = nullptr, *d_lot = nullptr, *d_order = nullptr;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = up((void**)&s->d_nodes, bvh.nodes.data(), bvh.nodes.size() * sizeof(float));
-    if (e == hipSuccess) e = up((void**)&s->d_tris, trec.data(), trec.size() * sizeof(float4));
-    if (e == hipSuccess && normals) e = up((void**)&s->d_nrm, nrec.data(), nrec.size() * sizeof(float4));
-    if (e == hipSuccess) e = up((void**)&s->d_lights, lights.data(), lights.size() * sizeof(int4));
-    if (e == hipSuccess) e = up((void**)&s->d_segemit, seg_emitter.data(), seg_emitter.size() * sizeof(int));
-    if (e == hipSuccess) e = up((void**)&s->d_pos_of, pos_of.data(), pos_of.size() * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc((void**)&s->d_err, sizeof(Counters));
-    if (e == hipSuccess) e = hipMemset(s->d_err, 0, sizeof(Counters));
-    if (e == hipSuccess)
-        e = hipMalloc((void**)&s->d_ovf_rays,
-                      sizeof(int) * (size_t)kOvfDepth * trace_rays_grid(s->num_cu) * kBlock);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = up((void**)&d_verts, verts, sizeof(float) * 3 * nv, true);
+    if (e == hipSuccess) e = up((void**)&d_tris, tris, sizeof(int) * 3 * nt, true);
+    if (e == hipSuccess) e = up((void**)&d_seg, tri_seg, sizeof(int) * nt, true);
+    if (e == hipSuccess) e = up((void**)&d_lot, light_of_tri.data(), sizeof(int) * nt, true);
+    if (e == hipSuccess && normals) e = up((void**)&d_vnrm, normals, sizeof(float) * 3 * nv, true);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         ipt_scene_free(s);
         return fail(e == hipErrorOutOfMemory ? IPT_ERR_OUT_OF_MEMORY : IPT_ERR_HIP, "scene upload: %s",
                     hipGetErrorString(e));
     }
+
+    // BVH: on the device (default) or the host reference builder
+    auto t0 = std::chrono::steady_clock::now();
+    int depth = 0;
+    double sah = 0.0;
+    int64_t nnodes = 0;
+    if (builder == IPT_BVH_GPU) {
+        GpuBvh gb;
+        std::string msg = build_bvh_gpu(d_verts, d_tris, nt, st, gb);
+        if (!msg.empty()) {
+            ipt_scene_free(s);
+            return fail(IPT_ERR_HIP, "%s", msg.c_str());
+        }
+        s->d_nodes = gb.nodes;
+        d_order = gb.leaf_order;
+        tmp.p.push_back(d_order);
+        depth = gb.depth;
+        sah = gb.sah_cost;
+        nnodes = gb.num_nodes;
+    } else {
+        BvhOut bvh;
+        if (!build_bvh_host(verts, tris, nt, bvh)) {
+            ipt_scene_free(s);
+            return fail(IPT_ERR_BAD_SCENE, "BVH build failed");
+        }
+        e = up((void**)&s->d_nodes, bvh.nodes.data(), bvh.nodes.size() * sizeof(float), false);
+        if (e == hipSuccess) e = up((void**)&d_order, bvh.leaf_order.data(), sizeof(int) * nt, true);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            ipt_scene_free(s);
+            return fail(IPT_ERR_HIP, "BVH upload: %s", hipGetErrorString(e));
+        }
+        depth = bvh.depth;
+        sah = bvh.sah_cost;
+        nnodes = bvh.num_nodes;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    if (depth > kShortStack + kOvfDepth) {
+        ipt_scene_free(s);
+        return fail(IPT_ERR_NOT_SUPPORTED, "BVH depth %d exceeds the traversal stack", depth);
+    }
+
+    // leaf-ordered triangle records, shading normals, inverse permutation, light table
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_tris, sizeof(float4) * 3 * nt);
+    if (e == hipSuccess && normals) e = hipMalloc((void**)&s->d_nrm, sizeof(float4) * 3 * nt);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_pos_of, sizeof(int) * std::max<int64_t>(nt, 4));
+    if (e == hipSuccess) e = up((void**)&s->d_lights, lights.data(), lights.size() * sizeof(int4), false);
+    if (e == hipSuccess) e = up((void**)&s->d_segemit, seg_emitter.data(), seg_emitter.size() * sizeof(int), false);
+    if (e == hipSuccess)
+        e = launch_scene_layout(d_verts, d_tris, d_seg, d_lot, d_vnrm, d_order, nt, s->d_tris, s->d_nrm, s->d_pos_of,
+                                s->d_lights, (int)lights.size(), st);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_err, sizeof(Counters));
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_err, 0, sizeof(Counters), st);
+    if (e == hipSuccess)
+        e = hipMalloc((void**)&s->d_ovf_rays,
+                      sizeof(int) * (size_t)kOvfDepth * trace_rays_grid(s->num_cu) * kBlock);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        ipt_scene_free(s);
+        return fail(e == hipErrorOutOfMemory ? IPT_ERR_OUT_OF_MEMORY : IPT_ERR_HIP, "scene layout: %s",
+                    hipGetErrorString(e));
+    }
     s->nt = nt;
     s->nv = nv;
-    s->nnodes = bvh.num_nodes;
+    s->nnodes = nnodes;
     s->S = num_segments;
     s->E = num_emitters;
     s->nlt = (int)lights.size();
-    s->depth = bvh.depth;
+    s->depth = depth;
     s->has_normals = normals != nullptr;
-    s->sah = bvh.sah_cost;
+    s->sah = sah;
+    s->bvh_builder = builder;
     s->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     s->diag = (float)diag;
     for (int a = 0; a < 3; ++a) { s->bb_lo[a] = lo[a]; s->bb_hi[a] = hi[a]; }
@@ -256,6 +301,14 @@ extern "C" ipt_status ipt_scene_build(const float* verts, int64_t nv, const floa
     s->dev.tmin = (float)(1e-6 * diag);
     *out = s;
     return IPT_OK;
+}
+
+extern "C" ipt_status ipt_scene_build(const float* verts, int64_t nv, const float* normals,
+                                      const int32_t* tris, const int32_t* tri_seg, int64_t nt,
+                                      int32_t num_segments, const int32_t* emitter_seg,
+                                      int32_t num_emitters, void* hip_stream, ipt_scene_t* out) {
+    return ipt_scene_build_ex(verts, nv, normals, tris, tri_seg, nt, num_segments, emitter_seg, num_emitters, nullptr,
+                              hip_stream, out);
 }
 
 extern "C" ipt_status ipt_scene_info(ipt_scene_t s, ipt_scene_info_t* out) {
@@ -276,6 +329,7 @@ extern "C" ipt_status ipt_scene_info(ipt_scene_t s, ipt_scene_info_t* out) {
     out->scene_diag = s->diag;
     out->nonfinite_paths = c.nonfinite;
     out->stack_overflows = c.overflow;
+    out->bvh_builder = s->bvh_builder;
     return IPT_OK;
 }
 

@@ -42,6 +42,12 @@ struct BNode {
 constexpr int kBins = 32;
 constexpr int kMaxLeaf = 4;
 
+// Slab of a centroid coordinate, clamped into [0, kBins - 1].
+inline int slab(float c, float lo, float k) {
+    float x = (c - lo) * k;
+    return x >= (float)(kBins - 1) ? kBins - 1 : (x > 0.0f ? (int)x : 0);
+}
+
 }  // namespace
 
 bool build_bvh_host(const float* verts, const int* tris, int64_t nt, BvhOut& out) {
@@ -92,7 +98,7 @@ bool build_bvh_host(const float* verts, const int* tris, int64_t nt, BvhOut& out
             float k = kBins / ext;
             for (int i = tk.first; i < tk.first + tk.count; ++i) {
                 int p = idx[i];
-                int b = std::min(kBins - 1, (int)((cen[3 * (int64_t)p + a] - cb.lo[a]) * k));
+                int b = slab(cen[3 * (int64_t)p + a], cb.lo[a], k);
                 bb[b].grow(pb[p]);
                 bc[b]++;
             }
@@ -123,7 +129,7 @@ bool build_bvh_host(const float* verts, const int* tris, int64_t nt, BvhOut& out
             float k = kBins / ext;
             int a = best_axis;
             auto it = std::partition(idx.begin() + tk.first, idx.begin() + tk.first + tk.count, [&](int p) {
-                int b = std::min(kBins - 1, (int)((cen[3 * (int64_t)p + a] - cb.lo[a]) * k));
+                int b = slab(cen[3 * (int64_t)p + a], cb.lo[a], k);
                 return b <= best_split;
             });
             mid = (int)(it - idx.begin());

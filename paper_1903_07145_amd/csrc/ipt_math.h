@@ -145,13 +145,19 @@ __device__ __forceinline__ bool tri_isect(const Ray& r, V3 p0, V3 p1, V3 p2, flo
 }
 
 // Slab test of one box; returns the entry distance or +inf on a miss.
-__device__ __forceinline__ float box_entry(const Ray& r, V3 lo, V3 hi, float tmin, float tmax) {
+// The exit distance gets a relative slack, so a triangle lying on a box face
+// is never culled.  The bound tmax (the best hit so far) gets an absolute
+// one, slack_abs: the triangle test's t carries an error of the order of the
+// rounding of the scene coordinates, not of t, so without it a flat box
+// could be culled against a hit whose t came out a few ulps of the
+// coordinates short, and a tie between coplanar triangles would be decided
+// by the tree instead of by the tie rule.
+__device__ __forceinline__ float box_entry(const Ray& r, V3 lo, V3 hi, float tmin, float tmax, float slack_abs) {
     float tx0 = (lo.x - r.o.x) * r.inv.x, tx1 = (hi.x - r.o.x) * r.inv.x;
     float ty0 = (lo.y - r.o.y) * r.inv.y, ty1 = (hi.y - r.o.y) * r.inv.y;
     float tz0 = (lo.z - r.o.z) * r.inv.z, tz1 = (hi.z - r.o.z) * r.inv.z;
     float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
-    float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
-    // padded so a triangle lying on the box face is never culled
+    float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax + slack_abs));
     return tn <= tf * 1.0000005f ? tn : __builtin_inff();
 }
 

@@ -169,8 +169,8 @@ __device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax
             const float4* n = sc.nodes + 4 * (size_t)entry;
             float4 n0 = n[0], n1 = n[1], n2 = n[2], n3 = n[3];
             int c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
-            float t0 = box_entry(r, v3(n0.x, n0.y, n0.z), v3(n0.w, n1.x, n1.y), tmin, best.t);
-            float t1 = box_entry(r, v3(n1.z, n1.w, n2.x), v3(n2.y, n2.z, n2.w), tmin, best.t);
+            float t0 = box_entry(r, v3(n0.x, n0.y, n0.z), v3(n0.w, n1.x, n1.y), tmin, best.t, sc.tmin);
+            float t1 = box_entry(r, v3(n1.z, n1.w, n2.x), v3(n2.y, n2.z, n2.w), tmin, best.t, sc.tmin);
             // box_entry returns +inf on a miss; best.t may itself be +inf
             bool h0 = t0 < __builtin_inff();
             bool h1 = (c1 != kNone) && t1 < __builtin_inff();

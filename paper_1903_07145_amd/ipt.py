@@ -19,7 +19,7 @@ IPT_OK = 0
 _STATUS = {0: "IPT_OK", 1: "IPT_ERR_INVALID_ARG", 2: "IPT_ERR_BAD_SCENE", 3: "IPT_ERR_OUT_OF_MEMORY",
            4: "IPT_ERR_WORKSPACE_TOO_SMALL", 5: "IPT_ERR_HIP", 6: "IPT_ERR_NOT_SUPPORTED"}
 
-EXPORTS = ["ipt_scene_build", "ipt_scene_free", "ipt_scene_info", "ipt_workspace_query", "ipt_render",
+EXPORTS = ["ipt_scene_build", "ipt_scene_build_ex", "ipt_scene_free", "ipt_scene_info", "ipt_workspace_query", "ipt_render",
            "ipt_render_grad", "ipt_loss_grad", "ipt_sgd_step", "ipt_trace_rays", "ipt_guide_create",
            "ipt_guide_free", "ipt_guide_eval", "ipt_guide_train", "ipt_guide_weights", "ipt_guide_records",
            "ipt_guide_loss_grad", "ipt_guide_add_records", "ipt_guide_read_records",
@@ -59,7 +59,15 @@ class SceneInfo(ctypes.Structure):
                 ("num_segments", ctypes.c_int32), ("num_emitters", ctypes.c_int32),
                 ("bvh_depth", ctypes.c_int32), ("has_normals", ctypes.c_int32),
                 ("sah_cost", ctypes.c_double), ("build_ms", ctypes.c_double), ("scene_diag", ctypes.c_float),
-                ("nonfinite_paths", ctypes.c_uint64), ("stack_overflows", ctypes.c_uint64)]
+                ("nonfinite_paths", ctypes.c_uint64), ("stack_overflows", ctypes.c_uint64),
+                ("bvh_builder", ctypes.c_int32)]
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("bvh_builder", ctypes.c_int32)]
+
+
+BVH_GPU, BVH_HOST = 0, 1
 
 
 class KernelProfile(ctypes.Structure):
@@ -90,6 +98,7 @@ def lib():
         P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         sig = {
             "ipt_scene_build": [P, I64, P, P, P, I64, I32, P, I32, P, P],
+            "ipt_scene_build_ex": [P, I64, P, P, P, I64, I32, P, I32, P, P, P],
             "ipt_scene_free": [P],
             "ipt_scene_info": [P, P],
             "ipt_workspace_query": [P, P, P, P, P],
@@ -184,7 +193,7 @@ def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=
 class Scene:
     """A built scene on the current device (ipt_scene_build)."""
 
-    def __init__(self, verts, tris, tri_seg, num_segments, emitter_seg, normals=None):
+    def __init__(self, verts, tris, tri_seg, num_segments, emitter_seg, normals=None, bvh_builder=BVH_GPU):
         v = np.ascontiguousarray(verts, np.float32)
         t = np.ascontiguousarray(tris, np.int32)
         s = np.ascontiguousarray(tri_seg, np.int32)
@@ -195,18 +204,19 @@ class Scene:
         self.P = 7 * self.num_segments + 3 * self.num_emitters
         h = ctypes.c_void_p()
         torch.cuda.init()
-        _check(lib().ipt_scene_build(v.ctypes.data_as(ctypes.c_void_p), v.shape[0],
-                                     None if n is None else n.ctypes.data_as(ctypes.c_void_p),
-                                     t.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p),
-                                     t.shape[0], self.num_segments, e.ctypes.data_as(ctypes.c_void_p),
-                                     e.size, _stream(), ctypes.byref(h)))
+        bo = BuildOpts(int(bvh_builder))
+        _check(lib().ipt_scene_build_ex(v.ctypes.data_as(ctypes.c_void_p), v.shape[0],
+                                        None if n is None else n.ctypes.data_as(ctypes.c_void_p),
+                                        t.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p),
+                                        t.shape[0], self.num_segments, e.ctypes.data_as(ctypes.c_void_p),
+                                        e.size, ctypes.byref(bo), _stream(), ctypes.byref(h)))
         self.handle = h
         self._ws = None
 
     @classmethod
-    def from_dict(cls, sc):
+    def from_dict(cls, sc, bvh_builder=BVH_GPU):
         return cls(sc["verts"], sc["tris"], sc["tri_seg"], sc["num_segments"], sc["emitter_seg"],
-                   sc.get("normals"))
+                   sc.get("normals"), bvh_builder=bvh_builder)
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -363,3 +373,55 @@ class Guide:
         c = ctypes.c_int64(0)
         _check(lib().ipt_guide_records(self.handle, ctypes.byref(c)))
         return int(c.value)
+
+
+# ---------------------------------------------------------------------------
+# torch.autograd integration (Sec. 3.3: the gradient is estimated from paths
+# independent of the colour estimate).
+# ---------------------------------------------------------------------------
+class _RenderFn(torch.autograd.Function):
+    """image = ipt_render(params) with stream-A options; the vector-Jacobian
+    product with an image cotangent w is ipt_render_grad(w) with the stream-B
+    options (the adjoint kernel: independent paths replayed from their
+    Philox counters, Eq. 5-6)."""
+
+    @staticmethod
+    def forward(ctx, params, scene, dcams, color_opts, grad_opts, sampling_params):
+        ctx.scene, ctx.dcams, ctx.grad_opts, ctx.sampling_params = scene, dcams, grad_opts, sampling_params
+        ctx.save_for_backward(params)
+        return scene.render(dcams, params.detach().contiguous(), color_opts, sampling_params=sampling_params)
+
+    @staticmethod
+    def backward(ctx, w):
+        (params,) = ctx.saved_tensors
+        g = ctx.scene.render_grad(ctx.dcams, params.detach().contiguous(), w.contiguous().float(), ctx.grad_opts,
+                                  sampling_params=ctx.sampling_params)
+        return g, None, None, None, None, None
+
+
+def render(scene, dcams, params, color_opts, grad_opts, sampling_params=None):
+    """Differentiable image [pixels, 3]: forward by ipt_render (color_opts),
+    backward by ipt_render_grad (grad_opts, an independent stream)."""
+    return _RenderFn.apply(params, scene, dcams, color_opts, grad_opts, sampling_params)
+
+
+class _LossFn(torch.autograd.Function):
+    """loss = ipt_loss_grad(params): the L2 (or L1) image loss of the stream-A
+    estimate against the target; its gradient is the stream-B estimate that
+    the same call computes, scaled by the incoming cotangent."""
+
+    @staticmethod
+    def forward(ctx, params, scene, dcams, target, color_opts, grad_opts, loss_kind):
+        loss, grad = scene.loss_grad(dcams, params.detach().contiguous(), target, color_opts, grad_opts, loss_kind)
+        ctx.save_for_backward(grad)
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return g * grad, None, None, None, None, None, None
+
+
+def loss(scene, dcams, params, target, color_opts, grad_opts, loss_kind=0):
+    """Differentiable scalar image loss (one ipt_loss_grad call)."""
+    return _LossFn.apply(params, scene, dcams, target, color_opts, grad_opts, loss_kind)
