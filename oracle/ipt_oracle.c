@@ -1160,7 +1160,7 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
 int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
                 const double *sampling_params, const orc_opts *o, const double *w,
                 const uint8_t *path_mask, double *image, double *grad, uint64_t *hashes,
-                double *path_L, double *margins, double *conds, double *vertices)
+                double *path_L, double *margins, double *conds, double *vertices, double *gconds)
 {
     const double *sp = sampling_params ? sampling_params : params;
     int64_t P = 7 * (int64_t)s->ns + 3 * (int64_t)s->ne;
@@ -1238,6 +1238,38 @@ int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
                     }
                 }
                 conds[i * o->spp + sidx] = c;
+            }
+            if (gconds && w) {
+                /* The same probe on the path's gradient contribution: the
+                 * largest relative change, under the +-1e-6 perturbation, of
+                 * any of its components that is at least 1e-3 of its largest
+                 * one.  Derivatives of sharp lobes amplify the perturbation
+                 * more than the radiance does. */
+                double *g0 = (double *)calloc((size_t)P, sizeof(double));
+                double *g1 = (double *)calloc((size_t)P, sizeof(double));
+                double L0[3], Lq[3];
+                uint64_t h0, h1;
+                trace_path(&C, org, dir, pid, wc, g0, L0, &h0, NULL);
+                double gmax = 0.0;
+                for (int64_t q = 0; q < P; ++q) gmax = fmax(gmax, fabs(g0[q]));
+                double c = 0.0;
+                for (int k = 0; k < 2 && isfinite(c) && gmax > 0.0; ++k) {
+                    ctx Cp = C;
+                    Cp.pert = k == 0 ? 1e-6 : -1e-6;
+                    Cp.pert_dir = nrm(mk(0.6, -0.48, 0.64));
+                    v3 d2 = nrm(add(dir, scl(Cp.pert_dir, Cp.pert)));
+                    memset(g1, 0, sizeof(double) * (size_t)P);
+                    trace_path(&Cp, org, d2, pid, wc, g1, Lq, &h1, NULL);
+                    if (h1 != h0) { c = INFINITY; break; }
+                    for (int64_t q = 0; q < P; ++q) {
+                        if (fabs(g0[q]) < 1e-3 * gmax) continue;
+                        double r = fabs(g1[q] - g0[q]) / fabs(g0[q]);
+                        if (r > c) c = r;
+                    }
+                }
+                gconds[i * o->spp + sidx] = c;
+                free(g0);
+                free(g1);
             }
             int fin = isfinite(Lp[0]) && isfinite(Lp[1]) && isfinite(Lp[2]);
             if (gp) for (int64_t q = 0; q < P && fin; ++q) if (!isfinite(gp[q])) fin = 0;

@@ -48,7 +48,7 @@ def lib():
         L.orc_scene_num_light_tris.restype = ctypes.c_int64
         L.orc_scene_num_light_tris.argtypes = [P]
         L.orc_run.restype = ctypes.c_int64
-        L.orc_run.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_run.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_ray_triangle.restype = ctypes.c_int
         L.orc_ray_triangle.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double, P]
@@ -235,7 +235,8 @@ class Scene:
         Returns dict(image [npix,3], grad [P] or None, hash [npix,spp] or None,
         path_L, margin [npix,spp] (near-tie margin of each path), cond
         [npix,spp] (relative radiance change when every vertex and direction
-        is perturbed by 1e-6 relative; inf if an event changes), vertices
+        is perturbed by 1e-6 relative; inf if an event changes), gcond (the
+        same for the path's gradient contribution, when w is given), vertices
         [npix,spp,D+1,16] (per vertex: triangle id, u, v, t, radiance so far
         after its emission and light sample, light flag; for a vertex that
         continues: product of continuation weights up to it (RGB), density
@@ -266,8 +267,9 @@ class Scene:
         mg = np.zeros((npix, spp)) if want_margin else None
         cd = np.zeros((npix, spp)) if want_cond else None
         vx = np.zeros((npix, spp, max_depth + 1, 16)) if want_vertices else None
+        gcd = np.zeros((npix, spp)) if (want_cond and ww is not None) else None
         dropped = lib().orc_run(self.h, ctypes.byref(C), _ptr(p), _ptr(sp), ctypes.byref(O),
                                 _ptr(ww), _ptr(pm), _ptr(img), _ptr(grad), _ptr(hsh), _ptr(pL),
-                                _ptr(mg), _ptr(cd), _ptr(vx))
+                                _ptr(mg), _ptr(cd), _ptr(vx), _ptr(gcd))
         return dict(image=img, grad=grad, hash=hsh, path_L=pL, margin=mg, cond=cd, vertices=vx,
-                    dropped=int(dropped))
+                    gcond=gcd, dropped=int(dropped))

@@ -365,7 +365,7 @@ static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Plan {
     int grid = 0;
     size_t off_counters = 0, off_cdf = 0, off_loss = 0, off_w = 0, off_img = 0, off_gpart = 0, off_ovf = 0,
-           off_ck = 0, end_fixed = 0;
+           off_part = 0, off_ck = 0, end_fixed = 0;
     int64_t chunk = 0;         // work pixels per gradient chunk
     size_t ck_per_pixel = 0;   // checkpoint bytes per work pixel
 };
@@ -378,6 +378,17 @@ static int path_grid(const ipt_scene_s* s, int P, int frozen, int guided) {
     return s->num_cu * occ;
 }
 
+// Samples per work unit.  With fewer than two pixels per lane of the grid a
+// pixel's samples are split over ceil(2 lanes / pixels) lanes (at most spp),
+// so a small image with many samples per pixel still fills the GPU.
+static void split_samples(int64_t npix, int spp, int grid, int& spc, int& nchunk) {
+    const int64_t lanes = (int64_t)grid * kBlock;
+    nchunk = 1;
+    if (npix < 2 * lanes && spp > 1) nchunk = (int)std::min<int64_t>(spp, (2 * lanes + npix - 1) / npix);
+    spc = (spp + nchunk - 1) / nchunk;
+    nchunk = (spp + spc - 1) / spc;
+}
+
 static void make_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t npix, bool with_loss, Plan& pl) {
     int P = 7 * s->S + 3 * s->E;
     const int guided = o->guide != nullptr;
@@ -388,8 +399,11 @@ static void make_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t np
     pl.off_loss = off; off = al256(off + sizeof(float) * 1024);
     pl.off_w = off; off = al256(off + (with_loss ? sizeof(float) * 3 * npix : 0));
     pl.off_img = off; off = al256(off + (with_loss ? sizeof(float) * 3 * npix : 0));
-    pl.off_gpart = off; off = al256(off + sizeof(float) * (size_t)pl.grid * P);
+    pl.off_gpart = off; off = al256(off + sizeof(double) * (size_t)pl.grid * P);
     pl.off_ovf = off; off = al256(off + sizeof(int) * (size_t)kOvfDepth * pl.grid * kBlock);
+    // colour sample sums when pixels are split over lanes: nchunk * npix <= 2 lanes + npix
+    const int64_t lanes = (int64_t)pl.grid * kBlock;
+    pl.off_part = off; off = al256(off + (npix < 2 * lanes ? sizeof(float) * 3 * (size_t)(2 * lanes + npix) : 0));
     pl.off_ck = off;
     pl.end_fixed = off;
     pl.ck_per_pixel = (size_t)(o->max_depth + 1) * o->spp * (sizeof(int4) + (guided ? 3 : 2) * sizeof(float4));
@@ -445,7 +459,7 @@ static PathArgs base_args(const ipt_scene_s* s, const ipt_cameras* cams, const f
     a.work = (unsigned*)(ws + pl.off_counters);
     a.err = s->d_err;
     a.ovf = (int*)(ws + pl.off_ovf);
-    a.grad_part = (float*)(ws + pl.off_gpart);
+    a.grad_part = (double*)(ws + pl.off_gpart);
     a.replay_traverse = o->replay_traverse;
     a.guided = o->guide != nullptr;
     a.gmix = a.guided ? o->guide_mix : 0.0f;
@@ -461,11 +475,14 @@ static ipt_status do_render(ipt_scene_t s, const ipt_cameras* cams, const float*
     a.image = image;
     a.pix_begin = 0;
     a.pix_count = npix;
+    split_samples(npix, o->spp, pl.grid, a.spc, a.nchunk);
+    a.part = a.nchunk > 1 ? (float*)(ws + pl.off_part) : nullptr;
     HIP_OK(launch_light_cdf(s->dev, a.sparams, (float*)(ws + pl.off_cdf), st));
     HIP_OK(launch_zero_u32(a.work, 1, st));
     size_t lds = path_lds_bytes(kColor, a.P, a.frozen, s->S, s->nlt, a.guided && a.gmix > 0.0f);
-    int grid = std::min<int64_t>(pl.grid, (npix + kBlock - 1) / kBlock);
+    int grid = (int)std::min<int64_t>(pl.grid, (npix * a.nchunk + kBlock - 1) / kBlock);
     HIP_OK(timed_launch(s, kColor, a, std::max(1, grid), lds, st));
+    if (a.nchunk > 1) HIP_OK(launch_colour_reduce(a.part, a.nchunk, npix, o->spp, image, st));
     return IPT_OK;
 }
 
@@ -474,6 +491,7 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
                           size_t ws_bytes, const Plan& pl, hipStream_t st) {
     PathArgs a = base_args(s, cams, params, sp, o, ws, pl);
     a.w = w;
+    split_samples(npix, o->spp, pl.grid, a.spc, a.nchunk);
     // chunk size from the space left for checkpoints
     size_t avail = ws_bytes > pl.end_fixed + 4 * 256 ? ws_bytes - pl.end_fixed - 4 * 256 : 0;
     int64_t chunk = (int64_t)(avail / pl.ck_per_pixel);
@@ -498,7 +516,7 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
     for (int64_t b = 0; b < npix; b += chunk) {
         a.pix_begin = b;
         a.pix_count = std::min<int64_t>(chunk, npix - b);
-        int grid = (int)std::max<int64_t>(1, std::min<int64_t>(pl.grid, (a.pix_count + kBlock - 1) / kBlock));
+        int grid = (int)std::max<int64_t>(1, std::min<int64_t>(pl.grid, (a.pix_count * a.nchunk + kBlock - 1) / kBlock));
         HIP_OK(launch_zero_u32(a.work, 1, st));
         HIP_OK(timed_launch(s, kGradFwd, a, grid, lds_f, st));
         if (a.guided) HIP_OK(launch_guide_records(a, st));

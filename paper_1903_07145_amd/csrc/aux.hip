@@ -125,16 +125,35 @@ hipError_t launch_loss_adjoint(const float* img, const float* target, int64_t n3
 }
 
 // grad[i] (+)= sum_b part[b][i], in block order (deterministic).
-__global__ __launch_bounds__(256) void grad_reduce_kernel(const float* part, int nblocks, int P, float* grad,
+// Pixel means from the per-unit sample sums of a colour pass whose pixels were
+// split over several lanes (fixed summation order: deterministic).
+__global__ __launch_bounds__(256) void colour_reduce_kernel(const float* part, int nchunk, int64_t pix_count,
+                                                            float inv_spp, float* image) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= 3 * pix_count) return;
+    float s = 0.0f;
+    for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * 3 * pix_count + i];
+    image[i] = s * inv_spp;
+}
+
+hipError_t launch_colour_reduce(const float* part, int nchunk, int64_t pix_count, int spp, float* image,
+                                hipStream_t st) {
+    int64_t n = 3 * pix_count;
+    hipLaunchKernelGGL(colour_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, nchunk,
+                       pix_count, 1.0f / (float)spp, image);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void grad_reduce_kernel(const double* part, int nblocks, int P, float* grad,
                                                           int accumulate) {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= P) return;
-    float s = 0.0f;
+    double s = 0.0;
     for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * P + i];
-    grad[i] = accumulate ? grad[i] + s : s;
+    grad[i] = accumulate ? (float)((double)grad[i] + s) : (float)s;
 }
 
-hipError_t launch_grad_reduce(const float* part, int nblocks, int P, float* grad, int accumulate,
+hipError_t launch_grad_reduce(const double* part, int nblocks, int P, float* grad, int accumulate,
                               hipStream_t st) {
     hipLaunchKernelGGL(grad_reduce_kernel, dim3((P + 255) / 256), dim3(256), 0, st, part, nblocks, P,
                        grad, accumulate);

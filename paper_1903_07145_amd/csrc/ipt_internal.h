@@ -62,7 +62,12 @@ struct PathArgs {
     int spp, D, rr_depth, mis, profile, jitter;
     const int64_t* pixel_list;
     int64_t pix_begin, pix_count;  // work-pixel chunk
+    // work unit = (sample chunk c, work pixel q): samples [c spc, min(spp, (c+1) spc))
+    // of pixel q; unit index c * pix_count + q.  nchunk > 1 when the pixels are
+    // too few to fill the grid one pixel per lane.
+    int spc, nchunk;
     float* image;                  // colour: [pixels][3]
+    float* part;                   // colour, nchunk > 1: per-unit sums [nchunk][pix_count][3]
     uint64_t* hash;                // [pixels*spp] or NULL
     float* path_L;                 // colour: [pixels*spp][3] per-path radiance or NULL
     float* dbg_vtx;                // colour: [pixels*spp][D+1][8] per-vertex record or NULL
@@ -71,7 +76,7 @@ struct PathArgs {
     float4* ck_a;
     float4* ck_c;
     const float* w;                // replay: adjoint image [pixels][3]
-    float* grad_part;              // replay: [gridDim.x][P]
+    double* grad_part;             // replay: [gridDim.x][P]
     unsigned* work;                // dynamic tile counter (zeroed before launch)
     Counters* err;
     int* ovf;                      // [kOvfDepth][grid threads]
@@ -99,7 +104,9 @@ hipError_t launch_light_cdf(const SceneDev& sc, const float* sparams, float* cdf
 hipError_t launch_loss_adjoint(const float* img, const float* target, int64_t n3, int kind,
                                float* w, float* partials, int nparts, float* loss,
                                hipStream_t st);
-hipError_t launch_grad_reduce(const float* part, int nblocks, int P, float* grad, int accumulate,
+hipError_t launch_colour_reduce(const float* part, int nchunk, int64_t pix_count, int spp, float* image,
+                                hipStream_t st);
+hipError_t launch_grad_reduce(const double* part, int nblocks, int P, float* grad, int accumulate,
                               hipStream_t st);
 hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int P, int step,
                        float lr, float b1, float b2, float eps, const float* scale,

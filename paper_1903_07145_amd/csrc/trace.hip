@@ -39,7 +39,7 @@ struct Lds {
     int* seg_emitter;
     float* cdf;
     int4* lights;
-    float* grad;
+    double* grad;       // replay: block gradient, float64 (the terms of some entries cancel)
     int* stack;
     bool lights_in_lds;
 };
@@ -54,7 +54,7 @@ size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guided) {
     if (frozen) b += al(sizeof(float) * P);           // sampling params
     b += al(sizeof(int) * S);                         // segment -> emitter
     if (nlt <= kMaxLdsLights) b += al(sizeof(float) * nlt) + al(sizeof(int4) * nlt);
-    if (mode == kReplay) b += al(sizeof(float) * P);  // block gradient
+    if (mode == kReplay) b += al(sizeof(double) * P); // block gradient
     b += sizeof(int) * kShortStack * kBlock;          // short stacks
     if (guided && mode != kReplay) b += kGuideLds;     // guide activations
     return b;
@@ -76,14 +76,14 @@ __device__ void carve_lds(const PathArgs& a, int mode, unsigned char* smem, Lds&
         lds.lights = (int4*)p; p += al(sizeof(int4) * a.sc.nlt);
     }
     lds.grad = nullptr;
-    if (mode == kReplay) { lds.grad = (float*)p; p += al(sizeof(float) * a.P); }
+    if (mode == kReplay) { lds.grad = (double*)p; p += al(sizeof(double) * a.P); }
     lds.stack = (int*)p;
     p += sizeof(int) * kShortStack * kBlock;
     lds.gact = (__bf16*)p + (threadIdx.x >> 6) * 64 * kGRowStride;
     for (int i = tid; i < a.P; i += kBlock) {
         lds.params[i] = a.params[i];
         if (a.frozen) lds.sparams[i] = a.sparams[i];
-        if (mode == kReplay) lds.grad[i] = 0.0f;
+        if (mode == kReplay) lds.grad[i] = 0.0;
     }
     for (int i = tid; i < a.sc.S; i += kBlock) lds.seg_emitter[i] = a.sc.seg_emitter[i];
     if (lds.lights_in_lds)
@@ -256,8 +256,8 @@ __device__ __forceinline__ void camera_ray(const PathArgs& a, int view, float px
     d = normalize(dw);
 }
 
-__device__ __forceinline__ void lds_add(float* g, int i, float x) {
-    if (x != 0.0f) atomicAdd(g + i, x);
+__device__ __forceinline__ void lds_add(double* g, int i, float x) {
+    if (x != 0.0f) atomicAdd(g + i, (double)x);
 }
 
 // ---------------------------------------------------------------------------
@@ -498,9 +498,10 @@ __global__ __launch_bounds__(kBlock) IPT_OCC void path_sm_kernel(PathArgs a) {
     uint32_t npaths = 0;
 
     int ph = kNeedPixel;
-    // pixel state
-    int64_t q = 0, wi = 0, pix = 0;
-    int view = 0, px = 0, py = 0, s = 0;
+    // work-unit state
+    int64_t q = 0, wi = 0, pix = 0, unit = 0;
+    int view = 0, px = 0, py = 0, s = 0, s_end = 0;
+    const int64_t nunits = a.pix_count * a.nchunk;
     V3 acc = v3(0.0f, 0.0f, 0.0f);
     // path state: k = index of the vertex last processed
     uint64_t pid = 0, h = 0;
@@ -545,24 +546,28 @@ __global__ __launch_bounds__(kBlock) IPT_OCC void path_sm_kernel(PathArgs a) {
             base = __shfl(base, first);
             if (ph == kNeedPixel) {
                 unsigned rank = (unsigned)__popcll(need & ((1ull << lane) - 1ull));
-                q = (int64_t)base + rank;
-                if (q >= a.pix_count) {
+                unit = (int64_t)base + rank;
+                if (unit >= nunits) {
                     ph = kExit;
                 } else {
+                    const int c = (int)(unit / a.pix_count);
+                    q = unit - (int64_t)c * a.pix_count;
+                    s = c * a.spc;
+                    s_end = min(a.spp, s + a.spc);
                     wi = a.pix_begin + q;
                     pix = a.pixel_list ? a.pixel_list[wi] : wi;
                     if (pix < 0 || pix >= npix_img) {
                         if (MODE == kColor) {
-                            a.image[3 * wi] = 0.0f;
-                            a.image[3 * wi + 1] = 0.0f;
-                            a.image[3 * wi + 2] = 0.0f;
+                            float* out = a.nchunk > 1 ? a.part + 3 * (size_t)unit : a.image + 3 * wi;
+                            out[0] = 0.0f;
+                            out[1] = 0.0f;
+                            out[2] = 0.0f;
                         }
                     } else {
                         view = (int)(pix / ((int64_t)a.W * a.H));
                         int64_t rem = pix - (int64_t)view * a.W * a.H;
                         py = (int)(rem / a.W);
                         px = (int)(rem - (int64_t)py * a.W);
-                        s = 0;
                         acc = v3(0.0f, 0.0f, 0.0f);
                         start_path();
                     }
@@ -759,14 +764,21 @@ __global__ __launch_bounds__(kBlock) IPT_OCC void path_sm_kernel(PathArgs a) {
             }
             if (a.hash) a.hash[pidx] = h;
             ++s;
-            if (s < a.spp) {
+            if (s < s_end) {
                 start_path();
             } else {
                 if (MODE == kColor) {
-                    float inv = 1.0f / (float)a.spp;
-                    a.image[3 * wi] = acc.x * inv;
-                    a.image[3 * wi + 1] = acc.y * inv;
-                    a.image[3 * wi + 2] = acc.z * inv;
+                    if (a.nchunk > 1) {   // sample sum of this unit; the reduce pass forms the mean
+                        float* out = a.part + 3 * (size_t)unit;
+                        out[0] = acc.x;
+                        out[1] = acc.y;
+                        out[2] = acc.z;
+                    } else {
+                        float inv = 1.0f / (float)a.spp;
+                        a.image[3 * wi] = acc.x * inv;
+                        a.image[3 * wi + 1] = acc.y * inv;
+                        a.image[3 * wi + 2] = acc.z * inv;
+                    }
                 }
                 ph = kNeedPixel;
             }
@@ -898,13 +910,17 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     const int64_t npix_img = (int64_t)a.V * a.W * a.H;
     Work wk{0u, 0u, 0u, 0u};
     uint32_t npaths = 0;
+    const int64_t nunits = a.pix_count * a.nchunk;
     while (true) {
         if (tid == 0) tile_sh = atomicAdd(a.work, 1u);
         __syncthreads();
-        int64_t q = (int64_t)tile_sh * kBlock + tid;
+        int64_t unit = (int64_t)tile_sh * kBlock + tid;
         __syncthreads();
-        if ((int64_t)tile_sh * kBlock >= a.pix_count) break;
-        if (q >= a.pix_count) continue;
+        if ((int64_t)tile_sh * kBlock >= nunits) break;
+        if (unit >= nunits) continue;
+        const int c = (int)(unit / a.pix_count);
+        const int64_t q = unit - (int64_t)c * a.pix_count;
+        const int s_begin = c * a.spc, s_end = min(a.spp, s_begin + a.spc);
         int64_t wi = a.pix_begin + q;
         int64_t pix = a.pixel_list ? a.pixel_list[wi] : wi;
         if (pix < 0 || pix >= npix_img) continue;
@@ -913,7 +929,7 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
         int py = (int)(rem / a.W), px = (int)(rem - (int64_t)py * a.W);
         float inv = 1.0f / (float)a.spp;
         V3 wpix = v3(a.w[3 * wi] * inv, a.w[3 * wi + 1] * inv, a.w[3 * wi + 2] * inv);
-        for (int s = 0; s < a.spp; ++s) {
+        for (int s = s_begin; s < s_end; ++s) {
             uint64_t pid = (uint64_t)pix * (uint64_t)a.spp + (uint64_t)s;
             size_t pidx = (size_t)wi * a.spp + s;
             if (a.mask && a.mask[pidx] == 0) continue;
@@ -928,7 +944,7 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     if (st.overflow) atomicAdd(&a.err->overflow, 1ull);
     flush_stats(a, kReplay, wk, npaths);
     __syncthreads();
-    float* out = a.grad_part + (size_t)blockIdx.x * a.P;
+    double* out = a.grad_part + (size_t)blockIdx.x * a.P;
     for (int i = tid; i < a.P; i += kBlock) out[i] = lds.grad[i];
 }
 

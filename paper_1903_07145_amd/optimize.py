@@ -37,6 +37,60 @@ def render_target(g, dc, p_true, spp_total, D, rr, seed=1, chunk=16):
     return target
 
 
+def coverage(g, sc):
+    """Pixels per segment hit by the pixel-centre camera rays of every view
+    (ipt_trace_rays)."""
+    cams = sc["cams"]
+    W, H = int(cams["width"]), int(cams["height"])
+    c2w = np.asarray(cams["cam_to_world"], np.float64)
+    fov = np.asarray(cams["fov_y"], np.float64).reshape(-1)
+    seg_of = torch.as_tensor(sc["tri_seg"], dtype=torch.int64, device="cuda")
+    cov = torch.zeros(sc["num_segments"], dtype=torch.int64, device="cuda")
+    ys, xs = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    for v in range(c2w.shape[0]):
+        t = np.tan(0.5 * fov[v])
+        d = np.stack([(2 * xs / W - 1) * t * W / H, (1 - 2 * ys / H) * t, -np.ones_like(xs)], -1).reshape(-1, 3)
+        d = d @ c2w[v, :3, :3].T
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        o = np.ascontiguousarray(np.broadcast_to(c2w[v, :3, 3], d.shape))
+        tri, _ = g.trace_rays(torch.as_tensor(o, dtype=torch.float32, device="cuda").contiguous(),
+                              torch.as_tensor(d, dtype=torch.float32, device="cuda").contiguous())
+        hit = tri >= 0
+        cov += torch.bincount(seg_of[tri[hit].long()], minlength=sc["num_segments"])
+    return cov.cpu().numpy()
+
+
+def identifiable_masks(sc, cov, min_pixels=100, min_ks=0.05, min_emitter_pixels=16):
+    """Which trainable parameters the images determine.
+
+    kd_e: the diffuse albedo of every non-emitting segment seen in at least
+    min_pixels pixels, and the emission of every emitter seen directly in at
+    least min_emitter_pixels pixels (an emitter's own reflectance is
+    negligible next to its emission).
+    This is the set the headline RMSE is taken over: the quantities the
+    paper's evaluation reports (albedo and emission).
+    all_id: kd_e plus specular reflectance of the seen segments, and their
+    roughness where the true specular reflectance (mean RGB) is >= min_ks."""
+    S = sc["num_segments"]
+    P = sc["params"].size
+    tr = sc["trainable"].astype(bool)
+    emit = set(int(x) for x in sc["emitter_seg"])
+    kd_e = np.zeros(P, bool)
+    all_id = np.zeros(P, bool)
+    for s in range(S):
+        if cov[s] < min_pixels or s in emit:
+            continue
+        kd_e[7 * s:7 * s + 3] = True
+        all_id[7 * s:7 * s + 6] = True
+        if sc["params"][7 * s + 3:7 * s + 6].mean() >= min_ks:
+            all_id[7 * s + 6] = True
+    for k, s in enumerate(sc["emitter_seg"]):
+        if cov[s] >= min_emitter_pixels:
+            kd_e[7 * S + 3 * k:7 * S + 3 * k + 3] = True
+            all_id[7 * S + 3 * k:7 * S + 3 * k + 3] = True
+    return kd_e & tr, all_id & tr
+
+
 def param_rmse(params, p_true, scale, trainable):
     """RMSE of the normalised trainable parameters."""
     m = trainable.bool()
@@ -56,17 +110,24 @@ def group_rmse(params, p_true, scale, trainable, S):
 
 def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guide_steps=10, guide_lr=2e-3,
              guide_batch=16384, record_stride=None, target_rmse=1e-2, stop_at_target=False, target=None,
-             g=None, log=None, spp=None, lr=None, lr_schedule="const"):
+             g=None, log=None, spp=None, lr=None, lr_schedule="const", masks=None, lr_final=None, log_every=10):
     """Runs the optimisation; returns a dict with the RMSE/loss history and timings.
 
-    Wall-clock time counts from the first iteration (scene build and target
-    render excluded) and includes guide training in the guided arm."""
+    The time to target is taken on the RMSE over masks[0] (identifiable
+    albedo and emission, see identifiable_masks); the RMSE over every
+    trainable parameter and over masks[1] is recorded beside it.  Wall-clock
+    time counts from the first iteration (scene build and target render
+    excluded) and includes guide training in the guided arm."""
     cfg = sc["render"]
     iters = iters or cfg["iters"]
     spp = spp or cfg["spp"]
     D, rr = cfg["max_depth"], cfg["rr_depth"]
     lr0 = lr or cfg["lr"]
     g = g or ipt.Scene.from_dict(sc)
+    if masks is None:
+        masks = identifiable_masks(sc, coverage(g, sc))
+    m_head = torch.as_tensor(masks[0].astype(np.uint8), device="cuda")
+    m_id = torch.as_tensor(masks[1].astype(np.uint8), device="cuda")
     dc = ipt.make_cameras(sc["cams"])
     npix = dc["num_views"] * dc["width"] * dc["height"]
     p_true = torch.as_tensor(sc["params"], device="cuda")
@@ -87,7 +148,7 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         stride = record_stride or max(1, (npix * spp * 3) // (1 << 20))
         gd = ipt.Guide(g, seed=seed, lr=guide_lr, batch=guide_batch, ring_capacity=1 << 21, record_stride=stride)
     g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr, guide=gd, guide_mix=guide_mix if gd else 0.0))
-    hist = dict(it=[], t=[], rmse=[], loss=[], guide_loss=[], groups=[])
+    hist = dict(it=[], t=[], rmse=[], rmse_all=[], rmse_id=[], loss=[], guide_loss=[], groups=[])
     torch.cuda.synchronize()
     t0 = time.time()
     t_hit = None
@@ -97,31 +158,39 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         co = ipt.render_opts(stream_tag=TAG_A, guide=gd if mix > 0 else None, guide_mix=mix, **kw)
         go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, **kw)
         g.loss_grad(dc, params, target, co, go, 0, loss=loss, grad=grad)
-        # constant, or cosine decay to lr/20 over the run
-        lr_it = lr0 if lr_schedule == "const" else lr0 * (0.05 + 0.95 * 0.5 * (1 + np.cos(np.pi * it / iters)))
+        # constant, or cosine decay from lr0 to lr_final (default lr0/20) over the run
+        lr_end = lr_final if lr_final is not None else lr0 / 20
+        lr_it = lr0 if lr_schedule == "const" else lr_end + (lr0 - lr_end) * 0.5 * (1 + np.cos(np.pi * it / iters))
         ipt.sgd_step(params, grad, m, v, it + 1, lr=lr_it, scale=scale, lo=lo, hi=hi, trainable=tr)
         gl = None
         if gd is not None and gd.records() >= guide_batch:
             gl = gd.train(guide_steps, want_loss=(it % 10 == 0))
-        r = param_rmse(params, p_true, scale, tr)   # synchronises
+        r = param_rmse(params, p_true, scale, m_head)   # synchronises
         t = time.time() - t0
         hist["it"].append(it)
         hist["t"].append(t)
         hist["rmse"].append(r)
+        hist["rmse_all"].append(param_rmse(params, p_true, scale, tr))
+        hist["rmse_id"].append(param_rmse(params, p_true, scale, m_id))
         hist["loss"].append(float(loss.cpu()))
         hist["guide_loss"].append(gl)
         hist["groups"].append(group_rmse(params, p_true, scale, tr, sc["num_segments"])
-                              if (it % 10 == 0 or it == iters - 1) else None)
+                              if (it % log_every == 0 or it == iters - 1) else None)
         if t_hit is None and r <= target_rmse:
             t_hit = t
             if stop_at_target:
                 break
-        if log and (it % 10 == 0 or it == iters - 1):
+        if log and (it % log_every == 0 or it == iters - 1):
             gr = " ".join("%s %.3f" % kv for kv in hist["groups"][-1].items())
-            log("it %4d  t %7.2fs  loss %.5f  rmse %.4f (%s)%s" % (it, t, hist["loss"][-1], r, gr,
-                                                                "" if gl is None else "  guide loss %.4f" % gl))
-    return dict(history=hist, time_to_target=t_hit, final_rmse=hist["rmse"][-1], seconds=hist["t"][-1],
-                iters=len(hist["it"]), guide=guide, seed=seed)
+            log("it %4d  t %7.2fs  loss %.5f  rmse %.4f (all %.4f, identifiable %.4f; %s)%s" % (
+                it, t, hist["loss"][-1], r, hist["rmse_all"][-1], hist["rmse_id"][-1], gr,
+                "" if gl is None else "  guide loss %.4f" % gl))
+    err = ((params - p_true) / scale).cpu().numpy()
+    worst = [(int(i), float(err[i])) for i in np.argsort(-np.abs(err * masks[0]))[:8]]
+    return dict(history=hist, time_to_target=t_hit, final_rmse=hist["rmse"][-1],
+                final_rmse_all=hist["rmse_all"][-1], final_rmse_id=hist["rmse_id"][-1], seconds=hist["t"][-1],
+                iters=len(hist["it"]), guide=guide, seed=seed, n_head=int(masks[0].sum()),
+                n_id=int(masks[1].sum()), worst=worst)
 
 
 def main(argv=None):
@@ -135,6 +204,10 @@ def main(argv=None):
     ap.add_argument("--guide-steps", type=int, default=10)
     ap.add_argument("--target-rmse", type=float, default=1e-2)
     ap.add_argument("--lr", type=float, default=None)
+    ap.add_argument("--spp", type=int, default=None)
+    ap.add_argument("--lr-final", type=float, default=None)
+    ap.add_argument("--target-spp", type=int, default=None)
+    ap.add_argument("--log-every", type=int, default=10)
     ap.add_argument("--lr-schedule", default="const", choices=["const", "cos"])
     ap.add_argument("--out", default=None, help="JSON lines file for the histories")
     a = ap.parse_args(argv)
@@ -143,20 +216,27 @@ def main(argv=None):
     g = ipt.Scene.from_dict(sc)
     dc = ipt.make_cameras(sc["cams"])
     cfg = sc["render"]
-    target = render_target(g, dc, torch.as_tensor(sc["params"], device="cuda"), cfg["target_spp"],
+    target = render_target(g, dc, torch.as_tensor(sc["params"], device="cuda"), a.target_spp or cfg["target_spp"],
                            cfg["max_depth"], cfg["rr_depth"])
     log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
+    cov = coverage(g, sc)
+    masks = identifiable_masks(sc, cov)
+    log("coverage: %d of %d segments seen in >= 100 pixels; emitter pixels: %s; headline set %d params, "
+        "identifiable %d of %d trainable" % ((cov >= 100).sum(), cov.size, cov[sc["emitter_seg"]].tolist(),
+                                              masks[0].sum(), masks[1].sum(), sc["trainable"].sum()))
     for seed in a.seeds:
         log("workload %s seed %d guide %s" % (a.workload, seed, a.guide))
         res = optimize(sc, iters=a.iters, seed=seed, guide=a.guide, guide_mix=a.guide_mix, warmup=a.warmup,
                        guide_steps=a.guide_steps, target_rmse=a.target_rmse, target=target, g=g, log=log,
-                       lr=a.lr, lr_schedule=a.lr_schedule)
+                       lr=a.lr, lr_schedule=a.lr_schedule, masks=masks, spp=a.spp, lr_final=a.lr_final,
+                       log_every=a.log_every)
         line = json.dumps(dict(workload=a.workload, **res))
         if a.out:
             with open(a.out, "a") as f:
                 f.write(line + "\n")
-        log("seed %d: final rmse %.4f after %d iters in %.1fs; time to %.0e: %s" % (
-            seed, res["final_rmse"], res["iters"], res["seconds"], a.target_rmse, res["time_to_target"]))
+        log("seed %d: final rmse %.4f (all %.4f, identifiable %.4f) after %d iters in %.1fs; time to %.0e: %s; "
+            "worst %s" % (seed, res["final_rmse"], res["final_rmse_all"], res["final_rmse_id"], res["iters"],
+                          res["seconds"], a.target_rmse, res["time_to_target"], res["worst"]))
 
 
 if __name__ == "__main__":

@@ -356,6 +356,7 @@ def _building(name, seed, grid, room, n_objects, target_tris, S, E, n_views, W, 
             b.cylinder(o[1], o[2], o[3], o[4], nr, nh)
     # emitters: ceiling quads 1e-3*height below the ceiling, facing down
     emitter_seg = []
+    emitter_pos = []
     for kk in range(E):
         ix, iz = rooms[kk % len(rooms)]
         j = kk // len(rooms)
@@ -365,17 +366,31 @@ def _building(name, seed, grid, room, n_objects, target_tris, S, E, n_views, W, 
         ez = iz * rd + rd * rng.uniform(0.3, 0.7)
         b.quad([ex, rh * (1 - 1e-3), ez], [0, -1, 0], [0.3, 0, 0], [0, 0, 0.3], emit_seg0 + kk)
         emitter_seg.append(emit_seg0 + kk)
+        emitter_pos.append((ex, ez))
     params, scale, lo, hi, tr = _param_vectors(S, E, emitter_seg, rng, (0.05, 0.9), (0.0, 0.3),
                                                (0.05, 0.8), (2.0, 20.0), False, 20.0)
-    # cameras: eye height 1.6 inside a room, away from objects, looking across it
+    # cameras: eye height 1.6 inside a room, away from objects.  The j-th view
+    # of a room with an emitter still unseen looks up towards that emitter from
+    # at least 2.6 m away (so every emitter is seen directly); the others look
+    # across the room.
+    room_emitters = {r: [] for r in range(len(rooms))}
+    for kk in range(E):
+        room_emitters[kk % len(rooms)].append(emitter_pos[kk])
     c2w = []
     for vi in range(n_views):
-        ix, iz = rooms[vi % len(rooms)]
+        ri = vi % len(rooms)
+        ix, iz = rooms[ri]
+        j = vi // len(rooms)
+        aim = room_emitters[ri][j] if j < len(room_emitters[ri]) else None
         for _ in range(5000):
             ex = rng.uniform(ix * rw + 0.4, (ix + 1) * rw - 0.4)
             ez = rng.uniform(iz * rd + 0.4, (iz + 1) * rd - 0.4)
-            if all(math.hypot(ex - px, ez - pz) > pr + 0.3 for px, pz, pr in placed):
+            far = aim is None or math.hypot(ex - aim[0], ez - aim[1]) >= 2.6
+            if far and all(math.hypot(ex - px, ez - pz) > pr + 0.3 for px, pz, pr in placed):
                 break
+        if aim is not None:
+            c2w.append(look_at([ex, 1.6, ez], [aim[0], 2.2, aim[1]]))
+            continue
         tx = (ix + 0.5) * rw + rng.uniform(-0.3, 0.3) * rw
         tz = (iz + 0.5) * rd + rng.uniform(-0.3, 0.3) * rd
         if math.hypot(tx - ex, tz - ez) < 1.0:

@@ -58,6 +58,8 @@ def oracle_opts(kw):
 
 NEAR_TIE = 1e-5   # relative margin under which float32 and float64 may legitimately disagree
 ILL_COND = 1e-3   # path radiance change under 1e-6 relative perturbations at every vertex
+GRAD_ILL_COND = 1e-2   # the same for a path's gradient contribution (10x the 1e-3 gradient bar,
+                       # as ILL_COND is 10x the 1e-4 pixel bar)
 
 
 def mismatch_stats(hash_g, hash_o, margin, cond=None):

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from _gpu import (NEAR_TIE, banner, both, comparable, dev, gpu_grad, gpu_render, image_parity,
+from _gpu import (GRAD_ILL_COND, NEAR_TIE, banner, both, comparable, dev, gpu_grad, gpu_render, image_parity,
                   mismatch_stats, oracle_opts)
 from paper_1903_07145_amd import ipt, scenes
 
@@ -193,8 +193,15 @@ def test_room_parity_crop():
     print("pixel rel err p50 %.2e p99 %.2e max %.2e" % tuple(np.percentile(err, [50, 99, 100])))
     assert err.max() <= PIX_REL, err.max()
     w = rng.normal(size=(pix.size, 3))
-    gg = gpu_grad(g, dc, sc["params"], w, kw, pixel_list=pix, mask=keep)
-    go = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, path_mask=keep.astype(np.uint8), want_grad=True,
+    # derivatives of sharp GGX lobes amplify rounding more than the radiance
+    # does: the oracle probes every path's gradient contribution the same way
+    # and both sides also drop the paths whose gradient is ill-conditioned
+    gcond = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, want_cond=True, **oracle_opts(kw))["gcond"]
+    keep_g = keep & (gcond <= GRAD_ILL_COND)
+    print("gradient: compared %.1f%% of paths" % (100 * keep_g.mean()))
+    assert keep_g.mean() > 0.8
+    gg = gpu_grad(g, dc, sc["params"], w, kw, pixel_list=pix, mask=keep_g)
+    go = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, path_mask=keep_g.astype(np.uint8), want_grad=True,
                **oracle_opts(kw))["grad"]
     emax, err = _grad_parity(gg, go)
     print("grad rel err max %.2e" % emax)

@@ -214,3 +214,30 @@ def test_light_probabilities(orc):
     p1[7 * S:7 * S + 3] = 0.0   # one dark emitter keeps a small floor probability
     pr1 = sc.light_probs(p1)
     assert pr1[0] > 0 and pr1[0] < 1e-3
+
+
+def test_conditioning_probes(orc):
+    """The parity probes: most Lambertian paths in the Cornell box are well
+    conditioned (radiance and gradient change by far less than 1e-4 under a
+    1e-6 perturbation), while sharp GGX lobes in the room make path gradients
+    more ill-conditioned than their radiance."""
+    s = scenes.cornell()
+    sc = _oscene(orc, s)
+    pix = np.arange(0, 64 * 64, 61, dtype=np.int64)
+    w = np.random.default_rng(3).normal(size=(pix.size, 3))
+    r = sc.run(s["cams"], s["params"], pixel_list=pix, w=w, want_cond=True, spp=4, max_depth=3, mis=2, seed=9)
+    assert r["gcond"].shape == r["cond"].shape
+    fin = np.isfinite(r["cond"])
+    assert fin.mean() > 0.95
+    for c in (r["cond"][fin], r["gcond"][fin]):
+        assert np.median(c) < 1e-5 and np.percentile(c, 95) < 1e-3
+    s2 = scenes.room()
+    sc2 = _oscene(orc, s2)
+    W, H = s2["cams"]["width"], s2["cams"]["height"]
+    pix2 = np.arange(0, 4 * W * H, 997, dtype=np.int64)
+    w2 = np.random.default_rng(4).normal(size=(pix2.size, 3))
+    r2 = sc2.run(s2["cams"], s2["params"], pixel_list=pix2, w=w2, want_cond=True, spp=4, max_depth=5, mis=2,
+                 seed=9)
+    both = np.isfinite(r2["cond"]) & np.isfinite(r2["gcond"])
+    assert np.median(r2["gcond"][both]) < 1e-3
+    assert (r2["gcond"][both] > r2["cond"][both]).mean() > 0.5
