@@ -24,17 +24,26 @@ from . import ipt, scenes
 TAG_TARGET, TAG_A, TAG_B = 0, 1, 2
 
 
-def render_target(g, dc, p_true, spp_total, D, rr, seed=1, chunk=16):
-    """Target images: the true parameters at spp_total samples (stream tag 0)."""
+def render_target(g, dc, p_true, spp_total, D, rr, seed=1, chunk=16, return_var=False):
+    """Target images: the true parameters at spp_total samples (stream tag 0),
+    rendered in passes of `chunk` samples; with return_var also the per-pixel
+    variance of the target (across passes, divided by their number)."""
     npix = dc["num_views"] * dc["width"] * dc["height"]
-    target = torch.zeros((npix, 3), dtype=torch.float32, device="cuda")
+    acc = torch.zeros((npix, 3), dtype=torch.float64, device="cuda")
+    sq = torch.zeros((npix, 3), dtype=torch.float64, device="cuda")
     npass = max(1, spp_total // chunk)
     for i in range(npass):
         o = ipt.render_opts(seed=seed, stream_tag=TAG_TARGET, iteration=i, spp=min(chunk, spp_total),
                             max_depth=D, rr_depth=rr, mis=2)
-        target += g.render(dc, p_true, o)
-    target /= npass
-    return target
+        img = g.render(dc, p_true, o).double()
+        acc += img
+        sq += img * img
+    mean = acc / npass
+    target = mean.float().contiguous()
+    if not return_var:
+        return target
+    var = (sq / npass - mean * mean).clamp_min(0.0) / max(1, npass - 1)
+    return target, var.float()
 
 
 def coverage(g, sc):
@@ -60,7 +69,54 @@ def coverage(g, sc):
     return cov.cpu().numpy()
 
 
-def identifiable_masks(sc, cov, min_pixels=100, min_ks=0.05, min_emitter_pixels=16):
+def target_precision(g, dc, sc, target_var, free=None, nproj=None, spp=16, seed=99, max_full=256):
+    """How precisely the target images determine each parameter, in
+    normalised units: the Cramer-Rao bound of the L2 fit under the target's
+    per-pixel variance S.  H = J^T S^-1 J (Gauss-Newton information) comes
+    from random projections of the adjoint: for Rademacher r and
+    w = S^-1/2 r, E[(J^T w)(J^T w)^T] = H; two independent gradient estimates
+    a, b per projection give the unbiased a b^T.  With at most max_full free
+    parameters the bound is sqrt(diag(H_ff^-1)) over the free set (so a
+    parameter whose effect other free parameters can mimic counts as poorly
+    determined); above that, the per-parameter bound 1 / sqrt(H_ii)."""
+    cfg = sc["render"]
+    D, rr = cfg["max_depth"], cfg["rr_depth"]
+    P = sc["params"].size
+    free = np.ones(P, bool) if free is None else free
+    idx = np.nonzero(free)[0]
+    full = idx.size <= max_full
+    nproj = nproj or (max(64, 8 * idx.size) if full else 16)
+    p = torch.as_tensor(sc["params"], device="cuda")
+    sig = target_var.double().sqrt()
+    sig = sig.clamp_min(1e-3 * float(sig.mean()) + 1e-12)
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    scale = torch.as_tensor(sc["scale"], dtype=torch.float64, device="cuda")
+    fi = torch.as_tensor(idx, device="cuda")
+    A, B = [], []
+    for k in range(nproj):
+        r = torch.randint(0, 2, sig.shape, generator=gen, device="cuda", dtype=torch.int64).double() * 2 - 1
+        w = (r / sig).float().contiguous()
+        ga = g.render_grad(dc, p, w, ipt.render_opts(seed=seed, stream_tag=TAG_B, iteration=2 * k, spp=spp,
+                                                     max_depth=D, rr_depth=rr, mis=2)).double() * scale
+        gb = g.render_grad(dc, p, w, ipt.render_opts(seed=seed, stream_tag=TAG_B, iteration=2 * k + 1, spp=spp,
+                                                     max_depth=D, rr_depth=rr, mis=2)).double() * scale
+        A.append(ga[fi])
+        B.append(gb[fi])
+    A = torch.stack(A)
+    B = torch.stack(B)
+    sigma = np.full(P, np.inf)
+    if full:
+        H = (A.T @ B + B.T @ A) / (2.0 * nproj)
+        H = H + 1e-9 * torch.trace(H) / idx.size * torch.eye(idx.size, dtype=H.dtype, device=H.device)
+        cov = torch.linalg.pinv(H, hermitian=True)
+        sigma[idx] = np.sqrt(np.maximum(torch.diagonal(cov).cpu().numpy(), 0.0))
+    else:
+        h = (A * B).mean(0).cpu().numpy()
+        sigma[idx] = 1.0 / np.sqrt(np.maximum(h, 1e-300))
+    return sigma
+
+
+def identifiable_masks(sc, cov, min_pixels=100, min_ks=0.05, min_emitter_pixels=16, sigma=None, max_sigma=2.5e-3):
     """Which trainable parameters the images determine.
 
     kd_e: the diffuse albedo of every non-emitting segment seen in at least
@@ -70,7 +126,9 @@ def identifiable_masks(sc, cov, min_pixels=100, min_ks=0.05, min_emitter_pixels=
     This is the set the headline RMSE is taken over: the quantities the
     paper's evaluation reports (albedo and emission).
     all_id: kd_e plus specular reflectance of the seen segments, and their
-    roughness where the true specular reflectance (mean RGB) is >= min_ks."""
+    roughness where the true specular reflectance (mean RGB) is >= min_ks.
+    With sigma (target_precision), a parameter also needs sigma <= max_sigma
+    (a quarter of the 1e-2 RMSE target): the target must be able to pin it."""
     S = sc["num_segments"]
     P = sc["params"].size
     tr = sc["trainable"].astype(bool)
@@ -88,7 +146,30 @@ def identifiable_masks(sc, cov, min_pixels=100, min_ks=0.05, min_emitter_pixels=
         if cov[s] >= min_emitter_pixels:
             kd_e[7 * S + 3 * k:7 * S + 3 * k + 3] = True
             all_id[7 * S + 3 * k:7 * S + 3 * k + 3] = True
+    if sigma is not None:
+        ok = sigma <= max_sigma
+        kd_e &= ok
+        all_id &= ok
     return kd_e & tr, all_id & tr
+
+
+def unrecoverable_mask(sc, cov, min_pixels=100, min_emitter_pixels=16):
+    """Parameters no view can recover: every parameter of a segment seen in
+    fewer than min_pixels pixels, the reflectance of emitting segments, and the
+    emission of emitters seen in fewer than min_emitter_pixels.  Left free they
+    drift and bias the parameters they light (an unseen box's albedo sets the
+    indirect light on a seen one), so the optimisation holds them at their true
+    values."""
+    S = sc["num_segments"]
+    fixed = np.zeros(sc["params"].size, bool)
+    emit = set(int(x) for x in sc["emitter_seg"])
+    for s in range(S):
+        if cov[s] < min_pixels or s in emit:
+            fixed[7 * s:7 * s + 7] = True
+    for k, s in enumerate(sc["emitter_seg"]):
+        if cov[s] < min_emitter_pixels:
+            fixed[7 * S + 3 * k:7 * S + 3 * k + 3] = True
+    return fixed
 
 
 def param_rmse(params, p_true, scale, trainable):
@@ -110,7 +191,8 @@ def group_rmse(params, p_true, scale, trainable, S):
 
 def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guide_steps=10, guide_lr=2e-3,
              guide_batch=16384, record_stride=None, target_rmse=1e-2, stop_at_target=False, target=None,
-             g=None, log=None, spp=None, lr=None, lr_schedule="const", masks=None, lr_final=None, log_every=10):
+             g=None, log=None, spp=None, lr=None, lr_schedule="const", masks=None, lr_final=None, log_every=10,
+             fixed=None, beta2=0.999):
     """Runs the optimisation; returns a dict with the RMSE/loss history and timings.
 
     The time to target is taken on the RMSE over masks[0] (identifiable
@@ -124,8 +206,10 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
     D, rr = cfg["max_depth"], cfg["rr_depth"]
     lr0 = lr or cfg["lr"]
     g = g or ipt.Scene.from_dict(sc)
-    if masks is None:
-        masks = identifiable_masks(sc, coverage(g, sc))
+    if masks is None or fixed is None:
+        cov = coverage(g, sc)
+        masks = masks if masks is not None else identifiable_masks(sc, cov)
+        fixed = fixed if fixed is not None else unrecoverable_mask(sc, cov)
     m_head = torch.as_tensor(masks[0].astype(np.uint8), device="cuda")
     m_id = torch.as_tensor(masks[1].astype(np.uint8), device="cuda")
     dc = ipt.make_cameras(sc["cams"])
@@ -133,11 +217,14 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
     p_true = torch.as_tensor(sc["params"], device="cuda")
     if target is None:
         target = render_target(g, dc, p_true, cfg["target_spp"], D, rr)
-    params = torch.as_tensor(scenes.init_theta(sc, cfg["init"], seed=seed), device="cuda")
+    p0 = scenes.init_theta(sc, cfg["init"], seed=seed)
+    p0[fixed] = sc["params"][fixed]
+    params = torch.as_tensor(p0, device="cuda")
     scale = torch.as_tensor(sc["scale"], device="cuda")
     lo = torch.as_tensor(sc["lo"], device="cuda")
     hi = torch.as_tensor(sc["hi"], device="cuda")
-    tr = torch.as_tensor(sc["trainable"], device="cuda")
+    tr_all = torch.as_tensor(sc["trainable"], device="cuda")
+    tr = torch.as_tensor((sc["trainable"].astype(bool) & ~fixed).astype(np.uint8), device="cuda")
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
@@ -161,7 +248,7 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         # constant, or cosine decay from lr0 to lr_final (default lr0/20) over the run
         lr_end = lr_final if lr_final is not None else lr0 / 20
         lr_it = lr0 if lr_schedule == "const" else lr_end + (lr0 - lr_end) * 0.5 * (1 + np.cos(np.pi * it / iters))
-        ipt.sgd_step(params, grad, m, v, it + 1, lr=lr_it, scale=scale, lo=lo, hi=hi, trainable=tr)
+        ipt.sgd_step(params, grad, m, v, it + 1, lr=lr_it, beta2=beta2, scale=scale, lo=lo, hi=hi, trainable=tr)
         gl = None
         if gd is not None and gd.records() >= guide_batch:
             gl = gd.train(guide_steps, want_loss=(it % 10 == 0))
@@ -170,7 +257,7 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         hist["it"].append(it)
         hist["t"].append(t)
         hist["rmse"].append(r)
-        hist["rmse_all"].append(param_rmse(params, p_true, scale, tr))
+        hist["rmse_all"].append(param_rmse(params, p_true, scale, tr_all))
         hist["rmse_id"].append(param_rmse(params, p_true, scale, m_id))
         hist["loss"].append(float(loss.cpu()))
         hist["guide_loss"].append(gl)
@@ -207,6 +294,7 @@ def main(argv=None):
     ap.add_argument("--spp", type=int, default=None)
     ap.add_argument("--lr-final", type=float, default=None)
     ap.add_argument("--target-spp", type=int, default=None)
+    ap.add_argument("--beta2", type=float, default=0.999)
     ap.add_argument("--log-every", type=int, default=10)
     ap.add_argument("--lr-schedule", default="const", choices=["const", "cos"])
     ap.add_argument("--out", default=None, help="JSON lines file for the histories")
@@ -216,20 +304,30 @@ def main(argv=None):
     g = ipt.Scene.from_dict(sc)
     dc = ipt.make_cameras(sc["cams"])
     cfg = sc["render"]
-    target = render_target(g, dc, torch.as_tensor(sc["params"], device="cuda"), a.target_spp or cfg["target_spp"],
-                           cfg["max_depth"], cfg["rr_depth"])
     log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
+    t0 = time.time()
+    target, tvar = render_target(g, dc, torch.as_tensor(sc["params"], device="cuda"),
+                                 a.target_spp or cfg["target_spp"], cfg["max_depth"], cfg["rr_depth"], return_var=True)
     cov = coverage(g, sc)
-    masks = identifiable_masks(sc, cov)
+    fixed = unrecoverable_mask(sc, cov)
+    tr = sc["trainable"].astype(bool)
+    sigma = target_precision(g, dc, sc, tvar, free=tr & ~fixed)
+    masks = identifiable_masks(sc, cov, sigma=sigma)
+    fr = tr & ~fixed
+    log("target %d spp, precision in %.1fs; target precision of the free parameters: median %.2e, p90 %.2e, "
+        "worst %s" % (a.target_spp or cfg["target_spp"], time.time() - t0, np.median(sigma[fr]),
+                      np.percentile(sigma[fr], 90), [(int(i), float("%.3g" % sigma[i])) for i in
+                                                      np.argsort(-np.where(fr, sigma, 0))[:5]]))
     log("coverage: %d of %d segments seen in >= 100 pixels; emitter pixels: %s; headline set %d params, "
-        "identifiable %d of %d trainable" % ((cov >= 100).sum(), cov.size, cov[sc["emitter_seg"]].tolist(),
-                                              masks[0].sum(), masks[1].sum(), sc["trainable"].sum()))
+        "identifiable %d of %d trainable, %d held at their true values" % (
+            (cov >= 100).sum(), cov.size, cov[sc["emitter_seg"]].tolist(), masks[0].sum(), masks[1].sum(),
+            sc["trainable"].sum(), (fixed & tr).sum()))
     for seed in a.seeds:
         log("workload %s seed %d guide %s" % (a.workload, seed, a.guide))
         res = optimize(sc, iters=a.iters, seed=seed, guide=a.guide, guide_mix=a.guide_mix, warmup=a.warmup,
                        guide_steps=a.guide_steps, target_rmse=a.target_rmse, target=target, g=g, log=log,
                        lr=a.lr, lr_schedule=a.lr_schedule, masks=masks, spp=a.spp, lr_final=a.lr_final,
-                       log_every=a.log_every)
+                       log_every=a.log_every, fixed=fixed, beta2=a.beta2)
         line = json.dumps(dict(workload=a.workload, **res))
         if a.out:
             with open(a.out, "a") as f:
