@@ -274,10 +274,47 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
                 "" if gl is None else "  guide loss %.4f" % gl))
     err = ((params - p_true) / scale).cpu().numpy()
     worst = [(int(i), float(err[i])) for i in np.argsort(-np.abs(err * masks[0]))[:8]]
+    optimize.last = dict(params=params, guide=gd, target=target, g=g, dc=dc, fixed=fixed)
     return dict(history=hist, time_to_target=t_hit, final_rmse=hist["rmse"][-1],
                 final_rmse_all=hist["rmse_all"][-1], final_rmse_id=hist["rmse_id"][-1], seconds=hist["t"][-1],
                 iters=len(hist["it"]), guide=guide, seed=seed, n_head=int(masks[0].sum()),
                 n_id=int(masks[1].sum()), worst=worst)
+
+
+def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, guide_mix=0.5, seed=555):
+    """Per-parameter variance of the loss gradient over K independent seeds at
+    fixed parameters, with plain BRDF sampling and with the learned proposal
+    (one-sample MIS at guide_mix), plus the mean time per gradient of each.
+    Returns a dict of summary statistics over the free parameters."""
+    cfg = sc["render"]
+    spp = spp or cfg["spp"]
+    D, rr = cfg["max_depth"], cfg["rr_depth"]
+    out = {}
+    for arm, gd, mix in (("brdf", None, 0.0), ("guided", guide, guide_mix)):
+        G = []
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for k in range(K):
+            kw = dict(seed=seed + k, iteration=k, spp=spp, max_depth=D, rr_depth=rr, mis=2)
+            co = ipt.render_opts(stream_tag=TAG_A, guide=gd, guide_mix=mix, **kw)
+            go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, **kw)
+            _, gr = g.loss_grad(dc, params, target, co, go, 0)
+            G.append(gr.double().clone())
+        torch.cuda.synchronize()
+        dt = (time.time() - t0) / K
+        G = torch.stack(G).cpu().numpy()[:, free]
+        out[arm] = dict(var=G.var(axis=0, ddof=1), mean=G.mean(axis=0), sec=dt)
+    vb, vg = out["brdf"]["var"], out["guided"]["var"]
+    ok = vb > 0
+    ratio = vb[ok] / np.maximum(vg[ok], 1e-300)
+    return dict(K=K, n_params=int(ok.sum()), sec_per_grad_brdf=out["brdf"]["sec"],
+                sec_per_grad_guided=out["guided"]["sec"], var_ratio_median=float(np.median(ratio)),
+                var_ratio_gmean=float(np.exp(np.mean(np.log(ratio)))),
+                frac_params_lower_var_guided=float((ratio > 1).mean()),
+                total_var_brdf=float(vb.sum()), total_var_guided=float(vg.sum()),
+                efficiency_gain=float(vb.sum() * out["brdf"]["sec"] / (vg.sum() * out["guided"]["sec"])),
+                mean_shift_z_median=float(np.median(np.abs(out["brdf"]["mean"] - out["guided"]["mean"]) /
+                                                    np.sqrt((vb + vg) / K + 1e-300))))
 
 
 def main(argv=None):
@@ -295,6 +332,9 @@ def main(argv=None):
     ap.add_argument("--lr-final", type=float, default=None)
     ap.add_argument("--target-spp", type=int, default=None)
     ap.add_argument("--beta2", type=float, default=0.999)
+    ap.add_argument("--variance", type=int, default=0,
+                    help="after the run (with --guide), compare the gradient variance of K seeds with and "
+                         "without the trained proposal at the final parameters")
     ap.add_argument("--log-every", type=int, default=10)
     ap.add_argument("--lr-schedule", default="const", choices=["const", "cos"])
     ap.add_argument("--out", default=None, help="JSON lines file for the histories")
@@ -328,6 +368,12 @@ def main(argv=None):
                        guide_steps=a.guide_steps, target_rmse=a.target_rmse, target=target, g=g, log=log,
                        lr=a.lr, lr_schedule=a.lr_schedule, masks=masks, spp=a.spp, lr_final=a.lr_final,
                        log_every=a.log_every, fixed=fixed, beta2=a.beta2)
+        if a.variance and a.guide:
+            L = optimize.last
+            vs = gradient_variance(g, dc, sc, L["params"], target, L["guide"], tr & ~fixed, K=a.variance,
+                                   spp=a.spp)
+            res["variance"] = vs
+            log("gradient variance over %d seeds at iteration %d: %s" % (a.variance, res["iters"], json.dumps(vs)))
         line = json.dumps(dict(workload=a.workload, **res))
         if a.out:
             with open(a.out, "a") as f:
