@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -370,10 +371,17 @@ struct Plan {
     size_t ck_per_pixel = 0;   // checkpoint bytes per work pixel
 };
 
+// Persistent grid: blocks per CU from the occupancy calculator (at most 8),
+// or IPT_BLOCKS_PER_CU when set (tuning).
 static int path_grid(const ipt_scene_s* s, int P, int frozen, int guided) {
     int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, guided), guided);
     occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, guided), guided));
     occ = std::min(occ, path_blocks_per_cu(kReplay, path_lds_bytes(kReplay, P, frozen, s->S, s->nlt)));
+    static const int forced = [] {
+        const char* e = std::getenv("IPT_BLOCKS_PER_CU");
+        return e ? std::atoi(e) : 0;
+    }();
+    if (forced > 0) occ = forced;
     occ = std::max(1, std::min(occ, 8));
     return s->num_cu * occ;
 }

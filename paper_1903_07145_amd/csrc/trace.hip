@@ -155,36 +155,61 @@ __device__ __forceinline__ void load_tri(const SceneDev& sc, int i, V3& p0, V3& 
 // Closest hit (any = false) or occlusion test (any = true: stops at the
 // first hit in (tmin, tmax)).  skip0/skip1 are leaf indices that are ignored.
 // Ties in t are resolved toward the smaller original id.
+//
+// Loop structure for 64-wide waves ("while-while" with speculative
+// traversal, Aila and Laine 2009): the node phase visits inner nodes until
+// every lane holds a leaf (a lane that already holds one keeps descending, and
+// stops only at a second leaf), then the leaf phase tests the held leaves of
+// all lanes together.  Node code and triangle code thus run with most lanes
+// doing the same thing, instead of every iteration paying for both.
+constexpr int kTravDone = (int)0x80000000;   // no node left (leaf codes are > INT_MIN)
+
 __device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax, int skip0, int skip1, bool any,
                         Stack& st, Work& wk) {
     Hit best{-1, tmax, 0.0f, 0.0f};
     int best_orig = 0x7FFFFFFF;
     wk.rays++;
     st.sp = 0;
-    int entry = 0;
-    bool done = false;
-    while (!done) {
-        if (entry >= 0) {
-            wk.nodes++;
-            const float4* n = sc.nodes + 4 * (size_t)entry;
-            float4 n0 = n[0], n1 = n[1], n2 = n[2], n3 = n[3];
-            int c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
-            float t0 = box_entry(r, v3(n0.x, n0.y, n0.z), v3(n0.w, n1.x, n1.y), tmin, best.t, sc.tmin);
-            float t1 = box_entry(r, v3(n1.z, n1.w, n2.x), v3(n2.y, n2.z, n2.w), tmin, best.t, sc.tmin);
-            // box_entry returns +inf on a miss; best.t may itself be +inf
-            bool h0 = t0 < __builtin_inff();
-            bool h1 = (c1 != kNone) && t1 < __builtin_inff();
-            if (h0 && h1) {
-                bool first0 = t0 <= t1;
-                st.push(first0 ? c1 : c0);
-                entry = first0 ? c0 : c1;
-                continue;
+    int cur = 0;             // next node: inner (>= 0), leaf code (< 0) or kTravDone
+    int pend = kTravDone;    // leaf held for the leaf phase
+    auto next_from_stack = [&]() -> int { return (st.sp > 0 && !st.overflow) ? st.pop() : kTravDone; };
+    while (true) {
+        // ---- node phase ----
+        while (true) {
+            if (cur < 0 && cur != kTravDone && pend == kTravDone) {
+                pend = cur;
+                cur = next_from_stack();
             }
-            if (h0) { entry = c0; continue; }
-            if (h1) { entry = c1; continue; }
-        } else {
-            int code = ~entry;
+            const bool inner = cur >= 0;
+            if (!__any(inner && pend == kTravDone)) break;
+            if (inner) {
+                wk.nodes++;
+                const float4* n = sc.nodes + 4 * (size_t)cur;
+                float4 n0 = n[0], n1 = n[1], n2 = n[2], n3 = n[3];
+                int c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
+                float t0 = box_entry(r, v3(n0.x, n0.y, n0.z), v3(n0.w, n1.x, n1.y), tmin, best.t, sc.tmin);
+                float t1 = box_entry(r, v3(n1.z, n1.w, n2.x), v3(n2.y, n2.z, n2.w), tmin, best.t, sc.tmin);
+                // box_entry returns +inf on a miss; best.t may itself be +inf
+                bool h0 = t0 < __builtin_inff();
+                bool h1 = (c1 != kNone) && t1 < __builtin_inff();
+                if (h0 && h1) {
+                    bool first0 = t0 <= t1;
+                    st.push(first0 ? c1 : c0);
+                    cur = first0 ? c0 : c1;
+                } else if (h0) {
+                    cur = c0;
+                } else if (h1) {
+                    cur = c1;
+                } else {
+                    cur = next_from_stack();
+                }
+            }
+        }
+        // ---- leaf phase ----
+        if (pend != kTravDone) {
+            int code = ~pend;
             int first = code >> 3, cnt = (code & 7) + 1;
+            pend = kTravDone;
             wk.tris += cnt;
             for (int i = first; i < first + cnt; ++i) {
                 if (i == skip0 || i == skip1) continue;
@@ -194,16 +219,18 @@ __device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax
                 float t, u, v;
                 if (!tri_isect(r, p0, p1, p2, tmin, t, u, v)) continue;
                 if (any) {
-                    if (t < tmax) { best.tri = i; best.t = t; done = true; break; }
+                    if (t < tmax) {
+                        best.tri = i; best.t = t;
+                        cur = kTravDone;
+                        break;
+                    }
                 } else if (t < best.t || (t == best.t && orig < best_orig)) {
                     best.tri = i; best.t = t; best.u = u; best.v = v;
                     best_orig = orig;
                 }
             }
-            if (done) break;
         }
-        if (st.sp == 0 || st.overflow) break;
-        entry = st.pop();
+        if (!__any(cur != kTravDone)) break;
     }
     if (!any && best.tri >= 0 && !(best.t < tmax)) best.tri = -1;
     return best;
