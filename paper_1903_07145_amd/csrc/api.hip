@@ -376,7 +376,6 @@ struct Plan {
 static int path_grid(const ipt_scene_s* s, int P, int frozen, int guided) {
     int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, guided), guided);
     occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, guided), guided));
-    occ = std::min(occ, path_blocks_per_cu(kReplay, path_lds_bytes(kReplay, P, frozen, s->S, s->nlt)));
     static const int forced = [] {
         const char* e = std::getenv("IPT_BLOCKS_PER_CU");
         return e ? std::atoi(e) : 0;
@@ -528,9 +527,11 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
         HIP_OK(launch_zero_u32(a.work, 1, st));
         HIP_OK(timed_launch(s, kGradFwd, a, grid, lds_f, st));
         if (a.guided) HIP_OK(launch_guide_records(a, st));
+        // the replay pulls tiles, so it runs on as many blocks as are resident
+        int grid_r = std::min(grid, s->num_cu * std::max(1, path_blocks_per_cu(kReplay, lds_r)));
         HIP_OK(launch_zero_u32(a.work, 1, st));
-        HIP_OK(timed_launch(s, kReplay, a, grid, lds_r, st));
-        HIP_OK(launch_grad_reduce(a.grad_part, grid, a.P, grad, b > 0 ? 1 : 0, st));
+        HIP_OK(timed_launch(s, kReplay, a, grid_r, lds_r, st));
+        HIP_OK(launch_grad_reduce(a.grad_part, grid_r, a.P, grad, b > 0 ? 1 : 0, st));
     }
     return IPT_OK;
 }

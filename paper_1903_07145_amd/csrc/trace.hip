@@ -500,11 +500,13 @@ __device__ __forceinline__ void flush_stats(const PathArgs& a, int mode, const W
 // ---------------------------------------------------------------------------
 enum Phase { kNeedPixel = 0, kClosest = 1, kShadow = 2, kExit = 3 };
 
-#ifdef IPT_WAVES_PER_EU
-#define IPT_OCC __attribute__((amdgpu_waves_per_eu(IPT_WAVES_PER_EU, 8)))
-#else
-#define IPT_OCC
+// At least 4 waves per SIMD: the path state needs ~158 VGPRs unconstrained
+// (3 waves), and the fourth wave hides more node-fetch latency than the
+// ~100 bytes of spilled state cost (apartment step 241 -> 214 ms).
+#ifndef IPT_WAVES_PER_EU
+#define IPT_WAVES_PER_EU 4
 #endif
+#define IPT_OCC __attribute__((amdgpu_waves_per_eu(IPT_WAVES_PER_EU, 8)))
 
 // GUIDE: 0 none, 1 bfloat16 MFMA evaluation, 2 float32 VALU evaluation
 template <int MODE, int GUIDE>
