@@ -40,6 +40,38 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+# sources the path kernels are built from: HBM traffic measured by counters
+# is reported only while these still hash to the profiled version
+KERNEL_SOURCES = ["paper_1903_07145_amd/csrc/" + f for f in
+                  ("trace.hip", "ipt_math.h", "ipt_internal.h", "guide_dev.h", "api.hip")] + \
+                 ["paper_1903_07145_amd/build.py"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a copy kernel of known size),
+    or None if there is none for the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    for line in open(path):
+        if line.startswith("traffic:"):
+            f = dict(kv.split("=", 1) for kv in line[len("traffic:"):].split())
+            if f.get("kernel") == kernel and f.get("workload") == workload and f.get("sources") == want:
+                return float(f["bytes_per_launch"])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,8 +181,10 @@ def main():
                          nodes_per_ray=k["nodes"] / max(1, k["rays"]), tris_per_ray=k["tris"] / max(1, k["rays"]))
     dom = max(per, key=lambda n: per[n]["avg_ms"])
     d = per[dom]
+    traffic = measured_traffic(dom, sc["name"])
     roofline = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "kernel_sources": kernel_source_hash(),
                 "avg_launch_ms": round(d["avg_ms"], 3), "algorithmic_bytes_per_launch": int(d["bytes_per_launch"]),
                 "nodes_per_ray": round(d["nodes_per_ray"], 2), "tris_per_ray": round(d["tris_per_ray"], 2)}
     info2 = g.info()
