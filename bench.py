@@ -81,6 +81,11 @@ def main():
     ap.add_argument("--target-spp", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--guide", action="store_true",
+                    help="learned proposal: trained online during the warm-up, then each step samples it "
+                         "(one-sample MIS with BRDF sampling, mix 0.5), writes training records and runs "
+                         "--guide-steps training steps")
+    ap.add_argument("--guide-steps", type=int, default=10)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -132,14 +137,24 @@ def main():
     grad = torch.zeros_like(params)
     lr = cfg["lr"]
 
+    gd = None
+    if args.guide:
+        stride = max(1, (npix * spp * 3) // (1 << 20))   # about one million records per step
+        gd = ipt.Guide(g, seed=7, batch=16384, ring_capacity=1 << 21, record_stride=stride)
+
     def step(it):
-        co = ipt.render_opts(seed=11, stream_tag=1, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2)
-        go = ipt.render_opts(seed=11, stream_tag=2, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2)
+        mix = 0.5 if (gd is not None and it >= 1) else 0.0
+        co = ipt.render_opts(seed=11, stream_tag=1, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2,
+                             guide=gd if mix > 0 else None, guide_mix=mix)
+        go = ipt.render_opts(seed=11, stream_tag=2, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2,
+                             guide=gd, guide_mix=mix)
         g.loss_grad(dc, params, target, co, go, 0, loss=loss, grad=grad)
         ipt.sgd_step(params, grad, m, v, it + 1, lr=lr, scale=scale, lo=lo, hi=hi, trainable=tr)
+        if gd is not None and gd.records() >= 16384:
+            gd.train(args.guide_steps, want_loss=False)
 
     # workspace sized once, outside the timed region
-    g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr))
+    g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr, guide=gd, guide_mix=0.5 if gd else 0.0))
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -209,7 +224,8 @@ def main():
         "config": {"workload": "%s: %d triangles, %d segments, %d emitters, %d views %dx%d, %d spp, depth %d%s" % (
             sc["name"], sc["tris"].shape[0], sc["num_segments"], len(sc["emitter_seg"]), V, W, H, spp, D,
             ", RR from %d" % rr if rr >= 0 else ""),
-            "step": "ipt_loss_grad (colour A + L2 loss/adjoint + gradient B fwd/replay/reduce) + ipt_sgd_step",
+            "step": "ipt_loss_grad (colour A + L2 loss/adjoint + gradient B fwd/replay/reduce) + ipt_sgd_step" +
+                    (" + %d guide training steps; learned proposal mixed at 0.5" % args.guide_steps if gd else ""),
             "paths_per_step": {"colour": paths_step, "gradient": paths_step},
             "parallelism": "1 GPU"},
         "breakdown": {"colour_paths_per_s": round(paths_step / (ms_col * 1e-3), 1),

@@ -507,10 +507,18 @@ enum Phase { kNeedPixel = 0, kClosest = 1, kShadow = 2, kExit = 3 };
 #define IPT_WAVES_PER_EU 4
 #endif
 #define IPT_OCC __attribute__((amdgpu_waves_per_eu(IPT_WAVES_PER_EU, 8)))
+// The guided kernels also hold the network's operands around the MLP call:
+// at 2 waves per SIMD nothing spills (apartment guided step 537 ms at 4
+// waves, 487 at 3, 449 at 2).
+#ifndef IPT_WAVES_PER_EU_GUIDED
+#define IPT_WAVES_PER_EU_GUIDED 2
+#endif
 
 // GUIDE: 0 none, 1 bfloat16 MFMA evaluation, 2 float32 VALU evaluation
 template <int MODE, int GUIDE>
-__global__ __launch_bounds__(kBlock) IPT_OCC void path_sm_kernel(PathArgs a) {
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(GUIDE ? IPT_WAVES_PER_EU_GUIDED : IPT_WAVES_PER_EU, 8))) void path_sm_kernel(
+    PathArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     Lds lds;
     carve_lds(a, MODE, smem, lds);
