@@ -106,7 +106,13 @@ struct TrainArgs {
     float* lsum;             // [1] sum of w log q
     float* gw;               // [kGParams] gradient
     float* gemb;             // [S][16] gradient
+    float* part;             // [gridDim.x][kGParams] per-block weight and bias gradients
+    int b0;                  // first batch position of this launch
 };
+
+// Records per training launch (one 64-record block each writes a partial
+// gradient row; a fixed-order reduction sums them).
+constexpr int kTrainChunkBlocks = 256;
 
 __device__ __forceinline__ int64_t batch_index(const TrainArgs& t, int b) {
     if (t.direct) return b;
@@ -195,8 +201,9 @@ __global__ __launch_bounds__(64) void guide_train_kernel(TrainArgs t) {
     const int lane = threadIdx.x;
     const int li = lane & 15, lk = (lane >> 4) * 8;
     const GuideDev& gd = t.gd;
-    const int b = blockIdx.x * 64 + lane;
+    const int b = t.b0 + blockIdx.x * 64 + lane;
     const bool ok = b < t.batch;
+    float* part = t.part + (size_t)blockIdx.x * kGParams;
     const float* rc = t.rec + kRecF * (ok ? batch_index(t, b) : 0);
     int seg = ok ? __float_as_int(rc[3]) : 0;
     // inputs
@@ -249,7 +256,9 @@ __global__ __launch_bounds__(64) void guide_train_kernel(TrainArgs t) {
         float w = ok ? rc[7] / fmaxf(*t.wsum, 1e-30f) : 0.0f;
         float dy[kGOut], lq = 0.0f;
         mixture_grad(yr, v3(rc[12], rc[13], rc[14]), w, dy, &lq);
-        if (ok && w > 0.0f) atomicAdd(t.lsum, w * lq);
+        float wl = (ok && w > 0.0f) ? w * lq : 0.0f;
+        for (int o = 32; o >= 1; o >>= 1) wl += __shfl_xor(wl, o, 64);
+        if (lane == 0 && wl != 0.0f) atomicAdd(t.lsum, wl);
         __bf16* row = dA + lane * kTS;
         for (int j = 0; j < 64; ++j) row[j] = (__bf16)((ok && j < kGOut) ? dy[j] : 0.0f);
     }
@@ -267,7 +276,7 @@ __global__ __launch_bounds__(64) void guide_train_kernel(TrainArgs t) {
         if (lane < nout) {
             float s = 0.0f;
             for (int q = 0; q < 64; ++q) s += (float)dz[q * kTS + lane];
-            atomicAdd(t.gw + bs[l] + lane, s);
+            part[bs[l] + lane] = s;
         }
         // dW[in][out] = sum_q in[q][in] dz[q][out]: A = in^T (M = inputs), B = dz (K = queries)
         const int mblk = l == 0 ? 2 : 4, nblk = l == 4 ? 3 : 4;
@@ -285,7 +294,7 @@ __global__ __launch_bounds__(64) void guide_train_kernel(TrainArgs t) {
                 int col = nb * 16 + li;
                 for (int r = 0; r < 4; ++r) {
                     int row = ib * 16 + (lane >> 4) * 4 + r;
-                    if (row < nin && col < nout) atomicAdd(t.gw + gwo[l] + row * nout + col, acc[nb][r]);
+                    if (row < nin && col < nout) part[gwo[l] + row * nout + col] = acc[nb][r];
                 }
             }
         }
@@ -380,6 +389,7 @@ struct ipt_guide_s {
     float* rec = nullptr;     // ring [cap][kRecF]
     unsigned* rec_count = nullptr;
     float* scal = nullptr;    // [0] wsum, [1] lsum
+    float* gpart = nullptr;   // [kTrainChunkBlocks][kGParams] per-block training gradients
     int cap = 0, batch = 0, stride = 1;
     float lr = 1e-3f;
     uint64_t seed = 0;
@@ -473,6 +483,7 @@ ipt_status guide_create_impl(int S, const float lo[3], const float hi[3], const 
     al((void**)&g->rec, (size_t)g->cap * kRecF * 4);
     al((void**)&g->rec_count, 64);
     al((void**)&g->scal, 64);
+    al((void**)&g->gpart, (size_t)kTrainChunkBlocks * kGParams * 4);
     if (e == hipSuccess) e = hipMemcpy(g->w, w0.data(), np * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(g->m, 0, np * 4);
     if (e == hipSuccess) e = hipMemset(g->v, 0, np * 4);
@@ -492,6 +503,7 @@ extern "C" ipt_status ipt_guide_free(ipt_guide_t g) {
     if (!g) return IPT_OK;
     hipFree(g->w); hipFree(g->m); hipFree(g->v); hipFree(g->g);
     hipFree(g->wb); hipFree(g->embb); hipFree(g->rec); hipFree(g->rec_count); hipFree(g->scal);
+    hipFree(g->gpart);
     delete g;
     return IPT_OK;
 }
@@ -513,6 +525,15 @@ extern "C" ipt_status ipt_guide_eval(ipt_guide_t g, const float* feat, const int
     return e == hipSuccess ? IPT_OK : ipt_fail(IPT_ERR_HIP, hipGetErrorString(e));
 }
 
+// grad[i] += sum over blocks of part[block][i], i < kGParams (fixed order).
+__global__ void guide_part_reduce_kernel(const float* part, int nblocks, float* grad) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kGParams) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * kGParams + i];
+    grad[i] += s;
+}
+
 // Loss and gradient of one batch into grad [np]; scal[0] = sum of weights,
 // scal[1] = sum_b (w_b / sum w) log q_b.
 static void launch_loss_grad(ipt_guide_s* g, const float* rec, int64_t nrec, int batch, int direct, float* grad,
@@ -531,10 +552,18 @@ static void launch_loss_grad(ipt_guide_s* g, const float* rec, int64_t nrec, int
     t.lsum = g->scal + 1;
     t.gw = grad;
     t.gemb = grad + kGParams;
+    t.part = g->gpart;
     hipLaunchKernelGGL(zero_f32_kernel, dim3((int)((np + 255) / 256)), dim3(256), 0, st, grad, (int)np);
     hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, st, g->scal, 2);
     hipLaunchKernelGGL(guide_wsum_kernel, dim3(64), dim3(256), 0, st, t);
-    hipLaunchKernelGGL(guide_train_kernel, dim3((t.batch + 63) / 64), dim3(64), 0, st, t);
+    const int chunk = kTrainChunkBlocks * 64;
+    for (int b0 = 0; b0 < t.batch; b0 += chunk) {
+        t.b0 = b0;
+        const int nb = (std::min(chunk, t.batch - b0) + 63) / 64;
+        hipLaunchKernelGGL(guide_train_kernel, dim3(nb), dim3(64), 0, st, t);
+        hipLaunchKernelGGL(guide_part_reduce_kernel, dim3((kGParams + 255) / 256), dim3(256), 0, st, g->gpart, nb,
+                           grad);
+    }
 }
 
 extern "C" ipt_status ipt_guide_loss_grad(ipt_guide_t g, const float* rec, int64_t n, float* loss, float* grad,
