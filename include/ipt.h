@@ -193,6 +193,16 @@ ipt_status ipt_sgd_step(float *params, const float *grad, float *m, float *v, in
                         const float *lo, const float *hi, const uint8_t *trainable,
                         void *hip_stream);
 
+/* L1 regulariser of the emission (Sec. 3, "Regularization"; App. A: an
+ * L1 term on all emission parameters, since most objects emit nothing):
+ * grad[i] += weight[i] * sgn(params[i]) and *loss += sum_i weight[i] |params[i]|,
+ * with sgn(0) = 0.  params, grad, weight [P] and loss [1] are DEVICE float32
+ * arrays; weight is 0 for the entries that are not regularised.  Call it
+ * after ipt_loss_grad and before ipt_sgd_step.  Errors: IPT_ERR_INVALID_ARG
+ * (NULL pointer, P < 1). */
+ipt_status ipt_l1_reg(const float *params, float *grad, const float *weight, int32_t P, float *loss,
+                      void *hip_stream);
+
 /* Closest hits of a batch of rays (the ray-casting step of every path
  * vertex).  origins/dirs [n][3]; out_tri [n] original triangle id or -1;
  * out_tuv [n][3] (t, u, v) with u, v the weights of vertices 1 and 2;

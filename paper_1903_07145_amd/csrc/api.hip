@@ -402,7 +402,7 @@ static void make_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t np
     pl.grid = path_grid(s, P, 1, guided && o->guide_mix > 0.0f);
     size_t off = 0;
     pl.off_counters = off; off = al256(off + 64 * sizeof(unsigned));
-    pl.off_cdf = off; off = al256(off + sizeof(float) * std::max(1, s->nlt));
+    pl.off_cdf = off; off = al256(off + 2 * sizeof(float) * std::max(1, s->nlt));   // prefix sums, probabilities
     pl.off_loss = off; off = al256(off + sizeof(float) * 1024);
     pl.off_w = off; off = al256(off + (with_loss ? sizeof(float) * 3 * npix : 0));
     pl.off_img = off; off = al256(off + (with_loss ? sizeof(float) * 3 * npix : 0));
@@ -603,6 +603,14 @@ extern "C" ipt_status ipt_sgd_step(float* params, const float* grad, float* m, f
         return fail(IPT_ERR_INVALID_ARG, "bad Adam hyper-parameters");
     HIP_OK(launch_adam(params, grad, m, v, P, step, adam->lr, adam->beta1, adam->beta2, adam->eps, scale, lo, hi,
                        trainable, (hipStream_t)hip_stream));
+    return IPT_OK;
+}
+
+extern "C" ipt_status ipt_l1_reg(const float* params, float* grad, const float* weight, int32_t P, float* loss,
+                                 void* hip_stream) {
+    if (!params || !grad || !weight || !loss) return fail(IPT_ERR_INVALID_ARG, "NULL argument");
+    if (P < 1) return fail(IPT_ERR_INVALID_ARG, "P must be >= 1");
+    HIP_OK(launch_l1_reg(params, grad, weight, P, loss, (hipStream_t)hip_stream));
     return IPT_OK;
 }
 

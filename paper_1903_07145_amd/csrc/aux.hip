@@ -65,6 +65,10 @@ __global__ __launch_bounds__(1024) void light_cdf_kernel(const int4* lights, int
         run += weight(j);
         cdf[j] = run;
     }
+    // selection probabilities directly as w_j / total: a difference of two
+    // prefix sums would lose digits when there are many lights
+    const float rtot = 1.0f / part[1023];
+    for (int j = b; j < e_; ++j) cdf[nlt + j] = weight(j) * rtot;
 }
 
 hipError_t launch_light_cdf(const SceneDev& sc, const float* sparams, float* cdf, hipStream_t st) {
@@ -182,6 +186,25 @@ __global__ __launch_bounds__(256) void adam_kernel(float* params, const float* g
     if (lo) th = fmaxf(th, lo[i]);
     if (hi) th = fminf(th, hi[i]);
     params[i] = th * sc;
+}
+
+// L1 term: grad += w sgn(p); loss += sum w |p| (one wave-reduced atomic per wave).
+__global__ __launch_bounds__(256) void l1_reg_kernel(const float* p, float* g, const float* w, int P, float* loss) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    float l = 0.0f;
+    if (i < P && w[i] != 0.0f) {
+        float x = p[i];
+        float sg = x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f);
+        g[i] += w[i] * sg;
+        l = w[i] * fabsf(x);
+    }
+    for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o, 64);
+    if ((threadIdx.x & 63) == 0 && l != 0.0f) atomicAdd(loss, l);
+}
+
+hipError_t launch_l1_reg(const float* p, float* g, const float* w, int P, float* loss, hipStream_t st) {
+    hipLaunchKernelGGL(l1_reg_kernel, dim3((P + 255) / 256), dim3(256), 0, st, p, g, w, P, loss);
+    return hipGetLastError();
 }
 
 hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int P, int step, float lr,

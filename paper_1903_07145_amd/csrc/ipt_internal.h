@@ -57,7 +57,7 @@ struct PathArgs {
     const float* sparams;
     int P;
     int frozen;              // sparams differs from params
-    const float* cdf;        // [nlt] inclusive prefix sums of light weights
+    const float* cdf;        // [2 nlt]: inclusive prefix sums of light weights, then probabilities
     Rng rng;
     int spp, D, rr_depth, mis, profile, jitter;
     const int64_t* pixel_list;
@@ -108,6 +108,7 @@ hipError_t launch_colour_reduce(const float* part, int nchunk, int64_t pix_count
                                 hipStream_t st);
 hipError_t launch_grad_reduce(const double* part, int nblocks, int P, float* grad, int accumulate,
                               hipStream_t st);
+hipError_t launch_l1_reg(const float* p, float* g, const float* w, int P, float* loss, hipStream_t st);
 hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int P, int step,
                        float lr, float b1, float b2, float eps, const float* scale,
                        const float* lo, const float* hi, const uint8_t* trainable,

@@ -53,7 +53,7 @@ size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guided) {
     b += al(sizeof(float) * P);                       // params
     if (frozen) b += al(sizeof(float) * P);           // sampling params
     b += al(sizeof(int) * S);                         // segment -> emitter
-    if (nlt <= kMaxLdsLights) b += al(sizeof(float) * nlt) + al(sizeof(int4) * nlt);
+    if (nlt <= kMaxLdsLights) b += al(2 * sizeof(float) * nlt) + al(sizeof(int4) * nlt);
     if (mode == kReplay) b += al(sizeof(double) * P); // block gradient
     b += sizeof(int) * kShortStack * kBlock;          // short stacks
     if (guided && mode != kReplay) b += kGuideLds;     // guide activations
@@ -72,7 +72,7 @@ __device__ void carve_lds(const PathArgs& a, int mode, unsigned char* smem, Lds&
     lds.cdf = nullptr;
     lds.lights = nullptr;
     if (lds.lights_in_lds) {
-        lds.cdf = (float*)p; p += al(sizeof(float) * a.sc.nlt);
+        lds.cdf = (float*)p; p += al(2 * sizeof(float) * a.sc.nlt);
         lds.lights = (int4*)p; p += al(sizeof(int4) * a.sc.nlt);
     }
     lds.grad = nullptr;
@@ -89,6 +89,7 @@ __device__ void carve_lds(const PathArgs& a, int mode, unsigned char* smem, Lds&
     if (lds.lights_in_lds)
         for (int i = tid; i < a.sc.nlt; i += kBlock) {
             lds.cdf[i] = a.cdf[i];
+            lds.cdf[a.sc.nlt + i] = a.cdf[a.sc.nlt + i];
             lds.lights[i] = a.sc.lights[i];
         }
     __syncthreads();
@@ -256,7 +257,8 @@ __device__ Hit brute_closest(const SceneDev& sc, int64_t nt, const Ray& r, float
 }
 
 // ---------------------------------------------------------------------------
-// Light selection from the cumulative table (first j with cdf[j] > u*total).
+// Light selection from the cumulative table (first j with cdf[j] > u*total);
+// cdf[n + j] holds light j's selection probability.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int pick_light(const float* cdf, int n, float u) {
     float x = u * cdf[n - 1];
@@ -268,8 +270,7 @@ __device__ __forceinline__ int pick_light(const float* cdf, int n, float u) {
     return lo;
 }
 __device__ __forceinline__ float light_prob(const float* cdf, int n, int j) {
-    float prev = j > 0 ? cdf[j - 1] : 0.0f;
-    return (cdf[j] - prev) / cdf[n - 1];
+    return cdf[n + j];
 }
 
 __device__ __forceinline__ void camera_ray(const PathArgs& a, int view, float px, float py, V3& o, V3& d) {

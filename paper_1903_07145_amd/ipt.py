@@ -20,7 +20,7 @@ _STATUS = {0: "IPT_OK", 1: "IPT_ERR_INVALID_ARG", 2: "IPT_ERR_BAD_SCENE", 3: "IP
            4: "IPT_ERR_WORKSPACE_TOO_SMALL", 5: "IPT_ERR_HIP", 6: "IPT_ERR_NOT_SUPPORTED"}
 
 EXPORTS = ["ipt_scene_build", "ipt_scene_build_ex", "ipt_scene_free", "ipt_scene_info", "ipt_workspace_query", "ipt_render",
-           "ipt_render_grad", "ipt_loss_grad", "ipt_sgd_step", "ipt_trace_rays", "ipt_guide_create",
+           "ipt_render_grad", "ipt_loss_grad", "ipt_sgd_step", "ipt_l1_reg", "ipt_trace_rays", "ipt_guide_create",
            "ipt_guide_free", "ipt_guide_eval", "ipt_guide_train", "ipt_guide_weights", "ipt_guide_records",
            "ipt_guide_loss_grad", "ipt_guide_add_records", "ipt_guide_read_records",
            "ipt_profile_enable", "ipt_profile_read",
@@ -106,6 +106,7 @@ def lib():
             "ipt_render_grad": [P, P, P, P, P, P, P, P, SZ, P],
             "ipt_loss_grad": [P, P, P, P, P, P, I32, P, P, P, P, SZ, P],
             "ipt_sgd_step": [P, P, P, P, I32, I32, P, P, P, P, P, P],
+            "ipt_l1_reg": [P, P, P, I32, P, P],
             "ipt_trace_rays": [P, P, P, P, I64, ctypes.c_float, I32, P, P, P],
             "ipt_guide_create": [P, P, P, P],
             "ipt_guide_free": [P],
@@ -299,6 +300,11 @@ def sgd_step(params, grad, m, v, step, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8
     a = AdamOpts(lr, beta1, beta2, eps)
     _check(lib().ipt_sgd_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(step),
                               ctypes.byref(a), _ptr(scale), _ptr(lo), _ptr(hi), _ptr(trainable), _stream()))
+
+
+def l1_reg(params, grad, weight, loss):
+    """Adds the L1 emission regulariser to grad and loss in place (ipt_l1_reg)."""
+    _check(lib().ipt_l1_reg(_ptr(params), _ptr(grad), _ptr(weight), params.numel(), _ptr(loss), _stream()))
 
 
 class Guide:

@@ -281,6 +281,97 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
                 n_id=int(masks[1].sum()), worst=worst)
 
 
+def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, lr=5e-3, lam=1e-3, beta2=0.999,
+                           target=None, g=None, log=None, log_every=100, target_rmse=1e-2, cov=None):
+    """The paper's own optimisation setting (Sec. 3, "Optimization Parameters";
+    App. A): every segment emissive (scenes.all_emissive), albedo and
+    emission initialised to zero, each iteration a batch of `batch` pixels
+    drawn uniformly from all pixels of all views with `spp` paths per pixel,
+    the L1 loss and its sign adjoint, an L1 regulariser of weight `lam` (per
+    unit of normalised emission) on every emission, Adam at lr 5e-3.
+
+    Headline RMSE: albedo of the seen segments that do not emit and emission
+    of every seen segment (zero for all but the scene's own emitters);
+    parameters of unseen segments and the emitters' reflectance are held at
+    their true values (as in optimize())."""
+    cfg = sc["render"]
+    D, rr = cfg["max_depth"], cfg["rr_depth"]
+    g = g or ipt.Scene.from_dict(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    npix = dc["num_views"] * dc["width"] * dc["height"]
+    S = sc["num_segments"]
+    p_true = torch.as_tensor(sc["params"], device="cuda")
+    if target is None:
+        target = render_target(g, dc, p_true, cfg["target_spp"], D, rr)
+    cov = coverage(g, sc) if cov is None else cov
+    true_emit = set(int(x) for x in sc.get("true_emitters", sc["emitter_seg"]))
+    tr_np = sc["trainable"].astype(bool)
+    fixed = np.zeros(sc["params"].size, bool)
+    head = np.zeros(sc["params"].size, bool)
+    for s_ in range(S):
+        seen = cov[s_] >= 100 or (s_ in true_emit and cov[s_] >= 16)
+        if not seen:
+            fixed[7 * s_:7 * s_ + 7] = True
+            fixed[7 * S + 3 * s_:7 * S + 3 * s_ + 3] = True
+            continue
+        if s_ in true_emit:
+            fixed[7 * s_:7 * s_ + 7] = True
+        else:
+            head[7 * s_:7 * s_ + 3] = True
+        head[7 * S + 3 * s_:7 * S + 3 * s_ + 3] = True
+    head &= tr_np & ~fixed
+    p0 = np.where(tr_np & ~fixed, 0.0, sc["params"]).astype(np.float32)
+    # ks and roughness (when trainable) start at the middle of their range
+    for s_ in range(S):
+        if not fixed[7 * s_] and tr_np[7 * s_ + 3]:
+            p0[7 * s_ + 3:7 * s_ + 6] = 0.5
+            p0[7 * s_ + 6] = 0.5
+    params = torch.as_tensor(p0, device="cuda")
+    scale = torch.as_tensor(sc["scale"], device="cuda")
+    lo = torch.as_tensor(sc["lo"], device="cuda")
+    hi = torch.as_tensor(sc["hi"], device="cuda")
+    tr = torch.as_tensor((tr_np & ~fixed).astype(np.uint8), device="cuda")
+    m_head = torch.as_tensor(head.astype(np.uint8), device="cuda")
+    w_l1 = np.zeros(sc["params"].size, np.float32)
+    w_l1[7 * S:] = lam / sc["scale"][7 * S:]
+    w_l1[fixed] = 0.0
+    w_l1 = torch.as_tensor(w_l1, device="cuda")
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    grad = torch.zeros_like(params)
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    pix0 = torch.zeros(batch, dtype=torch.int64, device="cuda")
+    g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr, pixel_list=pix0))
+    hist = dict(it=[], t=[], rmse=[], loss=[])
+    torch.cuda.synchronize()
+    t0 = time.time()
+    t_hit = None
+    for it in range(iters):
+        pix = torch.randint(0, npix, (batch,), generator=gen, device="cuda")
+        tgt = target.index_select(0, pix).contiguous()
+        kw = dict(seed=1000 * seed + 17, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2, pixel_list=pix)
+        g.loss_grad(dc, params, tgt, ipt.render_opts(stream_tag=TAG_A, **kw), ipt.render_opts(stream_tag=TAG_B, **kw),
+                    1, loss=loss, grad=grad)
+        ipt.l1_reg(params, grad, w_l1, loss)
+        ipt.sgd_step(params, grad, m, v, it + 1, lr=lr, beta2=beta2, scale=scale, lo=lo, hi=hi, trainable=tr)
+        if it % 10 == 0 or it == iters - 1:
+            r = param_rmse(params, p_true, scale, m_head)
+            t = time.time() - t0
+            hist["it"].append(it)
+            hist["t"].append(t)
+            hist["rmse"].append(r)
+            hist["loss"].append(float(loss.cpu()))
+            if t_hit is None and r <= target_rmse:
+                t_hit = t
+            if log and (it % log_every == 0 or it == iters - 1):
+                log("it %5d  t %7.2fs  batch loss %.5f  rmse %.4f" % (it, t, hist["loss"][-1], r))
+    err = ((params - p_true) / scale).cpu().numpy()
+    worst = [(int(i), float(err[i])) for i in np.argsort(-np.abs(err * head))[:6]]
+    return dict(history=hist, time_to_target=t_hit, final_rmse=hist["rmse"][-1], seconds=hist["t"][-1],
+                iters=iters, seed=seed, n_head=int(head.sum()), worst=worst, batch=batch, spp=spp, lr=lr, lam=lam)
+
+
 def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, guide_mix=0.5, seed=555):
     """Per-parameter variance of the loss gradient over K independent seeds at
     fixed parameters, with plain BRDF sampling and with the learned proposal
@@ -338,9 +429,34 @@ def main(argv=None):
     ap.add_argument("--log-every", type=int, default=10)
     ap.add_argument("--lr-schedule", default="const", choices=["const", "cos"])
     ap.add_argument("--out", default=None, help="JSON lines file for the histories")
+    ap.add_argument("--paper-setting", action="store_true",
+                    help="the paper's setting: every segment emissive, zero init, batches of --batch pixels at "
+                         "--spp paths each, L1 loss, L1 emission regulariser --lam, Adam lr 5e-3")
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lam", type=float, default=1e-3)
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     sc = scenes.WORKLOADS[a.workload]()
+    if a.paper_setting:
+        log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
+        sc = scenes.all_emissive(sc)
+        cfg = sc["render"]
+        g = ipt.Scene.from_dict(sc)
+        dc = ipt.make_cameras(sc["cams"])
+        target = render_target(g, dc, torch.as_tensor(sc["params"], device="cuda"),
+                               a.target_spp or cfg["target_spp"], cfg["max_depth"], cfg["rr_depth"])
+        cov = coverage(g, sc)
+        for seed in a.seeds:
+            res = optimize_paper_setting(sc, iters=a.iters or 2000, seed=seed, batch=a.batch, spp=a.spp or 512,
+                                         lr=a.lr or 5e-3, lam=a.lam, beta2=a.beta2, target=target, g=g, log=log,
+                                         log_every=a.log_every, target_rmse=a.target_rmse, cov=cov)
+            if a.out:
+                with open(a.out, "a") as f:
+                    f.write(json.dumps(dict(workload=sc["name"], mode="paper_setting", **res)) + "\n")
+            log("seed %d: final rmse %.4f after %d iters in %.1fs over %d headline parameters; time to %.0e: %s; "
+                "worst %s" % (seed, res["final_rmse"], res["iters"], res["seconds"], res["n_head"], a.target_rmse,
+                              res["time_to_target"], res["worst"]))
+        return
     g = ipt.Scene.from_dict(sc)
     dc = ipt.make_cameras(sc["cams"])
     cfg = sc["render"]

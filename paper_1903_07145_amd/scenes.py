@@ -426,6 +426,31 @@ WORKLOADS = {"cornell": cornell, "room": room, "apartment": apartment,
              "office_floor": office_floor}
 
 
+def all_emissive(sc):
+    """The paper's setting: every segment has an unknown emission (most of it
+    zero; the emission of the scene's own emitters keeps its value, the rest
+    is 0) besides its material.  Same geometry and cameras; the parameter
+    vector grows to 7 S + 3 S and emission is trainable on every segment."""
+    S = sc["num_segments"]
+    E0 = len(sc["emitter_seg"])
+    p_old, sc_old = sc["params"], sc["scale"]
+    e_max = float(sc_old[7 * S]) if E0 else 1.0
+    e_true = np.zeros((S, 3), np.float32)
+    for k, seg in enumerate(sc["emitter_seg"]):
+        e_true[int(seg)] = p_old[7 * S + 3 * k:7 * S + 3 * k + 3]
+    P = 10 * S
+    params = np.concatenate([p_old[:7 * S], e_true.reshape(-1)]).astype(np.float32)
+    scale = np.concatenate([sc_old[:7 * S], np.full(3 * S, e_max, np.float32)]).astype(np.float32)
+    lo = np.concatenate([sc["lo"][:7 * S], np.zeros(3 * S, np.float32)]).astype(np.float32)
+    hi = np.concatenate([sc["hi"][:7 * S], np.ones(3 * S, np.float32)]).astype(np.float32)
+    tr = np.concatenate([sc["trainable"][:7 * S], np.ones(3 * S, np.uint8)]).astype(np.uint8)
+    out = dict(sc)
+    out.update(name=sc["name"] + "_all_emissive", emitter_seg=np.arange(S, dtype=np.int32), params=params,
+               scale=scale, lo=lo, hi=hi, trainable=tr, true_emitters=np.asarray(sc["emitter_seg"], np.int32))
+    assert params.size == P
+    return out
+
+
 # --------------------------------------------------------------------------
 # Closed-form test scenes and tiny meshes.
 # --------------------------------------------------------------------------
