@@ -282,7 +282,7 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
 
 
 def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, lr=5e-3, lam=1e-3, beta2=0.999,
-                           target=None, g=None, log=None, log_every=100, target_rmse=1e-2, cov=None):
+                           target=None, g=None, log=None, log_every=100, target_rmse=1e-2, cov=None, loss_kind=1):
     """The paper's own optimisation setting (Sec. 3, "Optimization Parameters";
     App. A): every segment emissive (scenes.all_emissive), albedo and
     emission initialised to zero, each iteration a batch of `batch` pixels
@@ -352,7 +352,7 @@ def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, lr=5e-3, la
         tgt = target.index_select(0, pix).contiguous()
         kw = dict(seed=1000 * seed + 17, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2, pixel_list=pix)
         g.loss_grad(dc, params, tgt, ipt.render_opts(stream_tag=TAG_A, **kw), ipt.render_opts(stream_tag=TAG_B, **kw),
-                    1, loss=loss, grad=grad)
+                    loss_kind, loss=loss, grad=grad)
         ipt.l1_reg(params, grad, w_l1, loss)
         ipt.sgd_step(params, grad, m, v, it + 1, lr=lr, beta2=beta2, scale=scale, lo=lo, hi=hi, trainable=tr)
         if it % 10 == 0 or it == iters - 1:
@@ -369,7 +369,8 @@ def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, lr=5e-3, la
     err = ((params - p_true) / scale).cpu().numpy()
     worst = [(int(i), float(err[i])) for i in np.argsort(-np.abs(err * head))[:6]]
     return dict(history=hist, time_to_target=t_hit, final_rmse=hist["rmse"][-1], seconds=hist["t"][-1],
-                iters=iters, seed=seed, n_head=int(head.sum()), worst=worst, batch=batch, spp=spp, lr=lr, lam=lam)
+                iters=iters, seed=seed, n_head=int(head.sum()), worst=worst, batch=batch, spp=spp, lr=lr, lam=lam,
+                loss_kind=loss_kind, beta2=beta2)
 
 
 def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, guide_mix=0.5, seed=555):
@@ -434,6 +435,7 @@ def main(argv=None):
                          "--spp paths each, L1 loss, L1 emission regulariser --lam, Adam lr 5e-3")
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lam", type=float, default=1e-3)
+    ap.add_argument("--loss", default="l1", choices=["l1", "l2"], help="image loss of the paper setting")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     sc = scenes.WORKLOADS[a.workload]()
@@ -449,7 +451,8 @@ def main(argv=None):
         for seed in a.seeds:
             res = optimize_paper_setting(sc, iters=a.iters or 2000, seed=seed, batch=a.batch, spp=a.spp or 512,
                                          lr=a.lr or 5e-3, lam=a.lam, beta2=a.beta2, target=target, g=g, log=log,
-                                         log_every=a.log_every, target_rmse=a.target_rmse, cov=cov)
+                                         log_every=a.log_every, target_rmse=a.target_rmse, cov=cov,
+                                         loss_kind=1 if a.loss == "l1" else 0)
             if a.out:
                 with open(a.out, "a") as f:
                     f.write(json.dumps(dict(workload=sc["name"], mode="paper_setting", **res)) + "\n")
