@@ -72,6 +72,17 @@ def measured_traffic(kernel, workload):
     return None
 
 
+def copy_reference(nbytes=256 << 20, launches=3):
+    """A copy kernel of known size: each launch reads and writes `nbytes`."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(launches):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_reference_bytes": nbytes, "launches": launches}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,7 +97,13 @@ def main():
                          "(one-sample MIS with BRDF sampling, mix 0.5), writes training records and runs "
                          "--guide-steps training steps")
     ap.add_argument("--guide-steps", type=int, default=10)
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only run a plain device copy of 256 MiB three times (the kernel whose FETCH_SIZE and "
+                         "WRITE_SIZE counters scale those of the path kernels to bytes) and exit")
     args = ap.parse_args()
+    if args.copy_reference:
+        copy_reference()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: multi-GPU runs are not part of this build "
@@ -255,7 +272,7 @@ def cpu_baseline(sc, cfg, params, target, budget_s):
               rr_depth=cfg["rr_depth"], mis=2)
     rng = np.random.default_rng(0)
     # probe with a small sample, then size the timed sample to the budget
-    stride = max(1, npix // 500)
+    stride = max(1, npix // 20000)
     pix = np.arange(0, npix, stride, dtype=np.int64)
     w = rng.normal(size=(pix.size, 3))
     t0 = time.time()
