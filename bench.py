@@ -97,6 +97,9 @@ def main():
                          "(one-sample MIS with BRDF sampling, mix 0.5), writes training records and runs "
                          "--guide-steps training steps")
     ap.add_argument("--guide-steps", type=int, default=10)
+    ap.add_argument("--guide-cells", type=int, default=0,
+                    help="with --guide: sample the cached proposal (about this many cells per side, refilled "
+                         "after each training call) instead of evaluating the network at every path vertex")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain device copy of 256 MiB three times (the kernel whose FETCH_SIZE and "
                          "WRITE_SIZE counters scale those of the path kernels to bytes) and exit")
@@ -158,20 +161,27 @@ def main():
     if args.guide:
         stride = max(1, (npix * spp * 3) // (1 << 20))   # about one million records per step
         gd = ipt.Guide(g, seed=7, batch=16384, ring_capacity=1 << 21, record_stride=stride)
+    cached = 1 if (gd is not None and args.guide_cells > 0) else 0
+    if cached:
+        from paper_1903_07145_amd.optimize import cell_area_for
+        gd.cache_build(cell_area_for(sc, args.guide_cells))   # allocates the cell table and rows
 
     def step(it):
         mix = 0.5 if (gd is not None and it >= 1) else 0.0
         co = ipt.render_opts(seed=11, stream_tag=1, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2,
-                             guide=gd if mix > 0 else None, guide_mix=mix)
+                             guide=gd if mix > 0 else None, guide_mix=mix, guide_cached=cached)
         go = ipt.render_opts(seed=11, stream_tag=2, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2,
-                             guide=gd, guide_mix=mix)
+                             guide=gd, guide_mix=mix, guide_cached=cached)
         g.loss_grad(dc, params, target, co, go, 0, loss=loss, grad=grad)
         ipt.sgd_step(params, grad, m, v, it + 1, lr=lr, scale=scale, lo=lo, hi=hi, trainable=tr)
         if gd is not None and gd.records() >= 16384:
             gd.train(args.guide_steps, want_loss=False)
+            if cached:
+                gd.cache_build(gd.cell_area)
 
     # workspace sized once, outside the timed region
-    g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr, guide=gd, guide_mix=0.5 if gd else 0.0))
+    g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr, guide=gd, guide_mix=0.5 if gd else 0.0,
+                                    guide_cached=cached))
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -242,7 +252,9 @@ def main():
             sc["name"], sc["tris"].shape[0], sc["num_segments"], len(sc["emitter_seg"]), V, W, H, spp, D,
             ", RR from %d" % rr if rr >= 0 else ""),
             "step": "ipt_loss_grad (colour A + L2 loss/adjoint + gradient B fwd/replay/reduce) + ipt_sgd_step" +
-                    (" + %d guide training steps; learned proposal mixed at 0.5" % args.guide_steps if gd else ""),
+                    (" + %d guide training steps; learned proposal mixed at 0.5" % args.guide_steps if gd else "") +
+                    (" (cached: %d cells per side, refilled after training)" % gd.cache_build(gd.cell_area)
+                     if cached else ""),
             "paths_per_step": {"colour": paths_step, "gradient": paths_step},
             "parallelism": "1 GPU"},
         "breakdown": {"colour_paths_per_s": round(paths_step / (ms_col * 1e-3), 1),

@@ -96,6 +96,9 @@ typedef struct {
     float *debug_vertices;    /* DEVICE [pixels*spp][max_depth+1][8] or NULL (ipt_render
                                  only): per vertex input triangle id, u, v, t and the
                                  path radiance accumulated so far */
+    int32_t guide_cached;     /* 1: sample the guide's cached proposal (rows built by
+                                 ipt_guide_cache_build for this scene) instead of
+                                 evaluating the network at every vertex; 0: per vertex */
 } ipt_render_opts;
 
 typedef struct {
@@ -241,6 +244,26 @@ typedef struct {
 ipt_status ipt_guide_create(ipt_scene_t scene, const ipt_guide_opts *opts, void *hip_stream,
                             ipt_guide_t *out);
 ipt_status ipt_guide_free(ipt_guide_t guide);
+/* Cached proposal: the network evaluated once per surface cell and side
+ * instead of at every path vertex.  Every triangle's barycentric domain is cut
+ * into n^2 sub-triangles (grid squares of side 1/n in (u, v), each halved by
+ * its anti-diagonal), n the smallest integer in [1, 64] with
+ * |e1 x e2| <= 2 n^2 cell_area (decided in float32: squares compared, fixed
+ * operation order, no contraction).  A cell's query is its centroid, the
+ * shading normal there (negated for the back side) and an outgoing direction
+ * along that normal.  With ipt_render_opts.guide_cached = 1 a path vertex
+ * samples and weights with the row of the cell and side it hit, so the
+ * estimator stays unbiased (the proposal is any density; only the density it
+ * was sampled from enters the weights).  The first call for a scene, or with a
+ * new cell_area, allocates the cell table and the rows (192 B per cell and
+ * side; at most 2^24 cells per side, else IPT_ERR_INVALID_ARG) and
+ * synchronises the stream once; later calls only refill the rows from the
+ * current weights and allocate nothing.  mode 0: bfloat16 MFMA network, 1:
+ * float32 VALU (reference).  *num_cells (HOST, nullable): cells per side.
+ * Rebuild after training steps; rows are read by the render calls on the
+ * same stream.  Not part of the paper's method. */
+ipt_status ipt_guide_cache_build(ipt_guide_t guide, ipt_scene_t scene, float cell_area, int32_t mode,
+                                 int64_t *num_cells, void *hip_stream);
 /* Mixture for n queries: feat [n][9] (DEVICE: normalised position, normal,
  * outgoing direction), seg [n] (DEVICE); out [n][40] (DEVICE) = per lobe
  * (mu xyz, kappa, weight).  mode 0: bfloat16 MFMA, 1: float32 VALU. */

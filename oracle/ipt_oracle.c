@@ -695,6 +695,9 @@ typedef struct {
     /* learned proposal: float32 network weights (16744 + 16 S values), the
      * probability of sampling it, and the scene box used for its features */
     const float *guide_w; double guide_mix; double bb_lo[3], bb_inv[3];
+    /* > 0: the proposal of a vertex is the network evaluated at the cell of
+     * the surface it lies in (cells of about this area), not at the vertex */
+    double guide_cell_area;
 } orc_opts;
 
 typedef struct { int32_t num_views, width, height; const float *cam_to_world; const float *fov_y; } orc_cams;
@@ -809,6 +812,83 @@ static void guide_eval_vertex(const orc_opts *o, int nseg, int seg, v3 x, v3 n, 
     for (int i = 0; i < 16; ++i) f[9 + i] = emb[16 * seg + i];
     guide_mlp(o->guide_w, f, mix);
     guide_mixture(mix);
+}
+
+/* Cells of the cached proposal.  A triangle's barycentric domain (x = p0 +
+ * u e1 + v e2) is cut into n^2 sub-triangles: grid squares of side 1/n in
+ * (u, v), each halved by its anti-diagonal.  n is the smallest integer in
+ * [1, 64] with |e1 x e2| <= 2 n^2 cell_area, i.e. every cell has at most the
+ * given area; the comparison is made on squares in float32 with a fixed
+ * operation order, so that the integer comes out the same wherever it is
+ * computed. */
+static int cell_subdiv(const orc_scene *s, int64_t t, float cell_area)
+{
+    const int32_t *f = &s->F[3 * t];
+    float p[3][3];
+    for (int k = 0; k < 3; ++k)
+        for (int c = 0; c < 3; ++c) p[k][c] = (float)s->P[3 * (int64_t)f[k] + c];
+    float e1[3], e2[3];
+    for (int c = 0; c < 3; ++c) { e1[c] = p[1][c] - p[0][c]; e2[c] = p[2][c] - p[0][c]; }
+    float cx = e1[1] * e2[2] - e1[2] * e2[1];
+    float cy = e1[2] * e2[0] - e1[0] * e2[2];
+    float cz = e1[0] * e2[1] - e1[1] * e2[0];
+    float a2 = (cx * cx + cy * cy) + cz * cz;
+    float two = 2.0f * cell_area;
+    int n = 1;
+    for (; n < 64; ++n) {
+        float q = (float)(n * n) * two;
+        if (q * q >= a2) break;
+    }
+    return n;
+}
+
+/* Query point of the cell holding barycentrics (u, v) of triangle t: the
+ * cell's centroid, the shading normal there (negated on the back side) and
+ * the outgoing direction along it.  *mg collects the distance of (u, v) to
+ * the cell boundaries (near-tie margin). */
+static void cell_query(const orc_scene *s, int64_t t, double u, double v, int back, float cell_area,
+                       v3 *xq, v3 *nq, double *mg)
+{
+    const int n = cell_subdiv(s, t, cell_area);
+    const double x = u * n, y = v * n;
+    int i = (int)floor(x), j;
+    if (i < 0) i = 0;
+    if (i > n - 1) i = n - 1;
+    j = (int)floor(y);
+    if (j < 0) j = 0;
+    if (j > n - 1 - i) j = n - 1 - i;
+    const double fx = x - i, fy = y - j;
+    const int up = (i + j < n - 1) && (fx + fy > 1.0);
+    if (mg) {
+        double m = fmin(fabs(x - nearbyint(x)), fabs(y - nearbyint(y)));
+        if (i + j < n - 1) m = fmin(m, fabs(fx + fy - 1.0));
+        m /= n;
+        if (m < *mg) *mg = m;
+    }
+    const double o = up ? 2.0 / 3.0 : 1.0 / 3.0;
+    const double uc = (i + o) / n, vc = (j + o) / n;
+    const int32_t *f = &s->F[3 * t];
+    v3 p0 = vtx(s, f[0]), p1 = vtx(s, f[1]), p2 = vtx(s, f[2]);
+    v3 e1 = sub(p1, p0), e2 = sub(p2, p0);
+    *xq = add(p0, add(scl(e1, uc), scl(e2, vc)));
+    v3 ns = nrm(cross(e1, e2));
+    if (s->N) {
+        v3 n0 = mk(s->N[3 * (int64_t)f[0]], s->N[3 * (int64_t)f[0] + 1], s->N[3 * (int64_t)f[0] + 2]);
+        v3 n1 = mk(s->N[3 * (int64_t)f[1]], s->N[3 * (int64_t)f[1] + 1], s->N[3 * (int64_t)f[1] + 2]);
+        v3 n2 = mk(s->N[3 * (int64_t)f[2]], s->N[3 * (int64_t)f[2] + 1], s->N[3 * (int64_t)f[2] + 2]);
+        ns = nrm(add(scl(n0, 1.0 - uc - vc), add(scl(n1, uc), scl(n2, vc))));
+    }
+    *nq = back ? scl(ns, -1.0) : ns;
+}
+
+/* Exported for tests: subdivision of triangle t and the query (position,
+ * normal) of the cell holding (u, v) on the given side. */
+int orc_cell_query(const orc_scene *s, int64_t t, double u, double v, int back, float cell_area, double out[6])
+{
+    v3 xq, nq;
+    cell_query(s, t, u, v, back, cell_area, &xq, &nq, NULL);
+    out[0] = xq.x; out[1] = xq.y; out[2] = xq.z; out[3] = nq.x; out[4] = nq.y; out[5] = nq.z;
+    return cell_subdiv(s, t, cell_area);
 }
 
 /* Exported for tests: mixture parameters for n feature rows [n][9] + segments. */
@@ -1008,7 +1088,14 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
         /* --- learned proposal for this vertex (one-sample MIS with the BRDF) --- */
         double gmix[G_OUT];
         const int guided = C->o->guide_w && C->o->guide_mix > 0;
-        if (guided) guide_eval_vertex(C->o, s->ns, seg, x, ns, wo, gmix);
+        if (guided && C->o->guide_cell_area > 0) {
+            v3 xq, nq;
+            cell_query(s, hit.tri, hit.u, hit.v, dot(ng, wo) < 0, (float)C->o->guide_cell_area, &xq, &nq,
+                       M ? &mg : NULL);
+            guide_eval_vertex(C->o, s->ns, seg, xq, nq, nq, gmix);
+        } else if (guided) {
+            guide_eval_vertex(C->o, s->ns, seg, x, ns, wo, gmix);
+        }
         const double cg = guided ? C->o->guide_mix : 0.0;
         /* --- explicit light sampling (next-event estimation) --- */
         if (mis != 0 && s->nlt > 0) {

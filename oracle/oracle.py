@@ -70,6 +70,9 @@ def lib():
         L.orc_mixture_pdf.restype = ctypes.c_double
         L.orc_mixture_pdf.argtypes = [P, P]
         L.orc_mixture_sample.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        L.orc_cell_query.restype = ctypes.c_int
+        L.orc_cell_query.argtypes = [P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_float, P]
         _lib = L
     return _lib
 
@@ -86,7 +89,8 @@ class _Opts(ctypes.Structure):
                 ("jitter", ctypes.c_int32), ("brute_force", ctypes.c_int32),
                 ("pixel_list", ctypes.c_void_p), ("num_pixels", ctypes.c_int64),
                 ("guide_w", ctypes.c_void_p), ("guide_mix", ctypes.c_double),
-                ("bb_lo", ctypes.c_double * 3), ("bb_inv", ctypes.c_double * 3)]
+                ("bb_lo", ctypes.c_double * 3), ("bb_inv", ctypes.c_double * 3),
+                ("guide_cell_area", ctypes.c_double)]
 
 
 class _Cams(ctypes.Structure):
@@ -218,6 +222,14 @@ class Scene:
             return tri, out, float(mg[0])
         return tri, out
 
+    def cell_query(self, tri, u, v, back, cell_area):
+        """Cached-proposal cell of barycentrics (u, v) on input triangle tri:
+        (subdivision n, query position [3], query normal [3])."""
+        out = np.zeros(6)
+        n = lib().orc_cell_query(self.h, int(tri), float(u), float(v), int(bool(back)),
+                                 float(np.float32(cell_area)), _ptr(out))
+        return n, out[:3], out[3:]
+
     def light_probs(self, sampling_params):
         sp = np.ascontiguousarray(sampling_params, dtype=np.float64)
         out = np.zeros(self.num_light_tris)
@@ -228,7 +240,7 @@ class Scene:
             spp=4, max_depth=3, rr_depth=-1, mis=2, emission_profile=0, jitter=1,
             brute_force=False, pixel_list=None, w=None, path_mask=None, want_grad=False,
             want_hash=False, want_path_L=False, want_margin=False, want_cond=False,
-            want_vertices=False, guide_w=None, guide_mix=0.0, bb_lo=None, bb_inv=None):
+            want_vertices=False, guide_w=None, guide_mix=0.0, bb_lo=None, bb_inv=None, guide_cell_area=0.0):
         """Render (and optionally differentiate) pixels.
 
         cams: dict with cam_to_world [V,4,4] float32, fov_y [V], width, height.
@@ -254,7 +266,8 @@ class Scene:
         O = _Opts(seed, stream_tag, iteration, spp, max_depth, rr_depth, mis, emission_profile,
                   jitter, int(brute_force), _ptr(pl), 0 if pl is None else pl.size, _ptr(gw),
                   float(guide_mix), (ctypes.c_double * 3)(*(bb_lo if bb_lo is not None else (0, 0, 0))),
-                  (ctypes.c_double * 3)(*(bb_inv if bb_inv is not None else (1, 1, 1))))
+                  (ctypes.c_double * 3)(*(bb_inv if bb_inv is not None else (1, 1, 1))),
+                  float(np.float32(guide_cell_area)))
         p = np.ascontiguousarray(params, dtype=np.float64)
         sp = None if sampling_params is None else np.ascontiguousarray(sampling_params,
                                                                          dtype=np.float64)

@@ -46,6 +46,9 @@ float* guide_records(ipt_guide_s* g);
 unsigned* guide_record_count(ipt_guide_s* g);
 int guide_capacity(const ipt_guide_s* g);
 int guide_record_stride(const ipt_guide_s* g);
+int guide_cache_ready(const ipt_guide_s* g, const void* scene);
+ipt_status guide_cache_build_impl(ipt_guide_s* g, const void* scene, const float4* tris, const float4* nrm,
+                                  int64_t nt, float cell_area, int mode, hipStream_t st, int64_t* ncells);
 ipt_status ipt_fail(ipt_status s, const char* msg) { return fail(s, "%s", msg); }
 
 struct ipt_scene_s {
@@ -350,6 +353,9 @@ static ipt_status check_opts(const ipt_scene_s* s, const ipt_cameras* cams, cons
         return fail(IPT_ERR_NOT_SUPPORTED, "a guided gradient replays from vertex checkpoints only");
     if (!(o->guide_mix >= 0.0f && o->guide_mix < 1.0f)) return fail(IPT_ERR_INVALID_ARG, "guide_mix must be in [0, 1)");
     if (o->guide_mix > 0.0f && !o->guide) return fail(IPT_ERR_INVALID_ARG, "guide_mix > 0 needs a guide");
+    if (o->guide_cached != 0 && o->guide_cached != 1) return fail(IPT_ERR_INVALID_ARG, "guide_cached must be 0 or 1");
+    if (o->guide && o->guide_mix > 0.0f && o->guide_cached && !guide_cache_ready(o->guide, s))
+        return fail(IPT_ERR_INVALID_ARG, "guide_cached: no cached proposal built for this scene (ipt_guide_cache_build)");
     int64_t all = (int64_t)cams->num_views * cams->width * cams->height;
     if (o->pixel_list) {
         if (o->num_pixels < 1) return fail(IPT_ERR_INVALID_ARG, "num_pixels must be >= 1 with a pixel list");
@@ -357,8 +363,14 @@ static ipt_status check_opts(const ipt_scene_s* s, const ipt_cameras* cams, cons
     } else {
         *npix = all;
     }
-    (void)s;
     return IPT_OK;
+}
+
+// Which proposal the path kernels evaluate: 0 none sampled, 1 network per
+// vertex (bfloat16 MFMA), 2 network per vertex (float32 VALU), 3 cached rows.
+static int guide_kind(const ipt_render_opts* o) {
+    if (!o->guide || !(o->guide_mix > 0.0f)) return 0;
+    return o->guide_cached ? 3 : (o->guide_fp32 ? 2 : 1);
 }
 
 static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -373,9 +385,9 @@ struct Plan {
 
 // Persistent grid: blocks per CU from the occupancy calculator (at most 8),
 // or IPT_BLOCKS_PER_CU when set (tuning).
-static int path_grid(const ipt_scene_s* s, int P, int frozen, int guided) {
-    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, guided), guided);
-    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, guided), guided));
+static int path_grid(const ipt_scene_s* s, int P, int frozen, int gk) {
+    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, gk), gk);
+    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, gk), gk));
     static const int forced = [] {
         const char* e = std::getenv("IPT_BLOCKS_PER_CU");
         return e ? std::atoi(e) : 0;
@@ -399,7 +411,7 @@ static void split_samples(int64_t npix, int spp, int grid, int& spc, int& nchunk
 static void make_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t npix, bool with_loss, Plan& pl) {
     int P = 7 * s->S + 3 * s->E;
     const int guided = o->guide != nullptr;
-    pl.grid = path_grid(s, P, 1, guided && o->guide_mix > 0.0f);
+    pl.grid = path_grid(s, P, 1, guide_kind(o));
     size_t off = 0;
     pl.off_counters = off; off = al256(off + 64 * sizeof(unsigned));
     pl.off_cdf = off; off = al256(off + 2 * sizeof(float) * std::max(1, s->nlt));   // prefix sums, probabilities
@@ -470,7 +482,7 @@ static PathArgs base_args(const ipt_scene_s* s, const ipt_cameras* cams, const f
     a.replay_traverse = o->replay_traverse;
     a.guided = o->guide != nullptr;
     a.gmix = a.guided ? o->guide_mix : 0.0f;
-    a.guide_fp32 = o->guide_fp32;
+    a.guide_kind = guide_kind(o);
     if (a.guided) a.gd = guide_dev(o->guide);
     return a;
 }
@@ -486,7 +498,7 @@ static ipt_status do_render(ipt_scene_t s, const ipt_cameras* cams, const float*
     a.part = a.nchunk > 1 ? (float*)(ws + pl.off_part) : nullptr;
     HIP_OK(launch_light_cdf(s->dev, a.sparams, (float*)(ws + pl.off_cdf), st));
     HIP_OK(launch_zero_u32(a.work, 1, st));
-    size_t lds = path_lds_bytes(kColor, a.P, a.frozen, s->S, s->nlt, a.guided && a.gmix > 0.0f);
+    size_t lds = path_lds_bytes(kColor, a.P, a.frozen, s->S, s->nlt, a.guide_kind);
     int grid = (int)std::min<int64_t>(pl.grid, (npix * a.nchunk + kBlock - 1) / kBlock);
     HIP_OK(timed_launch(s, kColor, a, std::max(1, grid), lds, st));
     if (a.nchunk > 1) HIP_OK(launch_colour_reduce(a.part, a.nchunk, npix, o->spp, image, st));
@@ -518,7 +530,7 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
         a.grec_stride = guide_record_stride(o->guide);
     }
     HIP_OK(launch_light_cdf(s->dev, a.sparams, (float*)(ws + pl.off_cdf), st));
-    size_t lds_f = path_lds_bytes(kGradFwd, a.P, a.frozen, s->S, s->nlt, a.guided && a.gmix > 0.0f);
+    size_t lds_f = path_lds_bytes(kGradFwd, a.P, a.frozen, s->S, s->nlt, a.guide_kind);
     size_t lds_r = path_lds_bytes(kReplay, a.P, a.frozen, s->S, s->nlt);
     for (int64_t b = 0; b < npix; b += chunk) {
         a.pix_begin = b;
@@ -662,6 +674,12 @@ extern "C" ipt_status ipt_profile_read(ipt_scene_t s, int32_t kernel, ipt_kernel
 
 ipt_status guide_create_impl(int S, const float lo[3], const float hi[3], const ipt_guide_opts* o, void* stream,
                              ipt_guide_t* out);
+
+extern "C" ipt_status ipt_guide_cache_build(ipt_guide_t g, ipt_scene_t s, float cell_area, int32_t mode,
+                                            int64_t* num_cells, void* stream) {
+    if (!g || !s) return fail(IPT_ERR_INVALID_ARG, "NULL guide or scene");
+    return guide_cache_build_impl(g, s, s->d_tris, s->d_nrm, s->nt, cell_area, mode, (hipStream_t)stream, num_cells);
+}
 
 extern "C" ipt_status ipt_guide_create(ipt_scene_t s, const ipt_guide_opts* o, void* stream, ipt_guide_t* out) {
     if (!s || !o || !out) return fail(IPT_ERR_INVALID_ARG, "NULL argument");

@@ -22,6 +22,7 @@
 namespace ipt {
 
 constexpr int kRecF = 16;   // floats per training record
+constexpr long long kMaxCacheCells = 1ll << 24;   // cached proposal: cells per side
 
 // ---------------------------------------------------------------------------
 // Requantisation: float32 master -> bfloat16 operand copies.
@@ -89,6 +90,103 @@ __global__ __launch_bounds__(256) void guide_eval_fp32_kernel(GuideDev gd, const
         float* o = out + kGOut * i;
         guide_mlp_fp32(gd, f, seg[i], o);
         mixture_from_raw(o);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cached proposal: cell table (count, scan) and rows (network per cell and
+// side).  The query of a cell is its centroid, the shading normal there
+// (geometric normal without vertex normals), both negated for the back side,
+// and the outgoing direction taken along that normal.
+// ---------------------------------------------------------------------------
+__global__ void cell_count_kernel(const float4* tris, int64_t nt, float cell_area, int2* cells) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nt) return;
+    const V3 p0 = xyz(tris[3 * t]), p1 = xyz(tris[3 * t + 1]), p2 = xyz(tris[3 * t + 2]);
+    const int n = cell_subdiv(p1 - p0, p2 - p0, cell_area);
+    cells[t] = make_int2(n * n, n);
+}
+
+// Exclusive scan of the cell counts (x) in place, in triangle order, by one
+// block; *total = number of cells.
+__global__ __launch_bounds__(1024) void cell_scan_kernel(int2* cells, int64_t nt, long long* total) {
+    __shared__ long long part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (nt + 1023) / 1024;
+    const int64_t b = min(nt, (int64_t)tid * per), e = min(nt, b + per);
+    long long sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += cells[i].x;
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const long long v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    long long run = part[tid] - sum;
+    for (int64_t i = b; i < e; ++i) {
+        const int c = cells[i].x;
+        cells[i].x = (int)run;
+        run += c;
+    }
+    if (tid == 1023) *total = part[1023];
+}
+
+// Features and segment of cache row r (cell r / 2, side r % 2).
+__device__ __forceinline__ void cell_query(const GuideDev& gd, const float4* tris, const float4* nrm, int64_t nt,
+                                           int64_t r, float f[9], int& seg) {
+    const int64_t c = r >> 1;
+    int64_t lo = 0, hi = nt - 1;   // last triangle whose first cell is <= c
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)gd.cells[mid].x <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t t = lo;
+    const int2 cr = gd.cells[t];
+    float u, v;
+    cell_centroid((int)(c - cr.x), cr.y, u, v);
+    const float4 a0 = tris[3 * t], a1 = tris[3 * t + 1], a2 = tris[3 * t + 2];
+    const V3 p0 = xyz(a0), e1 = xyz(a1) - p0, e2 = xyz(a2) - p0;
+    const V3 x = p0 + e1 * u + e2 * v;
+    V3 ng = normalize(cross(e1, e2));
+    V3 ns = ng;
+    if (nrm) ns = normalize(xyz(nrm[3 * t]) * (1.0f - u - v) + xyz(nrm[3 * t + 1]) * u + xyz(nrm[3 * t + 2]) * v);
+    if (r & 1) ns = ns * -1.0f;
+    seg = __float_as_int(a1.w);
+    guide_features(gd, x, ns, ns, f);
+}
+
+__global__ __launch_bounds__(256) void guide_cache_fill_kernel(GuideDev gd, const float4* tris, const float4* nrm,
+                                                                int64_t nt, int64_t nrows, float* out) {
+    __shared__ __align__(16) __bf16 act_all[4 * 64 * kGRowStride];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __bf16* act = act_all + wave * 64 * kGRowStride;
+    for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64; base < nrows; base += (int64_t)gridDim.x * 256) {
+        const int64_t r = base + lane;
+        const bool ok = r < nrows;
+        float f[9];
+        int sg = 0;
+        cell_query(gd, tris, nrm, nt, ok ? r : nrows - 1, f, sg);
+        guide_put_inputs(gd, act, f, sg);
+        guide_mlp_wave(gd, act);
+        float* row = (float*)(act + lane * kGRowStride);
+        mixture_from_raw(row);
+        if (ok) write_cache_row(row, out + (size_t)r * kCacheRow);
+    }
+}
+
+__global__ __launch_bounds__(256) void guide_cache_fill_fp32_kernel(GuideDev gd, const float4* tris,
+                                                                     const float4* nrm, int64_t nt, int64_t nrows,
+                                                                     float* out) {
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * 256) {
+        float f[9], y[kGOut];
+        int sg = 0;
+        cell_query(gd, tris, nrm, nt, r, f, sg);
+        guide_mlp_fp32(gd, f, sg, y);
+        mixture_from_raw(y);
+        write_cache_row(y, out + (size_t)r * kCacheRow);
     }
 }
 
@@ -395,6 +493,14 @@ struct ipt_guide_s {
     uint64_t seed = 0;
     int step = 0;
     float last_loss = 0.0f;
+    // cached proposal (ipt_guide_cache_build)
+    const void* cache_scene = nullptr;
+    int64_t cache_nt = 0;
+    float cache_area = 0.0f;
+    int2* cells = nullptr;            // per leaf-ordered triangle: (first cell, n)
+    float* cache = nullptr;           // [2 cache_cells][kCacheRow]
+    long long* cache_total = nullptr;
+    int64_t cache_cells = 0;
 };
 
 extern "C" const char* ipt_last_error(void);
@@ -408,8 +514,11 @@ GuideDev guide_dev(const ipt_guide_s* g) {
     d.embb = g->embb;
     d.lo = g->lo;
     d.inv = g->inv;
+    d.cache = g->cache;
+    d.cells = g->cells;
     return d;
 }
+int guide_cache_ready(const ipt_guide_s* g, const void* scene) { return g->cache && g->cache_scene == scene; }
 float* guide_records(ipt_guide_s* g) { return g->rec; }
 unsigned* guide_record_count(ipt_guide_s* g) { return g->rec_count; }
 int guide_capacity(const ipt_guide_s* g) { return g->cap; }
@@ -504,7 +613,57 @@ extern "C" ipt_status ipt_guide_free(ipt_guide_t g) {
     hipFree(g->w); hipFree(g->m); hipFree(g->v); hipFree(g->g);
     hipFree(g->wb); hipFree(g->embb); hipFree(g->rec); hipFree(g->rec_count); hipFree(g->scal);
     hipFree(g->gpart);
+    hipFree(g->cells); hipFree(g->cache); hipFree(g->cache_total);
     delete g;
+    return IPT_OK;
+}
+
+// Cell table (when the scene or the cell area changed: allocates) and rows
+// (every call: refilled from the current weights; allocates nothing).
+ipt_status guide_cache_build_impl(ipt_guide_s* g, const void* scene, const float4* tris, const float4* nrm,
+                                  int64_t nt, float cell_area, int mode, hipStream_t st, int64_t* ncells) {
+    if (!(cell_area > 0.0f) || !std::isfinite(cell_area) || (mode != 0 && mode != 1) || nt < 1)
+        return ipt_fail(IPT_ERR_INVALID_ARG, "guide cache: cell_area > 0, mode 0 or 1, non-empty scene");
+    hipError_t e = hipSuccess;
+    if (!g->cache || g->cache_scene != scene || g->cache_nt != nt || g->cache_area != cell_area) {
+        hipFree(g->cells); hipFree(g->cache); hipFree(g->cache_total);
+        g->cells = nullptr; g->cache = nullptr; g->cache_total = nullptr;
+        g->cache_scene = nullptr; g->cache_cells = 0;
+        e = hipMalloc((void**)&g->cells, sizeof(int2) * (size_t)nt);
+        if (e == hipSuccess) e = hipMalloc((void**)&g->cache_total, 64);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(cell_count_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, tris, nt,
+                               cell_area, g->cells);
+            hipLaunchKernelGGL(cell_scan_kernel, dim3(1), dim3(1024), 0, st, g->cells, nt, g->cache_total);
+            e = hipGetLastError();
+        }
+        long long total = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&total, g->cache_total, sizeof(total), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess && total > kMaxCacheCells) {
+            hipFree(g->cells); hipFree(g->cache_total);
+            g->cells = nullptr; g->cache_total = nullptr;
+            return ipt_fail(IPT_ERR_INVALID_ARG, "guide cache: more than 2^24 cells; use a larger cell_area");
+        }
+        if (e == hipSuccess) e = hipMalloc((void**)&g->cache, sizeof(float) * kCacheRow * 2 * (size_t)total);
+        if (e != hipSuccess)
+            return ipt_fail(e == hipErrorOutOfMemory ? IPT_ERR_OUT_OF_MEMORY : IPT_ERR_HIP, hipGetErrorString(e));
+        g->cache_scene = scene;
+        g->cache_nt = nt;
+        g->cache_area = cell_area;
+        g->cache_cells = total;
+    }
+    const int64_t nrows = 2 * g->cache_cells;
+    const int blocks = (int)std::min<int64_t>((nrows + 255) / 256, 8192);
+    if (mode == 0)
+        hipLaunchKernelGGL(guide_cache_fill_kernel, dim3(blocks), dim3(256), 0, st, guide_dev(g), tris, nrm, nt,
+                           nrows, g->cache);
+    else
+        hipLaunchKernelGGL(guide_cache_fill_fp32_kernel, dim3(blocks), dim3(256), 0, st, guide_dev(g), tris, nrm,
+                           nt, nrows, g->cache);
+    e = hipGetLastError();
+    if (e != hipSuccess) return ipt_fail(IPT_ERR_HIP, hipGetErrorString(e));
+    if (ncells) *ncells = g->cache_cells;
     return IPT_OK;
 }
 

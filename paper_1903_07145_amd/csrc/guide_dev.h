@@ -62,12 +62,25 @@ constexpr int kGRowStride = 80;   // LDS activation row: 64 bf16 + pad (bank spr
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Cached proposal: the network evaluated once per surface cell and side.
+// Cells cut a triangle's barycentric domain into n^2 sub-triangles, n the
+// smallest integer in [1, kCellMaxN] with area / n^2 <= cell_area; a row
+// per (cell, side) holds the cell's mixture ready for the path kernels.
+// Row layout (48 float32, 192 B): per lobe j (mu xyz, kappa) at 4 j, then
+// lw[8] = log(weight_j * kappa_j / (2 pi (1 - e^{-2 kappa_j}))) at 32, then
+// the cumulative weights cw[8] at 40.  Density: sum_j exp(kappa_j (mu_j.w
+// - 1) + lw_j), one exponential per lobe.
+constexpr int kCacheRow = 48;
+constexpr int kCellMaxN = 64;
+
 struct GuideDev {
     const float* w;          // float32 master parameters [kGParams]
     const float* emb;        // [S][16]
     const __bf16* wb;        // bfloat16 copies [kGBf16]
     const __bf16* embb;      // [S][16] bfloat16
     float3 lo, inv;          // scene box: p_n = 2 (p - lo) * inv - 1
+    const float* cache;      // cached proposal rows [2 cells][kCacheRow] or NULL
+    const int2* cells;       // per leaf-ordered triangle: (first cell, n)
 };
 
 __device__ __forceinline__ float softplus(float x) { return x > 20.0f ? x : log1pf(expf(x)); }
@@ -245,6 +258,139 @@ __device__ __forceinline__ void guide_put_inputs(const GuideDev& gd, __bf16* act
     for (int i = 0; i < kGEmb; ++i) row[9 + i] = gd.embb[kGEmb * seg + i];
 #pragma unroll
     for (int i = kGIn; i < kGK1; ++i) row[i] = (__bf16)0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Cached proposal.
+// ---------------------------------------------------------------------------
+// Subdivision of a triangle with edges e1, e2: the smallest n in [1,
+// kCellMaxN] with |e1 x e2| <= 2 n^2 cell_area, decided in float32 with a
+// fixed operation order and no contraction (squared, so no square root).
+__device__ __forceinline__ int cell_subdiv(V3 e1, V3 e2, float cell_area) {
+#pragma clang fp contract(off)
+    const float cx = e1.y * e2.z - e1.z * e2.y;
+    const float cy = e1.z * e2.x - e1.x * e2.z;
+    const float cz = e1.x * e2.y - e1.y * e2.x;
+    const float a2 = (cx * cx + cy * cy) + cz * cz;
+    const float two = 2.0f * cell_area;
+    int n = 1;
+    for (; n < kCellMaxN; ++n) {
+        const float q = (float)(n * n) * two;
+        if (q * q >= a2) break;
+    }
+    return n;
+}
+
+// Cell of barycentrics (u, v) (x = p0 + u e1 + v e2) in a triangle cut into
+// n^2 sub-triangles: grid square (i, j) = (floor(n u), floor(n v)), lower
+// half (fractions summing to <= 1) or upper half; row i holds 2 (n - i) - 1
+// cells starting at 2 n i - i^2, lower half j at 2 j, upper half at 2 j + 1.
+__device__ __forceinline__ int cell_of(float u, float v, int n) {
+    const float x = u * (float)n, y = v * (float)n;
+    int i = min(max((int)x, 0), n - 1);
+    int j = min(max((int)y, 0), n - 1 - i);
+    const float fx = x - (float)i, fy = y - (float)j;
+    const int up = (i + j < n - 1 && fx + fy > 1.0f) ? 1 : 0;
+    return 2 * n * i - i * i + 2 * j + up;
+}
+
+// Barycentric centroid of cell c of an n^2 subdivision.
+__device__ __forceinline__ void cell_centroid(int c, int n, float& u, float& v) {
+    int i = 0;
+    while (c >= 2 * (n - i) - 1) {
+        c -= 2 * (n - i) - 1;
+        ++i;
+    }
+    const int j = c >> 1;
+    const float o = (c & 1) ? (2.0f / 3.0f) : (1.0f / 3.0f);
+    u = ((float)i + o) / (float)n;
+    v = ((float)j + o) / (float)n;
+}
+
+// Row of the cached proposal for a hit on leaf-ordered triangle tri at (u,
+// v), seen from its back side (geometric normal facing away) when back.
+__device__ __forceinline__ const float* cache_row_at(const GuideDev& gd, int tri, float u, float v, bool back) {
+    const int2 cr = gd.cells[tri];
+    const int64_t c = (int64_t)cr.x + cell_of(u, v, cr.y);
+    return gd.cache + (size_t)(2 * c + (back ? 1 : 0)) * kCacheRow;
+}
+
+// The row is read lobe by lobe (not unrolled): the path kernels keep their
+// state in registers, and holding all 48 values would spill it.
+__device__ __forceinline__ float cached_pdf(const float* row, V3 w) {
+    const float4* r = (const float4*)row;
+    float q = 0.0f;
+#pragma unroll 1
+    for (int j = 0; j < kGLobes; ++j) {
+        const float4 m = r[j];
+        q += __expf(m.w * ((m.x * w.x + m.y * w.y + m.z * w.z) - 1.0f) + row[32 + j]);
+    }
+    return q;
+}
+
+// Densities of two directions in one pass over the row (each lobe read
+// once): the continuation direction and the light sample of a vertex.
+#ifndef IPT_CACHE_UNROLL
+#define IPT_CACHE_UNROLL 2
+#endif
+__device__ __forceinline__ void cached_pdf2(const float* row, V3 w1, V3 w2, float& q1, float& q2) {
+    const float4* r = (const float4*)row;
+    float a = 0.0f, b = 0.0f;
+#pragma unroll IPT_CACHE_UNROLL
+    for (int j = 0; j < kGLobes; ++j) {
+        const float4 m = r[j];
+        const float lw = row[32 + j];
+        a += __expf(m.w * ((m.x * w1.x + m.y * w1.y + m.z * w1.z) - 1.0f) + lw);
+        b += __expf(m.w * ((m.x * w2.x + m.y * w2.y + m.z * w2.z) - 1.0f) + lw);
+    }
+    q1 = a;
+    q2 = b;
+}
+
+// Lobe by u3 against the cumulative weights, then the vMF sample by (u4, u5)
+// (the same steps as mixture_sample).
+__device__ __forceinline__ V3 cached_sample(const float* row, float u3, float u4, float u5) {
+    const float4* r = (const float4*)row;
+    const float4 c0 = r[10], c1 = r[11];
+    int j = kGLobes - 1;
+    if (u3 < c1.z) j = 6;
+    if (u3 < c1.y) j = 5;
+    if (u3 < c1.x) j = 4;
+    if (u3 < c0.w) j = 3;
+    if (u3 < c0.z) j = 2;
+    if (u3 < c0.y) j = 1;
+    if (u3 < c0.x) j = 0;
+    const float4 m = r[j];
+    V3 mu = v3(m.x, m.y, m.z);
+    const float kappa = m.w;
+    float w = 1.0f + log1pf(-(1.0f - u4) * -expm1f(-2.0f * kappa)) / kappa;
+    w = fminf(fmaxf(w, -1.0f), 1.0f);
+    const float sw = sqrtf(fmaxf(0.0f, 1.0f - w * w));
+    float s, c;
+    sincospif(2.0f * u5, &s, &c);
+    V3 t, b;
+    onb(mu, t, b);
+    return t * (sw * c) + b * (sw * s) + mu * w;
+}
+
+// Mixture (per lobe mu xyz, kappa, weight) -> cached row.
+__device__ __forceinline__ void write_cache_row(const float* mix, float* out) {
+    float4* o = (float4*)out;
+    float lw[8], cw[8];
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kGLobes; ++j) {
+        const float* l = mix + 5 * j;
+        const float kappa = l[3];
+        o[j] = make_float4(l[0], l[1], l[2], kappa);
+        lw[j] = logf(l[4]) + logf(kappa / (2.0f * kPi * (-expm1f(-2.0f * kappa))));
+        acc += l[4];
+        cw[j] = acc;
+    }
+    o[8] = make_float4(lw[0], lw[1], lw[2], lw[3]);
+    o[9] = make_float4(lw[4], lw[5], lw[6], lw[7]);
+    o[10] = make_float4(cw[0], cw[1], cw[2], cw[3]);
+    o[11] = make_float4(cw[4], cw[5], cw[6], cw[7]);
 }
 
 }  // namespace ipt

@@ -85,7 +85,8 @@ struct PathArgs {
     // learned proposal (one-sample MIS with BRDF sampling)
     GuideDev gd;
     int guided;                    // a guide is attached (checkpoint plane ck_d is written)
-    int guide_fp32;                // evaluate it in float32 on VALU
+    int guide_kind;                // proposal sampled: 0 none, 1 network (bfloat16 MFMA), 2 network
+                                   // (float32 VALU), 3 cached rows
     float gmix;                    // probability of sampling the guide
     float4* ck_d;                  // guided: [(k-1)*spp + s][pix_count] (sampled direction, NEE density)
     float* grec;                   // training-record ring [cap][16] or NULL
@@ -93,8 +94,8 @@ struct PathArgs {
     int grec_cap, grec_stride;
 };
 
-size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guided = 0);
-int path_blocks_per_cu(int mode, size_t lds, int guided = 0);
+size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guide_kind = 0);
+int path_blocks_per_cu(int mode, size_t lds, int guide_kind = 0);
 hipError_t launch_guide_records(const PathArgs& a, hipStream_t st);
 hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st);
 // guide handle internals (guide.hip)

@@ -47,7 +47,7 @@ struct Lds {
 // per-wave guide activation rows (64 x kGRowStride bf16), 4 waves per block
 constexpr size_t kGuideLds = 4 * 64 * kGRowStride * sizeof(__bf16);
 
-size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guided) {
+size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int gk) {
     size_t b = 0;
     auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
     b += al(sizeof(float) * P);                       // params
@@ -56,7 +56,7 @@ size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guided) {
     if (nlt <= kMaxLdsLights) b += al(2 * sizeof(float) * nlt) + al(sizeof(int4) * nlt);
     if (mode == kReplay) b += al(sizeof(double) * P); // block gradient
     b += sizeof(int) * kShortStack * kBlock;          // short stacks
-    if (guided && mode != kReplay) b += kGuideLds;     // guide activations
+    if ((gk == 1 || gk == 2) && mode != kReplay) b += kGuideLds;   // network activations / outputs
     return b;
 }
 
@@ -452,24 +452,71 @@ __device__ __forceinline__ ContS cont_eval(const PathArgs& a, const Shade& g, co
 // lobe mixture at sampling parameters.  With a guide: the technique is the
 // guide with probability gmix (u[7]), the BRDF otherwise, and the density is
 // the combined gmix q + (1 - gmix) p_brdf (one-sample MIS).
+// Density and sample of the proposal: the mixture of the network's outputs
+// (per-vertex kinds) or a cached row (kind 3).
+template <int GUIDE>
+__device__ __forceinline__ float guide_pdf(const float* mix, V3 w) {
+    if (GUIDE == 3) return cached_pdf(mix, w);
+    return mixture_pdf(mix, w);
+}
+template <int GUIDE>
+__device__ __forceinline__ V3 guide_sample(const float* mix, float u3, float u4, float u5) {
+    if (GUIDE == 3) return cached_sample(mix, u3, u4, u5);
+    return mixture_sample(mix, u3, u4, u5);
+}
+
+template <int GUIDE>
 __device__ __forceinline__ ContS cont_sample(const PathArgs& a, const Shade& g, const Mat& m, const Mat& ms,
                                              const float u[8], int k, V3 Ts, const float* mix, bool& used_guide) {
     V3 wi = v3(0.0f, 0.0f, 1.0f);
     int lobe = 0;
     used_guide = false;
     float pdf = 0.0f;
-    if (mix && u[7] < a.gmix) {
+    if (GUIDE && mix && u[7] < a.gmix) {
         used_guide = true;
-        wi = mixture_sample(mix, u[3], u[4], u[5]);
-        pdf = a.gmix * mixture_pdf(mix, wi) + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, wi);
+        wi = guide_sample<GUIDE>(mix, u[3], u[4], u[5]);
+        pdf = a.gmix * guide_pdf<GUIDE>(mix, wi) + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, wi);
     } else {
         bool okd = brdf_sample(ms, g.ns, g.wo, u[3], u[4], u[5], wi, lobe);
         if (okd && dot(wi, g.ngf) > 0.0f && dot(wi, g.ns) > 0.0f) {
             pdf = brdf_pdf(ms, g.ns, g.wo, wi);
-            if (mix) pdf = a.gmix * mixture_pdf(mix, wi) + (1.0f - a.gmix) * pdf;
+            if (GUIDE && mix) pdf = a.gmix * guide_pdf<GUIDE>(mix, wi) + (1.0f - a.gmix) * pdf;
         }
     }
     return cont_eval(a, g, m, ms, wi, pdf, lobe, u, k, Ts);
+}
+
+// The cached proposal's one-sample MIS in two steps, so that both densities a
+// vertex needs (continuation direction, light sample) come from one pass over
+// its row: first the technique (u[7]) and the direction (u[3..5]) ...
+struct ContDir {
+    V3 wi;
+    int lobe;
+    bool ok;      // BRDF technique: a direction above the surface
+    bool guide;   // the proposal's technique was chosen
+};
+__device__ __forceinline__ ContDir cont_direction_cached(const PathArgs& a, const Shade& g, const Mat& ms,
+                                                         const float u[8], const float* row) {
+    ContDir c;
+    c.lobe = 0;
+    c.guide = u[7] < a.gmix;
+    if (c.guide) {
+        c.wi = cached_sample(row, u[3], u[4], u[5]);
+        c.ok = true;
+    } else {
+        c.wi = v3(0.0f, 0.0f, 1.0f);
+        c.ok = brdf_sample(ms, g.ns, g.wo, u[3], u[4], u[5], c.wi, c.lobe) && dot(c.wi, g.ngf) > 0.0f &&
+               dot(c.wi, g.ns) > 0.0f;
+    }
+    return c;
+}
+// ... then, with the proposal's density q of that direction, the combined
+// density and the continuation weight (as cont_sample).
+__device__ __forceinline__ ContS cont_finish_cached(const PathArgs& a, const Shade& g, const Mat& m, const Mat& ms,
+                                                    const float u[8], int k, V3 Ts, const ContDir& c, float q) {
+    float pdf = 0.0f;
+    if (c.guide || c.ok) pdf = a.gmix * q + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, c.wi);
+    return cont_eval(a, g, m, ms, c.wi, pdf, c.lobe, u, k, Ts);
 }
 
 // Backward sweep of the gradient forward pass: R_{k+1} into the c slot of
@@ -518,7 +565,8 @@ enum Phase { kNeedPixel = 0, kClosest = 1, kShadow = 2, kExit = 3 };
 // GUIDE: 0 none, 1 bfloat16 MFMA evaluation, 2 float32 VALU evaluation
 template <int MODE, int GUIDE>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(GUIDE ? IPT_WAVES_PER_EU_GUIDED : IPT_WAVES_PER_EU, 8))) void path_sm_kernel(
+__attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU_GUIDED : IPT_WAVES_PER_EU,
+                                   8))) void path_sm_kernel(
     PathArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     Lds lds;
@@ -700,8 +748,11 @@ __attribute__((amdgpu_waves_per_eu(GUIDE ? IPT_WAVES_PER_EU_GUIDED : IPT_WAVES_P
         }
 
         // ---- guide evaluation for the lanes about to sample (all lanes active here) ----
-        float* mix = nullptr;
-        if (GUIDE) {
+        const float* mix = nullptr;
+        if (GUIDE == 3) {
+            // cached row of the hit's cell, on the side the path arrives from
+            if (shade) mix = cache_row_at(a.gd, g.tri, g.u, g.v, dot(g.ng, g.wo) < 0.0f);
+        } else if (GUIDE) {
             float* row = (float*)(lds.gact + lane * kGRowStride);
             if (GUIDE == 1) {
                 if (shade) {
@@ -731,11 +782,26 @@ __attribute__((amdgpu_waves_per_eu(GUIDE ? IPT_WAVES_PER_EU_GUIDED : IPT_WAVES_P
             float u[8];
             vertex_uniforms(a.rng, pid, k, u);
             float pb_nee = -1.0f;
-            if (a.mis != 0 && sc.nlt > 0) {
-                NeeS n = nee_setup(sc, cdf, lights, g, u);
+            const bool do_nee = a.mis != 0 && sc.nlt > 0;
+            NeeS n;
+            n.shoot = false;
+            n.lj = 0;
+            if (do_nee) {
+                n = nee_setup(sc, cdf, lights, g, u);
                 ev |= (uint32_t)n.lj << 8;
+            }
+            ContDir cd;
+            float q_wi = 0.0f, q_wl = 0.0f;
+            if (GUIDE == 3) {
+                cd = cont_direction_cached(a, g, ms, u, mix);
+                cached_pdf2(mix, cd.wi, n.shoot ? n.wl : cd.wi, q_wi, q_wl);
+            }
+            if (do_nee) {
                 if (n.shoot) {
-                    if (mix) pb_nee = a.gmix * mixture_pdf(mix, n.wl) + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, n.wl);
+                    if (GUIDE == 3)
+                        pb_nee = a.gmix * q_wl + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, n.wl);
+                    else if (GUIDE && mix)
+                        pb_nee = a.gmix * guide_pdf<GUIDE>(mix, n.wl) + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, n.wl);
                     NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n, pb_nee);
                     shoot = true;
                     nee_valid = nc.valid;
@@ -747,7 +813,13 @@ __attribute__((amdgpu_waves_per_eu(GUIDE ? IPT_WAVES_PER_EU_GUIDED : IPT_WAVES_P
                 }
             }
             bool used_guide = false;
-            ContS cs = cont_sample(a, g, m, ms, u, k, Ts, mix, used_guide);
+            ContS cs;
+            if (GUIDE == 3) {
+                cs = cont_finish_cached(a, g, m, ms, u, k, Ts, cd, q_wi);
+                used_guide = cd.guide;
+            } else {
+                cs = cont_sample<GUIDE>(a, g, m, ms, u, k, Ts, mix, used_guide);
+            }
             ev |= (uint32_t)cs.lobe << 3;
             if (used_guide) ev |= 64u;
             if (!cs.ok) {
@@ -916,7 +988,7 @@ __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& 
             cs = cont_eval(a, g, m, ms, v3(dk.x, dk.y, dk.z), a.ck_a[ck].w, 0, u, k, Ts);
         } else {
             bool ug;
-            cs = cont_sample(a, g, m, ms, u, k, Ts, nullptr, ug);
+            cs = cont_sample<0>(a, g, m, ms, u, k, Ts, nullptr, ug);
         }
         float rq = 1.0f / cs.qrr;
         int mb = 7 * g.seg;
@@ -1068,24 +1140,39 @@ static int occ(K kern, size_t lds) {
     return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 
-int path_blocks_per_cu(int mode, size_t lds, int guided) {
-    if (mode == kColor) return guided ? occ(path_sm_kernel<kColor, 1>, lds) : occ(path_sm_kernel<kColor, 0>, lds);
-    if (mode == kGradFwd)
-        return guided ? occ(path_sm_kernel<kGradFwd, 1>, lds) : occ(path_sm_kernel<kGradFwd, 0>, lds);
+template <int MODE>
+static int path_occ(int gk, size_t lds) {
+    switch (gk) {
+        case 1: return occ(path_sm_kernel<MODE, 1>, lds);
+        case 2: return occ(path_sm_kernel<MODE, 2>, lds);
+        case 3: return occ(path_sm_kernel<MODE, 3>, lds);
+        default: return occ(path_sm_kernel<MODE, 0>, lds);
+    }
+}
+
+template <int MODE>
+static void launch_path_kind(int gk, const PathArgs& a, int grid, size_t lds, hipStream_t st) {
+    switch (gk) {
+        case 1: hipLaunchKernelGGL((path_sm_kernel<MODE, 1>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((path_sm_kernel<MODE, 2>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        case 3: hipLaunchKernelGGL((path_sm_kernel<MODE, 3>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        default: hipLaunchKernelGGL((path_sm_kernel<MODE, 0>), dim3(grid), dim3(kBlock), lds, st, a); break;
+    }
+}
+
+int path_blocks_per_cu(int mode, size_t lds, int gk) {
+    if (mode == kColor) return path_occ<kColor>(gk, lds);
+    if (mode == kGradFwd) return path_occ<kGradFwd>(gk, lds);
     return occ(replay_kernel, lds);
 }
 
-// The guide evaluation is compiled in only when the guide is sampled (guide_mix > 0).
+// The proposal is compiled in only when it is sampled (guide_mix > 0); kind
+// as in PathArgs::guide_kind.
 hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st) {
-    int gk = (a.guided && a.gmix > 0.0f) ? (a.guide_fp32 ? 2 : 1) : 0;
     if (mode == kColor) {
-        if (gk == 1) hipLaunchKernelGGL((path_sm_kernel<kColor, 1>), dim3(grid), dim3(kBlock), lds, st, a);
-        else if (gk == 2) hipLaunchKernelGGL((path_sm_kernel<kColor, 2>), dim3(grid), dim3(kBlock), lds, st, a);
-        else hipLaunchKernelGGL((path_sm_kernel<kColor, 0>), dim3(grid), dim3(kBlock), lds, st, a);
+        launch_path_kind<kColor>(a.guide_kind, a, grid, lds, st);
     } else if (mode == kGradFwd) {
-        if (gk == 1) hipLaunchKernelGGL((path_sm_kernel<kGradFwd, 1>), dim3(grid), dim3(kBlock), lds, st, a);
-        else if (gk == 2) hipLaunchKernelGGL((path_sm_kernel<kGradFwd, 2>), dim3(grid), dim3(kBlock), lds, st, a);
-        else hipLaunchKernelGGL((path_sm_kernel<kGradFwd, 0>), dim3(grid), dim3(kBlock), lds, st, a);
+        launch_path_kind<kGradFwd>(a.guide_kind, a, grid, lds, st);
     } else {
         hipLaunchKernelGGL(replay_kernel, dim3(grid), dim3(kBlock), lds, st, a);
     }

@@ -22,7 +22,7 @@ _STATUS = {0: "IPT_OK", 1: "IPT_ERR_INVALID_ARG", 2: "IPT_ERR_BAD_SCENE", 3: "IP
 EXPORTS = ["ipt_scene_build", "ipt_scene_build_ex", "ipt_scene_free", "ipt_scene_info", "ipt_workspace_query", "ipt_render",
            "ipt_render_grad", "ipt_loss_grad", "ipt_sgd_step", "ipt_l1_reg", "ipt_trace_rays", "ipt_guide_create",
            "ipt_guide_free", "ipt_guide_eval", "ipt_guide_train", "ipt_guide_weights", "ipt_guide_records",
-           "ipt_guide_loss_grad", "ipt_guide_add_records", "ipt_guide_read_records",
+           "ipt_guide_loss_grad", "ipt_guide_add_records", "ipt_guide_read_records", "ipt_guide_cache_build",
            "ipt_profile_enable", "ipt_profile_read",
            "ipt_profile_reset", "ipt_last_error"]
 
@@ -45,7 +45,8 @@ class RenderOpts(ctypes.Structure):
                 ("replay_traverse", ctypes.c_int32), ("pixel_list", ctypes.c_void_p),
                 ("num_pixels", ctypes.c_int64), ("guide", ctypes.c_void_p), ("guide_mix", ctypes.c_float),
                 ("guide_fp32", ctypes.c_int32), ("debug_path_hash", ctypes.c_void_p), ("path_mask", ctypes.c_void_p),
-                ("debug_path_radiance", ctypes.c_void_p), ("debug_vertices", ctypes.c_void_p)]
+                ("debug_path_radiance", ctypes.c_void_p), ("debug_vertices", ctypes.c_void_p),
+                ("guide_cached", ctypes.c_int32)]
 
 
 class AdamOpts(ctypes.Structure):
@@ -117,6 +118,7 @@ def lib():
             "ipt_guide_loss_grad": [P, P, I64, P, P, P],
             "ipt_guide_add_records": [P, P, I64, P],
             "ipt_guide_read_records": [P, P, I64, P],
+            "ipt_guide_cache_build": [P, P, ctypes.c_float, I32, P, P],
             "ipt_profile_enable": [P, I32],
             "ipt_profile_read": [P, I32, P],
             "ipt_profile_reset": [P],
@@ -173,7 +175,7 @@ def _cams_struct(dc):
 def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=-1, mis=2,
                 emission_profile=0, jitter=1, replay_traverse=0, pixel_list=None, guide=None,
                 guide_mix=0.0, guide_fp32=0, debug_path_hash=None, path_mask=None,
-                debug_path_radiance=None, debug_vertices=None):
+                debug_path_radiance=None, debug_vertices=None, guide_cached=0):
     o = RenderOpts()
     o.seed, o.stream_tag, o.iteration = int(seed), int(stream_tag), int(iteration)
     o.spp, o.max_depth, o.rr_depth, o.mis = int(spp), int(max_depth), int(rr_depth), int(mis)
@@ -183,6 +185,7 @@ def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=
     o.guide = None if guide is None else guide.handle
     o.guide_mix = float(guide_mix)
     o.guide_fp32 = int(guide_fp32)
+    o.guide_cached = int(guide_cached)
     o.debug_path_hash = None if debug_path_hash is None else debug_path_hash.data_ptr()
     o.path_mask = None if path_mask is None else path_mask.data_ptr()
     o.debug_path_radiance = None if debug_path_radiance is None else debug_path_radiance.data_ptr()
@@ -336,6 +339,15 @@ class Guide:
         out = torch.empty((n, 40), dtype=torch.float32, device="cuda")
         _check(lib().ipt_guide_eval(self.handle, _ptr(feat), _ptr(seg), n, int(mode), _ptr(out), _stream()))
         return out
+
+    def cache_build(self, cell_area, mode=0):
+        """Builds (first call) or refills the cached proposal of the guide's
+        scene (ipt_guide_cache_build); returns the number of cells per side."""
+        n = ctypes.c_int64(0)
+        _check(lib().ipt_guide_cache_build(self.handle, self.scene.handle, float(cell_area), int(mode),
+                                           ctypes.byref(n), _stream()))
+        self.cell_area = float(cell_area)
+        return int(n.value)
 
     def train(self, steps=1, want_loss=True):
         loss = ctypes.c_float(0.0)

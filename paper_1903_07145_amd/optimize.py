@@ -189,17 +189,30 @@ def group_rmse(params, p_true, scale, trainable, S):
     return {k: float(np.sqrt(np.mean(d[m & t] ** 2))) for k, m in groups.items() if (m & t).any()}
 
 
+def cell_area_for(sc, cells):
+    """Cell area giving about `cells` cached-proposal cells per side over the
+    scene's surface (triangles smaller than a cell get one cell each)."""
+    v = np.asarray(sc["verts"], np.float64)
+    t = np.asarray(sc["tris"], np.int64)
+    area = 0.5 * np.linalg.norm(np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]]), axis=1).sum()
+    return float(np.float32(area / cells))
+
+
 def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guide_steps=10, guide_lr=2e-3,
              guide_batch=16384, record_stride=None, target_rmse=1e-2, stop_at_target=False, target=None,
              g=None, log=None, spp=None, lr=None, lr_schedule="const", masks=None, lr_final=None, log_every=10,
-             fixed=None, beta2=0.999):
+             fixed=None, beta2=0.999, guide_cells=0, guide_every=1):
     """Runs the optimisation; returns a dict with the RMSE/loss history and timings.
 
     The time to target is taken on the RMSE over masks[0] (identifiable
     albedo and emission, see identifiable_masks); the RMSE over every
     trainable parameter and over masks[1] is recorded beside it.  Wall-clock
     time counts from the first iteration (scene build and target render
-    excluded) and includes guide training in the guided arm."""
+    excluded) and includes guide training in the guided arm.  guide_cells > 0:
+    the path kernels sample the cached proposal (about that many cells per
+    side, refilled after every training call) instead of evaluating the
+    network at every vertex; guide_every: training (and refill) every that
+    many iterations."""
     cfg = sc["render"]
     iters = iters or cfg["iters"]
     spp = spp or cfg["spp"]
@@ -234,7 +247,11 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         # about one million training records per iteration
         stride = record_stride or max(1, (npix * spp * 3) // (1 << 20))
         gd = ipt.Guide(g, seed=seed, lr=guide_lr, batch=guide_batch, ring_capacity=1 << 21, record_stride=stride)
-    g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr, guide=gd, guide_mix=guide_mix if gd else 0.0))
+        if guide_cells:
+            gd.cache_build(cell_area_for(sc, guide_cells))
+    cached = 1 if (gd is not None and guide_cells) else 0
+    g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr, guide=gd, guide_mix=guide_mix if gd else 0.0,
+                                    guide_cached=cached))
     hist = dict(it=[], t=[], rmse=[], rmse_all=[], rmse_id=[], loss=[], guide_loss=[], groups=[])
     torch.cuda.synchronize()
     t0 = time.time()
@@ -242,16 +259,18 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
     for it in range(iters):
         mix = guide_mix if (gd is not None and it >= warmup) else 0.0
         kw = dict(seed=1000 * seed + 11, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2)
-        co = ipt.render_opts(stream_tag=TAG_A, guide=gd if mix > 0 else None, guide_mix=mix, **kw)
-        go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, **kw)
+        co = ipt.render_opts(stream_tag=TAG_A, guide=gd if mix > 0 else None, guide_mix=mix, guide_cached=cached, **kw)
+        go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, guide_cached=cached, **kw)
         g.loss_grad(dc, params, target, co, go, 0, loss=loss, grad=grad)
         # constant, or cosine decay from lr0 to lr_final (default lr0/20) over the run
         lr_end = lr_final if lr_final is not None else lr0 / 20
         lr_it = lr0 if lr_schedule == "const" else lr_end + (lr0 - lr_end) * 0.5 * (1 + np.cos(np.pi * it / iters))
         ipt.sgd_step(params, grad, m, v, it + 1, lr=lr_it, beta2=beta2, scale=scale, lo=lo, hi=hi, trainable=tr)
         gl = None
-        if gd is not None and gd.records() >= guide_batch:
+        if gd is not None and it % guide_every == 0 and gd.records() >= guide_batch:
             gl = gd.train(guide_steps, want_loss=(it % 10 == 0))
+            if cached:
+                gd.cache_build(gd.cell_area)
         r = param_rmse(params, p_true, scale, m_head)   # synchronises
         t = time.time() - t0
         hist["it"].append(it)
@@ -281,31 +300,18 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
                 n_id=int(masks[1].sum()), worst=worst)
 
 
-def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, lr=5e-3, lam=1e-3, beta2=0.999,
-                           target=None, g=None, log=None, log_every=100, target_rmse=1e-2, cov=None, loss_kind=1):
-    """The paper's own optimisation setting (Sec. 3, "Optimization Parameters";
-    App. A): every segment emissive (scenes.all_emissive), albedo and
-    emission initialised to zero, each iteration a batch of `batch` pixels
-    drawn uniformly from all pixels of all views with `spp` paths per pixel,
-    the L1 loss and its sign adjoint, an L1 regulariser of weight `lam` (per
-    unit of normalised emission) on every emission, Adam at lr 5e-3.
-
-    Headline RMSE: albedo of the seen segments that do not emit and emission
-    of every seen segment (zero for all but the scene's own emitters);
-    parameters of unseen segments and the emitters' reflectance are held at
-    their true values (as in optimize())."""
-    cfg = sc["render"]
-    D, rr = cfg["max_depth"], cfg["rr_depth"]
-    g = g or ipt.Scene.from_dict(sc)
-    dc = ipt.make_cameras(sc["cams"])
-    npix = dc["num_views"] * dc["width"] * dc["height"]
+def paper_setting_masks(sc, cov, sigma=None, max_sigma=2.5e-3):
+    """(fixed, head) for the all-emissive setting.  Held at their true values:
+    every parameter of a segment seen in fewer than 100 pixels (16 for the
+    scene's own emitters) and the reflectance of those emitters.  Headline:
+    albedo of the seen segments that do not emit and emission of every seen
+    segment (zero for all but the scene's own emitters), restricted, with
+    sigma (target_precision over the free set), to the parameters the target
+    pins to sigma <= max_sigma.  With every segment free to emit, an
+    indirectly lit surface's albedo and its own emission explain its pixels
+    almost equally well, so its albedo is often not pinned."""
     S = sc["num_segments"]
-    p_true = torch.as_tensor(sc["params"], device="cuda")
-    if target is None:
-        target = render_target(g, dc, p_true, cfg["target_spp"], D, rr)
-    cov = coverage(g, sc) if cov is None else cov
     true_emit = set(int(x) for x in sc.get("true_emitters", sc["emitter_seg"]))
-    tr_np = sc["trainable"].astype(bool)
     fixed = np.zeros(sc["params"].size, bool)
     head = np.zeros(sc["params"].size, bool)
     for s_ in range(S):
@@ -319,7 +325,37 @@ def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, lr=5e-3, la
         else:
             head[7 * s_:7 * s_ + 3] = True
         head[7 * S + 3 * s_:7 * S + 3 * s_ + 3] = True
-    head &= tr_np & ~fixed
+    head &= sc["trainable"].astype(bool) & ~fixed
+    if sigma is not None:
+        head &= sigma <= max_sigma
+    return fixed, head
+
+
+def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, grad_spp=1, lr=5e-3, lam=1e-3, beta2=0.999,
+                           target=None, g=None, log=None, log_every=100, target_rmse=1e-2, cov=None, loss_kind=1,
+                           masks=None):
+    """The paper's own optimisation setting (Sec. 3, "Optimization Parameters";
+    App. A): every segment emissive (scenes.all_emissive), albedo and
+    emission initialised to zero, each iteration a batch of `batch` pixels
+    drawn uniformly from all pixels of all views, `spp` paths per pixel for
+    the colour estimate and `grad_spp` (one, the split Sec. 4 finds best) for
+    the independent derivative estimate, the L1 loss and its sign adjoint, an
+    L1 regulariser of weight `lam` (per unit of normalised emission) on every
+    emission, Adam at lr 5e-3.  masks: (fixed, head) from
+    paper_setting_masks (coverage only when None)."""
+    cfg = sc["render"]
+    D, rr = cfg["max_depth"], cfg["rr_depth"]
+    g = g or ipt.Scene.from_dict(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    npix = dc["num_views"] * dc["width"] * dc["height"]
+    S = sc["num_segments"]
+    p_true = torch.as_tensor(sc["params"], device="cuda")
+    if target is None:
+        target = render_target(g, dc, p_true, cfg["target_spp"], D, rr)
+    if masks is None:
+        masks = paper_setting_masks(sc, coverage(g, sc) if cov is None else cov)
+    fixed, head = masks
+    tr_np = sc["trainable"].astype(bool)
     p0 = np.where(tr_np & ~fixed, 0.0, sc["params"]).astype(np.float32)
     # ks and roughness (when trainable) start at the middle of their range
     for s_ in range(S):
@@ -350,9 +386,9 @@ def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, lr=5e-3, la
     for it in range(iters):
         pix = torch.randint(0, npix, (batch,), generator=gen, device="cuda")
         tgt = target.index_select(0, pix).contiguous()
-        kw = dict(seed=1000 * seed + 17, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2, pixel_list=pix)
-        g.loss_grad(dc, params, tgt, ipt.render_opts(stream_tag=TAG_A, **kw), ipt.render_opts(stream_tag=TAG_B, **kw),
-                    loss_kind, loss=loss, grad=grad)
+        kw = dict(seed=1000 * seed + 17, iteration=it, max_depth=D, rr_depth=rr, mis=2, pixel_list=pix)
+        g.loss_grad(dc, params, tgt, ipt.render_opts(stream_tag=TAG_A, spp=spp, **kw),
+                    ipt.render_opts(stream_tag=TAG_B, spp=grad_spp, **kw), loss_kind, loss=loss, grad=grad)
         ipt.l1_reg(params, grad, w_l1, loss)
         ipt.sgd_step(params, grad, m, v, it + 1, lr=lr, beta2=beta2, scale=scale, lo=lo, hi=hi, trainable=tr)
         if it % 10 == 0 or it == iters - 1:
@@ -368,12 +404,15 @@ def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, lr=5e-3, la
                 log("it %5d  t %7.2fs  batch loss %.5f  rmse %.4f" % (it, t, hist["loss"][-1], r))
     err = ((params - p_true) / scale).cpu().numpy()
     worst = [(int(i), float(err[i])) for i in np.argsort(-np.abs(err * head))[:6]]
+    free = tr_np & ~fixed
     return dict(history=hist, time_to_target=t_hit, final_rmse=hist["rmse"][-1], seconds=hist["t"][-1],
-                iters=iters, seed=seed, n_head=int(head.sum()), worst=worst, batch=batch, spp=spp, lr=lr, lam=lam,
+                final_rmse_free=float(np.sqrt(np.mean(err[free] ** 2))),
+                iters=iters, seed=seed, n_head=int(head.sum()), worst=worst, batch=batch, spp=spp, grad_spp=grad_spp,
+                lr=lr, lam=lam,
                 loss_kind=loss_kind, beta2=beta2)
 
 
-def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, guide_mix=0.5, seed=555):
+def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, guide_mix=0.5, seed=555, cached=0):
     """Per-parameter variance of the loss gradient over K independent seeds at
     fixed parameters, with plain BRDF sampling and with the learned proposal
     (one-sample MIS at guide_mix), plus the mean time per gradient of each.
@@ -388,8 +427,8 @@ def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, gu
         t0 = time.time()
         for k in range(K):
             kw = dict(seed=seed + k, iteration=k, spp=spp, max_depth=D, rr_depth=rr, mis=2)
-            co = ipt.render_opts(stream_tag=TAG_A, guide=gd, guide_mix=mix, **kw)
-            go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, **kw)
+            co = ipt.render_opts(stream_tag=TAG_A, guide=gd, guide_mix=mix, guide_cached=cached if gd else 0, **kw)
+            go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, guide_cached=cached if gd else 0, **kw)
             _, gr = g.loss_grad(dc, params, target, co, go, 0)
             G.append(gr.double().clone())
         torch.cuda.synchronize()
@@ -418,6 +457,9 @@ def main(argv=None):
     ap.add_argument("--guide-mix", type=float, default=0.5)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--guide-steps", type=int, default=10)
+    ap.add_argument("--guide-cells", type=int, default=0,
+                    help="> 0: sample the cached proposal with about this many cells per side")
+    ap.add_argument("--guide-every", type=int, default=1, help="train the guide every this many iterations")
     ap.add_argument("--target-rmse", type=float, default=1e-2)
     ap.add_argument("--lr", type=float, default=None)
     ap.add_argument("--spp", type=int, default=None)
@@ -436,6 +478,7 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lam", type=float, default=1e-3)
     ap.add_argument("--loss", default="l1", choices=["l1", "l2"], help="image loss of the paper setting")
+    ap.add_argument("--grad-spp", type=int, default=1, help="paper setting: paths per pixel of the derivative estimate")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     sc = scenes.WORKLOADS[a.workload]()
@@ -445,20 +488,30 @@ def main(argv=None):
         cfg = sc["render"]
         g = ipt.Scene.from_dict(sc)
         dc = ipt.make_cameras(sc["cams"])
-        target = render_target(g, dc, torch.as_tensor(sc["params"], device="cuda"),
-                               a.target_spp or cfg["target_spp"], cfg["max_depth"], cfg["rr_depth"])
+        target, tvar = render_target(g, dc, torch.as_tensor(sc["params"], device="cuda"),
+                                     a.target_spp or cfg["target_spp"], cfg["max_depth"], cfg["rr_depth"],
+                                     return_var=True)
         cov = coverage(g, sc)
+        fixed, _ = paper_setting_masks(sc, cov)
+        fr = sc["trainable"].astype(bool) & ~fixed
+        sigma = target_precision(g, dc, sc, tvar, free=fr)
+        masks = paper_setting_masks(sc, cov, sigma=sigma)
+        log("paper setting: %d free parameters, %d headline (target precision <= 2.5e-3); not pinned: %s" % (
+            fr.sum(), masks[1].sum(), [(int(i), float("%.3g" % sigma[i])) for i in
+                                       np.nonzero(paper_setting_masks(sc, cov)[1] & ~masks[1])[0]]))
         for seed in a.seeds:
             res = optimize_paper_setting(sc, iters=a.iters or 2000, seed=seed, batch=a.batch, spp=a.spp or 512,
-                                         lr=a.lr or 5e-3, lam=a.lam, beta2=a.beta2, target=target, g=g, log=log,
-                                         log_every=a.log_every, target_rmse=a.target_rmse, cov=cov,
+                                         grad_spp=a.grad_spp, lr=a.lr or 5e-3, lam=a.lam, beta2=a.beta2,
+                                         target=target, g=g, log=log, log_every=a.log_every,
+                                         target_rmse=a.target_rmse, masks=masks,
                                          loss_kind=1 if a.loss == "l1" else 0)
             if a.out:
                 with open(a.out, "a") as f:
                     f.write(json.dumps(dict(workload=sc["name"], mode="paper_setting", **res)) + "\n")
-            log("seed %d: final rmse %.4f after %d iters in %.1fs over %d headline parameters; time to %.0e: %s; "
-                "worst %s" % (seed, res["final_rmse"], res["iters"], res["seconds"], res["n_head"], a.target_rmse,
-                              res["time_to_target"], res["worst"]))
+            log("seed %d: final rmse %.4f (all free %.4f) after %d iters in %.1fs over %d headline parameters; "
+                "time to %.0e: %s; worst %s" % (seed, res["final_rmse"], res["final_rmse_free"], res["iters"],
+                                                res["seconds"], res["n_head"], a.target_rmse, res["time_to_target"],
+                                                [(i, round(e, 3)) for i, e in res["worst"]]))
         return
     g = ipt.Scene.from_dict(sc)
     dc = ipt.make_cameras(sc["cams"])
@@ -486,11 +539,12 @@ def main(argv=None):
         res = optimize(sc, iters=a.iters, seed=seed, guide=a.guide, guide_mix=a.guide_mix, warmup=a.warmup,
                        guide_steps=a.guide_steps, target_rmse=a.target_rmse, target=target, g=g, log=log,
                        lr=a.lr, lr_schedule=a.lr_schedule, masks=masks, spp=a.spp, lr_final=a.lr_final,
-                       log_every=a.log_every, fixed=fixed, beta2=a.beta2)
+                       log_every=a.log_every, fixed=fixed, beta2=a.beta2, guide_cells=a.guide_cells,
+                       guide_every=a.guide_every)
         if a.variance and a.guide:
             L = optimize.last
             vs = gradient_variance(g, dc, sc, L["params"], target, L["guide"], tr & ~fixed, K=a.variance,
-                                   spp=a.spp)
+                                   spp=a.spp, cached=1 if a.guide_cells else 0)
             res["variance"] = vs
             log("gradient variance over %d seeds at iteration %d: %s" % (a.variance, res["iters"], json.dumps(vs)))
         line = json.dumps(dict(workload=a.workload, **res))
