@@ -293,7 +293,8 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
                 "" if gl is None else "  guide loss %.4f" % gl))
     err = ((params - p_true) / scale).cpu().numpy()
     worst = [(int(i), float(err[i])) for i in np.argsort(-np.abs(err * masks[0]))[:8]]
-    optimize.last = dict(params=params, guide=gd, target=target, g=g, dc=dc, fixed=fixed)
+    optimize.last = dict(params=params, guide=gd, target=target, g=g, dc=dc, fixed=fixed,
+                         init=torch.as_tensor(p0, device="cuda"))
     return dict(history=hist, time_to_target=t_hit, final_rmse=hist["rmse"][-1],
                 final_rmse_all=hist["rmse_all"][-1], final_rmse_id=hist["rmse_id"][-1], seconds=hist["t"][-1],
                 iters=len(hist["it"]), guide=guide, seed=seed, n_head=int(masks[0].sum()),
@@ -543,10 +544,12 @@ def main(argv=None):
                        guide_every=a.guide_every)
         if a.variance and a.guide:
             L = optimize.last
-            vs = gradient_variance(g, dc, sc, L["params"], target, L["guide"], tr & ~fixed, K=a.variance,
-                                   spp=a.spp, cached=1 if a.guide_cells else 0)
-            res["variance"] = vs
-            log("gradient variance over %d seeds at iteration %d: %s" % (a.variance, res["iters"], json.dumps(vs)))
+            for where, p_at in (("final", L["params"]), ("init", L["init"])):
+                vs = gradient_variance(g, dc, sc, p_at, target, L["guide"], tr & ~fixed, K=a.variance,
+                                       spp=a.spp, cached=1 if a.guide_cells else 0, guide_mix=a.guide_mix)
+                res["variance" if where == "final" else "variance_init"] = vs
+                log("gradient variance over %d seeds at the %s parameters (guide trained for %d iterations): %s"
+                    % (a.variance, where, res["iters"], json.dumps(vs)))
         line = json.dumps(dict(workload=a.workload, **res))
         if a.out:
             with open(a.out, "a") as f:
