@@ -114,14 +114,23 @@ typedef struct {
     uint64_t nonfinite_paths; /* paths dropped for a non-finite contribution */
     uint64_t stack_overflows; /* traversals that ran out of stack */
     int32_t bvh_builder;      /* the ipt_bvh_builder that built the BVH */
+    int32_t params_global;    /* 1: parameters in global memory (ipt_param_storage) */
 } ipt_scene_info_t;
 
 /* Where the BVH is built.  Both builders apply the same rule (binned SAH,
  * 32 slabs per axis, C_trav = C_isect = 1, leaves of at most 4 triangles)
  * and give the same tree; the host builder is kept as a reference. */
 typedef enum { IPT_BVH_GPU = 0, IPT_BVH_HOST = 1 } ipt_bvh_builder;
+/* Where the path kernels keep the parameter vector (7 S + 3 E floats) and
+ * the adjoint its gradient.  LDS: a copy per block and per-block float64
+ * partial gradients summed in a fixed order (deterministic).  GLOBAL: read
+ * through the caches, and the adjoint adds float64 atomics straight into one
+ * accumulator (summation order varies; for many segments, e.g. one per
+ * triangle, where contention is low).  AUTO: LDS up to 4096 parameters. */
+typedef enum { IPT_PARAMS_AUTO = 0, IPT_PARAMS_GLOBAL = 1 } ipt_param_storage;
 typedef struct {
     int32_t bvh_builder;      /* an ipt_bvh_builder */
+    int32_t param_storage;    /* an ipt_param_storage */
 } ipt_build_opts;
 
 /* Build a scene: upload geometry, build the BVH on the GPU (binned SAH,

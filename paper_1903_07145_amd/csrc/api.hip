@@ -64,7 +64,7 @@ struct ipt_scene_s {
     Counters* d_err = nullptr;
     int* d_ovf_rays = nullptr;   // overflow stacks of ipt_trace_rays
     int64_t nt = 0, nv = 0, nnodes = 0;
-    int S = 0, E = 0, nlt = 0, depth = 0, has_normals = 0, bvh_builder = 0;
+    int S = 0, E = 0, nlt = 0, depth = 0, has_normals = 0, bvh_builder = 0, params_global = 0;
     double sah = 0.0, build_ms = 0.0;
     float diag = 0.0f;
     float bb_lo[3] = {0, 0, 0}, bb_hi[3] = {0, 0, 0};
@@ -123,6 +123,9 @@ extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const f
                                          ipt_scene_t* out) {
     const int builder = bopts ? bopts->bvh_builder : IPT_BVH_GPU;
     if (builder != IPT_BVH_GPU && builder != IPT_BVH_HOST) return fail(IPT_ERR_INVALID_ARG, "unknown bvh_builder %d", builder);
+    const int storage = bopts ? bopts->param_storage : IPT_PARAMS_AUTO;
+    if (storage != IPT_PARAMS_AUTO && storage != IPT_PARAMS_GLOBAL)
+        return fail(IPT_ERR_INVALID_ARG, "unknown param_storage %d", storage);
     hipStream_t st = (hipStream_t)hip_stream;
     if (!out) return fail(IPT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -156,7 +159,8 @@ extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const f
         seg_emitter[s] = k;
     }
     int64_t P = 7 * (int64_t)num_segments + 3 * (int64_t)num_emitters;
-    if (P > 8192) return fail(IPT_ERR_NOT_SUPPORTED, "parameter vector too long (%lld > 8192)", (long long)P);
+    if (P > kMaxParams)
+        return fail(IPT_ERR_NOT_SUPPORTED, "parameter vector too long (%lld > %lld)", (long long)P, (long long)kMaxParams);
 
 
     // emitter table in ascending input-id order (leaf positions filled in on the device)
@@ -290,6 +294,7 @@ extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const f
     s->has_normals = normals != nullptr;
     s->sah = sah;
     s->bvh_builder = builder;
+    s->params_global = (storage == IPT_PARAMS_GLOBAL || P > kMaxLdsParams) ? 1 : 0;
     s->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     s->diag = (float)diag;
     for (int a = 0; a < 3; ++a) { s->bb_lo[a] = lo[a]; s->bb_hi[a] = hi[a]; }
@@ -334,6 +339,7 @@ extern "C" ipt_status ipt_scene_info(ipt_scene_t s, ipt_scene_info_t* out) {
     out->nonfinite_paths = c.nonfinite;
     out->stack_overflows = c.overflow;
     out->bvh_builder = s->bvh_builder;
+    out->params_global = s->params_global;
     return IPT_OK;
 }
 
@@ -386,8 +392,9 @@ struct Plan {
 // Persistent grid: blocks per CU from the occupancy calculator (at most 8),
 // or IPT_BLOCKS_PER_CU when set (tuning).
 static int path_grid(const ipt_scene_s* s, int P, int frozen, int gk) {
-    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, gk), gk);
-    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, gk), gk));
+    const int pg = s->params_global;
+    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, gk, pg), gk);
+    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, gk, pg), gk));
     static const int forced = [] {
         const char* e = std::getenv("IPT_BLOCKS_PER_CU");
         return e ? std::atoi(e) : 0;
@@ -418,7 +425,8 @@ static void make_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t np
     pl.off_loss = off; off = al256(off + sizeof(float) * 1024);
     pl.off_w = off; off = al256(off + (with_loss ? sizeof(float) * 3 * npix : 0));
     pl.off_img = off; off = al256(off + (with_loss ? sizeof(float) * 3 * npix : 0));
-    pl.off_gpart = off; off = al256(off + sizeof(double) * (size_t)pl.grid * P);
+    // replay gradient: per-block partials, or one accumulator with global parameters
+    pl.off_gpart = off; off = al256(off + sizeof(double) * (s->params_global ? (size_t)P : (size_t)pl.grid * P));
     pl.off_ovf = off; off = al256(off + sizeof(int) * (size_t)kOvfDepth * pl.grid * kBlock);
     // colour sample sums when pixels are split over lanes: nchunk * npix <= 2 lanes + npix
     const int64_t lanes = (int64_t)pl.grid * kBlock;
@@ -480,6 +488,7 @@ static PathArgs base_args(const ipt_scene_s* s, const ipt_cameras* cams, const f
     a.ovf = (int*)(ws + pl.off_ovf);
     a.grad_part = (double*)(ws + pl.off_gpart);
     a.replay_traverse = o->replay_traverse;
+    a.params_global = s->params_global;
     a.guided = o->guide != nullptr;
     a.gmix = a.guided ? o->guide_mix : 0.0f;
     a.guide_kind = guide_kind(o);
@@ -498,7 +507,7 @@ static ipt_status do_render(ipt_scene_t s, const ipt_cameras* cams, const float*
     a.part = a.nchunk > 1 ? (float*)(ws + pl.off_part) : nullptr;
     HIP_OK(launch_light_cdf(s->dev, a.sparams, (float*)(ws + pl.off_cdf), st));
     HIP_OK(launch_zero_u32(a.work, 1, st));
-    size_t lds = path_lds_bytes(kColor, a.P, a.frozen, s->S, s->nlt, a.guide_kind);
+    size_t lds = path_lds_bytes(kColor, a.P, a.frozen, s->S, s->nlt, a.guide_kind, a.params_global);
     int grid = (int)std::min<int64_t>(pl.grid, (npix * a.nchunk + kBlock - 1) / kBlock);
     HIP_OK(timed_launch(s, kColor, a, std::max(1, grid), lds, st));
     if (a.nchunk > 1) HIP_OK(launch_colour_reduce(a.part, a.nchunk, npix, o->spp, image, st));
@@ -530,8 +539,9 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
         a.grec_stride = guide_record_stride(o->guide);
     }
     HIP_OK(launch_light_cdf(s->dev, a.sparams, (float*)(ws + pl.off_cdf), st));
-    size_t lds_f = path_lds_bytes(kGradFwd, a.P, a.frozen, s->S, s->nlt, a.guide_kind);
-    size_t lds_r = path_lds_bytes(kReplay, a.P, a.frozen, s->S, s->nlt);
+    size_t lds_f = path_lds_bytes(kGradFwd, a.P, a.frozen, s->S, s->nlt, a.guide_kind, a.params_global);
+    size_t lds_r = path_lds_bytes(kReplay, a.P, a.frozen, s->S, s->nlt, 0, a.params_global);
+    if (a.params_global) HIP_OK(launch_zero_u32((unsigned*)a.grad_part, 2 * a.P, st));
     for (int64_t b = 0; b < npix; b += chunk) {
         a.pix_begin = b;
         a.pix_count = std::min<int64_t>(chunk, npix - b);
@@ -543,8 +553,9 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
         int grid_r = std::min(grid, s->num_cu * std::max(1, path_blocks_per_cu(kReplay, lds_r)));
         HIP_OK(launch_zero_u32(a.work, 1, st));
         HIP_OK(timed_launch(s, kReplay, a, grid_r, lds_r, st));
-        HIP_OK(launch_grad_reduce(a.grad_part, grid_r, a.P, grad, b > 0 ? 1 : 0, st));
+        if (!a.params_global) HIP_OK(launch_grad_reduce(a.grad_part, grid_r, a.P, grad, b > 0 ? 1 : 0, st));
     }
+    if (a.params_global) HIP_OK(launch_grad_reduce(a.grad_part, 1, a.P, grad, 0, st));
     return IPT_OK;
 }
 

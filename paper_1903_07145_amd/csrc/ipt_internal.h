@@ -14,6 +14,8 @@ constexpr int kOvfDepth = 48;     // per-lane global overflow entries
 constexpr int kNone = 0x7FFFFFFF; // empty child slot
 constexpr int kMaxDepth = 16;     // max scattering vertices per path
 constexpr int kMaxLdsLights = 1024;
+constexpr int kMaxLdsParams = 4096;  // larger parameter vectors stay in global memory
+constexpr int64_t kMaxParams = 1ll << 26;
 
 // Checkpoint record flags (packed with tri+1 in the low 28 bits).
 constexpr uint32_t kCkTriMask = 0x0FFFFFFFu;
@@ -81,6 +83,9 @@ struct PathArgs {
     Counters* err;
     int* ovf;                      // [kOvfDepth][grid threads]
     int replay_traverse;
+    int params_global;             // parameters read from global memory; the adjoint adds float64
+                                   // atomics into grad_part[P] (else per-block LDS copies and
+                                   // partials grad_part[gridDim.x][P])
     int count_stats;               // accumulate KStats into err->k[mode]
     // learned proposal (one-sample MIS with BRDF sampling)
     GuideDev gd;
@@ -94,7 +99,7 @@ struct PathArgs {
     int grec_cap, grec_stride;
 };
 
-size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guide_kind = 0);
+size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guide_kind = 0, int params_global = 0);
 int path_blocks_per_cu(int mode, size_t lds, int guide_kind = 0);
 hipError_t launch_guide_records(const PathArgs& a, hipStream_t st);
 hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st);

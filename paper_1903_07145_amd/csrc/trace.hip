@@ -47,9 +47,10 @@ struct Lds {
 // per-wave guide activation rows (64 x kGRowStride bf16), 4 waves per block
 constexpr size_t kGuideLds = 4 * 64 * kGRowStride * sizeof(__bf16);
 
-size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int gk) {
+size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int gk, int pglobal) {
     size_t b = 0;
     auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
+    if (pglobal) P = S = 0;                           // read from global memory
     b += al(sizeof(float) * P);                       // params
     if (frozen) b += al(sizeof(float) * P);           // sampling params
     b += al(sizeof(int) * S);                         // segment -> emitter
@@ -64,10 +65,18 @@ __device__ void carve_lds(const PathArgs& a, int mode, unsigned char* smem, Lds&
     const int tid = threadIdx.x;
     unsigned char* p = smem;
     auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
-    lds.params = (float*)p; p += al(sizeof(float) * a.P);
-    lds.sparams = lds.params;
-    if (a.frozen) { lds.sparams = (float*)p; p += al(sizeof(float) * a.P); }
-    lds.seg_emitter = (int*)p; p += al(sizeof(int) * a.sc.S);
+    const int pg = a.params_global;
+    if (pg) {
+        // parameters, segment table and the replay's gradient accumulator in global memory
+        lds.params = (float*)a.params;
+        lds.sparams = (float*)a.sparams;
+        lds.seg_emitter = (int*)a.sc.seg_emitter;
+    } else {
+        lds.params = (float*)p; p += al(sizeof(float) * a.P);
+        lds.sparams = lds.params;
+        if (a.frozen) { lds.sparams = (float*)p; p += al(sizeof(float) * a.P); }
+        lds.seg_emitter = (int*)p; p += al(sizeof(int) * a.sc.S);
+    }
     lds.lights_in_lds = a.sc.nlt <= kMaxLdsLights;
     lds.cdf = nullptr;
     lds.lights = nullptr;
@@ -76,16 +85,21 @@ __device__ void carve_lds(const PathArgs& a, int mode, unsigned char* smem, Lds&
         lds.lights = (int4*)p; p += al(sizeof(int4) * a.sc.nlt);
     }
     lds.grad = nullptr;
-    if (mode == kReplay) { lds.grad = (double*)p; p += al(sizeof(double) * a.P); }
+    if (mode == kReplay) {
+        if (pg) lds.grad = a.grad_part;
+        else { lds.grad = (double*)p; p += al(sizeof(double) * a.P); }
+    }
     lds.stack = (int*)p;
     p += sizeof(int) * kShortStack * kBlock;
     lds.gact = (__bf16*)p + (threadIdx.x >> 6) * 64 * kGRowStride;
-    for (int i = tid; i < a.P; i += kBlock) {
-        lds.params[i] = a.params[i];
-        if (a.frozen) lds.sparams[i] = a.sparams[i];
-        if (mode == kReplay) lds.grad[i] = 0.0;
+    if (!pg) {
+        for (int i = tid; i < a.P; i += kBlock) {
+            lds.params[i] = a.params[i];
+            if (a.frozen) lds.sparams[i] = a.sparams[i];
+            if (mode == kReplay) lds.grad[i] = 0.0;
+        }
+        for (int i = tid; i < a.sc.S; i += kBlock) lds.seg_emitter[i] = a.sc.seg_emitter[i];
     }
-    for (int i = tid; i < a.sc.S; i += kBlock) lds.seg_emitter[i] = a.sc.seg_emitter[i];
     if (lds.lights_in_lds)
         for (int i = tid; i < a.sc.nlt; i += kBlock) {
             lds.cdf[i] = a.cdf[i];
@@ -1053,6 +1067,7 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     }
     if (st.overflow) atomicAdd(&a.err->overflow, 1ull);
     flush_stats(a, kReplay, wk, npaths);
+    if (a.params_global) return;   // the atomics went straight to the accumulator
     __syncthreads();
     double* out = a.grad_part + (size_t)blockIdx.x * a.P;
     for (int i = tid; i < a.P; i += kBlock) out[i] = lds.grad[i];

@@ -61,14 +61,15 @@ class SceneInfo(ctypes.Structure):
                 ("bvh_depth", ctypes.c_int32), ("has_normals", ctypes.c_int32),
                 ("sah_cost", ctypes.c_double), ("build_ms", ctypes.c_double), ("scene_diag", ctypes.c_float),
                 ("nonfinite_paths", ctypes.c_uint64), ("stack_overflows", ctypes.c_uint64),
-                ("bvh_builder", ctypes.c_int32)]
+                ("bvh_builder", ctypes.c_int32), ("params_global", ctypes.c_int32)]
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("bvh_builder", ctypes.c_int32)]
+    _fields_ = [("bvh_builder", ctypes.c_int32), ("param_storage", ctypes.c_int32)]
 
 
 BVH_GPU, BVH_HOST = 0, 1
+PARAMS_AUTO, PARAMS_GLOBAL = 0, 1
 
 
 class KernelProfile(ctypes.Structure):
@@ -197,7 +198,8 @@ def render_opts(seed=0, stream_tag=1, iteration=0, spp=4, max_depth=3, rr_depth=
 class Scene:
     """A built scene on the current device (ipt_scene_build)."""
 
-    def __init__(self, verts, tris, tri_seg, num_segments, emitter_seg, normals=None, bvh_builder=BVH_GPU):
+    def __init__(self, verts, tris, tri_seg, num_segments, emitter_seg, normals=None, bvh_builder=BVH_GPU,
+                 param_storage=PARAMS_AUTO):
         v = np.ascontiguousarray(verts, np.float32)
         t = np.ascontiguousarray(tris, np.int32)
         s = np.ascontiguousarray(tri_seg, np.int32)
@@ -208,7 +210,7 @@ class Scene:
         self.P = 7 * self.num_segments + 3 * self.num_emitters
         h = ctypes.c_void_p()
         torch.cuda.init()
-        bo = BuildOpts(int(bvh_builder))
+        bo = BuildOpts(int(bvh_builder), int(param_storage))
         _check(lib().ipt_scene_build_ex(v.ctypes.data_as(ctypes.c_void_p), v.shape[0],
                                         None if n is None else n.ctypes.data_as(ctypes.c_void_p),
                                         t.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p),
@@ -218,9 +220,9 @@ class Scene:
         self._ws = None
 
     @classmethod
-    def from_dict(cls, sc, bvh_builder=BVH_GPU):
+    def from_dict(cls, sc, bvh_builder=BVH_GPU, param_storage=PARAMS_AUTO):
         return cls(sc["verts"], sc["tris"], sc["tri_seg"], sc["num_segments"], sc["emitter_seg"],
-                   sc.get("normals"), bvh_builder=bvh_builder)
+                   sc.get("normals"), bvh_builder=bvh_builder, param_storage=param_storage)
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -201,7 +201,7 @@ def cell_area_for(sc, cells):
 def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guide_steps=10, guide_lr=2e-3,
              guide_batch=16384, record_stride=None, target_rmse=1e-2, stop_at_target=False, target=None,
              g=None, log=None, spp=None, lr=None, lr_schedule="const", masks=None, lr_final=None, log_every=10,
-             fixed=None, beta2=0.999, guide_cells=0, guide_every=1):
+             fixed=None, beta2=0.999, guide_cells=0, guide_every=1, p_init=None):
     """Runs the optimisation; returns a dict with the RMSE/loss history and timings.
 
     The time to target is taken on the RMSE over masks[0] (identifiable
@@ -230,7 +230,7 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
     p_true = torch.as_tensor(sc["params"], device="cuda")
     if target is None:
         target = render_target(g, dc, p_true, cfg["target_spp"], D, rr)
-    p0 = scenes.init_theta(sc, cfg["init"], seed=seed)
+    p0 = scenes.init_theta(sc, cfg["init"], seed=seed) if p_init is None else np.array(p_init, np.float32)
     p0[fixed] = sc["params"][fixed]
     params = torch.as_tensor(p0, device="cuda")
     scale = torch.as_tensor(sc["scale"], device="cuda")
@@ -334,7 +334,7 @@ def paper_setting_masks(sc, cov, sigma=None, max_sigma=2.5e-3):
 
 def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, grad_spp=1, lr=5e-3, lam=1e-3, beta2=0.999,
                            target=None, g=None, log=None, log_every=100, target_rmse=1e-2, cov=None, loss_kind=1,
-                           masks=None):
+                           masks=None, max_depth=None, mis=2, time_budget=None):
     """The paper's own optimisation setting (Sec. 3, "Optimization Parameters";
     App. A): every segment emissive (scenes.all_emissive), albedo and
     emission initialised to zero, each iteration a batch of `batch` pixels
@@ -343,9 +343,10 @@ def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, grad_spp=1,
     the independent derivative estimate, the L1 loss and its sign adjoint, an
     L1 regulariser of weight `lam` (per unit of normalised emission) on every
     emission, Adam at lr 5e-3.  masks: (fixed, head) from
-    paper_setting_masks (coverage only when None)."""
+    paper_setting_masks (coverage only when None).  max_depth / mis override
+    the workload's; time_budget (seconds) ends the run early."""
     cfg = sc["render"]
-    D, rr = cfg["max_depth"], cfg["rr_depth"]
+    D, rr = max_depth or cfg["max_depth"], cfg["rr_depth"]
     g = g or ipt.Scene.from_dict(sc)
     dc = ipt.make_cameras(sc["cams"])
     npix = dc["num_views"] * dc["width"] * dc["height"]
@@ -387,7 +388,7 @@ def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, grad_spp=1,
     for it in range(iters):
         pix = torch.randint(0, npix, (batch,), generator=gen, device="cuda")
         tgt = target.index_select(0, pix).contiguous()
-        kw = dict(seed=1000 * seed + 17, iteration=it, max_depth=D, rr_depth=rr, mis=2, pixel_list=pix)
+        kw = dict(seed=1000 * seed + 17, iteration=it, max_depth=D, rr_depth=rr, mis=mis, pixel_list=pix)
         g.loss_grad(dc, params, tgt, ipt.render_opts(stream_tag=TAG_A, spp=spp, **kw),
                     ipt.render_opts(stream_tag=TAG_B, spp=grad_spp, **kw), loss_kind, loss=loss, grad=grad)
         ipt.l1_reg(params, grad, w_l1, loss)
@@ -403,6 +404,9 @@ def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, grad_spp=1,
                 t_hit = t
             if log and (it % log_every == 0 or it == iters - 1):
                 log("it %5d  t %7.2fs  batch loss %.5f  rmse %.4f" % (it, t, hist["loss"][-1], r))
+            if time_budget is not None and t >= time_budget:
+                iters = it + 1
+                break
     err = ((params - p_true) / scale).cpu().numpy()
     worst = [(int(i), float(err[i])) for i in np.argsort(-np.abs(err * head))[:6]]
     free = tr_np & ~fixed
@@ -411,6 +415,199 @@ def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, grad_spp=1,
                 iters=iters, seed=seed, n_head=int(head.sum()), worst=worst, batch=batch, spp=spp, grad_spp=grad_spp,
                 lr=lr, lam=lam,
                 loss_kind=loss_kind, beta2=beta2)
+
+
+# The paper's optimiser ablations (Sec. 4, "Optimizer Ablation"; supplement:
+# batch size, variance reduction, number of bounces), each as variants of the
+# pixel-batch optimiser under one wall-clock budget.  Fixed: L1 loss, Adam lr
+# 5e-3, the workload's emitters (not all-emissive), zero init.
+ABLATIONS = {
+    # paths per pixel of the colour estimate (one derivative path)
+    "spp": [dict(spp=s, grad_spp=1) for s in (1, 8, 128, 1024)],
+    # a budget of 128 paths per pixel split between colour and derivative
+    "split": [dict(spp=128 - d, grad_spp=d) for d in (1, 32, 64, 96, 127)],
+    # pixels per batch at 128 + 1 paths per pixel
+    "batch": [dict(batch=b, spp=128, grad_spp=1) for b in (1, 8, 64, 512)],
+    # light sampling + MIS against BRDF sampling only
+    "mis": [dict(mis=2, spp=128, grad_spp=1), dict(mis=0, spp=128, grad_spp=1)],
+    # bounces used by the optimiser, against a 10-bounce target
+    "bounces": [dict(max_depth=d, spp=128, grad_spp=1) for d in (1, 2, 3)],
+}
+
+
+def run_ablation(sc, kind, budget, seeds, target_spp=4096, log=None, lam=1e-3):
+    """Headline RMSE of each variant per seed: at a quarter of the budget and
+    averaged over its second half (at a constant learning rate the iterate
+    keeps fluctuating, so a single final value is noisy).  The bounce
+    ablation renders its target with 10 bounces."""
+    cfg = sc["render"]
+    g = ipt.Scene.from_dict(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    tD = 10 if kind == "bounces" else cfg["max_depth"]
+    target, tvar = render_target(g, dc, torch.as_tensor(sc["params"], device="cuda"), target_spp, tD,
+                                 cfg["rr_depth"], return_var=True)
+    cov = coverage(g, sc)
+    fixed, _ = paper_setting_masks(sc, cov)
+    sigma = target_precision(g, dc, sc, tvar, free=sc["trainable"].astype(bool) & ~fixed)
+    masks = paper_setting_masks(sc, cov, sigma=sigma)
+    out = []
+    for v in ABLATIONS[kind]:
+        row = dict(variant=v, final=[], quarter=[], late_mean=[], iters=[])
+        for seed in seeds:
+            kw = dict(batch=8, spp=128, grad_spp=1)
+            kw.update(v)
+            res = optimize_paper_setting(sc, iters=10 ** 7, seed=seed, lr=5e-3, lam=lam, beta2=0.999, target=target,
+                                         g=g, masks=masks, time_budget=budget, **kw)
+            h = res["history"]
+            t = np.asarray(h["t"])
+            r = np.asarray(h["rmse"])
+            row["final"].append(res["final_rmse"])
+            row["quarter"].append(float(r[min(len(r) - 1, int(np.searchsorted(t, budget / 4)))]))
+            row["late_mean"].append(float(r[t >= budget / 2].mean()))
+            row["iters"].append(res["iters"])
+        if log:
+            log("ablation %s %s: rmse at %.1fs median %.4f; mean over [%.1fs, %.1fs] median %.4f (seeds %s); "
+                "iterations %d" % (kind, v, budget / 4, np.median(row["quarter"]), budget / 2, budget,
+                                   np.median(row["late_mean"]), np.round(row["late_mean"], 4).tolist(),
+                                   int(np.median(row["iters"]))))
+        out.append(row)
+    return out
+
+
+def train_guide_at(g, dc, sc, params, target, iters=100, warmup=5, guide_steps=10, guide_mix=0.5, seed=7,
+                   guide_cells=0, guide_lr=2e-3, guide_batch=16384, spp=None):
+    """A guide trained online at fixed parameters: every iteration a gradient
+    pass writes records (sampling the guide after `warmup` iterations) and
+    the guide takes `guide_steps` training steps; the parameters do not
+    change.  Returns the guide (its cached rows refilled when guide_cells)."""
+    cfg = sc["render"]
+    spp = spp or cfg["spp"]
+    D, rr = cfg["max_depth"], cfg["rr_depth"]
+    npix = dc["num_views"] * dc["width"] * dc["height"]
+    stride = max(1, (npix * spp * 3) // (1 << 20))
+    gd = ipt.Guide(g, seed=seed, lr=guide_lr, batch=guide_batch, ring_capacity=1 << 21, record_stride=stride)
+    cached = 0
+    if guide_cells:
+        gd.cache_build(cell_area_for(sc, guide_cells))
+        cached = 1
+    for it in range(iters):
+        mix = guide_mix if it >= warmup else 0.0
+        kw = dict(seed=1000 * seed + 13, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2)
+        co = ipt.render_opts(stream_tag=TAG_A, **kw)
+        go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, guide_cached=cached, **kw)
+        g.loss_grad(dc, params, target, co, go, 0)
+        if gd.records() >= guide_batch:
+            gd.train(guide_steps, want_loss=False)
+            if cached:
+                gd.cache_build(gd.cell_area)
+    torch.cuda.synchronize()
+    return gd
+
+
+def pixel_triangles(g, sc):
+    """Input triangle hit by the centre ray of every pixel of every view, in
+    the images' pixel order (-1: none)."""
+    cams = sc["cams"]
+    W, H = int(cams["width"]), int(cams["height"])
+    c2w = np.asarray(cams["cam_to_world"], np.float64)
+    fov = np.asarray(cams["fov_y"], np.float64).reshape(-1)
+    ys, xs = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    out = []
+    for v in range(c2w.shape[0]):
+        t = np.tan(0.5 * fov[v])
+        d = np.stack([(2 * xs / W - 1) * t * W / H, (1 - 2 * ys / H) * t, -np.ones_like(xs)], -1).reshape(-1, 3)
+        d = d @ c2w[v, :3, :3].T
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        o = np.ascontiguousarray(np.broadcast_to(c2w[v, :3, 3], d.shape))
+        tri, _ = g.trace_rays(torch.as_tensor(o, dtype=torch.float32, device="cuda").contiguous(),
+                              torch.as_tensor(d, dtype=torch.float32, device="cuda").contiguous())
+        out.append(tri.cpu().numpy().astype(np.int64))
+    return np.concatenate(out)
+
+
+def triangle_errors(image, target, pix_tri, T):
+    """Mean l2 error (mean over channels of (image - target)^2) of the pixels
+    each triangle covers (the refinement criterion of the paper's textured
+    scenes, supplement Sec. "Results on Scenes with Textures"), and the pixel
+    count per triangle."""
+    e = ((image - target) ** 2).mean(dim=1).double().cpu().numpy()
+    m = pix_tri >= 0
+    cnt = np.bincount(pix_tri[m], minlength=T)
+    tot = np.bincount(pix_tri[m], weights=e[m], minlength=T)
+    return np.where(cnt > 0, tot / np.maximum(cnt, 1), 0.0), cnt
+
+
+def texture_rmse(sc, params, tri_kd, cnt):
+    """Albedo error per triangle (each triangle's own or its segment's kd
+    against its true kd), RMSE weighted by the pixels each triangle covers."""
+    p = params.cpu().numpy() if torch.is_tensor(params) else np.asarray(params)
+    seg = np.asarray(sc["tri_seg"], np.int64)
+    kd = p[7 * seg[:, None] + np.arange(3)[None, :]]
+    w = cnt.astype(np.float64)
+    return float(np.sqrt((w[:, None] * (kd - tri_kd) ** 2).sum() / (3 * w.sum())))
+
+
+def coarse_to_fine(sc, iters_coarse=300, iters_fine=300, seed=7, spp=None, refine="above_mean", log=None,
+                   lr=1e-2, beta2=0.9):
+    """Coarse-to-fine optimisation on a textured scene (App. A; supplement,
+    scenes with textures): one material per object first, then every
+    triangle whose covered pixels have a mean l2 error above the mean over
+    all covered pixels gets a material of its own, and the optimisation
+    continues from the coarse estimate.  sc: a per-object scene with
+    `tri_params` (true per-triangle materials).  Emission stays at its coarse
+    estimate's training (it remains trainable).  Returns the texture RMSE and
+    image error after each phase."""
+    cfg = sc["render"]
+    D, rr = cfg["max_depth"], cfg["rr_depth"]
+    spp = spp or cfg["spp"]
+    tri_kd = np.asarray(sc["tri_params"], np.float64)[:, :3]
+    T = sc["tris"].shape[0]
+    gt = scenes.per_triangle(sc, tri_params=sc["tri_params"])
+    g_gt = ipt.Scene.from_dict(gt)
+    dc = ipt.make_cameras(sc["cams"])
+    target = render_target(g_gt, dc, torch.as_tensor(gt["params"], device="cuda"), cfg["target_spp"], D, rr)
+    del g_gt
+    g = ipt.Scene.from_dict(sc)
+    pix_tri = pixel_triangles(g, sc)
+    out = {}
+    tr = sc["trainable"].astype(bool)
+    emit = set(int(x) for x in sc["emitter_seg"])
+    fixed = np.zeros(sc["params"].size, bool)
+    for s_ in emit:
+        fixed[7 * s_:7 * s_ + 7] = True
+    head = tr & ~fixed
+    res = optimize(sc, iters=iters_coarse, seed=seed, target=target, g=g, spp=spp, lr=lr, lr_schedule="cos",
+                   masks=(head, head), fixed=fixed, beta2=beta2, log=log, log_every=100)
+    p_c = optimize.last["params"]
+    img = g.render(dc, p_c, ipt.render_opts(seed=5, stream_tag=1, spp=64, max_depth=D, rr_depth=rr, mis=2))
+    err, cnt = triangle_errors(img, target, pix_tri, T)
+    out["coarse"] = dict(texture_rmse=texture_rmse(sc, p_c, tri_kd, cnt), image_l2=float(((img - target) ** 2).mean()),
+                         seconds=res["seconds"], segments=sc["num_segments"])
+    # refine the triangles whose pixels carry more than the mean error
+    mean_err = (err * cnt).sum() / max(cnt.sum(), 1)
+    pick = np.nonzero((cnt > 0) & (err > mean_err))[0] if refine == "above_mean" else np.nonzero(cnt > 0)[0]
+    fine = scenes.per_triangle(dict(sc, params=p_c.cpu().numpy()), tris=pick)
+    # truth of the refined parameterisation (for the progress RMSE only): refined triangles their own
+    # albedo, the rest the object's mean
+    truth = scenes.per_triangle(sc, tris=pick, tri_params=sc["tri_params"])["params"]
+    fine_eval = dict(fine, params=truth)
+    g2 = ipt.Scene.from_dict(fine)
+    tr2 = fine["trainable"].astype(bool)
+    fixed2 = np.zeros(fine["params"].size, bool)
+    for s_ in fine["emitter_seg"]:
+        fixed2[7 * int(s_):7 * int(s_) + 7] = True
+    head2 = tr2 & ~fixed2
+    res2 = optimize(fine_eval, iters=iters_fine, seed=seed + 1, target=target, g=g2, spp=spp, lr=lr,
+                    lr_schedule="cos", masks=(head2, head2), fixed=fixed2, beta2=beta2, log=log, log_every=100,
+                    p_init=fine["params"])
+    p_f = optimize.last["params"]
+    img2 = g2.render(dc, p_f, ipt.render_opts(seed=5, stream_tag=1, spp=64, max_depth=D, rr_depth=rr, mis=2))
+    out["fine"] = dict(texture_rmse=texture_rmse(fine, p_f, tri_kd, cnt),
+                       image_l2=float(((img2 - target) ** 2).mean()), seconds=res2["seconds"],
+                       segments=fine["num_segments"], refined_triangles=int(pick.size),
+                       params_global=int(g2.info()["params_global"]))
+    out["seen_triangles"] = int((cnt > 0).sum())
+    return out
 
 
 def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, guide_mix=0.5, seed=555, cached=0):
@@ -480,9 +677,32 @@ def main(argv=None):
     ap.add_argument("--lam", type=float, default=1e-3)
     ap.add_argument("--loss", default="l1", choices=["l1", "l2"], help="image loss of the paper setting")
     ap.add_argument("--grad-spp", type=int, default=1, help="paper setting: paths per pixel of the derivative estimate")
+    ap.add_argument("--ablation", default=None, choices=sorted(ABLATIONS),
+                    help="the paper's optimiser ablations on the workload, --budget seconds per run")
+    ap.add_argument("--budget", type=float, default=5.0)
+    ap.add_argument("--coarse-to-fine", action="store_true",
+                    help="textured Cornell: per-object optimisation, then per-triangle refinement where the "
+                         "re-rendering error is high")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     sc = scenes.WORKLOADS[a.workload]()
+    if a.coarse_to_fine:
+        log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
+        for seed in a.seeds:
+            r = coarse_to_fine(scenes.textured_cornell(), iters_coarse=a.iters or 300, iters_fine=a.iters or 300,
+                               seed=seed, log=log)
+            log("coarse to fine (seed %d): %s" % (seed, json.dumps(r)))
+            if a.out:
+                with open(a.out, "a") as f:
+                    f.write(json.dumps(dict(workload="textured_cornell", mode="coarse_to_fine", seed=seed, **r)) + "\n")
+        return
+    if a.ablation:
+        log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
+        rows = run_ablation(sc, a.ablation, a.budget, a.seeds, target_spp=a.target_spp or 4096, log=log, lam=a.lam)
+        if a.out:
+            with open(a.out, "a") as f:
+                f.write(json.dumps(dict(workload=sc["name"], ablation=a.ablation, budget=a.budget, rows=rows)) + "\n")
+        return
     if a.paper_setting:
         log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
         sc = scenes.all_emissive(sc)
@@ -544,12 +764,19 @@ def main(argv=None):
                        guide_every=a.guide_every)
         if a.variance and a.guide:
             L = optimize.last
-            for where, p_at in (("final", L["params"]), ("init", L["init"])):
-                vs = gradient_variance(g, dc, sc, p_at, target, L["guide"], tr & ~fixed, K=a.variance,
-                                       spp=a.spp, cached=1 if a.guide_cells else 0, guide_mix=a.guide_mix)
-                res["variance" if where == "final" else "variance_init"] = vs
-                log("gradient variance over %d seeds at the %s parameters (guide trained for %d iterations): %s"
-                    % (a.variance, where, res["iters"], json.dumps(vs)))
+            vs = gradient_variance(g, dc, sc, L["params"], target, L["guide"], tr & ~fixed, K=a.variance,
+                                   spp=a.spp, cached=1 if a.guide_cells else 0, guide_mix=a.guide_mix)
+            res["variance"] = vs
+            log("gradient variance over %d seeds at the final parameters (guide trained online over the %d "
+                "iterations): %s" % (a.variance, res["iters"], json.dumps(vs)))
+            # at the initial parameters, with a guide trained online at those parameters
+            gi = train_guide_at(g, dc, sc, L["init"], target, iters=100, guide_steps=a.guide_steps,
+                                guide_mix=a.guide_mix, seed=seed, guide_cells=a.guide_cells, spp=a.spp)
+            vs = gradient_variance(g, dc, sc, L["init"], target, gi, tr & ~fixed, K=a.variance, spp=a.spp,
+                                   cached=1 if a.guide_cells else 0, guide_mix=a.guide_mix)
+            res["variance_init"] = vs
+            log("gradient variance over %d seeds at the initial parameters (guide trained there for 100 "
+                "iterations): %s" % (a.variance, json.dumps(vs)))
         line = json.dumps(dict(workload=a.workload, **res))
         if a.out:
             with open(a.out, "a") as f:

@@ -451,6 +451,102 @@ def all_emissive(sc):
     return out
 
 
+def per_triangle(sc, tris=None, tri_params=None):
+    """Per-triangle refinement (App. A, coarse to fine): every triangle in
+    `tris` (default: every triangle of a segment that does not emit) becomes a
+    segment of its own with its own material, starting from its old
+    segment's values (or from tri_params [T, 7] when given).  Emitter segments
+    stay whole, so the emission entries keep their order.  The result has
+    `parent` (new segment -> old segment) and `seg_of_tri`."""
+    S, E = sc["num_segments"], len(sc["emitter_seg"])
+    T = sc["tris"].shape[0]
+    old = np.asarray(sc["tri_seg"], np.int64)
+    emit = set(int(x) for x in sc["emitter_seg"])
+    split = np.zeros(T, bool)
+    if tris is None:
+        split[:] = [int(x) not in emit for x in old]
+    else:
+        split[np.asarray(tris, np.int64)] = True
+        split &= np.array([int(x) not in emit for x in old])
+    # old segments that keep at least one triangle stay segments (first), then
+    # one new segment per split triangle
+    keep = sorted(set(old[~split].tolist()))
+    new_of_old = {o: i for i, o in enumerate(keep)}
+    seg = np.empty(T, np.int64)
+    parent = list(keep)
+    for t in range(T):
+        if split[t]:
+            seg[t] = len(parent)
+            parent.append(int(old[t]))
+        else:
+            seg[t] = new_of_old[int(old[t])]
+    S2 = len(parent)
+    P2 = 7 * S2 + 3 * E
+    pick = lambda a: np.concatenate([np.asarray(a)[7 * np.asarray(parent)[:, None] + np.arange(7)[None, :]].reshape(-1),
+                                     np.asarray(a)[7 * S:]])
+    params, scale, lo, hi, tr = (pick(sc[k]) for k in ("params", "scale", "lo", "hi", "trainable"))
+    if tri_params is not None:
+        tp = np.asarray(tri_params, np.float32)
+        for t in np.nonzero(split)[0]:
+            params[7 * seg[t]:7 * seg[t] + 7] = tp[t]
+    emitter_seg = np.array([new_of_old[int(x)] for x in sc["emitter_seg"]], np.int32)
+    out = dict(sc)
+    out.update(name=sc["name"] + "_per_triangle", tri_seg=seg.astype(np.int32), num_segments=S2,
+               emitter_seg=emitter_seg, params=params.astype(np.float32), scale=scale.astype(np.float32),
+               lo=lo.astype(np.float32), hi=hi.astype(np.float32), trainable=tr.astype(np.uint8),
+               parent=np.asarray(parent, np.int32), seg_of_tri=seg.astype(np.int32))
+    assert params.size == P2
+    return out
+
+
+def textured_cornell(seed=1, n=12):
+    """Cornell box whose walls and floor carry a texture: each is an n x n
+    grid of quads, and the albedo varies per triangle (a smooth two-tone
+    pattern per wall), so one constant albedo per object cannot match the
+    images while one per triangle can.  Returns the per-object scene (the
+    parameters hold each object's mean albedo) with `tri_kd` [T, 3], the true
+    albedo of every triangle; `per_triangle(sc, tri_params=...)` with it is
+    the ground truth."""
+    rng = np.random.default_rng(seed)
+    b = MeshBuilder()
+    c = np.array([0.5, 0.5, 0.5])
+    X, Y, Z = np.array([0.5, 0, 0]), np.array([0, 0.5, 0]), np.array([0, 0, 0.5])
+    b.quad(c - Y, [0, 1, 0], X, Z, 0, n, n)        # floor
+    b.quad(c + Y, [0, -1, 0], X, Z, 1)             # ceiling
+    b.quad(c - Z, [0, 0, 1], X, Y, 2, n, n)        # back
+    b.quad(c - X, [1, 0, 0], Y, Z, 3, n, n)        # left
+    b.quad(c + X, [-1, 0, 0], Y, Z, 4, n, n)       # right
+    b.box([0.15, 0.0, 0.2], [0.45, 0.6, 0.5], 5)
+    b.box([0.6, 0.0, 0.55], [0.9, 0.3, 0.85], 6)
+    b.quad([0.5, 1.0 - 1e-3, 0.5], [0, -1, 0], [0.125, 0, 0], [0, 0, 0.125], 7)
+    S, E = 8, 1
+    params, scale, lo, hi, tr = _param_vectors(S, E, [7], rng, (0.2, 0.8), None, None, (5.0, 15.0), True, 15.0)
+    v, nrm, f, sg = b.arrays()
+    T = f.shape[0]
+    tri_kd = np.repeat(params[:7 * S].reshape(S, 7)[:, :3][sg], 1, axis=0).astype(np.float64)
+    cen = v[f].mean(axis=1).astype(np.float64)
+    for s_ in (0, 2, 3, 4):
+        m = sg == s_
+        a, b2 = rng.uniform(0.15, 0.45, 3), rng.uniform(0.55, 0.9, 3)
+        k = rng.uniform(4.0, 9.0, 3)
+        ph = rng.uniform(0, 2 * math.pi)
+        w = 0.5 + 0.5 * np.sin(k[0] * cen[m, 0] + k[1] * cen[m, 1] + k[2] * cen[m, 2] + ph)
+        tri_kd[m] = a[None, :] + (b2 - a)[None, :] * w[:, None]
+        params[7 * s_:7 * s_ + 3] = tri_kd[m].mean(axis=0)
+    cams = dict(cam_to_world=look_at([0.5, 0.5, 1.9], [0.5, 0.5, 0.0])[None],
+                fov_y=np.array([math.radians(40.0)], np.float32), width=128, height=128)
+    render = dict(spp=16, max_depth=3, rr_depth=-1, target_spp=1024, iters=300, lr=1e-2, init="half")
+    out = dict(name="textured_cornell", verts=v, normals=None, tris=f, tri_seg=sg, num_segments=S,
+               emitter_seg=np.array([7], np.int32), cams=cams, params=params,
+               scale=scale.astype(np.float32), lo=lo.astype(np.float32), hi=hi.astype(np.float32),
+               trainable=tr, render=render)
+    tp = np.zeros((T, 7), np.float32)
+    tp[:, :3] = tri_kd
+    tp[:, 6] = 0.5
+    out["tri_params"] = tp
+    return out
+
+
 # --------------------------------------------------------------------------
 # Closed-form test scenes and tiny meshes.
 # --------------------------------------------------------------------------

@@ -1,0 +1,114 @@
+"""Parameters in global memory (ipt_build_opts.param_storage, automatic above
+4096 parameters) through the C ABI: per-triangle materials (the paper's
+coarse-to-fine refinement, App. A) make the parameter vector grow with the
+triangle count, so the path kernels read it through the caches and the
+adjoint adds float64 atomics into one accumulator instead of per-block LDS
+copies and partials.
+
+* Same scene, LDS vs forced global storage: images bit-identical (the same
+  values are read), gradients equal up to summation order.
+* Against the oracle at the usual bars: per-triangle Cornell (forced global),
+  the textured Cornell ground truth (8256 parameters, global by size) and the
+  per-triangle room (about 49k segments, 345k parameters) on pixel subsets.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from _gpu import GRAD_ILL_COND, banner, comparable, dev, gpu_grad, gpu_render, mismatch_stats, oracle_opts
+from oracle import oracle
+from paper_1903_07145_amd import ipt, scenes
+
+pytestmark = pytest.mark.gpu
+
+PIX_REL = 1e-4
+GRAD_REL = 1e-3
+
+
+def _oracle(sc):
+    return oracle.Scene(sc["verts"], sc["tris"], sc["tri_seg"], sc["num_segments"], sc["emitter_seg"],
+                        sc["normals"])
+
+
+def _parity(sc, g, o, kw, pix=None, min_keep=0.9):
+    dc = ipt.make_cameras(sc["cams"])
+    p = sc["params"]
+    _, h_g = gpu_render(g, dc, p, kw, pixel_list=pix)
+    r = o.run(sc["cams"], p, pixel_list=pix, want_hash=True, want_margin=True, want_cond=True, **oracle_opts(kw))
+    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"], r["cond"])
+    keep = comparable(h_g, r)
+    print("paths %d mismatching %d (hard %d), compared %.1f%%" % (h_g.size, n_mis, n_hard, 100 * keep.mean()))
+    assert n_hard <= 1e-5 * 3 * h_g.size
+    assert keep.mean() > min_keep
+    img_g, _ = gpu_render(g, dc, p, kw, pixel_list=pix, mask=keep)
+    ro = o.run(sc["cams"], p, pixel_list=pix, path_mask=keep.astype(np.uint8), **oracle_opts(kw))
+    mean = np.abs(ro["image"]).mean()
+    err = np.abs(img_g - ro["image"]) / np.maximum(np.abs(ro["image"]), 1e-4 * mean)
+    print("pixel rel err max %.2e" % err.max())
+    assert err.max() <= PIX_REL
+    wimg = np.random.default_rng(4).normal(size=(img_g.shape[0], 3))
+    gcond = o.run(sc["cams"], p, pixel_list=pix, w=wimg, want_cond=True, **oracle_opts(kw))["gcond"]
+    keep_g = keep & (gcond <= GRAD_ILL_COND)
+    gg = gpu_grad(g, dc, p, wimg, kw, pixel_list=pix, mask=keep_g)
+    go = o.run(sc["cams"], p, pixel_list=pix, w=wimg, path_mask=keep_g.astype(np.uint8), want_grad=True,
+               **oracle_opts(kw))["grad"]
+    rms = math.sqrt(np.mean(go ** 2))
+    gerr = np.abs(gg - go) / np.maximum(np.abs(go), 1e-2 * rms)
+    print("grad rel err max %.2e over %d parameters (%d nonzero)" % (gerr.max(), go.size, int((go != 0).sum())))
+    assert gerr.max() <= GRAD_REL
+    return gg, go
+
+
+def test_lds_and_global_storage_agree():
+    banner("per-triangle Cornell: LDS vs global parameter storage")
+    sc = scenes.per_triangle(scenes.cornell())
+    ga = ipt.Scene.from_dict(sc)
+    gb = ipt.Scene.from_dict(sc, param_storage=ipt.PARAMS_GLOBAL)
+    assert ga.info()["params_global"] == 0 and gb.info()["params_global"] == 1
+    dc = ipt.make_cameras(sc["cams"])
+    kw = dict(seed=3, stream_tag=1, iteration=1, spp=8, max_depth=3, mis=2)
+    ia, ha = gpu_render(ga, dc, sc["params"], kw)
+    ib, hb = gpu_render(gb, dc, sc["params"], kw)
+    assert np.array_equal(ha, hb)
+    assert np.array_equal(ia, ib)
+    w = np.random.default_rng(1).normal(size=(64 * 64, 3))
+    gk = dict(kw, stream_tag=2)
+    a = gpu_grad(ga, dc, sc["params"], w, gk)
+    b = gpu_grad(gb, dc, sc["params"], w, gk)
+    rms = math.sqrt(np.mean(a ** 2))
+    print("grad max diff %.2e (rms %.2e)" % (np.abs(a - b).max(), rms))
+    assert np.abs(a - b).max() <= 1e-5 * rms
+    # the workspace of the global mode holds one accumulator, not one per block
+    o = ipt.render_opts(**gk)
+    assert gb.workspace_query(dc, o)[0] < ga.workspace_query(dc, o)[0]
+
+
+def test_global_storage_parity_cornell():
+    banner("per-triangle Cornell, global storage, vs oracle")
+    sc = scenes.per_triangle(scenes.cornell())
+    g = ipt.Scene.from_dict(sc, param_storage=ipt.PARAMS_GLOBAL)
+    _parity(sc, g, _oracle(sc), dict(seed=7, stream_tag=1, iteration=2, spp=4, max_depth=3, mis=2))
+
+
+def test_global_storage_parity_textured():
+    banner("textured Cornell ground truth: 1179 segments, 8256 parameters (global by size)")
+    tc = scenes.textured_cornell()
+    sc = scenes.per_triangle(tc, tri_params=tc["tri_params"])
+    g = ipt.Scene.from_dict(sc)
+    assert g.info()["params_global"] == 1
+    pix = np.sort(np.random.default_rng(2).choice(128 * 128, size=1500, replace=False)).astype(np.int64)
+    gg, go = _parity(sc, g, _oracle(sc), dict(seed=9, stream_tag=1, iteration=1, spp=8, max_depth=3, mis=2), pix=pix)
+    assert (go != 0).sum() > 300
+
+
+def test_global_storage_parity_room_per_triangle():
+    banner("per-triangle room: ~49k segments, ~345k parameters")
+    sc = scenes.per_triangle(scenes.room())
+    g = ipt.Scene.from_dict(sc)
+    assert g.info()["params_global"] == 1
+    W, H = sc["cams"]["width"], sc["cams"]["height"]
+    pix = np.sort(np.random.default_rng(3).choice(4 * W * H, size=400, replace=False)).astype(np.int64)
+    _parity(sc, g, _oracle(sc), dict(seed=11, stream_tag=1, iteration=1, spp=4, max_depth=3, mis=2), pix=pix,
+            min_keep=0.85)
