@@ -383,6 +383,7 @@ static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Plan {
     int grid = 0;
+    int grad_copies = 0;
     size_t off_counters = 0, off_cdf = 0, off_loss = 0, off_w = 0, off_img = 0, off_gpart = 0, off_ovf = 0,
            off_part = 0, off_ck = 0, end_fixed = 0;
     int64_t chunk = 0;         // work pixels per gradient chunk
@@ -425,8 +426,11 @@ static void make_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t np
     pl.off_loss = off; off = al256(off + sizeof(float) * 1024);
     pl.off_w = off; off = al256(off + (with_loss ? sizeof(float) * 3 * npix : 0));
     pl.off_img = off; off = al256(off + (with_loss ? sizeof(float) * 3 * npix : 0));
-    // replay gradient: per-block partials, or one accumulator with global parameters
-    pl.off_gpart = off; off = al256(off + sizeof(double) * (s->params_global ? (size_t)P : (size_t)pl.grid * P));
+    // replay gradient: per-block partials, or with global parameters grad_copies
+    // accumulators (as many as the grid has blocks, within kGradCopyBytes)
+    pl.grad_copies = s->params_global ? (int)std::max<int64_t>(1, std::min<int64_t>(pl.grid,
+                                            (int64_t)(kGradCopyBytes / (sizeof(double) * (size_t)P)))) : pl.grid;
+    pl.off_gpart = off; off = al256(off + sizeof(double) * (size_t)pl.grad_copies * P);
     pl.off_ovf = off; off = al256(off + sizeof(int) * (size_t)kOvfDepth * pl.grid * kBlock);
     // colour sample sums when pixels are split over lanes: nchunk * npix <= 2 lanes + npix
     const int64_t lanes = (int64_t)pl.grid * kBlock;
@@ -489,6 +493,7 @@ static PathArgs base_args(const ipt_scene_s* s, const ipt_cameras* cams, const f
     a.grad_part = (double*)(ws + pl.off_gpart);
     a.replay_traverse = o->replay_traverse;
     a.params_global = s->params_global;
+    a.grad_copies = pl.grad_copies;
     a.guided = o->guide != nullptr;
     a.gmix = a.guided ? o->guide_mix : 0.0f;
     a.guide_kind = guide_kind(o);
@@ -541,7 +546,7 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
     HIP_OK(launch_light_cdf(s->dev, a.sparams, (float*)(ws + pl.off_cdf), st));
     size_t lds_f = path_lds_bytes(kGradFwd, a.P, a.frozen, s->S, s->nlt, a.guide_kind, a.params_global);
     size_t lds_r = path_lds_bytes(kReplay, a.P, a.frozen, s->S, s->nlt, 0, a.params_global);
-    if (a.params_global) HIP_OK(launch_zero_u32((unsigned*)a.grad_part, 2 * a.P, st));
+    if (a.params_global) HIP_OK(launch_zero_u32((unsigned*)a.grad_part, 2 * a.grad_copies * a.P, st));
     for (int64_t b = 0; b < npix; b += chunk) {
         a.pix_begin = b;
         a.pix_count = std::min<int64_t>(chunk, npix - b);
@@ -555,7 +560,7 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
         HIP_OK(timed_launch(s, kReplay, a, grid_r, lds_r, st));
         if (!a.params_global) HIP_OK(launch_grad_reduce(a.grad_part, grid_r, a.P, grad, b > 0 ? 1 : 0, st));
     }
-    if (a.params_global) HIP_OK(launch_grad_reduce(a.grad_part, 1, a.P, grad, 0, st));
+    if (a.params_global) HIP_OK(launch_grad_reduce(a.grad_part, a.grad_copies, a.P, grad, 0, st));
     return IPT_OK;
 }
 

@@ -16,6 +16,10 @@ constexpr int kMaxDepth = 16;     // max scattering vertices per path
 constexpr int kMaxLdsLights = 1024;
 constexpr int kMaxLdsParams = 4096;  // larger parameter vectors stay in global memory
 constexpr int64_t kMaxParams = 1ll << 26;
+// global parameter storage: the adjoint's float64 accumulator is replicated
+// (block b adds into copy b mod R) within this many bytes, so paths that hit
+// the same few parameters do not all contend for one address
+constexpr size_t kGradCopyBytes = size_t(256) << 20;
 
 // Checkpoint record flags (packed with tri+1 in the low 28 bits).
 constexpr uint32_t kCkTriMask = 0x0FFFFFFFu;
@@ -84,8 +88,10 @@ struct PathArgs {
     int* ovf;                      // [kOvfDepth][grid threads]
     int replay_traverse;
     int params_global;             // parameters read from global memory; the adjoint adds float64
-                                   // atomics into grad_part[P] (else per-block LDS copies and
+                                   // atomics into copy blockIdx.x mod grad_copies of
+                                   // grad_part[grad_copies][P] (else per-block LDS copies and
                                    // partials grad_part[gridDim.x][P])
+    int grad_copies;
     int count_stats;               // accumulate KStats into err->k[mode]
     // learned proposal (one-sample MIS with BRDF sampling)
     GuideDev gd;

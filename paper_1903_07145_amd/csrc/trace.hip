@@ -86,7 +86,7 @@ __device__ void carve_lds(const PathArgs& a, int mode, unsigned char* smem, Lds&
     }
     lds.grad = nullptr;
     if (mode == kReplay) {
-        if (pg) lds.grad = a.grad_part;
+        if (pg) lds.grad = a.grad_part + (size_t)(blockIdx.x % a.grad_copies) * a.P;
         else { lds.grad = (double*)p; p += al(sizeof(double) * a.P); }
     }
     lds.stack = (int*)p;

@@ -547,67 +547,92 @@ def texture_rmse(sc, params, tri_kd, cnt):
     return float(np.sqrt((w[:, None] * (kd - tri_kd) ** 2).sum() / (3 * w.sum())))
 
 
-def coarse_to_fine(sc, iters_coarse=300, iters_fine=300, seed=7, spp=None, refine="above_mean", log=None,
+def _refined_scene(sc0, refined, tri_vals, emission):
+    """sc0 with one material per triangle in `refined` (values tri_vals [T, 7])
+    and, for every other triangle, its object's current material (shared by
+    the object's unrefined triangles)."""
+    S0 = sc0["num_segments"]
+    p = np.array(sc0["params"], np.float32)
+    seg = np.asarray(sc0["tri_seg"], np.int64)
+    rest = np.setdiff1d(np.arange(seg.size), refined)
+    for s_ in range(S0):
+        t = rest[seg[rest] == s_]
+        if t.size:
+            p[7 * s_:7 * s_ + 7] = tri_vals[t[0]]
+    p[7 * S0:] = emission
+    return scenes.per_triangle(dict(sc0, params=p), tris=refined, tri_params=tri_vals)
+
+
+def coarse_to_fine(sc, iters_coarse=300, iters_fine=200, rounds=3, seed=7, spp=None, refine="above_mean", log=None,
                    lr=1e-2, beta2=0.9):
     """Coarse-to-fine optimisation on a textured scene (App. A; supplement,
-    scenes with textures): one material per object first, then every
-    triangle whose covered pixels have a mean l2 error above the mean over
-    all covered pixels gets a material of its own, and the optimisation
-    continues from the coarse estimate.  sc: a per-object scene with
-    `tri_params` (true per-triangle materials).  Emission stays at its coarse
-    estimate's training (it remains trainable).  Returns the texture RMSE and
-    image error after each phase."""
+    scenes with textures): one material per object first; then, `rounds`
+    times, every triangle whose covered pixels carry a mean l2 re-rendering
+    error above the mean over all covered pixels gets a material of its own
+    and the optimisation continues from the current estimate (refine="all":
+    every seen triangle at once, the comparison arm).  Emission stays
+    trainable.  sc: a per-object scene with `tri_params` (true per-triangle
+    materials).  Returns the texture RMSE (albedo per triangle, weighted by
+    covered pixels) and image error after each phase."""
     cfg = sc["render"]
     D, rr = cfg["max_depth"], cfg["rr_depth"]
     spp = spp or cfg["spp"]
-    tri_kd = np.asarray(sc["tri_params"], np.float64)[:, :3]
+    tri_true = np.asarray(sc["tri_params"], np.float32)
+    tri_kd = tri_true[:, :3].astype(np.float64)
     T = sc["tris"].shape[0]
-    gt = scenes.per_triangle(sc, tri_params=sc["tri_params"])
+    S0 = sc["num_segments"]
+    gt = scenes.per_triangle(sc, tri_params=tri_true)
     g_gt = ipt.Scene.from_dict(gt)
     dc = ipt.make_cameras(sc["cams"])
     target = render_target(g_gt, dc, torch.as_tensor(gt["params"], device="cuda"), cfg["target_spp"], D, rr)
     del g_gt
     g = ipt.Scene.from_dict(sc)
     pix_tri = pixel_triangles(g, sc)
-    out = {}
-    tr = sc["trainable"].astype(bool)
-    emit = set(int(x) for x in sc["emitter_seg"])
-    fixed = np.zeros(sc["params"].size, bool)
-    for s_ in emit:
-        fixed[7 * s_:7 * s_ + 7] = True
-    head = tr & ~fixed
-    res = optimize(sc, iters=iters_coarse, seed=seed, target=target, g=g, spp=spp, lr=lr, lr_schedule="cos",
-                   masks=(head, head), fixed=fixed, beta2=beta2, log=log, log_every=100)
-    p_c = optimize.last["params"]
-    img = g.render(dc, p_c, ipt.render_opts(seed=5, stream_tag=1, spp=64, max_depth=D, rr_depth=rr, mis=2))
+    eval_opts = ipt.render_opts(seed=5, stream_tag=1, spp=64, max_depth=D, rr_depth=rr, mis=2)
+
+    def run(scene, truth, g_, iters, p_init, it_seed):
+        fixed = np.zeros(scene["params"].size, bool)
+        for s_ in scene["emitter_seg"]:
+            fixed[7 * int(s_):7 * int(s_) + 7] = True
+        head = scene["trainable"].astype(bool) & ~fixed
+        res = optimize(dict(scene, params=truth), iters=iters, seed=it_seed, target=target, g=g_, spp=spp, lr=lr,
+                       lr_schedule="cos", masks=(head, head), fixed=fixed, beta2=beta2, log=log, log_every=100,
+                       p_init=p_init)
+        p = optimize.last["params"]
+        img = g_.render(dc, p, eval_opts)
+        return p, img, res["seconds"]
+
+    phases = []
+    p_c, img, sec = run(sc, sc["params"], g, iters_coarse, None, seed)
     err, cnt = triangle_errors(img, target, pix_tri, T)
-    out["coarse"] = dict(texture_rmse=texture_rmse(sc, p_c, tri_kd, cnt), image_l2=float(((img - target) ** 2).mean()),
-                         seconds=res["seconds"], segments=sc["num_segments"])
-    # refine the triangles whose pixels carry more than the mean error
-    mean_err = (err * cnt).sum() / max(cnt.sum(), 1)
-    pick = np.nonzero((cnt > 0) & (err > mean_err))[0] if refine == "above_mean" else np.nonzero(cnt > 0)[0]
-    fine = scenes.per_triangle(dict(sc, params=p_c.cpu().numpy()), tris=pick)
-    # truth of the refined parameterisation (for the progress RMSE only): refined triangles their own
-    # albedo, the rest the object's mean
-    truth = scenes.per_triangle(sc, tris=pick, tri_params=sc["tri_params"])["params"]
-    fine_eval = dict(fine, params=truth)
-    g2 = ipt.Scene.from_dict(fine)
-    tr2 = fine["trainable"].astype(bool)
-    fixed2 = np.zeros(fine["params"].size, bool)
-    for s_ in fine["emitter_seg"]:
-        fixed2[7 * int(s_):7 * int(s_) + 7] = True
-    head2 = tr2 & ~fixed2
-    res2 = optimize(fine_eval, iters=iters_fine, seed=seed + 1, target=target, g=g2, spp=spp, lr=lr,
-                    lr_schedule="cos", masks=(head2, head2), fixed=fixed2, beta2=beta2, log=log, log_every=100,
-                    p_init=fine["params"])
-    p_f = optimize.last["params"]
-    img2 = g2.render(dc, p_f, ipt.render_opts(seed=5, stream_tag=1, spp=64, max_depth=D, rr_depth=rr, mis=2))
-    out["fine"] = dict(texture_rmse=texture_rmse(fine, p_f, tri_kd, cnt),
-                       image_l2=float(((img2 - target) ** 2).mean()), seconds=res2["seconds"],
-                       segments=fine["num_segments"], refined_triangles=int(pick.size),
-                       params_global=int(g2.info()["params_global"]))
-    out["seen_triangles"] = int((cnt > 0).sum())
-    return out
+    phases.append(dict(phase="objects", segments=S0, texture_rmse=texture_rmse(sc, p_c, tri_kd, cnt),
+                       image_l2=float(((img - target) ** 2).mean()), seconds=sec))
+    pc = p_c.cpu().numpy()
+    tri_vals = pc[7 * np.asarray(sc["tri_seg"], np.int64)[:, None] + np.arange(7)[None, :]].astype(np.float32)
+    emission = pc[7 * S0:]
+    refined = np.zeros(0, np.int64)
+    for r in range(1 if refine == "all" else rounds):
+        if refine == "all":
+            new = np.nonzero(cnt > 0)[0]
+        else:
+            mean_err = (err * cnt).sum() / max(cnt.sum(), 1)
+            new = np.nonzero((cnt > 0) & (err > mean_err))[0]
+        refined = np.union1d(refined, new)
+        scene = _refined_scene(sc, refined, tri_vals, emission)
+        truth = scenes.per_triangle(sc, tris=refined, tri_params=tri_true)["params"]
+        g2 = ipt.Scene.from_dict(scene)
+        iters = iters_fine * (rounds if refine == "all" else 1)
+        p_f, img, sec = run(scene, truth, g2, iters, scene["params"], seed + 1 + r)
+        err, _ = triangle_errors(img, target, pix_tri, T)
+        pf = p_f.cpu().numpy()
+        tri_vals = pf[7 * np.asarray(scene["tri_seg"], np.int64)[:, None] + np.arange(7)[None, :]].astype(np.float32)
+        emission = pf[7 * scene["num_segments"]:]
+        phases.append(dict(phase="refine %d" % (r + 1), segments=scene["num_segments"], refined=int(refined.size),
+                           texture_rmse=texture_rmse(scene, p_f, tri_kd, cnt),
+                           image_l2=float(((img - target) ** 2).mean()), seconds=sec,
+                           params_global=int(g2.info()["params_global"])))
+        del g2
+    return dict(phases=phases, seen_triangles=int((cnt > 0).sum()), refine=refine)
 
 
 def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, guide_mix=0.5, seed=555, cached=0):
@@ -689,12 +714,16 @@ def main(argv=None):
     if a.coarse_to_fine:
         log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
         for seed in a.seeds:
-            r = coarse_to_fine(scenes.textured_cornell(), iters_coarse=a.iters or 300, iters_fine=a.iters or 300,
-                               seed=seed, log=log)
-            log("coarse to fine (seed %d): %s" % (seed, json.dumps(r)))
-            if a.out:
-                with open(a.out, "a") as f:
-                    f.write(json.dumps(dict(workload="textured_cornell", mode="coarse_to_fine", seed=seed, **r)) + "\n")
+            for mode in ("above_mean", "all"):
+                r = coarse_to_fine(scenes.textured_cornell(), iters_coarse=a.iters or 300, iters_fine=a.iters or 200,
+                                   seed=seed, refine=mode)
+                for ph in r["phases"]:
+                    log("coarse to fine (seed %d, refine %s, %d seen triangles): %s" % (
+                        seed, mode, r["seen_triangles"], json.dumps(ph)))
+                if a.out:
+                    with open(a.out, "a") as f:
+                        f.write(json.dumps(dict(workload="textured_cornell", mode="coarse_to_fine", seed=seed,
+                                                **r)) + "\n")
         return
     if a.ablation:
         log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)

@@ -6,10 +6,14 @@ adjoint adds float64 atomics into one accumulator instead of per-block LDS
 copies and partials.
 
 * Same scene, LDS vs forced global storage: images bit-identical (the same
-  values are read), gradients equal up to summation order.
+  values are read), gradients equal up to summation order (global storage
+  sums float64 atomics into replicated accumulators, then the copies in a
+  fixed order).
 * Against the oracle at the usual bars: per-triangle Cornell (forced global),
   the textured Cornell ground truth (8256 parameters, global by size) and the
   per-triangle room (about 49k segments, 345k parameters) on pixel subsets.
+  Parameters no compared path reaches must be zero on both sides; the rms
+  that scales the gradient bar is taken over the parameters reached.
 """
 import math
 
@@ -54,9 +58,17 @@ def _parity(sc, g, o, kw, pix=None, min_keep=0.9):
     gg = gpu_grad(g, dc, p, wimg, kw, pixel_list=pix, mask=keep_g)
     go = o.run(sc["cams"], p, pixel_list=pix, w=wimg, path_mask=keep_g.astype(np.uint8), want_grad=True,
                **oracle_opts(kw))["grad"]
-    rms = math.sqrt(np.mean(go ** 2))
+    # with one material per triangle most parameters are reached by none of
+    # the compared paths: those must be exactly zero on both sides, and the
+    # scale of the relative bar (rms) is taken over the parameters reached,
+    # not diluted by the structural zeros
+    touched = go != 0
+    assert np.all(gg[~touched] == 0.0)
+    rms = math.sqrt(np.mean(go[touched] ** 2))
     gerr = np.abs(gg - go) / np.maximum(np.abs(go), 1e-2 * rms)
-    print("grad rel err max %.2e over %d parameters (%d nonzero)" % (gerr.max(), go.size, int((go != 0).sum())))
+    worst = int(np.argmax(gerr))
+    print("grad rel err max %.2e over %d parameters (%d reached; worst %d, entry %d of its block)" % (
+        gerr.max(), go.size, int(touched.sum()), worst, worst % 7 if worst < 7 * sc["num_segments"] else -1))
     assert gerr.max() <= GRAD_REL
     return gg, go
 
@@ -80,9 +92,6 @@ def test_lds_and_global_storage_agree():
     rms = math.sqrt(np.mean(a ** 2))
     print("grad max diff %.2e (rms %.2e)" % (np.abs(a - b).max(), rms))
     assert np.abs(a - b).max() <= 1e-5 * rms
-    # the workspace of the global mode holds one accumulator, not one per block
-    o = ipt.render_opts(**gk)
-    assert gb.workspace_query(dc, o)[0] < ga.workspace_query(dc, o)[0]
 
 
 def test_global_storage_parity_cornell():
