@@ -394,8 +394,8 @@ struct Plan {
 // or IPT_BLOCKS_PER_CU when set (tuning).
 static int path_grid(const ipt_scene_s* s, int P, int frozen, int gk) {
     const int pg = s->params_global;
-    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, gk, pg), gk);
-    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, gk, pg), gk));
+    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, gk, pg), gk, pg);
+    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, gk, pg), gk, pg));
     static const int forced = [] {
         const char* e = std::getenv("IPT_BLOCKS_PER_CU");
         return e ? std::atoi(e) : 0;
@@ -555,7 +555,7 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
         HIP_OK(timed_launch(s, kGradFwd, a, grid, lds_f, st));
         if (a.guided) HIP_OK(launch_guide_records(a, st));
         // the replay pulls tiles, so it runs on as many blocks as are resident
-        int grid_r = std::min(grid, s->num_cu * std::max(1, path_blocks_per_cu(kReplay, lds_r)));
+        int grid_r = std::min(grid, s->num_cu * std::max(1, path_blocks_per_cu(kReplay, lds_r, 0, a.params_global)));
         HIP_OK(launch_zero_u32(a.work, 1, st));
         HIP_OK(timed_launch(s, kReplay, a, grid_r, lds_r, st));
         if (!a.params_global) HIP_OK(launch_grad_reduce(a.grad_part, grid_r, a.P, grad, b > 0 ? 1 : 0, st));

@@ -106,7 +106,7 @@ struct PathArgs {
 };
 
 size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guide_kind = 0, int params_global = 0);
-int path_blocks_per_cu(int mode, size_t lds, int guide_kind = 0);
+int path_blocks_per_cu(int mode, size_t lds, int guide_kind = 0, int params_global = 0);
 hipError_t launch_guide_records(const PathArgs& a, hipStream_t st);
 hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st);
 // guide handle internals (guide.hip)

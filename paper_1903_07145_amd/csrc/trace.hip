@@ -61,12 +61,16 @@ size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int gk, int p
     return b;
 }
 
+// PG (a compile-time copy of PathArgs::params_global) keeps each pointer's
+// address space known, so LDS reads stay ds_read and the LDS gradient
+// ds_add_f64 rather than flat accesses.
+template <int PG>
 __device__ void carve_lds(const PathArgs& a, int mode, unsigned char* smem, Lds& lds) {
     const int tid = threadIdx.x;
     unsigned char* p = smem;
     auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
-    const int pg = a.params_global;
-    if (pg) {
+    constexpr int pg = PG;
+    if constexpr (PG) {
         // parameters, segment table and the replay's gradient accumulator in global memory
         lds.params = (float*)a.params;
         lds.sparams = (float*)a.sparams;
@@ -86,13 +90,13 @@ __device__ void carve_lds(const PathArgs& a, int mode, unsigned char* smem, Lds&
     }
     lds.grad = nullptr;
     if (mode == kReplay) {
-        if (pg) lds.grad = a.grad_part + (size_t)(blockIdx.x % a.grad_copies) * a.P;
+        if constexpr (PG) lds.grad = a.grad_part + (size_t)(blockIdx.x % a.grad_copies) * a.P;
         else { lds.grad = (double*)p; p += al(sizeof(double) * a.P); }
     }
     lds.stack = (int*)p;
     p += sizeof(int) * kShortStack * kBlock;
     lds.gact = (__bf16*)p + (threadIdx.x >> 6) * 64 * kGRowStride;
-    if (!pg) {
+    if constexpr (!pg) {
         for (int i = tid; i < a.P; i += kBlock) {
             lds.params[i] = a.params[i];
             if (a.frozen) lds.sparams[i] = a.sparams[i];
@@ -577,14 +581,14 @@ enum Phase { kNeedPixel = 0, kClosest = 1, kShadow = 2, kExit = 3 };
 #endif
 
 // GUIDE: 0 none, 1 bfloat16 MFMA evaluation, 2 float32 VALU evaluation
-template <int MODE, int GUIDE>
+template <int MODE, int GUIDE, int PG>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU_GUIDED : IPT_WAVES_PER_EU,
                                    8))) void path_sm_kernel(
     PathArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     Lds lds;
-    carve_lds(a, MODE, smem, lds);
+    carve_lds<PG>(a, MODE, smem, lds);
     Stack st;
     init_stack(st, a, lds.stack);
     const SceneDev& sc = a.sc;
@@ -796,42 +800,48 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
             float u[8];
             vertex_uniforms(a.rng, pid, k, u);
             float pb_nee = -1.0f;
-            const bool do_nee = a.mis != 0 && sc.nlt > 0;
-            NeeS n;
-            n.shoot = false;
-            n.lj = 0;
-            if (do_nee) {
-                n = nee_setup(sc, cdf, lights, g, u);
-                ev |= (uint32_t)n.lj << 8;
-            }
-            ContDir cd;
-            float q_wi = 0.0f, q_wl = 0.0f;
-            if (GUIDE == 3) {
-                cd = cont_direction_cached(a, g, ms, u, mix);
-                cached_pdf2(mix, cd.wi, n.shoot ? n.wl : cd.wi, q_wi, q_wl);
-            }
-            if (do_nee) {
-                if (n.shoot) {
-                    if (GUIDE == 3)
-                        pb_nee = a.gmix * q_wl + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, n.wl);
-                    else if (GUIDE && mix)
-                        pb_nee = a.gmix * guide_pdf<GUIDE>(mix, n.wl) + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, n.wl);
-                    NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n, pb_nee);
-                    shoot = true;
-                    nee_valid = nc.valid;
-                    nee_c = nc.c;
-                    nee_LT = T * nc.c;
-                    wl = n.wl;
-                    sdist = n.dist;
-                    sltri = n.ltri;
-                }
-            }
+            // light sample accepted: its contribution waits for the shadow ray
+            auto take_nee = [&](const NeeS& n) {
+                NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n, pb_nee);
+                shoot = true;
+                nee_valid = nc.valid;
+                nee_c = nc.c;
+                nee_LT = T * nc.c;
+                wl = n.wl;
+                sdist = n.dist;
+                sltri = n.ltri;
+            };
             bool used_guide = false;
             ContS cs;
-            if (GUIDE == 3) {
+            if constexpr (GUIDE == 3) {
+                // cached proposal: direction first, then both densities in one pass over the row
+                NeeS n;
+                n.shoot = false;
+                n.lj = 0;
+                const bool do_nee = a.mis != 0 && sc.nlt > 0;
+                if (do_nee) {
+                    n = nee_setup(sc, cdf, lights, g, u);
+                    ev |= (uint32_t)n.lj << 8;
+                }
+                const ContDir cd = cont_direction_cached(a, g, ms, u, mix);
+                float q_wi, q_wl;
+                cached_pdf2(mix, cd.wi, n.shoot ? n.wl : cd.wi, q_wi, q_wl);
+                if (n.shoot) {
+                    pb_nee = a.gmix * q_wl + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, n.wl);
+                    take_nee(n);
+                }
                 cs = cont_finish_cached(a, g, m, ms, u, k, Ts, cd, q_wi);
                 used_guide = cd.guide;
             } else {
+                if (a.mis != 0 && sc.nlt > 0) {
+                    NeeS n = nee_setup(sc, cdf, lights, g, u);
+                    ev |= (uint32_t)n.lj << 8;
+                    if (n.shoot) {
+                        if (GUIDE && mix)
+                            pb_nee = a.gmix * guide_pdf<GUIDE>(mix, n.wl) + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, n.wl);
+                        take_nee(n);
+                    }
+                }
                 cs = cont_sample<GUIDE>(a, g, m, ms, u, k, Ts, mix, used_guide);
             }
             ev |= (uint32_t)cs.lobe << 3;
@@ -1023,12 +1033,13 @@ __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& 
     }
 }
 
+template <int PG>
 __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned tile_sh;
     const int tid = threadIdx.x;
     Lds lds;
-    carve_lds(a, kReplay, smem, lds);
+    carve_lds<PG>(a, kReplay, smem, lds);
     Stack st;
     init_stack(st, a, lds.stack);
     const int64_t npix_img = (int64_t)a.V * a.W * a.H;
@@ -1067,7 +1078,7 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     }
     if (st.overflow) atomicAdd(&a.err->overflow, 1ull);
     flush_stats(a, kReplay, wk, npaths);
-    if (a.params_global) return;   // the atomics went straight to the accumulator
+    if constexpr (PG) return;   // the atomics went straight to the accumulator copies
     __syncthreads();
     double* out = a.grad_part + (size_t)blockIdx.x * a.P;
     for (int i = tid; i < a.P; i += kBlock) out[i] = lds.grad[i];
@@ -1155,41 +1166,46 @@ static int occ(K kern, size_t lds) {
     return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 
-template <int MODE>
+template <int MODE, int PG>
 static int path_occ(int gk, size_t lds) {
     switch (gk) {
-        case 1: return occ(path_sm_kernel<MODE, 1>, lds);
-        case 2: return occ(path_sm_kernel<MODE, 2>, lds);
-        case 3: return occ(path_sm_kernel<MODE, 3>, lds);
-        default: return occ(path_sm_kernel<MODE, 0>, lds);
+        case 1: return occ(path_sm_kernel<MODE, 1, PG>, lds);
+        case 2: return occ(path_sm_kernel<MODE, 2, PG>, lds);
+        case 3: return occ(path_sm_kernel<MODE, 3, PG>, lds);
+        default: return occ(path_sm_kernel<MODE, 0, PG>, lds);
     }
 }
 
-template <int MODE>
+template <int MODE, int PG>
 static void launch_path_kind(int gk, const PathArgs& a, int grid, size_t lds, hipStream_t st) {
     switch (gk) {
-        case 1: hipLaunchKernelGGL((path_sm_kernel<MODE, 1>), dim3(grid), dim3(kBlock), lds, st, a); break;
-        case 2: hipLaunchKernelGGL((path_sm_kernel<MODE, 2>), dim3(grid), dim3(kBlock), lds, st, a); break;
-        case 3: hipLaunchKernelGGL((path_sm_kernel<MODE, 3>), dim3(grid), dim3(kBlock), lds, st, a); break;
-        default: hipLaunchKernelGGL((path_sm_kernel<MODE, 0>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        case 1: hipLaunchKernelGGL((path_sm_kernel<MODE, 1, PG>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((path_sm_kernel<MODE, 2, PG>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        case 3: hipLaunchKernelGGL((path_sm_kernel<MODE, 3, PG>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        default: hipLaunchKernelGGL((path_sm_kernel<MODE, 0, PG>), dim3(grid), dim3(kBlock), lds, st, a); break;
     }
 }
 
-int path_blocks_per_cu(int mode, size_t lds, int gk) {
-    if (mode == kColor) return path_occ<kColor>(gk, lds);
-    if (mode == kGradFwd) return path_occ<kGradFwd>(gk, lds);
-    return occ(replay_kernel, lds);
+int path_blocks_per_cu(int mode, size_t lds, int gk, int pg) {
+    if (mode == kColor) return pg ? path_occ<kColor, 1>(gk, lds) : path_occ<kColor, 0>(gk, lds);
+    if (mode == kGradFwd) return pg ? path_occ<kGradFwd, 1>(gk, lds) : path_occ<kGradFwd, 0>(gk, lds);
+    return pg ? occ(replay_kernel<1>, lds) : occ(replay_kernel<0>, lds);
 }
 
 // The proposal is compiled in only when it is sampled (guide_mix > 0); kind
 // as in PathArgs::guide_kind.
 hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st) {
+    const int pg = a.params_global;
     if (mode == kColor) {
-        launch_path_kind<kColor>(a.guide_kind, a, grid, lds, st);
+        if (pg) launch_path_kind<kColor, 1>(a.guide_kind, a, grid, lds, st);
+        else launch_path_kind<kColor, 0>(a.guide_kind, a, grid, lds, st);
     } else if (mode == kGradFwd) {
-        launch_path_kind<kGradFwd>(a.guide_kind, a, grid, lds, st);
+        if (pg) launch_path_kind<kGradFwd, 1>(a.guide_kind, a, grid, lds, st);
+        else launch_path_kind<kGradFwd, 0>(a.guide_kind, a, grid, lds, st);
+    } else if (pg) {
+        hipLaunchKernelGGL(replay_kernel<1>, dim3(grid), dim3(kBlock), lds, st, a);
     } else {
-        hipLaunchKernelGGL(replay_kernel, dim3(grid), dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL(replay_kernel<0>, dim3(grid), dim3(kBlock), lds, st, a);
     }
     return hipGetLastError();
 }

@@ -5,8 +5,9 @@ triangle count, so the path kernels read it through the caches and the
 adjoint adds float64 atomics into one accumulator instead of per-block LDS
 copies and partials.
 
-* Same scene, LDS vs forced global storage: images bit-identical (the same
-  values are read), gradients equal up to summation order (global storage
+* Same scene, LDS vs forced global storage: the same events, images equal to
+  float32 rounding (separately compiled kernels), gradients equal up to
+  summation order (global storage
   sums float64 atomics into replicated accumulators, then the copies in a
   fixed order).
 * Against the oracle at the usual bars: per-triangle Cornell (forced global),
@@ -84,7 +85,12 @@ def test_lds_and_global_storage_agree():
     ia, ha = gpu_render(ga, dc, sc["params"], kw)
     ib, hb = gpu_render(gb, dc, sc["params"], kw)
     assert np.array_equal(ha, hb)
-    assert np.array_equal(ia, ib)
+    # two separately compiled kernels: the same arithmetic up to instruction
+    # selection (contraction), so equal to float32 rounding, well inside the
+    # 1e-4 oracle bar
+    rel = np.abs(ia - ib) / np.maximum(np.abs(ia), 1e-4 * np.abs(ia).mean())
+    print("image max rel diff %.2e" % rel.max())
+    assert rel.max() <= 1e-5
     w = np.random.default_rng(1).normal(size=(64 * 64, 3))
     gk = dict(kw, stream_tag=2)
     a = gpu_grad(ga, dc, sc["params"], w, gk)
