@@ -73,14 +73,23 @@ def measured_traffic(kernel, workload):
 
 
 def copy_reference(nbytes=256 << 20, launches=3):
-    """A copy kernel of known size: each launch reads and writes `nbytes`."""
+    """A copy kernel of known size: each launch reads and writes `nbytes`.
+    Also reports the achieved copy bandwidth (read + write bytes over the
+    event-timed duration of 20 more launches): the practical HBM ceiling."""
     import torch
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(launches):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_reference_bytes": nbytes, "launches": launches}), flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    print(json.dumps({"copy_reference_bytes": nbytes, "launches": launches, "copy_gbs": round(gbs, 1)}), flush=True)
 
 
 def main():
