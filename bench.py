@@ -317,9 +317,18 @@ def cpu_baseline(sc, cfg, params, target, budget_s):
     except OSError:
         pass
     log("oracle: %d gradient paths in %.1fs on %d threads" % (paths, dt, threads))
+    # the same on one core, on a sixteenth of the sample
+    pix1 = pix[::16]
+    old = oracle.set_threads(1)
+    t0 = time.time()
+    o.run(sc["cams"], params, pixel_list=pix1, w=w[::16], want_grad=True, **kw)
+    dt1 = time.time() - t0
+    oracle.set_threads(old)
+    log("oracle on one core: %d gradient paths in %.1fs" % (pix1.size * cfg["spp"], dt1))
     return {"value": round(paths / dt, 1), "unit": "grad paths/s", "cores": threads, "kind": "oracle",
             "sample": "every %d-th pixel of all %d views (%d pixels) at %d spp, forward+derivatives in FP64; "
-                      "%.1f s; %s" % (stride, V, pix.size, cfg["spp"], dt, cpu_model)}
+                      "%.1f s; %s" % (stride, V, pix.size, cfg["spp"], dt, cpu_model),
+            "single_core_value": round(pix1.size * cfg["spp"] / dt1, 1)}
 
 
 if __name__ == "__main__":

@@ -891,6 +891,20 @@ int orc_cell_query(const orc_scene *s, int64_t t, double u, double v, int back, 
     return cell_subdiv(s, t, cell_area);
 }
 
+/* Threads of the OpenMP loops (timing on one core or all of them);
+ * returns the previous setting. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    int old = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return old;
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* Exported for tests: mixture parameters for n feature rows [n][9] + segments. */
 void orc_guide_eval(const float *w, const double *feat, const int32_t *seg, int64_t n, double *out)
 {

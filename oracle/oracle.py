@@ -70,6 +70,8 @@ def lib():
         L.orc_mixture_pdf.restype = ctypes.c_double
         L.orc_mixture_pdf.argtypes = [P, P]
         L.orc_mixture_sample.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        L.orc_set_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_cell_query.restype = ctypes.c_int
         L.orc_cell_query.argtypes = [P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                      ctypes.c_float, P]
@@ -146,6 +148,11 @@ def guide_eval(weights, feat, seg):
     out = np.zeros((f.shape[0], 40))
     lib().orc_guide_eval(_ptr(w), _ptr(f), _ptr(sg), f.shape[0], _ptr(out))
     return out
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's loops; returns the previous setting."""
+    return lib().orc_set_threads(int(n))
 
 
 def mixture_pdf(mix, w):
