@@ -52,3 +52,77 @@ def test_textured_cornell_object_means():
         assert tc["tri_params"][tc["tri_seg"] == s, :3].std(axis=0).min() > 0.02
     for s in (1, 5, 6):
         assert tc["tri_params"][tc["tri_seg"] == s, :3].std(axis=0).max() < 1e-6
+
+
+def test_cell_area_for_matches_surface_area():
+    import torch  # noqa: F401  (optimize imports torch)
+    from paper_1903_07145_amd import optimize
+    sc = scenes.cornell()
+    # unit room: floor, ceiling and three walls (5 m^2), two boxes and the emitter quad
+    v = sc["verts"].astype(np.float64)
+    t = sc["tris"].astype(np.int64)
+    area = 0.5 * np.linalg.norm(np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]]), axis=1).sum()
+    boxes = 2 * (0.3 * 0.6 + 0.3 * 0.3 + 0.6 * 0.3) + 2 * (3 * 0.3 * 0.3)
+    assert abs(area - (5.0 + boxes + 0.0625)) < 1e-5
+    assert abs(optimize.cell_area_for(sc, 1000) - area / 1000) < 1e-6 * area
+
+
+def test_texture_rmse_and_triangle_errors():
+    import torch
+    from paper_1903_07145_amd import optimize
+    tc = scenes.textured_cornell()
+    T = tc["tris"].shape[0]
+    tri_kd = tc["tri_params"][:, :3].astype(np.float64)
+    cnt = np.ones(T)
+    # per-object parameters (object means): the RMSE is the texture's spread
+    r = optimize.texture_rmse(tc, tc["params"], tri_kd, cnt)
+    seg = tc["tri_seg"]
+    kd = tc["params"][7 * seg[:, None] + np.arange(3)[None, :]]
+    assert abs(r - np.sqrt(np.mean((kd - tri_kd) ** 2))) < 1e-9 and r > 0.05
+    # the ground truth has none
+    gt = scenes.per_triangle(tc, tri_params=tc["tri_params"])
+    assert optimize.texture_rmse(gt, gt["params"], tri_kd, cnt) < 1e-6
+    # triangle errors: mean over the pixels each triangle covers
+    img = torch.zeros((6, 3))
+    tgt = torch.tensor([[1.0, 1, 1], [2, 2, 2], [0, 0, 0], [3, 3, 3], [0, 0, 0], [0, 0, 0]])
+    pix_tri = np.array([0, 0, 1, 2, -1, 1])
+    err, c = optimize.triangle_errors(img, tgt, pix_tri, 4)
+    assert np.allclose(c, [2, 2, 1, 0])
+    assert np.allclose(err, [(1 + 4) / 2, 0.0, 9.0, 0.0])
+
+
+def test_refined_scene_inherits_current_values():
+    from paper_1903_07145_amd import optimize
+    sc = scenes.cornell()
+    T = sc["tris"].shape[0]
+    vals = np.random.default_rng(3).uniform(0, 1, (T, 7)).astype(np.float32)
+    # unrefined triangles of an object share its value
+    for s in range(sc["num_segments"]):
+        m = sc["tri_seg"] == s
+        vals[m] = vals[np.nonzero(m)[0][0]]
+    refined = np.array([0, 3, 12])
+    vals[refined] = np.random.default_rng(4).uniform(0, 1, (3, 7))
+    em = np.array([1.0, 2.0, 3.0], np.float32)
+    ns = optimize._refined_scene(sc, refined, vals, em)
+    for t in range(T):
+        assert np.array_equal(ns["params"][7 * ns["tri_seg"][t]:7 * ns["tri_seg"][t] + 7], vals[t])
+    assert np.array_equal(ns["params"][-3:], em)
+    assert len(set(ns["tri_seg"][refined].tolist())) == 3
+
+
+def test_paper_setting_masks():
+    from paper_1903_07145_amd import optimize
+    sc = scenes.all_emissive(scenes.cornell())
+    S = sc["num_segments"]
+    cov = np.full(S, 500)
+    cov[6] = 50            # a box seen in too few pixels: held fixed
+    fixed, head = optimize.paper_setting_masks(sc, cov)
+    e0 = int(sc["true_emitters"][0])
+    assert fixed[7 * 6:7 * 6 + 7].all() and fixed[7 * S + 18:7 * S + 21].all()
+    assert fixed[7 * e0:7 * e0 + 7].all() and not fixed[7 * S + 3 * e0]
+    assert head[0:3].all() and not head[3:7].any()          # albedo only (ks, roughness not trainable)
+    assert head[7 * S:7 * S + 3].all()                       # every seen segment's emission
+    sigma = np.zeros(sc["params"].size)
+    sigma[1] = 1.0
+    _, head2 = optimize.paper_setting_masks(sc, cov, sigma=sigma)
+    assert not head2[1] and head2[0]
