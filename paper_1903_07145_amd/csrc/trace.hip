@@ -171,26 +171,36 @@ __device__ __forceinline__ void load_tri(const SceneDev& sc, int i, V3& p0, V3& 
     light = __float_as_int(c.w);
 }
 
-// Closest hit (any = false) or occlusion test (any = true: stops at the
-// first hit in (tmin, tmax)).  skip0/skip1 are leaf indices that are ignored.
-// Ties in t are resolved toward the smaller original id.
-//
-// Loop structure for 64-wide waves ("while-while" with speculative
-// traversal, Aila and Laine 2009): the node phase visits inner nodes until
-// every lane holds a leaf (a lane that already holds one keeps descending, and
-// stops only at a second leaf), then the leaf phase tests the held leaves of
-// all lanes together.  Node code and triangle code thus run with most lanes
-// doing the same thing, instead of every iteration paying for both.
 constexpr int kTravDone = (int)0x80000000;   // no node left (leaf codes are > INT_MIN)
 
-__device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax, int skip0, int skip1, bool any,
-                        Stack& st, Work& wk) {
-    Hit best{-1, tmax, 0.0f, 0.0f};
-    int best_orig = 0x7FFFFFFF;
-    wk.rays++;
+// Traversal state of one lane, kept across calls when a call returns early.
+struct Trav {
+    int cur;        // next node: inner (>= 0), leaf code (< 0) or kTravDone
+    int pend;       // leaf held for the leaf phase
+    int best_orig;  // original id of the best hit (tie rule)
+    Hit best;
+};
+
+__device__ __forceinline__ void trav_init(Trav& tv, float tmax, Stack& st, Work& wk) {
+    tv.cur = 0;
+    tv.pend = kTravDone;
+    tv.best_orig = 0x7FFFFFFF;
+    tv.best = Hit{-1, tmax, 0.0f, 0.0f};
     st.sp = 0;
-    int cur = 0;             // next node: inner (>= 0), leaf code (< 0) or kTravDone
-    int pend = kTravDone;    // leaf held for the leaf phase
+    wk.rays++;
+}
+
+// Advances the lanes' traversals; returns true for a lane whose traversal
+// has finished (its hit is then in tv.best).  With exit_lanes > 0 the call
+// also returns, after at least one node phase and one leaf phase (so every
+// call advances every unfinished lane), as soon as no more than exit_lanes
+// lanes of the wave are still traversing: those keep their state and resume
+// on the next call, while the others shade and start new rays, instead of
+// idling through the slowest rays' tail.
+__device__ bool traverse_resume(const SceneDev& sc, const Ray& r, float tmin, float tmax, int skip0, int skip1,
+                                bool any, Stack& st, Work& wk, Trav& tv, int exit_lanes) {
+    int cur = tv.cur, pend = tv.pend, best_orig = tv.best_orig;
+    Hit best = tv.best;
     auto next_from_stack = [&]() -> int { return (st.sp > 0 && !st.overflow) ? st.pop() : kTravDone; };
     while (true) {
         // ---- node phase ----
@@ -249,10 +259,36 @@ __device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax
                 }
             }
         }
-        if (!__any(cur != kTravDone)) break;
+        const uint64_t live = __ballot(cur != kTravDone);
+        if (!live) break;
+        if (exit_lanes > 0 && __popcll(live) <= exit_lanes) break;
     }
-    if (!any && best.tri >= 0 && !(best.t < tmax)) best.tri = -1;
-    return best;
+    tv.cur = cur;
+    tv.pend = pend;
+    tv.best_orig = best_orig;
+    const bool done = cur == kTravDone;
+    if (done && !any && best.tri >= 0 && !(best.t < tmax)) best.tri = -1;
+    tv.best = best;
+    return done;
+}
+
+// Closest hit (any = false) or occlusion test (any = true: stops at the
+// first hit in (tmin, tmax)), run to completion.  skip0/skip1 are leaf
+// indices that are ignored.  Ties in t are resolved toward the smaller
+// original id.
+//
+// Loop structure for 64-wide waves ("while-while" with speculative
+// traversal, Aila and Laine 2009): the node phase visits inner nodes until
+// every lane holds a leaf (a lane that already holds one keeps descending, and
+// stops only at a second leaf), then the leaf phase tests the held leaves of
+// all lanes together.  Node code and triangle code thus run with most lanes
+// doing the same thing, instead of every iteration paying for both.
+__device__ Hit traverse(const SceneDev& sc, const Ray& r, float tmin, float tmax, int skip0, int skip1, bool any,
+                        Stack& st, Work& wk) {
+    Trav tv;
+    trav_init(tv, tmax, st, wk);
+    traverse_resume(sc, r, tmin, tmax, skip0, skip1, any, st, wk, tv, 0);
+    return tv.best;
 }
 
 // Brute-force closest hit (reference for the BVH).
@@ -580,6 +616,12 @@ enum Phase { kNeedPixel = 0, kClosest = 1, kShadow = 2, kExit = 3 };
 #define IPT_WAVES_PER_EU_GUIDED 2
 #endif
 
+// A traversal call returns once no more than this many lanes of the wave
+// are still traversing (0: every traversal runs to completion in one call).
+// Apartment step: 203 ms at 0, 188 / 187 / 190 / 195 ms at 8 / 16 / 24 / 32.
+#ifndef IPT_TRAV_EXIT_LANES
+#define IPT_TRAV_EXIT_LANES 16
+#endif
 // GUIDE: 0 none, 1 bfloat16 MFMA evaluation, 2 float32 VALU evaluation
 template <int MODE, int GUIDE, int PG>
 __global__ __launch_bounds__(kBlock)
@@ -602,6 +644,8 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
     uint32_t npaths = 0;
 
     int ph = kNeedPixel;
+    Trav tv;                 // traversal in progress (tracing) across iterations
+    bool tracing = false;
     // work-unit state
     int64_t q = 0, wi = 0, pix = 0, unit = 0;
     int view = 0, px = 0, py = 0, s = 0, s_end = 0;
@@ -689,11 +733,22 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
         size_t ck = 0;
         if (ph == kClosest || ph == kShadow) {
             // ---- one traversal call site for closest-hit and shadow rays ----
+            // a lane whose traversal returned unfinished resumes it here and
+            // skips the rest of the iteration until it is done
             const bool any = ph == kShadow;
+            const float tmax = any ? sdist * (1.0f - 1e-5f) : __builtin_inff();
             Ray ray = make_ray(o, any ? wl : d);
-            hr = traverse(sc, ray, sc.tmin, any ? sdist * (1.0f - 1e-5f) : __builtin_inff(), prev_tri,
-                          any ? sltri : -1, any, st, wk);
-            if (any) {
+            if (!tracing) {
+                trav_init(tv, tmax, st, wk);
+                tracing = true;
+            }
+            const bool done = traverse_resume(sc, ray, sc.tmin, tmax, prev_tri, any ? sltri : -1, any, st, wk, tv,
+                                              IPT_TRAV_EXIT_LANES);
+            if (done) tracing = false;
+            hr = tv.best;
+            if (!done) {
+                // still traversing
+            } else if (any) {
                 // ---- finish the vertex that waited for its shadow ray ----
                 bool vis = hr.tri < 0;
                 ev |= (uint32_t)vis << 2;
