@@ -69,6 +69,45 @@ def coverage(g, sc):
     return cov.cpu().numpy()
 
 
+def target_precision_fd(g, dc, sc, target_var, free, stride=16, spp=16, h=1e-3, seed=98):
+    """The Cramer-Rao bound of the L2 fit with the full Gauss-Newton
+    information H = J^T S^-1 J over the free set, J from central differences
+    of renders at frozen sampling parameters (the same paths on both sides,
+    so the difference is smooth) on every stride-th pixel, scaled by stride
+    (a uniform pixel sample of the sum).  For free sets too large for the
+    random projections of target_precision to estimate H: one render pair
+    per parameter instead of several projections per parameter."""
+    cfg = sc["render"]
+    D, rr = cfg["max_depth"], cfg["rr_depth"]
+    P = sc["params"].size
+    idx = np.nonzero(free)[0]
+    npix = dc["num_views"] * dc["width"] * dc["height"]
+    pix = torch.arange(0, npix, stride, dtype=torch.int64, device="cuda")
+    p = torch.as_tensor(sc["params"], device="cuda")
+    scale = sc["scale"].astype(np.float64)
+    lo, hi = sc["lo"].astype(np.float64), sc["hi"].astype(np.float64)
+    sig = target_var.double().sqrt()
+    sig = sig.clamp_min(1e-3 * float(sig.mean()) + 1e-12).index_select(0, pix).reshape(-1)
+    o = ipt.render_opts(seed=seed, stream_tag=TAG_B, spp=spp, max_depth=D, rr_depth=rr, mis=2, pixel_list=pix)
+    J = torch.empty((pix.numel() * 3, idx.size), dtype=torch.float32, device="cuda")
+    for j, i in enumerate(idx):
+        # a step in normalised units, kept inside the parameter's bounds
+        th = float(p[i]) / scale[i]
+        a, b = max(lo[i], th - h), min(hi[i], th + h)
+        pp, pm = p.clone(), p.clone()
+        pp[i] = b * scale[i]
+        pm[i] = a * scale[i]
+        ip = g.render(dc, pp, o, sampling_params=p).reshape(-1).double()
+        im = g.render(dc, pm, o, sampling_params=p).reshape(-1).double()
+        J[:, j] = ((ip - im) / (b - a) / sig).float()
+    H = (J.T.double() @ J.double()) * stride
+    H = H + 1e-9 * torch.trace(H) / idx.size * torch.eye(idx.size, dtype=H.dtype, device=H.device)
+    cov = torch.linalg.pinv(H, hermitian=True)
+    sigma = np.full(P, np.inf)
+    sigma[idx] = np.sqrt(np.maximum(torch.diagonal(cov).cpu().numpy(), 0.0))
+    return sigma
+
+
 def target_precision(g, dc, sc, target_var, free=None, nproj=None, spp=16, seed=99, max_full=256):
     """How precisely the target images determine each parameter, in
     normalised units: the Cramer-Rao bound of the L2 fit under the target's
@@ -705,6 +744,10 @@ def main(argv=None):
     ap.add_argument("--ablation", default=None, choices=sorted(ABLATIONS),
                     help="the paper's optimiser ablations on the workload, --budget seconds per run")
     ap.add_argument("--budget", type=float, default=5.0)
+    ap.add_argument("--precision", default="projections", choices=["projections", "fd"],
+                    help="target precision (headline set): random projections of the adjoint (full inverse up to "
+                         "256 free parameters, else the diagonal), or the full Gauss-Newton inverse from central "
+                         "differences on a pixel sample")
     ap.add_argument("--coarse-to-fine", action="store_true",
                     help="textured Cornell: per-object optimisation, then per-triangle refinement where the "
                          "re-rendering error is high")
@@ -773,9 +816,12 @@ def main(argv=None):
     cov = coverage(g, sc)
     fixed = unrecoverable_mask(sc, cov)
     tr = sc["trainable"].astype(bool)
-    sigma = target_precision(g, dc, sc, tvar, free=tr & ~fixed)
-    masks = identifiable_masks(sc, cov, sigma=sigma)
     fr = tr & ~fixed
+    if a.precision == "fd":
+        sigma = target_precision_fd(g, dc, sc, tvar, fr)
+    else:
+        sigma = target_precision(g, dc, sc, tvar, free=fr)
+    masks = identifiable_masks(sc, cov, sigma=sigma)
     log("target %d spp, precision in %.1fs; target precision of the free parameters: median %.2e, p90 %.2e, "
         "worst %s" % (a.target_spp or cfg["target_spp"], time.time() - t0, np.median(sigma[fr]),
                       np.percentile(sigma[fr], 90), [(int(i), float("%.3g" % sigma[i])) for i in
