@@ -240,7 +240,7 @@ def cell_area_for(sc, cells):
 def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guide_steps=10, guide_lr=2e-3,
              guide_batch=16384, record_stride=None, target_rmse=1e-2, stop_at_target=False, target=None,
              g=None, log=None, spp=None, lr=None, lr_schedule="const", masks=None, lr_final=None, log_every=10,
-             fixed=None, beta2=0.999, guide_cells=0, guide_every=1, p_init=None):
+             fixed=None, beta2=0.999, guide_cells=0, guide_every=1, p_init=None, mis=2):
     """Runs the optimisation; returns a dict with the RMSE/loss history and timings.
 
     The time to target is taken on the RMSE over masks[0] (identifiable
@@ -297,7 +297,7 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
     t_hit = None
     for it in range(iters):
         mix = guide_mix if (gd is not None and it >= warmup) else 0.0
-        kw = dict(seed=1000 * seed + 11, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2)
+        kw = dict(seed=1000 * seed + 11, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=mis)
         co = ipt.render_opts(stream_tag=TAG_A, guide=gd if mix > 0 else None, guide_mix=mix, guide_cached=cached, **kw)
         go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, guide_cached=cached, **kw)
         g.loss_grad(dc, params, target, co, go, 0, loss=loss, grad=grad)
@@ -514,7 +514,7 @@ def run_ablation(sc, kind, budget, seeds, target_spp=4096, log=None, lam=1e-3):
 
 
 def train_guide_at(g, dc, sc, params, target, iters=100, warmup=5, guide_steps=10, guide_mix=0.5, seed=7,
-                   guide_cells=0, guide_lr=2e-3, guide_batch=16384, spp=None):
+                   guide_cells=0, guide_lr=2e-3, guide_batch=16384, spp=None, mis=2):
     """A guide trained online at fixed parameters: every iteration a gradient
     pass writes records (sampling the guide after `warmup` iterations) and
     the guide takes `guide_steps` training steps; the parameters do not
@@ -531,7 +531,7 @@ def train_guide_at(g, dc, sc, params, target, iters=100, warmup=5, guide_steps=1
         cached = 1
     for it in range(iters):
         mix = guide_mix if it >= warmup else 0.0
-        kw = dict(seed=1000 * seed + 13, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=2)
+        kw = dict(seed=1000 * seed + 13, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=mis)
         co = ipt.render_opts(stream_tag=TAG_A, **kw)
         go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, guide_cached=cached, **kw)
         g.loss_grad(dc, params, target, co, go, 0)
@@ -674,7 +674,8 @@ def coarse_to_fine(sc, iters_coarse=300, iters_fine=200, rounds=3, seed=7, spp=N
     return dict(phases=phases, seen_triangles=int((cnt > 0).sum()), refine=refine)
 
 
-def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, guide_mix=0.5, seed=555, cached=0):
+def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, guide_mix=0.5, seed=555, cached=0,
+                      mis=2):
     """Per-parameter variance of the loss gradient over K independent seeds at
     fixed parameters, with plain BRDF sampling and with the learned proposal
     (one-sample MIS at guide_mix), plus the mean time per gradient of each.
@@ -688,7 +689,7 @@ def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, gu
         torch.cuda.synchronize()
         t0 = time.time()
         for k in range(K):
-            kw = dict(seed=seed + k, iteration=k, spp=spp, max_depth=D, rr_depth=rr, mis=2)
+            kw = dict(seed=seed + k, iteration=k, spp=spp, max_depth=D, rr_depth=rr, mis=mis)
             co = ipt.render_opts(stream_tag=TAG_A, guide=gd, guide_mix=mix, guide_cached=cached if gd else 0, **kw)
             go = ipt.render_opts(stream_tag=TAG_B, guide=gd, guide_mix=mix, guide_cached=cached if gd else 0, **kw)
             _, gr = g.loss_grad(dc, params, target, co, go, 0)
@@ -722,6 +723,8 @@ def main(argv=None):
     ap.add_argument("--guide-cells", type=int, default=0,
                     help="> 0: sample the cached proposal with about this many cells per side")
     ap.add_argument("--guide-every", type=int, default=1, help="train the guide every this many iterations")
+    ap.add_argument("--mis", type=int, default=2, choices=[0, 1, 2, 3],
+                    help="light transport: 0 BRDF sampling only, 1 light sampling only, 2 balance MIS, 3 power")
     ap.add_argument("--target-rmse", type=float, default=1e-2)
     ap.add_argument("--lr", type=float, default=None)
     ap.add_argument("--spp", type=int, default=None)
@@ -836,19 +839,19 @@ def main(argv=None):
                        guide_steps=a.guide_steps, target_rmse=a.target_rmse, target=target, g=g, log=log,
                        lr=a.lr, lr_schedule=a.lr_schedule, masks=masks, spp=a.spp, lr_final=a.lr_final,
                        log_every=a.log_every, fixed=fixed, beta2=a.beta2, guide_cells=a.guide_cells,
-                       guide_every=a.guide_every)
+                       guide_every=a.guide_every, mis=a.mis)
         if a.variance and a.guide:
             L = optimize.last
             vs = gradient_variance(g, dc, sc, L["params"], target, L["guide"], tr & ~fixed, K=a.variance,
-                                   spp=a.spp, cached=1 if a.guide_cells else 0, guide_mix=a.guide_mix)
+                                   spp=a.spp, cached=1 if a.guide_cells else 0, guide_mix=a.guide_mix, mis=a.mis)
             res["variance"] = vs
             log("gradient variance over %d seeds at the final parameters (guide trained online over the %d "
                 "iterations): %s" % (a.variance, res["iters"], json.dumps(vs)))
             # at the initial parameters, with a guide trained online at those parameters
             gi = train_guide_at(g, dc, sc, L["init"], target, iters=100, guide_steps=a.guide_steps,
-                                guide_mix=a.guide_mix, seed=seed, guide_cells=a.guide_cells, spp=a.spp)
+                                guide_mix=a.guide_mix, seed=seed, guide_cells=a.guide_cells, spp=a.spp, mis=a.mis)
             vs = gradient_variance(g, dc, sc, L["init"], target, gi, tr & ~fixed, K=a.variance, spp=a.spp,
-                                   cached=1 if a.guide_cells else 0, guide_mix=a.guide_mix)
+                                   cached=1 if a.guide_cells else 0, guide_mix=a.guide_mix, mis=a.mis)
             res["variance_init"] = vs
             log("gradient variance over %d seeds at the initial parameters (guide trained there for 100 "
                 "iterations): %s" % (a.variance, json.dumps(vs)))

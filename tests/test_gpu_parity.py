@@ -264,3 +264,28 @@ def test_pixel_list_edge_cases(cornell):
     one = np.array([1234], np.int64)
     img1, _ = gpu_render(g, dc, sc["params"], dict(kw, spp=1), pixel_list=one)
     assert img1.shape == (1, 3)
+
+
+def test_colour_pass_is_deterministic():
+    """Pixels are fetched by a dynamic work counter and traversals return
+    early and resume (a lane's path advances whenever its traversal is done),
+    so the order in which lanes do their work varies between launches.  Each
+    pixel's samples are still summed by one lane in sample order (or by a
+    fixed-order reduce over sample chunks), so the image and the per-path
+    hashes are bit-identical on every call.  (The gradient is not: atomics
+    within a block add in varying order.)"""
+    banner("determinism: colour pass, two calls")
+    sc = scenes.room()
+    g = ipt.Scene.from_dict(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    kw = dict(seed=13, stream_tag=1, iteration=5, spp=4, max_depth=5, rr_depth=3, mis=2)
+    a, ha = gpu_render(g, dc, sc["params"], kw)
+    b, hb = gpu_render(g, dc, sc["params"], kw)
+    assert np.array_equal(ha, hb)
+    assert np.array_equal(a, b)
+    # 2 pixels, 512 samples: the samples are split over lanes and reduced in a fixed order
+    pix = np.array([1000, 77777], np.int64)
+    kw2 = dict(kw, spp=512)
+    c, _ = gpu_render(g, dc, sc["params"], kw2, pixel_list=pix)
+    d, _ = gpu_render(g, dc, sc["params"], kw2, pixel_list=pix)
+    assert np.array_equal(c, d)
