@@ -118,7 +118,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: multi-GPU runs are not part of this build "
+        print("bench.py measures one GPU only; runs on several GPUs are not implemented "
               "(paths would shard by pixel tiles with one gradient all-reduce per step).", file=sys.stderr)
         sys.exit(2)
 
