@@ -602,14 +602,18 @@ def _refined_scene(sc0, refined, tri_vals, emission):
     return scenes.per_triangle(dict(sc0, params=p), tris=refined, tri_params=tri_vals)
 
 
-def coarse_to_fine(sc, iters_coarse=300, iters_fine=200, rounds=3, seed=7, spp=None, refine="above_mean", log=None,
+def coarse_to_fine(sc, iters_coarse=300, iters_fine=200, rounds=3, seed=7, spp=None, refine="excess", log=None,
                    lr=1e-2, beta2=0.9):
     """Coarse-to-fine optimisation on a textured scene (App. A; supplement,
     scenes with textures): one material per object first; then, `rounds`
     times, every triangle whose covered pixels carry a mean l2 re-rendering
-    error above the mean over all covered pixels gets a material of its own
-    and the optimisation continues from the current estimate (refine="all":
-    every seen triangle at once, the comparison arm).  Emission stays
+    error above a threshold gets a material of its own and the optimisation
+    continues from the current estimate.  refine="above_mean": the mean over
+    all covered pixels; refine="excess" (default): the error expected from
+    Monte Carlo noise alone (half the mean squared difference of two
+    independent renders of the estimate, plus the target's variance) by more
+    than 3 standard errors; refine="all": every seen triangle at once (the
+    comparison arm).  Emission stays
     trainable.  sc: a per-object scene with `tri_params` (true per-triangle
     materials).  Returns the texture RMSE (albedo per triangle, weighted by
     covered pixels) and image error after each phase."""
@@ -623,11 +627,27 @@ def coarse_to_fine(sc, iters_coarse=300, iters_fine=200, rounds=3, seed=7, spp=N
     gt = scenes.per_triangle(sc, tri_params=tri_true)
     g_gt = ipt.Scene.from_dict(gt)
     dc = ipt.make_cameras(sc["cams"])
-    target = render_target(g_gt, dc, torch.as_tensor(gt["params"], device="cuda"), cfg["target_spp"], D, rr)
+    target, tvar = render_target(g_gt, dc, torch.as_tensor(gt["params"], device="cuda"), cfg["target_spp"], D, rr,
+                                 return_var=True)
     del g_gt
     g = ipt.Scene.from_dict(sc)
     pix_tri = pixel_triangles(g, sc)
     eval_opts = ipt.render_opts(seed=5, stream_tag=1, spp=64, max_depth=D, rr_depth=rr, mis=2)
+    eval_opts2 = ipt.render_opts(seed=6, stream_tag=1, spp=64, max_depth=D, rr_depth=rr, mis=2)
+
+    def excess_pick(g_, p, img):
+        # per triangle: mean squared error against the target, against what
+        # noise alone gives (render variance from two independent renders,
+        # plus the target's variance); refine where it is 3 standard errors above
+        img2 = g_.render(dc, p, eval_opts2)
+        e, cnt_ = triangle_errors(img, target, pix_tri, T)
+        nv = ((img - img2) ** 2).mean(dim=1) / 2 + tvar.mean(dim=1)
+        m = pix_tri >= 0
+        noise = np.bincount(pix_tri[m], weights=nv.double().cpu().numpy()[m], minlength=T) / np.maximum(cnt_, 1)
+        e2 = ((img - target) ** 2).mean(dim=1).double().cpu().numpy()
+        sq = np.bincount(pix_tri[m], weights=e2[m] ** 2, minlength=T) / np.maximum(cnt_, 1)
+        se = np.sqrt(np.maximum(sq - e ** 2, 0.0) / np.maximum(cnt_, 1))
+        return np.nonzero((cnt_ > 0) & (e - noise > 3.0 * se))[0]
 
     def run(scene, truth, g_, iters, p_init, it_seed):
         fixed = np.zeros(scene["params"].size, bool)
@@ -643,6 +663,7 @@ def coarse_to_fine(sc, iters_coarse=300, iters_fine=200, rounds=3, seed=7, spp=N
 
     phases = []
     p_c, img, sec = run(sc, sc["params"], g, iters_coarse, None, seed)
+    g_cur, p_cur = g, p_c
     err, cnt = triangle_errors(img, target, pix_tri, T)
     phases.append(dict(phase="objects", segments=S0, texture_rmse=texture_rmse(sc, p_c, tri_kd, cnt),
                        image_l2=float(((img - target) ** 2).mean()), seconds=sec))
@@ -653,6 +674,8 @@ def coarse_to_fine(sc, iters_coarse=300, iters_fine=200, rounds=3, seed=7, spp=N
     for r in range(1 if refine == "all" else rounds):
         if refine == "all":
             new = np.nonzero(cnt > 0)[0]
+        elif refine == "excess":
+            new = excess_pick(g_cur, p_cur, img)
         else:
             mean_err = (err * cnt).sum() / max(cnt.sum(), 1)
             new = np.nonzero((cnt > 0) & (err > mean_err))[0]
@@ -670,7 +693,7 @@ def coarse_to_fine(sc, iters_coarse=300, iters_fine=200, rounds=3, seed=7, spp=N
                            texture_rmse=texture_rmse(scene, p_f, tri_kd, cnt),
                            image_l2=float(((img - target) ** 2).mean()), seconds=sec,
                            params_global=int(g2.info()["params_global"])))
-        del g2
+        g_cur, p_cur = g2, p_f
     return dict(phases=phases, seen_triangles=int((cnt > 0).sum()), refine=refine)
 
 
@@ -760,7 +783,7 @@ def main(argv=None):
     if a.coarse_to_fine:
         log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
         for seed in a.seeds:
-            for mode in ("above_mean", "all"):
+            for mode in ("excess", "above_mean", "all"):
                 r = coarse_to_fine(scenes.textured_cornell(), iters_coarse=a.iters or 300, iters_fine=a.iters or 200,
                                    seed=seed, refine=mode)
                 for ph in r["phases"]:
