@@ -697,6 +697,100 @@ def coarse_to_fine(sc, iters_coarse=300, iters_fine=200, rounds=3, seed=7, spp=N
     return dict(phases=phases, seen_triangles=int((cnt > 0).sum()), refine=refine)
 
 
+def fine_texture(n_gt=24, n_opt=6, rounds=2, iters_objects=300, iters=300, seed=7, lr=1e-2, beta2=0.9, spp=None,
+                 log=None):
+    """Texture finer than the mesh (supplement, scenes with textures): the
+    target comes from walls tessellated n_gt x n_gt with one albedo per
+    triangle; the optimisation starts from an n_opt x n_opt mesh with one
+    material per object, then gives every triangle its own material, then
+    `rounds` times splits the triangles whose re-rendering error exceeds the
+    noise floor (R-31) into four (scenes.subdivide) and continues.  The
+    measure is the albedo seen at each pixel (the estimate of the triangle
+    the pixel's centre ray hits against the ground truth's)."""
+    tex_gt = scenes.textured_cornell(n=n_gt)
+    cfg = tex_gt["render"]
+    D, rr = cfg["max_depth"], cfg["rr_depth"]
+    spp = spp or cfg["spp"]
+    gt = scenes.per_triangle(tex_gt, tri_params=tex_gt["tri_params"])
+    g_gt = ipt.Scene.from_dict(gt)
+    dc = ipt.make_cameras(tex_gt["cams"])
+    target, tvar = render_target(g_gt, dc, torch.as_tensor(gt["params"], device="cuda"), cfg["target_spp"], D, rr,
+                                 return_var=True)
+    pix_gt = pixel_triangles(g_gt, gt)
+    del g_gt
+    seen = pix_gt >= 0
+    kd_gt = np.asarray(tex_gt["tri_params"], np.float64)[np.maximum(pix_gt, 0), :3]
+    eval1 = ipt.render_opts(seed=5, stream_tag=1, spp=64, max_depth=D, rr_depth=rr, mis=2)
+    eval2 = ipt.render_opts(seed=6, stream_tag=1, spp=64, max_depth=D, rr_depth=rr, mis=2)
+
+    def pixel_albedo_rmse(scene, g_, p):
+        pt = pixel_triangles(g_, scene)
+        ok = seen & (pt >= 0)
+        pp = p.cpu().numpy()
+        seg = np.asarray(scene["tri_seg"], np.int64)[np.maximum(pt, 0)]
+        kd = pp[7 * seg[:, None] + np.arange(3)[None, :]]
+        return float(np.sqrt(((kd - kd_gt)[ok] ** 2).mean())), pt
+
+    def run(scene, g_, iters_, p_init, it_seed):
+        fixed = np.zeros(scene["params"].size, bool)
+        for s_ in scene["emitter_seg"]:
+            fixed[7 * int(s_):7 * int(s_) + 7] = True
+        head = scene["trainable"].astype(bool) & ~fixed
+        # the progress RMSE is against the estimate's own start (no per-parameter truth exists here)
+        res = optimize(scene, iters=iters_, seed=it_seed, target=target, g=g_, spp=spp, lr=lr, lr_schedule="cos",
+                       masks=(head, head), fixed=fixed, beta2=beta2, log=None, p_init=p_init)
+        return optimize.last["params"], res["seconds"]
+
+    def noisy_tris(scene, g_, p, pt):
+        img = g_.render(dc, p, eval1)
+        img2 = g_.render(dc, p, eval2)
+        T = scene["tris"].shape[0]
+        e, cnt = triangle_errors(img, target, pt, T)
+        nv = ((img - img2) ** 2).mean(dim=1) / 2 + tvar.mean(dim=1)
+        m = pt >= 0
+        noise = np.bincount(pt[m], weights=nv.double().cpu().numpy()[m], minlength=T) / np.maximum(cnt, 1)
+        e2 = ((img - target) ** 2).mean(dim=1).double().cpu().numpy()
+        sq = np.bincount(pt[m], weights=e2[m] ** 2, minlength=T) / np.maximum(cnt, 1)
+        se = np.sqrt(np.maximum(sq - e ** 2, 0.0) / np.maximum(cnt, 1))
+        return np.nonzero((cnt > 0) & (e - noise > 3.0 * se))[0], float(((img - target) ** 2).mean())
+
+    phases = []
+    scene = scenes.textured_cornell(n=n_opt)
+    scene.pop("tri_params", None)
+    scene.pop("albedo_at", None)
+    g = ipt.Scene.from_dict(scene)
+    p, sec = run(scene, g, iters_objects, None, seed)
+    r, pt = pixel_albedo_rmse(scene, g, p)
+    _, l2 = noisy_tris(scene, g, p, pt)
+    phases.append(dict(phase="objects", triangles=int(scene["tris"].shape[0]), segments=scene["num_segments"],
+                       pixel_albedo_rmse=r, image_l2=l2, seconds=sec))
+    # one material per triangle
+    scene = scenes.per_triangle(dict(scene, params=p.cpu().numpy()))
+    g = ipt.Scene.from_dict(scene)
+    p, sec = run(scene, g, iters, scene["params"], seed + 1)
+    r, pt = pixel_albedo_rmse(scene, g, p)
+    pick, l2 = noisy_tris(scene, g, p, pt)
+    phases.append(dict(phase="per triangle", triangles=int(scene["tris"].shape[0]), segments=scene["num_segments"],
+                       pixel_albedo_rmse=r, image_l2=l2, seconds=sec))
+    for k in range(rounds):
+        if pick.size == 0:
+            break
+        sub = scenes.subdivide(dict(scene, params=p.cpu().numpy()), pick)
+        children = np.nonzero(np.isin(sub["parent_tri"], pick))[0]
+        scene = scenes.per_triangle(sub, tris=children)
+        g = ipt.Scene.from_dict(scene)
+        p, sec = run(scene, g, iters, scene["params"], seed + 2 + k)
+        r, pt = pixel_albedo_rmse(scene, g, p)
+        pick, l2 = noisy_tris(scene, g, p, pt)
+        phases.append(dict(phase="subdivide %d" % (k + 1), split=int(children.size // 4),
+                           triangles=int(scene["tris"].shape[0]), segments=scene["num_segments"],
+                           pixel_albedo_rmse=r, image_l2=l2, seconds=sec,
+                           params_global=int(g.info()["params_global"])))
+        if log:
+            log("fine texture: %s" % phases[-1])
+    return dict(phases=phases, n_gt=n_gt, n_opt=n_opt)
+
+
 def gradient_variance(g, dc, sc, params, target, guide, free, K=32, spp=None, guide_mix=0.5, seed=555, cached=0,
                       mis=2):
     """Per-parameter variance of the loss gradient over K independent seeds at
@@ -774,12 +868,26 @@ def main(argv=None):
                     help="target precision (headline set): random projections of the adjoint (full inverse up to "
                          "256 free parameters, else the diagonal), or the full Gauss-Newton inverse from central "
                          "differences on a pixel sample")
+    ap.add_argument("--fine-texture", action="store_true",
+                    help="texture finer than the mesh: per-object, per-triangle, then subdivision where the "
+                         "re-rendering error exceeds the noise")
     ap.add_argument("--coarse-to-fine", action="store_true",
                     help="textured Cornell: per-object optimisation, then per-triangle refinement where the "
                          "re-rendering error is high")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     sc = scenes.WORKLOADS[a.workload]()
+    if a.fine_texture:
+        log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
+        for seed in a.seeds:
+            r = fine_texture(seed=seed, iters=a.iters or 300)
+            for ph in r["phases"]:
+                log("fine texture (seed %d, ground truth %dx%d per wall, mesh %dx%d): %s" % (
+                    seed, r["n_gt"], r["n_gt"], r["n_opt"], r["n_opt"], json.dumps(ph)))
+            if a.out:
+                with open(a.out, "a") as f:
+                    f.write(json.dumps(dict(workload="textured_cornell", mode="fine_texture", seed=seed, **r)) + "\n")
+        return
     if a.coarse_to_fine:
         log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
         for seed in a.seeds:

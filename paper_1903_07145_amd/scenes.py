@@ -499,6 +499,53 @@ def per_triangle(sc, tris=None, tri_params=None):
     return out
 
 
+def subdivide(sc, tris):
+    """Splits every triangle in `tris` into four at its edge midpoints (the
+    supplement's subdivision of textured regions).  A midpoint is shared by
+    the split triangles on both sides of an edge; next to an unsplit
+    neighbour it lies on that neighbour's edge.  Children keep their
+    parent's segment (and so its material), vertex normals are interpolated
+    and renormalised.  The result has `parent_tri` (new triangle -> old)."""
+    v = np.asarray(sc["verts"], np.float64)
+    nrm = None if sc.get("normals") is None else np.asarray(sc["normals"], np.float64)
+    f = np.asarray(sc["tris"], np.int64)
+    seg = np.asarray(sc["tri_seg"], np.int64)
+    split = np.zeros(f.shape[0], bool)
+    split[np.asarray(tris, np.int64)] = True
+    verts, norms = [v], [nrm] if nrm is not None else None
+    mid = {}
+    nv = v.shape[0]
+
+    def midpoint(a, b):
+        nonlocal nv
+        key = (min(a, b), max(a, b))
+        if key not in mid:
+            verts.append(0.5 * (v[a] + v[b])[None, :])
+            if norms is not None:
+                m = nrm[a] + nrm[b]
+                norms.append((m / max(np.linalg.norm(m), 1e-30))[None, :])
+            mid[key] = nv
+            nv += 1
+        return mid[key]
+
+    out_f, out_s, parent = [], [], []
+    for t in range(f.shape[0]):
+        a, b, c = (int(x) for x in f[t])
+        if not split[t]:
+            out_f.append((a, b, c)); out_s.append(seg[t]); parent.append(t)
+            continue
+        ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+        for tri in ((a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca)):
+            out_f.append(tri); out_s.append(seg[t]); parent.append(t)
+    out = dict(sc)
+    out.update(verts=np.vstack(verts).astype(np.float32),
+               normals=None if norms is None else np.vstack(norms).astype(np.float32),
+               tris=np.asarray(out_f, np.int32), tri_seg=np.asarray(out_s, np.int32),
+               parent_tri=np.asarray(parent, np.int64))
+    out.pop("tri_params", None)
+    return out
+
+
 def textured_cornell(seed=1, n=12):
     """Cornell box whose walls and floor carry a texture: each is an n x n
     grid of quads, and the albedo varies per triangle (a smooth two-tone
@@ -523,16 +570,31 @@ def textured_cornell(seed=1, n=12):
     params, scale, lo, hi, tr = _param_vectors(S, E, [7], rng, (0.2, 0.8), None, None, (5.0, 15.0), True, 15.0)
     v, nrm, f, sg = b.arrays()
     T = f.shape[0]
-    tri_kd = np.repeat(params[:7 * S].reshape(S, 7)[:, :3][sg], 1, axis=0).astype(np.float64)
-    cen = v[f].mean(axis=1).astype(np.float64)
+    # the texture of each textured object: two tones mixed by a seeded sinusoid of position
+    tex = {}
     for s_ in (0, 2, 3, 4):
-        m = sg == s_
         a, b2 = rng.uniform(0.15, 0.45, 3), rng.uniform(0.55, 0.9, 3)
         k = rng.uniform(4.0, 9.0, 3)
         ph = rng.uniform(0, 2 * math.pi)
-        w = 0.5 + 0.5 * np.sin(k[0] * cen[m, 0] + k[1] * cen[m, 1] + k[2] * cen[m, 2] + ph)
-        tri_kd[m] = a[None, :] + (b2 - a)[None, :] * w[:, None]
-        params[7 * s_:7 * s_ + 3] = tri_kd[m].mean(axis=0)
+        tex[s_] = (a, b2, k, ph)
+
+    def albedo_at(s_, x):
+        """True albedo of object s_ at points x [n, 3] (its constant albedo if untextured)."""
+        x = np.asarray(x, np.float64).reshape(-1, 3)
+        if s_ not in tex:
+            return np.repeat(params[7 * s_:7 * s_ + 3][None, :].astype(np.float64), x.shape[0], axis=0)
+        a, b2, k, ph = tex[s_]
+        w = 0.5 + 0.5 * np.sin(k[0] * x[:, 0] + k[1] * x[:, 1] + k[2] * x[:, 2] + ph)
+        return a[None, :] + (b2 - a)[None, :] * w[:, None]
+
+    cen = v[f].mean(axis=1).astype(np.float64)
+    tri_kd = np.zeros((T, 3))
+    for s_ in range(S):
+        m = sg == s_
+        if m.any():
+            tri_kd[m] = albedo_at(s_, cen[m])
+            if s_ in tex:
+                params[7 * s_:7 * s_ + 3] = tri_kd[m].mean(axis=0)
     cams = dict(cam_to_world=look_at([0.5, 0.5, 1.9], [0.5, 0.5, 0.0])[None],
                 fov_y=np.array([math.radians(40.0)], np.float32), width=128, height=128)
     render = dict(spp=16, max_depth=3, rr_depth=-1, target_spp=1024, iters=300, lr=1e-2, init="half")
@@ -544,6 +606,7 @@ def textured_cornell(seed=1, n=12):
     tp[:, :3] = tri_kd
     tp[:, 6] = 0.5
     out["tri_params"] = tp
+    out["albedo_at"] = albedo_at
     return out
 
 

@@ -126,3 +126,30 @@ def test_paper_setting_masks():
     sigma[1] = 1.0
     _, head2 = optimize.paper_setting_masks(sc, cov, sigma=sigma)
     assert not head2[1] and head2[0]
+
+
+def test_subdivide_shares_midpoints_and_keeps_area():
+    sc = scenes.cornell()
+    T = sc["tris"].shape[0]
+    pick = np.array([0, 1])          # the two triangles of the floor quad share an edge
+    sd = scenes.subdivide(sc, pick)
+    assert sd["tris"].shape[0] == T + 3 * pick.size
+    # 3 midpoints each, the shared edge's once: 5 new vertices
+    assert sd["verts"].shape[0] == sc["verts"].shape[0] + 5
+    assert np.array_equal(np.bincount(sd["parent_tri"], minlength=T), np.where(np.isin(np.arange(T), pick), 4, 1))
+    # children keep the parent's segment; every child lies in its parent's plane, areas add up
+    v = sd["verts"].astype(np.float64)
+    f = sd["tris"].astype(np.int64)
+    area = 0.5 * np.linalg.norm(np.cross(v[f[:, 1]] - v[f[:, 0]], v[f[:, 2]] - v[f[:, 0]]), axis=1)
+    v0 = sc["verts"].astype(np.float64)
+    f0 = sc["tris"].astype(np.int64)
+    area0 = 0.5 * np.linalg.norm(np.cross(v0[f0[:, 1]] - v0[f0[:, 0]], v0[f0[:, 2]] - v0[f0[:, 0]]), axis=1)
+    for t in pick:
+        ch = np.nonzero(sd["parent_tri"] == t)[0]
+        assert np.all(sd["tri_seg"][ch] == sc["tri_seg"][t])
+        assert np.allclose(area[ch], area0[t] / 4)
+        n0 = np.cross(v0[f0[t, 1]] - v0[f0[t, 0]], v0[f0[t, 2]] - v0[f0[t, 0]])
+        for c in ch:
+            n = np.cross(v[f[c, 1]] - v[f[c, 0]], v[f[c, 2]] - v[f[c, 0]])
+            assert np.dot(n, n0) > 0 and np.linalg.norm(np.cross(n, n0)) < 1e-9 * np.linalg.norm(n0) ** 2
+    assert abs(area.sum() - area0.sum()) < 1e-9
