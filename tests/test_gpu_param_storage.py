@@ -127,3 +127,46 @@ def test_global_storage_parity_room_per_triangle():
     pix = np.sort(np.random.default_rng(3).choice(4 * W * H, size=400, replace=False)).astype(np.int64)
     _parity(sc, g, _oracle(sc), dict(seed=11, stream_tag=1, iteration=1, spp=4, max_depth=3, mis=2), pix=pix,
             min_keep=0.85)
+
+
+def test_global_storage_with_cached_proposal():
+    """The cached proposal on a scene whose parameters are in global memory
+    (the kernels of proposal kind 3 with global storage): images and
+    gradients against the oracle's guided estimator, and the guide's
+    training records written by the gradient pass."""
+    banner("per-triangle Cornell (global storage) with the cached proposal")
+    import _guide
+    sc = scenes.per_triangle(scenes.cornell())
+    g = ipt.Scene.from_dict(sc, param_storage=ipt.PARAMS_GLOBAL)
+    o = _oracle(sc)
+    w = _guide.random_weights(sc["num_segments"], seed=31, out_gain=3.0, kappa_bias=1.0)
+    gd = ipt.Guide(g, record_stride=1)
+    gd.set_weights(w)
+    cell_area = 2e-3
+    gd.cache_build(cell_area, mode=1)
+    lo, inv = _guide.box(sc["verts"])
+    kw = dict(seed=17, stream_tag=1, iteration=3, spp=4, max_depth=3, mis=2, guide=gd, guide_mix=0.5, guide_cached=1)
+    okw = dict(guide_w=w, guide_mix=0.5, bb_lo=lo, bb_inv=inv, guide_cell_area=cell_area)
+    dc = ipt.make_cameras(sc["cams"])
+    p = sc["params"]
+    _, h_g = gpu_render(g, dc, p, kw)
+    r = o.run(sc["cams"], p, want_hash=True, want_margin=True, want_cond=True, **oracle_opts(kw), **okw)
+    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"], r["cond"])
+    keep = comparable(h_g, r)
+    print("paths %d mismatching %d (hard %d), compared %.1f%%" % (h_g.size, n_mis, n_hard, 100 * keep.mean()))
+    assert n_hard <= 1e-5 * 3 * h_g.size and keep.mean() > 0.9
+    img_g, _ = gpu_render(g, dc, p, kw, mask=keep)
+    ro = o.run(sc["cams"], p, path_mask=keep.astype(np.uint8), **oracle_opts(kw), **okw)
+    err = np.abs(img_g - ro["image"]) / np.maximum(np.abs(ro["image"]), 1e-4 * np.abs(ro["image"]).mean())
+    print("pixel rel err max %.2e" % err.max())
+    assert err.max() <= PIX_REL
+    wimg = np.random.default_rng(6).normal(size=(64 * 64, 3))
+    n0 = gd.records()
+    gg = gpu_grad(g, dc, p, wimg, kw, mask=keep)
+    go = o.run(sc["cams"], p, w=wimg, path_mask=keep.astype(np.uint8), want_grad=True, **oracle_opts(kw), **okw)["grad"]
+    touched = go != 0
+    rms = math.sqrt(np.mean(go[touched] ** 2))
+    gerr = np.abs(gg - go) / np.maximum(np.abs(go), 1e-2 * rms)
+    print("grad rel err max %.2e; training records written %d" % (gerr.max(), gd.records() - n0))
+    assert gerr.max() <= GRAD_REL
+    assert gd.records() - n0 > 1000
