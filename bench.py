@@ -10,7 +10,7 @@ Prints ONE JSON line.  value = gradient paths per second of the whole step
 (B paths / step time); the breakdown gives colour paths/s and the
 fwd+adjoint-only gradient paths/s.  The roofline entry is for the dominant
 kernel, timed with HIP events inside the library on the stream it runs on;
-algorithmic bytes come from the kernels' own work counters (BVH nodes x 64 B
+algorithmic bytes come from the kernels' own work counters (BVH nodes x 112 B read
 + triangles x 48 B + checkpoint traffic).  cpu_baseline times the FP64 oracle
 on a bounded pixel sample on this host's cores.
 """
@@ -27,7 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-NODE_B, TRI_B = 64, 48
+TRI_B = 48
+# BVH node bytes read per visit: 4-wide nodes (128 B in memory) read seven
+# float4 rows (boxes and child references, 112 B); binary nodes 64 B
+NODE_READ_B = {128: 112, 64: 64}
 # checkpoint traffic of the gradient forward pass per path vertex: hit record,
 # a and c written (3 x 16 B), a and c read back by the backward sweep (32 B),
 # suffix radiance written (16 B)
@@ -219,8 +222,10 @@ def main():
     log("step %.1f ms (wall %.1f ms): colour %.1f ms, grad fwd %.1f ms, replay %.1f ms" % (
         ms_step, 1e3 * wall / args.steps, ms_col, k_fwd["total_ms"] / args.steps, k_rep["total_ms"] / args.steps))
 
+    node_b = NODE_READ_B[info["node_bytes"]]
+
     def kbytes(k, extra_per_vertex):
-        return k["nodes"] * NODE_B + k["tris"] * TRI_B + k["vertices"] * extra_per_vertex
+        return k["nodes"] * node_b + k["tris"] * TRI_B + k["vertices"] * extra_per_vertex
 
     per = {}
     for name, k, extra in (("colour", k_col, 0), ("grad_forward", k_fwd, CK_FWD_B), ("adjoint_replay", k_rep, CK_REPLAY_B)):

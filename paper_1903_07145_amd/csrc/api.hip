@@ -72,6 +72,88 @@ struct ipt_scene_s {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
 };
 
+// 4-wide nodes (default): every other level of the binary tree is folded
+// into its parent, so a node holds up to four children -- its grandchildren
+// where a child is an inner node, the child itself where it is a leaf -- with
+// the binary tree's (padded) child boxes.  Layout per node, 8 float4 =
+// 128 B: lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of the four children, then the
+// four child references (inner node index, leaf code, or kNone), then
+// padding.  Children of a node are stored contiguously, depth first.
+static int bits_i(float f) { int i; std::memcpy(&i, &f, sizeof i); return i; }
+static float bits_f(int i) { float f; std::memcpy(&f, &i, sizeof f); return f; }
+
+static hipError_t collapse_bvh4(float4*& d_nodes, int64_t& nnodes, hipStream_t st) {
+    std::vector<float4> b2(4 * (size_t)nnodes);
+    hipError_t e = hipMemcpyAsync(b2.data(), d_nodes, sizeof(float4) * b2.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    struct Ch { float lo[3], hi[3]; int ref; };
+    auto children = [&](int r, Ch out[2]) {
+        const float4* n = &b2[4 * (size_t)r];
+        out[0] = Ch{{n[0].x, n[0].y, n[0].z}, {n[0].w, n[1].x, n[1].y}, bits_i(n[3].x)};
+        out[1] = Ch{{n[1].z, n[1].w, n[2].x}, {n[2].y, n[2].z, n[2].w}, bits_i(n[3].y)};
+    };
+    std::vector<int> rec_of{0};        // 4-wide node id -> binary record
+    std::vector<float4> b4;
+    b4.reserve(8 * (size_t)nnodes);
+    std::vector<int> stack{0};         // 4-wide node ids to write
+    b4.resize(8);
+    while (!stack.empty()) {
+        const int id = stack.back();
+        stack.pop_back();
+        Ch c2[2], g[4];
+        children(rec_of[id], c2);
+        int m = 0;
+        for (int k = 0; k < 2; ++k) {
+            if (c2[k].ref == kNone) continue;
+            if (c2[k].ref >= 0) {
+                Ch gc[2];
+                children(c2[k].ref, gc);
+                for (int j = 0; j < 2; ++j)
+                    if (gc[j].ref != kNone) g[m++] = gc[j];
+            } else {
+                g[m++] = c2[k];
+            }
+        }
+        int ref[4] = {kNone, kNone, kNone, kNone};
+        std::vector<int> inner;
+        for (int j = 0; j < m; ++j) {
+            if (g[j].ref >= 0) {
+                ref[j] = (int)rec_of.size();
+                rec_of.push_back(g[j].ref);
+                b4.resize(b4.size() + 8);
+                inner.push_back(ref[j]);
+            } else {
+                ref[j] = g[j].ref;
+            }
+        }
+        for (size_t k = inner.size(); k-- > 0;) stack.push_back(inner[k]);
+        float v[6][4];
+        for (int j = 0; j < 4; ++j)
+            for (int a = 0; a < 3; ++a) {
+                v[2 * a][j] = j < m ? g[j].lo[a] : 0.0f;
+                v[2 * a + 1][j] = j < m ? g[j].hi[a] : 0.0f;
+            }
+        float4* o = &b4[8 * (size_t)id];
+        for (int row = 0; row < 6; ++row) o[row] = make_float4(v[row][0], v[row][1], v[row][2], v[row][3]);
+        o[6] = make_float4(bits_f(ref[0]), bits_f(ref[1]), bits_f(ref[2]),
+                           bits_f(ref[3]));
+        o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    float4* d4 = nullptr;
+    e = hipMalloc((void**)&d4, sizeof(float4) * b4.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(d4, b4.data(), sizeof(float4) * b4.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        hipFree(d4);
+        return e;
+    }
+    hipFree(d_nodes);
+    d_nodes = d4;
+    nnodes = (int64_t)rec_of.size();
+    return hipSuccess;
+}
+
 static void prof_clear_events(ipt_scene_s* s) {
     for (auto& v : s->ev) {
         for (auto& p : v) {
@@ -258,8 +340,16 @@ extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const f
         sah = bvh.sah_cost;
         nnodes = bvh.num_nodes;
     }
+    if (kNodeWidth == 4) {
+        e = collapse_bvh4(s->d_nodes, nnodes, st);
+        if (e != hipSuccess) {
+            ipt_scene_free(s);
+            return fail(IPT_ERR_HIP, "BVH layout: %s", hipGetErrorString(e));
+        }
+    }
     auto t1 = std::chrono::steady_clock::now();
-    if (depth > kShortStack + kOvfDepth) {
+    // a node pushes at most width - 1 entries
+    if ((kNodeWidth == 4 ? 3 * ((depth + 1) / 2) : depth) > kShortStack + kOvfDepth) {
         ipt_scene_free(s);
         return fail(IPT_ERR_NOT_SUPPORTED, "BVH depth %d exceeds the traversal stack", depth);
     }
@@ -340,6 +430,7 @@ extern "C" ipt_status ipt_scene_info(ipt_scene_t s, ipt_scene_info_t* out) {
     out->stack_overflows = c.overflow;
     out->bvh_builder = s->bvh_builder;
     out->params_global = s->params_global;
+    out->node_bytes = kNodeWidth == 4 ? 128 : 64;
     return IPT_OK;
 }
 

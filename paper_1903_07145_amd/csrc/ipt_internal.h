@@ -12,6 +12,12 @@ constexpr int kBlock = 256;       // threads per block of the path kernels
 constexpr int kShortStack = 16;   // per-lane LDS stack entries (power of two)
 constexpr int kOvfDepth = 48;     // per-lane global overflow entries
 constexpr int kNone = 0x7FFFFFFF; // empty child slot
+// BVH node width of the traversal: 4 (binary levels folded pairwise into
+// 128 B nodes) or 2 (the binary tree's 64 B child-pair nodes)
+#ifndef IPT_NODE_WIDTH
+#define IPT_NODE_WIDTH 4
+#endif
+constexpr int kNodeWidth = IPT_NODE_WIDTH;
 constexpr int kMaxDepth = 16;     // max scattering vertices per path
 constexpr int kMaxLdsLights = 1024;
 constexpr int kMaxLdsParams = 4096;  // larger parameter vectors stay in global memory

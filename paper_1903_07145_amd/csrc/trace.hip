@@ -211,7 +211,37 @@ __device__ bool traverse_resume(const SceneDev& sc, const Ray& r, float tmin, fl
             }
             const bool inner = cur >= 0;
             if (!__any(inner && pend == kTravDone)) break;
-            if (inner) {
+            if (inner && kNodeWidth == 4) {
+                // four children: the nearest hit next, the others pushed far to near
+                wk.nodes++;
+                const float4* n = sc.nodes + 8 * (size_t)cur;
+                const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], cr = n[6];
+                const float inf = __builtin_inff();
+                float t[4];
+                int c[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
+                t[0] = box_entry(r, v3(lx.x, ly.x, lz.x), v3(hx.x, hy.x, hz.x), tmin, best.t, sc.tmin);
+                t[1] = box_entry(r, v3(lx.y, ly.y, lz.y), v3(hx.y, hy.y, hz.y), tmin, best.t, sc.tmin);
+                t[2] = box_entry(r, v3(lx.z, ly.z, lz.z), v3(hx.z, hy.z, hz.z), tmin, best.t, sc.tmin);
+                t[3] = box_entry(r, v3(lx.w, ly.w, lz.w), v3(hx.w, hy.w, hz.w), tmin, best.t, sc.tmin);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (c[j] == kNone) t[j] = inf;
+                auto cas = [&](int i, int j) {
+                    if (t[j] < t[i]) {
+                        const float tt = t[i]; t[i] = t[j]; t[j] = tt;
+                        const int cc = c[i]; c[i] = c[j]; c[j] = cc;
+                    }
+                };
+                cas(0, 1); cas(2, 3); cas(0, 2); cas(1, 3); cas(1, 2);
+                if (t[0] < inf) {
+                    if (t[3] < inf) st.push(c[3]);
+                    if (t[2] < inf) st.push(c[2]);
+                    if (t[1] < inf) st.push(c[1]);
+                    cur = c[0];
+                } else {
+                    cur = next_from_stack();
+                }
+            } else if (inner) {
                 wk.nodes++;
                 const float4* n = sc.nodes + 4 * (size_t)cur;
                 float4 n0 = n[0], n1 = n[1], n2 = n[2], n3 = n[3];

@@ -61,7 +61,8 @@ class SceneInfo(ctypes.Structure):
                 ("bvh_depth", ctypes.c_int32), ("has_normals", ctypes.c_int32),
                 ("sah_cost", ctypes.c_double), ("build_ms", ctypes.c_double), ("scene_diag", ctypes.c_float),
                 ("nonfinite_paths", ctypes.c_uint64), ("stack_overflows", ctypes.c_uint64),
-                ("bvh_builder", ctypes.c_int32), ("params_global", ctypes.c_int32)]
+                ("bvh_builder", ctypes.c_int32), ("params_global", ctypes.c_int32),
+                ("node_bytes", ctypes.c_int32)]
 
 
 class BuildOpts(ctypes.Structure):
