@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -128,11 +129,14 @@ static hipError_t collapse_bvh4(float4*& d_nodes, int64_t& nnodes, hipStream_t s
             }
         }
         for (size_t k = inner.size(); k-- > 0;) stack.push_back(inner[k]);
+        // an empty slot gets lo = hi = +inf on every axis: the slab test
+        // gives it an entry distance of +inf (never entered)
+        const float inf = std::numeric_limits<float>::infinity();
         float v[6][4];
         for (int j = 0; j < 4; ++j)
             for (int a = 0; a < 3; ++a) {
-                v[2 * a][j] = j < m ? g[j].lo[a] : 0.0f;
-                v[2 * a + 1][j] = j < m ? g[j].hi[a] : 0.0f;
+                v[2 * a][j] = j < m ? g[j].lo[a] : inf;
+                v[2 * a + 1][j] = j < m ? g[j].hi[a] : inf;
             }
         float4* o = &b4[8 * (size_t)id];
         for (int row = 0; row < 6; ++row) o[row] = make_float4(v[row][0], v[row][1], v[row][2], v[row][3]);

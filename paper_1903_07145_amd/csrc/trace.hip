@@ -134,6 +134,23 @@ struct Stack {
         lds[slot * kBlock + tid] = x;
         ++sp;
     }
+    // Pushes the n (0..3) entries x0..x(n-1), x0 deepest.  With room for
+    // three in the LDS window (and so no entry to move to the overflow
+    // stack) all three slots are written, whatever n: the slots above the
+    // new top hold no live entry.
+    __device__ __forceinline__ void push_upto3(int n, int x0, int x1, int x2) {
+        if (sp + 3 <= kShortStack) {
+            int* s = lds + sp * kBlock + tid;
+            s[0] = x0;
+            s[kBlock] = x1;
+            s[2 * kBlock] = x2;
+            sp += n;
+        } else {
+            if (n > 0) push(x0);
+            if (n > 1) push(x1);
+            if (n > 2) push(x2);
+        }
+    }
     __device__ __forceinline__ int pop() {
         --sp;
         int slot = sp & (kShortStack - 1);
@@ -217,26 +234,31 @@ __device__ bool traverse_resume(const SceneDev& sc, const Ray& r, float tmin, fl
                 const float4* n = sc.nodes + 8 * (size_t)cur;
                 const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], cr = n[6];
                 const float inf = __builtin_inff();
+                // an empty slot's box is +inf on every axis, so its entry
+                // distance is +inf and it sorts last without a check
                 float t[4];
                 int c[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
                 t[0] = box_entry(r, v3(lx.x, ly.x, lz.x), v3(hx.x, hy.x, hz.x), tmin, best.t, sc.tmin);
                 t[1] = box_entry(r, v3(lx.y, ly.y, lz.y), v3(hx.y, hy.y, hz.y), tmin, best.t, sc.tmin);
                 t[2] = box_entry(r, v3(lx.z, ly.z, lz.z), v3(hx.z, hy.z, hz.z), tmin, best.t, sc.tmin);
                 t[3] = box_entry(r, v3(lx.w, ly.w, lz.w), v3(hx.w, hy.w, hz.w), tmin, best.t, sc.tmin);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (c[j] == kNone) t[j] = inf;
+                // sorting network on (t, child) with selects, no branches;
+                // equal distances keep their slot order
                 auto cas = [&](int i, int j) {
-                    if (t[j] < t[i]) {
-                        const float tt = t[i]; t[i] = t[j]; t[j] = tt;
-                        const int cc = c[i]; c[i] = c[j]; c[j] = cc;
-                    }
+                    const bool sw = t[j] < t[i];
+                    const float ti = t[i], tj = t[j];
+                    const int ci = c[i], cj = c[j];
+                    t[i] = sw ? tj : ti;
+                    t[j] = sw ? ti : tj;
+                    c[i] = sw ? cj : ci;
+                    c[j] = sw ? ci : cj;
                 };
                 cas(0, 1); cas(2, 3); cas(0, 2); cas(1, 3); cas(1, 2);
                 if (t[0] < inf) {
-                    if (t[3] < inf) st.push(c[3]);
-                    if (t[2] < inf) st.push(c[2]);
-                    if (t[1] < inf) st.push(c[1]);
+                    // the entered children are a prefix of the sorted slots:
+                    // push the nf after the nearest, farthest first
+                    const int nf = (t[1] < inf ? 1 : 0) + (t[2] < inf ? 1 : 0) + (t[3] < inf ? 1 : 0);
+                    st.push_upto3(nf, nf == 3 ? c[3] : (nf == 2 ? c[2] : c[1]), nf == 3 ? c[2] : c[1], c[1]);
                     cur = c[0];
                 } else {
                     cur = next_from_stack();
