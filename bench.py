@@ -31,11 +31,13 @@ TRI_B = 48
 # BVH node bytes read per visit: 4-wide nodes (128 B in memory) read seven
 # float4 rows (boxes and child references, 112 B); binary nodes 64 B
 NODE_READ_B = {128: 112, 64: 64}
-# checkpoint traffic of the gradient forward pass per path vertex: hit record,
-# a and c written (3 x 16 B), a and c read back by the backward sweep (32 B),
-# suffix radiance written (16 B)
-CK_FWD_B = 96
-# replay reads hit record + suffix radiance per vertex
+# checkpoint traffic per path vertex: the gradient forward pass writes the hit
+# record, a and c (3 x 16 B); the backward sweep reads a and c back (32 B) and
+# writes the suffix radiance (16 B), in the forward pass when a guide collects
+# training records, else at the start of the replay; the replay reads the hit
+# record and the suffix radiance (32 B)
+CK_WRITE_B = 48
+CK_SWEEP_B = 48
 CK_REPLAY_B = 32
 
 
@@ -228,7 +230,9 @@ def main():
         return k["nodes"] * node_b + k["tris"] * TRI_B + k["vertices"] * extra_per_vertex
 
     per = {}
-    for name, k, extra in (("colour", k_col, 0), ("grad_forward", k_fwd, CK_FWD_B), ("adjoint_replay", k_rep, CK_REPLAY_B)):
+    sweep_fwd = CK_SWEEP_B if args.guide else 0
+    for name, k, extra in (("colour", k_col, 0), ("grad_forward", k_fwd, CK_WRITE_B + sweep_fwd),
+                           ("adjoint_replay", k_rep, CK_REPLAY_B + CK_SWEEP_B - sweep_fwd)):
         launches = max(1, k["launches"])
         avg_ms = k["total_ms"] / launches
         b = kbytes(k, extra) / launches

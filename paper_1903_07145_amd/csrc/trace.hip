@@ -1002,11 +1002,21 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
             size_t pidx = (size_t)wi * a.spp + s;
             bool use = a.mask ? a.mask[pidx] != 0 : true;
             if (MODE == kGradFwd) {
-                V3 R = suffix_sweep(a, klast, s, q);
-                if (!finite3(R) || !finite3(L)) {
-                    size_t c1 = (size_t)s * plane + q;
+                const size_t c1 = (size_t)s * plane + q;
+                if (a.guided) {
+                    // the training records read R_{k+1} before the replay runs
+                    V3 R = suffix_sweep(a, klast, s, q);
+                    if (!finite3(R) || !finite3(L)) {
+                        a.ck_hit[c1].x = (int)((uint32_t)a.ck_hit[c1].x | kCkDrop);
+                        atomicAdd(&a.err->nonfinite, 1ull);
+                    }
+                } else if (!finite3(L)) {
                     a.ck_hit[c1].x = (int)((uint32_t)a.ck_hit[c1].x | kCkDrop);
                     atomicAdd(&a.err->nonfinite, 1ull);
+                } else {
+                    // the replay runs the sweep: the index of the path's last
+                    // vertex goes into the unused fourth slot of vertex 1's c
+                    a.ck_c[c1].w = __int_as_float(klast);
                 }
             } else {
                 if (!finite3(L)) atomicAdd(&a.err->nonfinite, 1ull);
@@ -1053,6 +1063,18 @@ __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& 
     const int4* lights = lds.lights_in_lds ? lds.lights : sc.lights;
     const size_t plane = (size_t)a.pix_count;
     if ((uint32_t)a.ck_hit[(size_t)s * plane + q].x & kCkDrop) return;
+    if (!a.guided) {
+        // the backward sweep, here rather than at the end of each path in the
+        // forward pass: every lane of the wave starts a path at once, so the
+        // sweeps' round trips to memory overlap instead of holding up a wave
+        // in which a few lanes end their paths
+        const int klast = min(max(__float_as_int(a.ck_c[(size_t)s * plane + q].w), 0), a.D + 1);
+        const V3 R = suffix_sweep(a, klast, s, q);
+        if (!finite3(R)) {
+            atomicAdd(&a.err->nonfinite, 1ull);
+            return;
+        }
+    }
     V3 T = v3(1.0f, 1.0f, 1.0f), Ts = T;
     float prev_pdf = 0.0f;
     int prev_tri = -1;
