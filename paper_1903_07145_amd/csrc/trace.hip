@@ -639,6 +639,20 @@ __device__ __forceinline__ ContS cont_finish_cached(const PathArgs& a, const Sha
     return cont_eval(a, g, m, ms, c.wi, pdf, c.lobe, u, k, Ts);
 }
 
+// Streaming store of one 16 B checkpoint record: the records are read again
+// only by a later kernel, so they should not displace the scene's nodes and
+// triangles in the caches.
+__device__ __forceinline__ void st_stream(float4* p, float4 v) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, reinterpret_cast<f4*>(p));
+}
+__device__ __forceinline__ void st_stream(int4* p, int4 v) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const i4 x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, reinterpret_cast<i4*>(p));
+}
+
 // Backward sweep of the gradient forward pass: R_{k+1} into the c slot of
 // vertex k; returns the path radiance.
 __device__ __forceinline__ V3 suffix_sweep(const PathArgs& a, int klast, int s, int64_t q) {
@@ -827,7 +841,7 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
                 if (MODE == kGradFwd) {
                     ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
                     if (vis) a.ck_hit[ck].x = (int)(ckx | kCkVis);
-                    a.ck_c[ck] = make_float4(cpart.x, cpart.y, cpart.z, 0.0f);
+                    st_stream(&a.ck_c[ck], make_float4(cpart.x, cpart.y, cpart.z, 0.0f));
                 }
                 end_path = evtail != 0;
                 ph = kClosest;
@@ -839,7 +853,7 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
                 ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
                 if (hr.tri < 0) {
                     h = fnv1a(h, 0xFFFFFFFFu);
-                    if (MODE == kGradFwd) a.ck_hit[ck] = make_int4(0, 0, 0, 0);
+                    if (MODE == kGradFwd) st_stream(&a.ck_hit[ck], make_int4(0, 0, 0, 0));
                     klast = k - 1;   // a miss contributes nothing: the sweep starts below it
                     end_path = true;
                 } else {
@@ -874,10 +888,10 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
                         h = fnv1a(h, ev);
                         prev_tri = g.tri;
                         if (MODE == kGradFwd) {
-                            a.ck_hit[ck] = make_int4(g.tri + 1, __float_as_int(hr.u), __float_as_int(hr.v),
-                                                     __float_as_int(hr.t));
-                            a.ck_a[ck] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                            a.ck_c[ck] = make_float4(cpart.x, cpart.y, cpart.z, 0.0f);
+                            st_stream(&a.ck_hit[ck], make_int4(g.tri + 1, __float_as_int(hr.u),
+                                                               __float_as_int(hr.v), __float_as_int(hr.t)));
+                            st_stream(&a.ck_a[ck], make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+                            st_stream(&a.ck_c[ck], make_float4(cpart.x, cpart.y, cpart.z, 0.0f));
                         }
                     } else {
                         shade = true;
@@ -984,15 +998,16 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
             o = g.x;
             if (MODE == kGradFwd) {
                 ckx = (uint32_t)(g.tri + 1) | flags;
-                a.ck_hit[ck] = make_int4((int)ckx, __float_as_int(hr.u), __float_as_int(hr.v), __float_as_int(hr.t));
-                a.ck_a[ck] = make_float4(av.x, av.y, av.z, cs.pdf);
-                if (a.guided) a.ck_d[ck] = make_float4(cs.wi.x, cs.wi.y, cs.wi.z, pb_nee);
+                st_stream(&a.ck_hit[ck], make_int4((int)ckx, __float_as_int(hr.u), __float_as_int(hr.v),
+                                                   __float_as_int(hr.t)));
+                st_stream(&a.ck_a[ck], make_float4(av.x, av.y, av.z, cs.pdf));
+                if (a.guided) st_stream(&a.ck_d[ck], make_float4(cs.wi.x, cs.wi.y, cs.wi.z, pb_nee));
             }
             if (shoot) {
                 ph = kShadow;   // the vertex finishes after its shadow ray
             } else {
                 h = fnv1a(h, ev | evtail);
-                if (MODE == kGradFwd) a.ck_c[ck] = make_float4(cpart.x, cpart.y, cpart.z, 0.0f);
+                if (MODE == kGradFwd) st_stream(&a.ck_c[ck], make_float4(cpart.x, cpart.y, cpart.z, 0.0f));
                 end_path = evtail != 0;
             }
         }
