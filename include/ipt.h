@@ -19,9 +19,11 @@
  *   - Every call returns an ipt_status and never aborts.  Arguments are
  *     validated on the host before anything is enqueued; on error nothing is
  *     enqueued and ipt_last_error() returns a message (thread-local).
- *   - The library allocates device memory only in ipt_scene_build and
- *     ipt_guide_create (owned by the handle, freed by the matching _free).
- *     Per-call scratch space is the caller's workspace.
+ *   - The library allocates device memory only in ipt_scene_build,
+ *     ipt_guide_create and the first ipt_guide_cache_build call of a guide on
+ *     a scene (or with a new cell area); all of it is owned by the handle and
+ *     freed by the matching _free.  Per-call scratch space is the caller's
+ *     workspace.
  *
  * Parameter vector (float32, raw physical values, length P = 7 S + 3 E):
  *   segment s   [7s .. 7s+6]  kd_r kd_g kd_b  ks_r ks_g ks_b  alpha
@@ -126,9 +128,11 @@ typedef enum { IPT_BVH_GPU = 0, IPT_BVH_HOST = 1 } ipt_bvh_builder;
 /* Where the path kernels keep the parameter vector (7 S + 3 E floats) and
  * the adjoint its gradient.  LDS: a copy per block and per-block float64
  * partial gradients summed in a fixed order (deterministic).  GLOBAL: read
- * through the caches, and the adjoint adds float64 atomics straight into one
- * accumulator (summation order varies; for many segments, e.g. one per
- * triangle, where contention is low).  AUTO: LDS up to 4096 parameters. */
+ * through the caches, and the adjoint adds float64 atomics into R replicas of
+ * the gradient (block b into replica b mod R, R bounded by 256 MB of
+ * workspace), summed in a fixed order afterwards (summation order within a
+ * replica varies; for many segments, e.g. one per triangle, where contention
+ * is low).  AUTO: LDS up to 4096 parameters. */
 typedef enum { IPT_PARAMS_AUTO = 0, IPT_PARAMS_GLOBAL = 1 } ipt_param_storage;
 typedef struct {
     int32_t bvh_builder;      /* an ipt_bvh_builder */
@@ -207,7 +211,7 @@ ipt_status ipt_sgd_step(float *params, const float *grad, float *m, float *v, in
                         const float *lo, const float *hi, const uint8_t *trainable,
                         void *hip_stream);
 
-/* L1 regulariser of the emission (Sec. 3, "Regularization"; App. A: an
+/* L1 regulariser of the emission (Sec. 4.4, "Regularization"; App. E: an
  * L1 term on all emission parameters, since most objects emit nothing):
  * grad[i] += weight[i] * sgn(params[i]) and *loss += sum_i weight[i] |params[i]|,
  * with sgn(0) = 0.  params, grad, weight [P] and loss [1] are DEVICE float32

@@ -1207,9 +1207,12 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     while (true) {
         if (tid == 0) tile_sh = atomicAdd(a.work, 1u);
         __syncthreads();
-        int64_t unit = (int64_t)tile_sh * kBlock + tid;
+        // every thread reads the tile before the second barrier: after it,
+        // thread 0 may already be writing the next tile into tile_sh
+        const int64_t tile0 = (int64_t)tile_sh * kBlock;
         __syncthreads();
-        if ((int64_t)tile_sh * kBlock >= nunits) break;
+        if (tile0 >= nunits) break;
+        const int64_t unit = tile0 + tid;
         if (unit >= nunits) continue;
         const int c = (int)(unit / a.pix_count);
         const int64_t q = unit - (int64_t)c * a.pix_count;

@@ -374,8 +374,8 @@ def paper_setting_masks(sc, cov, sigma=None, max_sigma=2.5e-3):
 def optimize_paper_setting(sc, iters=2000, seed=7, batch=8, spp=512, grad_spp=1, lr=5e-3, lam=1e-3, beta2=0.999,
                            target=None, g=None, log=None, log_every=100, target_rmse=1e-2, cov=None, loss_kind=1,
                            masks=None, max_depth=None, mis=2, time_budget=None):
-    """The paper's own optimisation setting (Sec. 3, "Optimization Parameters";
-    App. A): every segment emissive (scenes.all_emissive), albedo and
+    """The paper's own optimisation setting (Sec. 4.5, "Optimization Parameters";
+    App. E): every segment emissive (scenes.all_emissive), albedo and
     emission initialised to zero, each iteration a batch of `batch` pixels
     drawn uniformly from all pixels of all views, `spp` paths per pixel for
     the colour estimate and `grad_spp` (one, the split Sec. 4 finds best) for
@@ -604,7 +604,7 @@ def _refined_scene(sc0, refined, tri_vals, emission):
 
 def coarse_to_fine(sc, iters_coarse=300, iters_fine=200, rounds=3, seed=7, spp=None, refine="excess", log=None,
                    lr=1e-2, beta2=0.9):
-    """Coarse-to-fine optimisation on a textured scene (App. A; supplement,
+    """Coarse-to-fine optimisation on a textured scene (App. E; App. B,
     scenes with textures): one material per object first; then, `rounds`
     times, every triangle whose covered pixels carry a mean l2 re-rendering
     error above a threshold gets a material of its own and the optimisation

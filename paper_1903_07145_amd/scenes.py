@@ -452,7 +452,7 @@ def all_emissive(sc):
 
 
 def per_triangle(sc, tris=None, tri_params=None):
-    """Per-triangle refinement (App. A, coarse to fine): every triangle in
+    """Per-triangle refinement (App. E, coarse to fine): every triangle in
     `tris` (default: every triangle of a segment that does not emit) becomes a
     segment of its own with its own material, starting from its old
     segment's values (or from tri_params [T, 7] when given).  Emitter segments

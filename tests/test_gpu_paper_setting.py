@@ -1,9 +1,9 @@
 """The paper's own optimisation setting on the HIP path, against the FP64
-oracle: every segment emissive (App. A: an unknown emission per object, most
+oracle: every segment emissive (App. E: an unknown emission per object, most
 of it zero, light selection proportional to the current emission), small
 pixel batches with many paths per pixel, the L1 loss with its sign adjoint
 (Sec. 3.2, Eq. 3; Sec. 3.3, Eq. 4) and the L1 emission regulariser
-(Sec. 3, "Regularization")."""
+(Sec. 4.4, "Regularization")."""
 import math
 
 import numpy as np

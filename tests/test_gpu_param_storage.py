@@ -1,6 +1,6 @@
 """Parameters in global memory (ipt_build_opts.param_storage, automatic above
 4096 parameters) through the C ABI: per-triangle materials (the paper's
-coarse-to-fine refinement, App. A) make the parameter vector grow with the
+coarse-to-fine refinement, App. E) make the parameter vector grow with the
 triangle count, so the path kernels read it through the caches and the
 adjoint adds float64 atomics into one accumulator instead of per-block LDS
 copies and partials.

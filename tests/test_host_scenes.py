@@ -1,5 +1,5 @@
 """Host-side scene tools (no GPU): the per-triangle re-parameterisation of the
-coarse-to-fine refinement (App. A) and the textured Cornell box."""
+coarse-to-fine refinement (App. E) and the textured Cornell box."""
 import numpy as np
 
 from paper_1903_07145_amd import scenes
