@@ -319,12 +319,16 @@ ipt_status ipt_guide_read_records(ipt_guide_t guide, float *out, int64_t n, void
  * 0: colour pass, 1: gradient forward pass, 2: adjoint replay).  While
  * enabled, every launch is bracketed by HIP events on the stream it is
  * launched on, and the kernels add their work (rays cast, BVH nodes fetched,
- * triangles tested, paths, path vertices) into per-scene device counters.
+ * triangles tested, paths, path vertices, work units) into per-scene device
+ * counters.  A work unit is one pixel with all its samples when there are at
+ * least two pixels per lane of the grid (a lane then walks every sample of
+ * its pixel and forms the mean in registers), else a chunk of a pixel's
+ * samples; units == pixels means the first mode.
  * ipt_profile_read synchronises the device; ipt_profile_reset clears both. */
 typedef struct {
     int64_t launches;
     double total_ms;          /* sum of event-measured launch durations */
-    uint64_t rays, nodes, tris, paths, vertices;
+    uint64_t rays, nodes, tris, paths, vertices, units;
 } ipt_kernel_profile;
 
 ipt_status ipt_profile_enable(ipt_scene_t scene, int32_t enable);

@@ -1253,6 +1253,32 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
 #undef NEAR
 }
 
+/* Conditioning probes (parity bookkeeping; they never change a result).
+ * Probes 0 and 1 perturb, by a relative -+1e-6 along one fixed direction,
+ * every vertex position and every direction of the path.  Probes 2..7 shift
+ * only the camera ray's origin, by 1e-6 of its coordinate scale along +-x,
+ * +-y, +-z, and let the path's own dynamics carry the change: a hit point
+ * that moves on a smoothly shaded curved surface turns its shading normal and
+ * so the next direction, which is how float32 rounding grows along chaotic
+ * paths (the per-vertex probes alone under-report those paths, because a
+ * common shift of every vertex partly cancels the growth). */
+#define ORC_NPROBE 8
+static void probe_setup(ctx *Cp, int k, v3 org, v3 dir, v3 *o2, v3 *d2)
+{
+    *o2 = org;
+    *d2 = dir;
+    if (k < 2) {
+        Cp->pert = k == 0 ? 1e-6 : -1e-6;
+        Cp->pert_dir = nrm(mk(0.6, -0.48, 0.64));
+        *d2 = nrm(add(dir, scl(Cp->pert_dir, Cp->pert)));
+        return;
+    }
+    Cp->pert = 0.0;
+    int axis = (k - 2) / 2;
+    double sh = ((k - 2) % 2 == 0 ? 1e-6 : -1e-6) * rel_scale(org);
+    *o2 = add(org, mk(axis == 0 ? sh : 0.0, axis == 1 ? sh : 0.0, axis == 2 ? sh : 0.0));
+}
+
 /* Render (and, when w != NULL and grad != NULL, differentiate) a set of
  * pixels.  image[npix*3] receives the per-pixel mean over spp; grad[P]
  * receives sum_j sum_c (w_jc / spp) d(sum_s L_sc)/dtheta.  path_mask (if not
@@ -1315,37 +1341,39 @@ int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
             trace_path_v(&C, org, dir, pid, wc, gp, Lp, &hsh, margins ? &mgn : NULL, vdd.v ? &vdd : NULL);
             if (margins) margins[i * o->spp + sidx] = mgn;
             if (conds) {
-                /* Conditioning of the path: relative change of its radiance when
-                 * every vertex position and every direction is perturbed by a
-                 * relative 1e-6 along a fixed direction (two signs), infinite if a
-                 * discrete event changes.  Float32 rounding injects ~1e-7 at every
-                 * vertex; paths that amplify such perturbations (e.g. repeated
-                 * reflections between curved, smoothly shaded surfaces diverge
-                 * exponentially) cannot be reproduced to 1e-4 in float32. */
+                /* Conditioning of the path: the largest relative change of a
+                 * channel of its radiance under the probe perturbations
+                 * (infinite if a discrete event changes).  Float32 rounding injects ~1e-7 at
+                 * every vertex; paths that amplify such perturbations (e.g.
+                 * repeated reflections between curved, smoothly shaded
+                 * surfaces diverge exponentially) cannot be reproduced to 1e-4
+                 * in float32. */
                 double c = 0.0;
                 double lm = fmax(fmax(fabs(Lp[0]), fabs(Lp[1])), fabs(Lp[2]));
-                for (int k = 0; k < 2 && isfinite(c); ++k) {
+                for (int k = 0; k < ORC_NPROBE && isfinite(c); ++k) {
                     ctx Cp = C;
-                    Cp.pert = k == 0 ? 1e-6 : -1e-6;
-                    Cp.pert_dir = nrm(mk(0.6, -0.48, 0.64));
-                    v3 d2 = nrm(add(dir, scl(Cp.pert_dir, Cp.pert)));
+                    v3 o2, d2;
+                    probe_setup(&Cp, k, org, dir, &o2, &d2);
                     double L2[3];
                     uint64_t h2;
-                    trace_path(&Cp, org, d2, pid, wc, NULL, L2, &h2, NULL);
+                    trace_path(&Cp, o2, d2, pid, wc, NULL, L2, &h2, NULL);
                     if (h2 != hsh) { c = INFINITY; break; }
+                    /* relative change per channel (the comparisons are per
+                     * channel), over the channels of at least 1e-3 of the
+                     * brightest one, as for the gradient components below */
                     for (int q = 0; q < 3; ++q) {
-                        double r = fabs(L2[q] - Lp[q]) / fmax(lm, 1e-12);
+                        if (fabs(Lp[q]) < 1e-3 * lm) continue;
+                        double r = fabs(L2[q] - Lp[q]) / fmax(fabs(Lp[q]), 1e-300);
                         if (r > c) c = r;
                     }
                 }
                 conds[i * o->spp + sidx] = c;
             }
             if (gconds && w) {
-                /* The same probe on the path's gradient contribution: the
-                 * largest relative change, under the +-1e-6 perturbation, of
-                 * any of its components that is at least 1e-3 of its largest
-                 * one.  Derivatives of sharp lobes amplify the perturbation
-                 * more than the radiance does. */
+                /* The same probes on the path's gradient contribution: the
+                 * largest relative change of any of its components that is at
+                 * least 1e-3 of its largest one.  Derivatives of sharp lobes
+                 * amplify the perturbation more than the radiance does. */
                 double *g0 = (double *)calloc((size_t)P, sizeof(double));
                 double *g1 = (double *)calloc((size_t)P, sizeof(double));
                 double L0[3], Lq[3];
@@ -1354,13 +1382,12 @@ int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
                 double gmax = 0.0;
                 for (int64_t q = 0; q < P; ++q) gmax = fmax(gmax, fabs(g0[q]));
                 double c = 0.0;
-                for (int k = 0; k < 2 && isfinite(c) && gmax > 0.0; ++k) {
+                for (int k = 0; k < ORC_NPROBE && isfinite(c) && gmax > 0.0; ++k) {
                     ctx Cp = C;
-                    Cp.pert = k == 0 ? 1e-6 : -1e-6;
-                    Cp.pert_dir = nrm(mk(0.6, -0.48, 0.64));
-                    v3 d2 = nrm(add(dir, scl(Cp.pert_dir, Cp.pert)));
+                    v3 o2, d2;
+                    probe_setup(&Cp, k, org, dir, &o2, &d2);
                     memset(g1, 0, sizeof(double) * (size_t)P);
-                    trace_path(&Cp, org, d2, pid, wc, g1, Lq, &h1, NULL);
+                    trace_path(&Cp, o2, d2, pid, wc, g1, Lq, &h1, NULL);
                     if (h1 != h0) { c = INFINITY; break; }
                     for (int64_t q = 0; q < P; ++q) {
                         if (fabs(g0[q]) < 1e-3 * gmax) continue;

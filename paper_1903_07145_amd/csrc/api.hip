@@ -780,6 +780,7 @@ extern "C" ipt_status ipt_profile_read(ipt_scene_t s, int32_t kernel, ipt_kernel
     out->tris = c.k[kernel].tris;
     out->paths = c.k[kernel].paths;
     out->vertices = c.k[kernel].vertices;
+    out->units = c.k[kernel].units;
     return IPT_OK;
 }
 

@@ -47,9 +47,11 @@ struct SceneDev {
 };
 
 // Per-kernel work counters (kernel modes 0..2): rays cast, BVH nodes
-// fetched, triangles tested, paths, path vertices.
+// fetched, triangles tested, paths, path vertices, work units taken (a work
+// unit is a pixel's whole sample range, or a chunk of it when a pixel's
+// samples are split over lanes).
 struct KStats {
-    unsigned long long rays, nodes, tris, paths, vertices;
+    unsigned long long rays, nodes, tris, paths, vertices, units;
 };
 
 struct Counters {

@@ -268,8 +268,12 @@ __device__ __forceinline__ bool brdf_sample(const Mat& m, V3 n, V3 wo, float u3,
     if (u3 < ps) {
         lobe = 1;
         float a = clamp_alpha(m.alpha);
-        // Walter et al. 2007: tan^2 = a^2 u / (1 - u), cos^2 and sin^2 without cancellation
-        float den = 1.0f + (a * a - 1.0f) * u4;
+        // Walter et al. 2007: tan^2 = a^2 u / (1 - u), cos^2 and sin^2 without
+        // cancellation.  Their denominator 1 + (a^2 - 1) u is formed as
+        // (1 - u) + a^2 u: 1 - u is exact for these 24-bit uniforms, while
+        // rounding a^2 - 1 to float32 costs up to 6e-8 / den relative, 1e-3
+        // for a near-mirror lobe (a ~ 5e-3) and u near 1
+        float den = (1.0f - u4) + a * a * u4;
         float ch = sqrtf((1.0f - u4) / den), sh = sqrtf(a * a * u4 / den);
         V3 h = t * (sh * c) + b * (sh * s) + n * ch;
         float oh = dot(wo, h);

@@ -176,7 +176,7 @@ struct Hit {
 };
 
 struct Work {
-    uint32_t rays, nodes, tris, vertices;
+    uint32_t rays, nodes, tris, vertices, units;
 };
 
 __device__ __forceinline__ void load_tri(const SceneDev& sc, int i, V3& p0, V3& p1, V3& p2, int& orig,
@@ -675,6 +675,7 @@ __device__ __forceinline__ void flush_stats(const PathArgs& a, int mode, const W
     atomicAdd(&ks->tris, (unsigned long long)wk.tris);
     atomicAdd(&ks->paths, (unsigned long long)npaths);
     atomicAdd(&ks->vertices, (unsigned long long)wk.vertices);
+    atomicAdd(&ks->units, (unsigned long long)wk.units);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,7 +721,7 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
     const int64_t npix_img = (int64_t)a.V * a.W * a.H;
     const size_t plane = (size_t)a.pix_count;
     const int D = a.D;
-    Work wk{0u, 0u, 0u, 0u};
+    Work wk{0u, 0u, 0u, 0u, 0u};
     uint32_t npaths = 0;
 
     int ph = kNeedPixel;
@@ -778,6 +779,7 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
                 if (unit >= nunits) {
                     ph = kExit;
                 } else {
+                    wk.units++;
                     const int c = (int)(unit / a.pix_count);
                     q = unit - (int64_t)c * a.pix_count;
                     s = c * a.spc;
@@ -1201,7 +1203,7 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     Stack st;
     init_stack(st, a, lds.stack);
     const int64_t npix_img = (int64_t)a.V * a.W * a.H;
-    Work wk{0u, 0u, 0u, 0u};
+    Work wk{0u, 0u, 0u, 0u, 0u};
     uint32_t npaths = 0;
     const int64_t nunits = a.pix_count * a.nchunk;
     while (true) {
@@ -1214,6 +1216,7 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
         if (tile0 >= nunits) break;
         const int64_t unit = tile0 + tid;
         if (unit >= nunits) continue;
+        wk.units++;
         const int c = (int)(unit / a.pix_count);
         const int64_t q = unit - (int64_t)c * a.pix_count;
         const int s_begin = c * a.spc, s_end = min(a.spp, s_begin + a.spc);
@@ -1387,7 +1390,7 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(SceneDev sc, const f
     st.gthreads = gridDim.x * kBlock;
     st.overflow = false;
     st.sp = 0;
-    Work wk{0u, 0u, 0u, 0u};
+    Work wk{0u, 0u, 0u, 0u, 0u};
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
         Ray r = make_ray(v3(o[3 * i], o[3 * i + 1], o[3 * i + 2]), v3(d[3 * i], d[3 * i + 1], d[3 * i + 2]));
         int sk = (skip && skip[i] >= 0 && skip[i] < nt) ? sc.pos_of[skip[i]] : -1;

@@ -76,7 +76,7 @@ PARAMS_AUTO, PARAMS_GLOBAL = 0, 1
 class KernelProfile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("rays", ctypes.c_uint64),
                 ("nodes", ctypes.c_uint64), ("tris", ctypes.c_uint64), ("paths", ctypes.c_uint64),
-                ("vertices", ctypes.c_uint64)]
+                ("vertices", ctypes.c_uint64), ("units", ctypes.c_uint64)]
 
 
 KERNELS = {0: "colour", 1: "grad_forward", 2: "adjoint_replay"}

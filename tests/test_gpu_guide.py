@@ -19,7 +19,7 @@ import pytest
 import torch
 
 import _guide
-from _gpu import (ILL_COND, NEAR_TIE, banner, both, comparable, dev, gpu_grad, gpu_render, mismatch_stats,
+from _gpu import (check_mismatches, ILL_COND, NEAR_TIE, banner, both, comparable, dev, gpu_grad, gpu_render, mismatch_stats,
                   oracle_opts)
 from oracle import guide_ref, oracle
 from paper_1903_07145_amd import ipt, scenes
@@ -130,7 +130,8 @@ def test_guided_render_and_grad_parity_fp32(cornell, mis):
     _, h_g = gpu_render(g, dc, sc["params"], _guided_kw(kw, gd))
     r = o.run(sc["cams"], sc["params"], want_hash=True, want_margin=True, want_cond=True, **oracle_opts(kw),
               **_oracle_guided(lo, inv, w))
-    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"], r["cond"])
+    b = check_mismatches(h_g, r, 3, label="guided")
+    n_mis, n_hard = b["mismatch"], b["hard"]
     keep = comparable(h_g, r)
     print("paths %d mismatching %d (hard %d), compared %.1f%%" % (h_g.size, n_mis, n_hard, 100 * keep.mean()))
     assert n_hard <= 1e-5 * 3 * h_g.size

@@ -18,7 +18,7 @@ import pytest
 import torch
 
 import _guide
-from _gpu import GRAD_ILL_COND, banner, both, comparable, dev, gpu_grad, gpu_render, mismatch_stats, oracle_opts
+from _gpu import check_mismatches, GRAD_ILL_COND, banner, both, comparable, dev, gpu_grad, gpu_render, mismatch_stats, oracle_opts
 from paper_1903_07145_amd import ipt, scenes
 
 pytestmark = pytest.mark.gpu
@@ -43,7 +43,8 @@ def _parity(sc, g, o, dc, gd, w, cell_area, kw, pix=None, mix=0.5):
     _, h_g = gpu_render(g, dc, sc["params"], _kw(kw, gd, mix), pixel_list=pix)
     r = o.run(sc["cams"], sc["params"], pixel_list=pix, want_hash=True, want_margin=True, want_cond=True,
               **oracle_opts(kw), **ok)
-    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"], r["cond"])
+    b = check_mismatches(h_g, r, 3, label="cached proposal")
+    n_mis, n_hard = b["mismatch"], b["hard"]
     keep = comparable(h_g, r)
     print("paths %d mismatching %d (hard %d), compared %.1f%%" % (h_g.size, n_mis, n_hard, 100 * keep.mean()))
     assert n_hard <= 1e-5 * 3 * h_g.size

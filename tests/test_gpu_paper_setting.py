@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from _gpu import (GRAD_ILL_COND, banner, both, comparable, dev, gpu_grad, gpu_render, image_parity,
+from _gpu import (check_mismatches, GRAD_ILL_COND, banner, both, comparable, dev, gpu_grad, gpu_render, image_parity,
                   mismatch_stats, oracle_opts)
 from paper_1903_07145_amd import ipt, scenes
 
@@ -71,7 +71,12 @@ def test_all_emissive_room_global_light_table():
     kw = dict(seed=8, stream_tag=2, iteration=1, spp=8, max_depth=3, mis=2)
     img_g, h_g = gpu_render(g, dc, p, kw, pixel_list=pix)
     r = o.run(sc["cams"], p, pixel_list=pix, want_hash=True, want_margin=True, want_cond=True, **oracle_opts(kw))
-    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"], r["cond"])
+    # ~49k light triangles: the light pick compares u against a table of
+    # float32 prefix sums whose neighbouring entries lie ~2e-5 of the total
+    # apart, so about every path meets a pick near a boundary and a few
+    # percent take the neighbouring light (near-ties, bounded here at 3%)
+    b = check_mismatches(h_g, r, 3, label="paper setting", near_tie_bar=0.03)
+    n_mis, n_hard = b["mismatch"], b["hard"]
     keep = comparable(h_g, r)
     print("paths %d mismatching %d (hard %d), compared %.1f%%" % (h_g.size, n_mis, n_hard, 100 * keep.mean()))
     assert n_hard <= 1e-5 * 3 * h_g.size

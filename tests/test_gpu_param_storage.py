@@ -22,7 +22,7 @@ import numpy as np
 import pytest
 import torch
 
-from _gpu import GRAD_ILL_COND, banner, comparable, dev, gpu_grad, gpu_render, mismatch_stats, oracle_opts
+from _gpu import check_mismatches, GRAD_ILL_COND, banner, comparable, dev, gpu_grad, gpu_render, mismatch_stats, oracle_opts
 from oracle import oracle
 from paper_1903_07145_amd import ipt, scenes
 
@@ -42,7 +42,8 @@ def _parity(sc, g, o, kw, pix=None, min_keep=0.9):
     p = sc["params"]
     _, h_g = gpu_render(g, dc, p, kw, pixel_list=pix)
     r = o.run(sc["cams"], p, pixel_list=pix, want_hash=True, want_margin=True, want_cond=True, **oracle_opts(kw))
-    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"], r["cond"])
+    b = check_mismatches(h_g, r, 3, label="global params")
+    n_mis, n_hard = b["mismatch"], b["hard"]
     keep = comparable(h_g, r)
     print("paths %d mismatching %d (hard %d), compared %.1f%%" % (h_g.size, n_mis, n_hard, 100 * keep.mean()))
     assert n_hard <= 1e-5 * 3 * h_g.size
@@ -151,7 +152,8 @@ def test_global_storage_with_cached_proposal():
     p = sc["params"]
     _, h_g = gpu_render(g, dc, p, kw)
     r = o.run(sc["cams"], p, want_hash=True, want_margin=True, want_cond=True, **oracle_opts(kw), **okw)
-    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"], r["cond"])
+    b = check_mismatches(h_g, r, 3, label="global params")
+    n_mis, n_hard = b["mismatch"], b["hard"]
     keep = comparable(h_g, r)
     print("paths %d mismatching %d (hard %d), compared %.1f%%" % (h_g.size, n_mis, n_hard, 100 * keep.mean()))
     assert n_hard <= 1e-5 * 3 * h_g.size and keep.mean() > 0.9

@@ -11,8 +11,8 @@ import numpy as np
 import pytest
 import torch
 
-from _gpu import (GRAD_ILL_COND, NEAR_TIE, banner, both, comparable, dev, gpu_grad, gpu_render, image_parity,
-                  mismatch_stats, oracle_opts)
+from _gpu import (LOOSE_REL, NEAR_TIE, banner, both, chaotic_agreement, check_mismatches, dev, emission_linearity,
+                  gpu_grad, gpu_render, image_parity, mask_report, mismatch_stats, oracle_opts, rel_err)
 from paper_1903_07145_amd import ipt, scenes
 
 pytestmark = pytest.mark.gpu
@@ -95,11 +95,14 @@ def test_render_parity_cornell_rr_profile_spp1(cornell):
     assert emax <= PIX_REL
 
 
-def test_grad_parity_cornell(cornell):
-    banner("gradient parity cornell")
+@pytest.mark.parametrize("D,rr", [(3, -1), (7, 2), (7, 3)])
+def test_grad_parity_cornell(cornell, D, rr):
+    """Gradient parity, also with Russian roulette (the survivor's 1/q in the
+    forward weights and in the replay's T and Ts) at the benchmark's depth."""
+    banner("gradient parity cornell D=%d rr=%d" % (D, rr))
     sc, g, o, dc = cornell
     rng = np.random.default_rng(1)
-    kw = dict(seed=12, stream_tag=2, iteration=7, spp=4, max_depth=3, mis=2)
+    kw = dict(seed=12, stream_tag=2, iteration=7, spp=4, max_depth=D, rr_depth=rr, mis=2)
     _, h_g = gpu_render(g, dc, sc["params"], kw)
     r = o.run(sc["cams"], sc["params"], want_hash=True, **oracle_opts(kw))
     mask = (h_g == r["hash"]).astype(np.uint8)
@@ -164,48 +167,66 @@ def test_furnace_closed_form_gpu():
         assert abs(gr[8] - 64 * sum(rho ** k for k in range(D + 1))) < 1e-5 * 64 * (D + 1)
 
 
-def test_room_parity_crop():
-    """50k triangles, GGX, smooth cylinder normals, depth 5.  Paths that bounce
-    between curved smoothly shaded objects are chaotic (float32 rounding at one
-    vertex grows ~10x per bounce); the oracle measures every path's
-    conditioning and both sides drop the paths that are near-ties or
-    ill-conditioned (a path mask), then compare pixel means at 1e-4."""
-    banner("room (50k triangles, GGX) parity on a crop")
+@pytest.mark.parametrize("D,rr", [(5, -1), (7, 3)])
+def test_room_parity_crop(D, rr):
+    """50k triangles, GGX, smooth cylinder normals; depth 5 without and depth
+    7 with Russian roulette from vertex 3.  Paths that bounce between curved
+    smoothly shaded objects are chaotic (float32 rounding at one vertex grows
+    ~10x per bounce); the oracle measures every path's conditioning.  Paths
+    with the same events split into tiers by it and by the near-tie margin:
+    tight (pixel means at 1e-4 with a path mask on both sides; with a
+    well-conditioned gradient contribution, gradient at 1e-3), loose (1e-2)
+    and irregular (mean radiance within 5 standard errors; the GPU gradient's
+    linearity in emission).  The fraction of every tier is printed and
+    bounded."""
+    banner("room (50k triangles, GGX) parity on a crop, D=%d rr=%d" % (D, rr))
     sc = scenes.room()
     g, o = both(sc)
     dc = ipt.make_cameras(sc["cams"])
     W, H = sc["cams"]["width"], sc["cams"]["height"]
     rng = np.random.default_rng(4)
     pix = np.sort(rng.choice(4 * W * H, size=1500, replace=False)).astype(np.int64)
-    kw = dict(seed=21, stream_tag=2, iteration=2, spp=16, max_depth=5, mis=2)
-    _, h_g = gpu_render(g, dc, sc["params"], kw, pixel_list=pix)
-    r = o.run(sc["cams"], sc["params"], pixel_list=pix, want_hash=True, want_margin=True, want_cond=True,
-              **oracle_opts(kw))
-    n_mis, n_hard = mismatch_stats(h_g, r["hash"], r["margin"], r["cond"])
-    keep = comparable(h_g, r)
-    print("paths %d mismatching %d (hard %d), compared %.1f%%" % (h_g.size, n_mis, n_hard, 100 * keep.mean()))
-    assert n_hard <= RAY_BAR * _rays(5, h_g.size), n_hard
-    assert keep.mean() > 0.85
-    img_g, _ = gpu_render(g, dc, sc["params"], kw, pixel_list=pix, mask=keep)
-    ro = o.run(sc["cams"], sc["params"], pixel_list=pix, path_mask=keep.astype(np.uint8), **oracle_opts(kw))
-    mean = np.abs(ro["image"]).mean()
-    err = np.abs(img_g - ro["image"]) / np.maximum(np.abs(ro["image"]), 1e-4 * mean)
+    kw = dict(seed=21, stream_tag=2, iteration=2, spp=16, max_depth=D, rr_depth=rr, mis=2)
+    _, h_g, pL_g = gpu_render(g, dc, sc["params"], kw, pixel_list=pix, want_path_L=True)
+    w = rng.normal(size=(pix.size, 3))
+    r = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, want_hash=True, want_margin=True, want_cond=True,
+              want_path_L=True, **oracle_opts(kw))
+    check_mismatches(h_g, r, 3, RAY_BAR, label="room crop", depth=D)
+    mk = mask_report(h_g, r, gcond=r["gcond"], label="room crop", use_margin=False)
+    assert mk["f_tight"] > 0.7 and mk["f_tight_g"] > 0.75 and mk["f_irregular_g"] < 0.2, mk
+    tight = mk["tight"]
+    img_g, _ = gpu_render(g, dc, sc["params"], kw, pixel_list=pix, mask=tight)
+    ro = o.run(sc["cams"], sc["params"], pixel_list=pix, path_mask=tight.astype(np.uint8), **oracle_opts(kw))
+    mean = np.abs(r["image"]).mean()
+    err = rel_err(img_g, ro["image"], 1e-4 * mean)
     print("pixel rel err p50 %.2e p99 %.2e max %.2e" % tuple(np.percentile(err, [50, 99, 100])))
     assert err.max() <= PIX_REL, err.max()
-    w = rng.normal(size=(pix.size, 3))
+    # loose paths, path by path; chaotic paths statistically
+    lo = mk["loose"]
+    e2 = rel_err(pL_g[lo], r["path_L"][lo], 1e-4 * mean)
+    print("%d loose paths: rel err p50 %.2e max %.2e" % (lo.sum(), np.median(e2) if e2.size else 0, e2.max(initial=0)))
+    assert e2.max(initial=0) <= LOOSE_REL
+    chaotic_agreement(pL_g[mk["irregular"]], r["path_L"][mk["irregular"]], label="room crop")
     # derivatives of sharp GGX lobes amplify rounding more than the radiance
-    # does: the oracle probes every path's gradient contribution the same way
-    # and both sides also drop the paths whose gradient is ill-conditioned
-    gcond = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, want_cond=True, **oracle_opts(kw))["gcond"]
-    keep_g = keep & (gcond <= GRAD_ILL_COND)
-    print("gradient: compared %.1f%% of paths" % (100 * keep_g.mean()))
-    assert keep_g.mean() > 0.8
-    gg = gpu_grad(g, dc, sc["params"], w, kw, pixel_list=pix, mask=keep_g)
-    go = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, path_mask=keep_g.astype(np.uint8), want_grad=True,
+    # does: the gradient tiers also use the probe of the gradient contribution
+    tg = mk["tight_g"]
+    gg = gpu_grad(g, dc, sc["params"], w, kw, pixel_list=pix, mask=tg)
+    go = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, path_mask=tg.astype(np.uint8), want_grad=True,
                **oracle_opts(kw))["grad"]
     emax, err = _grad_parity(gg, go)
     print("grad rel err max %.2e" % emax)
     assert emax <= GRAD_REL, (emax, np.argmax(err))
+    lg = mk["loose_g"]
+    gl = gpu_grad(g, dc, sc["params"], w, kw, pixel_list=pix, mask=lg)
+    gol = o.run(sc["cams"], sc["params"], pixel_list=pix, w=w, path_mask=lg.astype(np.uint8), want_grad=True,
+                **oracle_opts(kw))["grad"]
+    el, _ = _grad_parity(gl, gol)
+    print("%d loose paths: grad rel err max %.2e" % (lg.sum(), el))
+    assert el <= LOOSE_REL, el
+    ir = mk["irregular_g"]
+    gi = gpu_grad(g, dc, sc["params"], w, kw, pixel_list=pix, mask=ir)
+    img_i, _ = gpu_render(g, dc, sc["params"], kw, pixel_list=pix, mask=ir)
+    emission_linearity(w, img_i, gi, sc["params"], sc["num_segments"], label="room crop %d irregular paths:" % ir.sum())
 
 
 def test_loss_grad_and_adam_vs_oracle(cornell):
