@@ -180,6 +180,24 @@ ipt_status ipt_render(ipt_scene_t scene, const ipt_cameras *cams, const float *p
                       const float *sampling_params, const ipt_render_opts *opts, float *image,
                       void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* ipt_render for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same image estimate with no workspace argument.  Its scratch (work counter,
+ * light-selection table, traversal overflow stacks, per-chunk sample sums)
+ * is a fixed 40 MiB device array inside the library, one per device, held
+ * until the process ends; the call allocates nothing, host or device, and
+ * launches at most 2 blocks per CU of the colour kernel.  All calls on one
+ * device share that array, so calls that overlap on one device (concurrent
+ * streams, threads) race and must be serialised by the caller.  Inputs and
+ * outputs as for ipt_render (the debug outputs of opts included).  Errors:
+ * as ipt_render, plus IPT_ERR_NOT_SUPPORTED when the scratch would exceed
+ * 40 MiB (about a million light triangles, or a pixel count whose per-chunk
+ * sums do not fit) and IPT_ERR_INVALID_ARG when the scene was built on
+ * another device than the current one. */
+ipt_status ipt_render_static(ipt_scene_t scene, const ipt_cameras *cams, const float *params,
+                             const float *sampling_params, const ipt_render_opts *opts, float *image,
+                             void *hip_stream);
+
 /* Vector-Jacobian product of the image estimate (Sec. 3.3, Eq. 5-6):
  * grad [P] = sum_j sum_c w[j][c] d I_jc / d theta, with w [pixels][3] the
  * adjoint image.  The estimate uses the samples of opts (stream B); pdfs are

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -598,7 +599,7 @@ static PathArgs base_args(const ipt_scene_s* s, const ipt_cameras* cams, const f
 
 static ipt_status do_render(ipt_scene_t s, const ipt_cameras* cams, const float* params, const float* sp,
                             const ipt_render_opts* o, int64_t npix, float* image, unsigned char* ws,
-                            const Plan& pl, hipStream_t st) {
+                            const Plan& pl, hipStream_t st, bool allow_profile = true) {
     PathArgs a = base_args(s, cams, params, sp, o, ws, pl);
     a.image = image;
     a.pix_begin = 0;
@@ -609,7 +610,12 @@ static ipt_status do_render(ipt_scene_t s, const ipt_cameras* cams, const float*
     HIP_OK(launch_zero_u32(a.work, 1, st));
     size_t lds = path_lds_bytes(kColor, a.P, a.frozen, s->S, s->nlt, a.guide_kind, a.params_global);
     int grid = (int)std::min<int64_t>(pl.grid, (npix * a.nchunk + kBlock - 1) / kBlock);
-    HIP_OK(timed_launch(s, kColor, a, std::max(1, grid), lds, st));
+    if (allow_profile) {
+        HIP_OK(timed_launch(s, kColor, a, std::max(1, grid), lds, st));
+    } else {
+        a.count_stats = 0;
+        HIP_OK(launch_paths(kColor, a, std::max(1, grid), lds, st));
+    }
     if (a.nchunk > 1) HIP_OK(launch_colour_reduce(a.part, a.nchunk, npix, o->spp, image, st));
     return IPT_OK;
 }
@@ -672,6 +678,76 @@ extern "C" ipt_status ipt_render(ipt_scene_t s, const ipt_cameras* cams, const f
         return fail(IPT_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", pl.end_fixed);
     return do_render(s, cams, params, sampling_params, o, npix, image, (unsigned char*)workspace, pl,
                      (hipStream_t)hip_stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free colour pass: the scratch that ipt_render takes from the
+// caller's workspace (work counter, light table, traversal overflow stacks,
+// per-chunk sample sums) lives in this file-scope device array instead.
+// Host code must not use the name `scratch` as an address: it stands for
+// the device symbol; the pointer comes from hipGetSymbolAddress, once per
+// device, with that device current.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(40) << 20;
+constexpr int kStaticBlocksPerCu = 2;     // bounds the overflow stacks to 48 x 512 x 256 ints
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_ptr[kMaxDevices];   // per device, set on its first call
+
+static ipt_status scratch_for_device(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(IPT_ERR_NOT_SUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(IPT_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = (unsigned char*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return IPT_OK;
+}
+
+// Layout of the colour pass's scratch for a grid of at most
+// kStaticBlocksPerCu blocks per CU; returns the bytes it needs.
+static size_t static_render_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t npix, Plan& pl) {
+    const int P = 7 * s->S + 3 * s->E;
+    pl.grid = std::min(path_grid(s, P, 1, guide_kind(o)), s->num_cu * kStaticBlocksPerCu);
+    size_t off = 0;
+    pl.off_counters = off; off = al256(off + 64 * sizeof(unsigned));
+    pl.off_cdf = off; off = al256(off + 2 * sizeof(float) * std::max(1, s->nlt));
+    pl.off_loss = pl.off_w = pl.off_img = pl.off_gpart = off;   // unused by the colour pass
+    pl.grad_copies = 0;
+    pl.off_ovf = off; off = al256(off + sizeof(int) * (size_t)kOvfDepth * pl.grid * kBlock);
+    const int64_t lanes = (int64_t)pl.grid * kBlock;
+    pl.off_part = off; off = al256(off + (npix < 2 * lanes ? sizeof(float) * 3 * (size_t)(2 * lanes + npix) : 0));
+    pl.off_ck = off;
+    pl.end_fixed = off;
+    return off;
+}
+
+extern "C" ipt_status ipt_render_static(ipt_scene_t s, const ipt_cameras* cams, const float* params,
+                                        const float* sampling_params, const ipt_render_opts* o, float* image,
+                                        void* hip_stream) {
+    if (!s || !params || !image) return fail(IPT_ERR_INVALID_ARG, "NULL scene/params/image");
+    int64_t npix = 0;
+    ipt_status stt = check_opts(s, cams, o, &npix);
+    if (stt != IPT_OK) return stt;
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != s->device) return fail(IPT_ERR_INVALID_ARG, "scene built on device %d, current device %d", s->device, dev);
+    Plan pl;
+    const size_t need = static_render_plan(s, o, npix, pl);
+    if (need > kStaticScratchBytes)
+        return fail(IPT_ERR_NOT_SUPPORTED, "ipt_render_static needs %zu bytes of scratch (%d light triangles, "
+                    "%lld pixels), more than its fixed %zu; use ipt_render with a workspace", need, s->nlt,
+                    (long long)npix, kStaticScratchBytes);
+    unsigned char* ws = nullptr;
+    stt = scratch_for_device(dev, &ws);
+    if (stt != IPT_OK) return stt;
+    return do_render(s, cams, params, sampling_params, o, npix, image, ws, pl, (hipStream_t)hip_stream, false);
 }
 
 extern "C" ipt_status ipt_render_grad(ipt_scene_t s, const ipt_cameras* cams, const float* params,

@@ -20,6 +20,7 @@ _STATUS = {0: "IPT_OK", 1: "IPT_ERR_INVALID_ARG", 2: "IPT_ERR_BAD_SCENE", 3: "IP
            4: "IPT_ERR_WORKSPACE_TOO_SMALL", 5: "IPT_ERR_HIP", 6: "IPT_ERR_NOT_SUPPORTED"}
 
 EXPORTS = ["ipt_scene_build", "ipt_scene_build_ex", "ipt_scene_free", "ipt_scene_info", "ipt_workspace_query", "ipt_render",
+           "ipt_render_static",
            "ipt_render_grad", "ipt_loss_grad", "ipt_sgd_step", "ipt_l1_reg", "ipt_trace_rays", "ipt_guide_create",
            "ipt_guide_free", "ipt_guide_eval", "ipt_guide_train", "ipt_guide_weights", "ipt_guide_records",
            "ipt_guide_loss_grad", "ipt_guide_add_records", "ipt_guide_read_records", "ipt_guide_cache_build",
@@ -106,6 +107,7 @@ def lib():
             "ipt_scene_info": [P, P],
             "ipt_workspace_query": [P, P, P, P, P],
             "ipt_render": [P, P, P, P, P, P, P, SZ, P],
+            "ipt_render_static": [P, P, P, P, P, P, P],
             "ipt_render_grad": [P, P, P, P, P, P, P, P, SZ, P],
             "ipt_loss_grad": [P, P, P, P, P, P, I32, P, P, P, P, SZ, P],
             "ipt_sgd_step": [P, P, P, P, I32, I32, P, P, P, P, P, P],
@@ -269,6 +271,16 @@ class Scene:
         C = _cams_struct(dcams)
         _check(lib().ipt_render(self.handle, ctypes.byref(C), _ptr(params), _ptr(sampling_params),
                                 ctypes.byref(opts), _ptr(img), _ptr(ws), ws.numel(), _stream()))
+        return img
+
+    def render_static(self, dcams, params, opts, sampling_params=None, out=None):
+        """ipt_render_static: the colour estimate without a workspace (the
+        library's fixed device scratch; nothing is allocated by the call)."""
+        npix = opts.num_pixels or dcams["num_views"] * dcams["width"] * dcams["height"]
+        img = out if out is not None else torch.empty((npix, 3), dtype=torch.float32, device="cuda")
+        C = _cams_struct(dcams)
+        _check(lib().ipt_render_static(self.handle, ctypes.byref(C), _ptr(params), _ptr(sampling_params),
+                                       ctypes.byref(opts), _ptr(img), _stream()))
         return img
 
     def render_grad(self, dcams, params, w, opts, sampling_params=None, out=None, workspace_bytes=None):
