@@ -27,6 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU peaks of MI355X (256 CUs x 4 SIMDs, 2.4 GHz): a SIMD retires one
+# wave64 VALU instruction per 4 cycles (16 lanes per cycle), so the chip
+# issues 256 x 4 x 2.4e9 / 4 = 6.14e11 wave instructions/s, i.e. 3.93e13
+# lane instructions/s when all 64 lanes of every wave are active (fp32 FMA
+# counted as one instruction; the 157.3 TFLOP/s vector figure counts an FMA
+# as two flops and packed fp32 as two lanes)
+VALU_WAVE_INST_PEAK = 256 * 4 * 2.4e9 / 4
+VALU_LANE_INST_PEAK = VALU_WAVE_INST_PEAK * 64
 TRI_B = 48
 # BVH node bytes read per visit: 4-wide nodes (128 B in memory) read seven
 # float4 rows (boxes and child references, 112 B); binary nodes 64 B
@@ -61,20 +69,28 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, each scaled by a copy kernel of known size),
-    or None if there is none for the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
-    if not os.path.exists(path):
-        return None
+def measured_counters(kernel, workload):
+    """Per-launch hardware counters of `kernel` from the committed summaries
+    under profiles/ (rocprofv3 --pmc runs of this script): VALU instructions
+    and lane utilisation, and HBM bytes (FETCH_SIZE and WRITE_SIZE, each
+    scaled by what the same counter reads for a plain copy of known size).
+    Only lines whose kernel-source hash matches the current sources count;
+    returns {} when there are none."""
     want = kernel_source_hash()
-    for line in open(path):
-        if line.startswith("traffic:"):
-            f = dict(kv.split("=", 1) for kv in line[len("traffic:"):].split())
+    out = {}
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return out
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        for line in open(os.path.join(pdir, name)):
+            if not line.startswith("counters:"):
+                continue
+            f = dict(kv.split("=", 1) for kv in line[len("counters:"):].split())
             if f.get("kernel") == kernel and f.get("workload") == workload and f.get("sources") == want:
-                return float(f["bytes_per_launch"])
-    return None
+                out.update({k: float(v) for k, v in f.items() if k not in ("kernel", "workload", "sources")})
+    return out
 
 
 def copy_reference(nbytes=256 << 20, launches=3):
@@ -241,12 +257,31 @@ def main():
                          nodes_per_ray=k["nodes"] / max(1, k["rays"]), tris_per_ray=k["tris"] / max(1, k["rays"]))
     dom = max(per, key=lambda n: per[n]["avg_ms"])
     d = per[dom]
-    traffic = measured_traffic(dom, sc["name"])
-    roofline = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "kernel_sources": kernel_source_hash(),
-                "avg_launch_ms": round(d["avg_ms"], 3), "algorithmic_bytes_per_launch": int(d["bytes_per_launch"]),
-                "nodes_per_ray": round(d["nodes_per_ray"], 2), "tris_per_ray": round(d["tris_per_ray"], 2)}
+    cnt = measured_counters(dom, sc["name"])
+    traffic = cnt.get("hbm_bytes_per_launch")
+    valu = None
+    if "valu_insts_per_launch" in cnt:
+        issue = cnt["valu_insts_per_launch"] / (d["avg_ms"] * 1e-3)
+        lanes = cnt["lane_util"]
+        valu = {"issued_wave_inst_per_s": round(issue, 1), "issue_peak": VALU_WAVE_INST_PEAK,
+                "issue_frac": round(issue / VALU_WAVE_INST_PEAK, 4), "lane_util": round(lanes, 4),
+                "valu_insts_per_launch": cnt["valu_insts_per_launch"],
+                "source": "SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_THREAD_CYCLES_VALU per launch (profiles/)"}
+    hbm = {"algorithmic_gbs": round(d["gbs"], 1), "peak_gbs": HBM_PEAK_GBS,
+           "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": int(d["bytes_per_launch"]),
+           "measured_gbs": round(traffic / (d["avg_ms"] * 1e-3) / 1e9, 1) if traffic else None}
+    if valu is not None:
+        # the counters show a VALU-issue-bound kernel: its roofline is the
+        # VALU lane throughput, achieved = active lane instructions per second
+        lane_rate = valu["issued_wave_inst_per_s"] * 64 * valu["lane_util"]
+        roofline = {"bound": "alu", "achieved": round(lane_rate / 1e12, 3), "peak": round(VALU_LANE_INST_PEAK / 1e12, 3),
+                    "unit": "Tlane-inst/s", "frac": round(lane_rate / VALU_LANE_INST_PEAK, 4), "traffic": traffic}
+    else:
+        roofline = {"bound": "hbm", "achieved": hbm["algorithmic_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": hbm["frac"], "traffic": traffic}
+    roofline.update({"kernel": dom, "kernel_sources": kernel_source_hash(), "avg_launch_ms": round(d["avg_ms"], 3),
+                     "valu": valu, "hbm": hbm,
+                     "nodes_per_ray": round(d["nodes_per_ray"], 2), "tris_per_ray": round(d["tris_per_ray"], 2)})
     info2 = g.info()
 
     cpu = None

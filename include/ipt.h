@@ -191,9 +191,10 @@ ipt_status ipt_render(ipt_scene_t scene, const ipt_cameras *cams, const float *p
  * streams, threads) race and must be serialised by the caller.  Inputs and
  * outputs as for ipt_render (the debug outputs of opts included).  Errors:
  * as ipt_render, plus IPT_ERR_NOT_SUPPORTED when the scratch would exceed
- * 40 MiB (about a million light triangles, or a pixel count whose per-chunk
- * sums do not fit) and IPT_ERR_INVALID_ARG when the scene was built on
- * another device than the current one. */
+ * 40 MiB (25 MiB of overflow stacks, up to 4.5 MiB of per-chunk sums and 8 B
+ * per light triangle: scenes of more than about 1.4 million light
+ * triangles) and IPT_ERR_INVALID_ARG when the scene was built on another
+ * device than the current one. */
 ipt_status ipt_render_static(ipt_scene_t scene, const ipt_cameras *cams, const float *params,
                              const float *sampling_params, const ipt_render_opts *opts, float *image,
                              void *hip_stream);

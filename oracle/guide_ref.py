@@ -129,3 +129,63 @@ def loss_grad(params, rec, bf16=False):
     L = loss(p, rec, bf16=bf16)
     L.backward()
     return float(L.detach()), p.grad.numpy().copy()
+
+
+def loss_grad_mfma(params, rec, round_bf16=True, want_abs=False):
+    """(loss, gradient) with the backward pass of the bfloat16 matrix-core
+    path: the forward pass as network(bf16=True); the gradient with respect
+    to the raw outputs, in float64, is rounded to bfloat16, and so is every
+    layer's upstream gradient after the ReLU mask of the layer below;
+    weights enter the products rounded to bfloat16 (as in the forward
+    pass); products are summed exactly; the embedding gradient (the input
+    gradient of the first layer) is not rounded.  With round_bf16=False no
+    rounding happens anywhere and the result is the exact gradient of
+    loss(bf16=False), which pins the bookkeeping of this manual backward
+    against autograd.  want_abs also returns, per parameter, the sum over
+    records of the absolute values of the products that make up its
+    gradient (how much the gradient is a cancellation)."""
+    q = (lambda t: _bf16(t, straight_through=False)) if round_bf16 else (lambda t: t)
+    feat, seg, wt, d = records_split(rec)
+    p = torch.as_tensor(np.asarray(params, np.float64))
+    layers, emb = unpack(p)
+    f = torch.as_tensor(feat).to(torch.float32).to(_DT)
+    segt = torch.as_tensor(seg)
+    x = q(torch.cat([f, emb[segt]], dim=1))
+    acts = [x]
+    for li, (W, b) in enumerate(layers):
+        y = x @ q(W) + b
+        if li < 4:
+            y = q(torch.relu(y))
+            acts.append(y)
+        x = y
+    Y = x.detach().clone().requires_grad_(True)
+    mu, kappa, weight = mixture(Y)
+    w = torch.as_tensor(wt)
+    L = -(w * log_q(mu, kappa, weight, torch.as_tensor(d))).sum() / w.sum()
+    L.backward()
+    dz = q(Y.grad)
+    gW, gb, aW, ab = [None] * 5, [None] * 5, [None] * 5, [None] * 5
+    gemb = torch.zeros_like(emb)
+    aemb = torch.zeros_like(emb)
+    for l in range(4, -1, -1):
+        W, _ = layers[l]
+        gb[l] = dz.sum(0)
+        gW[l] = acts[l].T @ dz
+        ab[l] = dz.abs().sum(0)
+        aW[l] = acts[l].abs().T @ dz.abs()
+        din = dz @ q(W).T
+        if l > 0:
+            dz = q(din * (acts[l] > 0).to(_DT))
+        else:
+            gemb.index_add_(0, segt, din[:, 9:9 + N_EMB])
+            aemb.index_add_(0, segt, (dz.abs() @ q(W).abs().T)[:, 9:9 + N_EMB])
+    parts, aparts = [], []
+    for l in range(5):
+        parts += [gW[l].reshape(-1), gb[l]]
+        aparts += [aW[l].reshape(-1), ab[l]]
+    parts.append(gemb.reshape(-1))
+    aparts.append(aemb.reshape(-1))
+    if want_abs:
+        return float(L.detach()), torch.cat(parts).numpy(), torch.cat(aparts).numpy()
+    return float(L.detach()), torch.cat(parts).numpy()
+

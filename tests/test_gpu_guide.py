@@ -2,9 +2,14 @@
 
 * Network: float32 VALU evaluation against the float64 oracle network (same
   float32 weights) at 1e-4; bfloat16 MFMA evaluation against the oracle's
-  bfloat16-emulating network at 1e-2 (mixture density).
+  bfloat16-emulating network at 1e-2, as mixture densities and element by
+  element over the 40 outputs (at most 1e-3 of the elements outside).
 * Training: loss and parameter gradient of the MFMA training kernel against
-  the oracle's reverse-mode gradient of the same loss at 1e-2.
+  the oracle's reverse-mode gradient of the same loss at 1e-2 per block, and
+  element by element against the oracle's backward that rounds to bfloat16
+  at the kernel's points: 1e-2 relative, or 1e-4 of the sum of absolute
+  products for an element that is a heavy cancellation, with at most 1e-3 of
+  the elements outside.
 * Guided estimator with a frozen guide evaluated in float32: images at 1e-4
   and gradients at 1e-3 against the oracle's guided estimator, with the
   same path masks as the unguided parity tests.
@@ -81,6 +86,16 @@ def test_guide_eval_fp32_and_mfma(cornell):
     e16 = np.abs(q(out16) - q(ref16)) / q(ref16)
     print("bf16 density rel err p50 %.2e max %.2e" % (np.median(e16), e16.max()))
     assert e16.max() <= BF16_REL
+    # element by element, all 40 outputs (per lobe mu xyz, kappa, weight):
+    # relative to max(|ref|, 1e-2) (mu components and weights live in [-1, 1]),
+    # at 1e-2, with at most 1e-3 of the elements outside (a bfloat16 rounding
+    # of an intermediate activation that lands on the other side of a
+    # half-ulp in the two implementations moves its descendants by ~1 ulp)
+    ee = np.abs(out16 - ref16) / np.maximum(np.abs(ref16), 1e-2)
+    frac = (ee > BF16_REL).mean()
+    print("bf16 outputs element-wise rel err p50 %.2e p99.9 %.2e max %.2e, %.1e of %d elements above 1e-2" % (
+        np.median(ee), np.percentile(ee, 99.9), ee.max(), frac, ee.size))
+    assert frac <= 1e-3, frac
     # n = 0 is a no-op, n = 1 a single ragged wave
     f1, s1 = feat[:1], seg[:1]
     assert np.allclose(gd.eval(f1, s1, mode=0).cpu().numpy(), out16[:1], rtol=1e-6, atol=1e-7)
@@ -100,6 +115,26 @@ def test_guide_loss_grad_vs_oracle(cornell):
         L_ref, g_ref = guide_ref.loss_grad(w, rec, bf16=True)
         print("n %d loss gpu %.6f oracle %.6f" % (n, loss, L_ref))
         assert abs(loss - L_ref) <= BF16_REL * abs(L_ref)
+        # element by element against the backward that rounds to bfloat16 where
+        # the kernel does (upstream gradients and weights of every product):
+        # relative to max(|g|, 1e-2 rms g) at 1e-2, with at most 1e-3 of the
+        # elements outside (a bfloat16 rounding that lands on the other side
+        # of a half-ulp in float32 and float64)
+        # An element whose sum cancels heavily (|g| far below the sum of the
+        # absolute products that make it up, sum|c|) moves by a visible
+        # fraction of |g| when one bfloat16 operand of one product rounds the
+        # other way (an ulp is 3.9e-3 of it): such an element is held to
+        # 1e-4 of sum|c| instead.
+        _, g_mf, g_abs = guide_ref.loss_grad_mfma(w, rec, want_abs=True)
+        rms = np.sqrt(np.mean(g_mf ** 2))
+        err = np.abs(grad - g_mf)
+        eg = err / np.maximum(np.abs(g_mf), 1e-2 * rms)
+        outside = (eg > BF16_REL) & (err > 1e-4 * g_abs)
+        print("  gradient element-wise rel err p50 %.2e p99.9 %.2e max %.2e; above 1e-2: %d, of which within "
+              "1e-4 of sum|c|: %d; outside %.1e of %d" % (np.median(eg), np.percentile(eg, 99.9), eg.max(),
+                                                          (eg > BF16_REL).sum(), ((eg > BF16_REL) & ~outside).sum(),
+                                                          outside.mean(), eg.size))
+        assert outside.mean() <= 1e-3, outside.mean()
         # per parameter block: W1 b1 ... W5 b5 embedding
         sizes = [25 * 64, 64, 64 * 64, 64, 64 * 64, 64, 64 * 64, 64, 64 * 40, 40, 16 * S]
         off = 0

@@ -202,3 +202,22 @@ def test_guided_furnace_unbiased(orc, mis):
     npix = 64
     dL_drho = E * sum(k * rho ** (k - 1) for k in range(1, D + 1))
     assert abs(g[0] / npix - dL_drho) < 0.1 * dL_drho
+
+
+def test_mfma_backward_reference_bookkeeping():
+    """The manual backward that rounds where the matrix-core path rounds
+    (guide_ref.loss_grad_mfma) equals autograd exactly when no rounding is
+    applied, and stays within bfloat16 accuracy of the straight-through
+    gradient when it is."""
+    S = 5
+    w = _guide.random_weights(S, seed=3, out_gain=2.0)
+    rec = _guide.random_records(700, S, seed=4)
+    L0, g0 = guide_ref.loss_grad(w, rec, bf16=False)
+    L1, g1 = guide_ref.loss_grad_mfma(w, rec, round_bf16=False)
+    assert abs(L0 - L1) <= 1e-12 * abs(L0)
+    assert np.allclose(g1, g0, rtol=1e-10, atol=1e-14 * np.abs(g0).max())
+    L2, g2 = guide_ref.loss_grad(w, rec, bf16=True)
+    L3, g3 = guide_ref.loss_grad_mfma(w, rec, round_bf16=True)
+    assert abs(L2 - L3) <= 1e-12 * abs(L2)
+    assert np.linalg.norm(g3 - g2) <= 2e-2 * np.linalg.norm(g2)
+
