@@ -132,6 +132,8 @@ typedef struct orc_scene {
     int32_t *light_tri; /* emitter triangles in ascending id order */
     double *light_area;
     double diag;        /* scene bounding-box diagonal */
+    int32_t material;   /* 0: Lambert + GGX (7 parameters per segment), 1: Disney (13) */
+    int32_t nm;         /* parameters per segment */
     /* median-split BVH over triangles */
     onode *nodes; int64_t nnodes; int32_t *order;
 } orc_scene;
@@ -209,6 +211,7 @@ orc_scene *orc_scene_create(const float *verts, int64_t nv, const float *normals
 {
     orc_scene *s = (orc_scene *)calloc(1, sizeof(orc_scene));
     s->nv = nv; s->nt = nt; s->ns = num_segments; s->ne = num_emitters;
+    s->material = 0; s->nm = 7;
     s->P = (double *)malloc(sizeof(double) * 3 * (size_t)nv);
     for (int64_t i = 0; i < 3 * nv; ++i) s->P[i] = (double)verts[i];
     if (normals) {
@@ -251,6 +254,14 @@ orc_scene *orc_scene_create(const float *verts, int64_t nv, const float *normals
     s->nnodes = 0;
     if (nt > 0) build_node(s, 0, (int)nt);
     return s;
+}
+
+/* Material model of the scene: 0 Lambert + GGX (7 parameters per segment),
+ * 1 Disney (13). */
+void orc_scene_set_material(orc_scene *s, int32_t material)
+{
+    s->material = material == 1 ? 1 : 0;
+    s->nm = s->material == 1 ? 13 : 7;   /* Disney: DS_N */
 }
 
 void orc_scene_free(orc_scene *s)
@@ -627,6 +638,259 @@ int orc_brdf_sample(const double *mp, const double n_[3], const double wo_[3], d
 }
 
 /* ------------------------------------------------------------------------- */
+/* Disney material model (Burley 2012, "Physically-Based Shading at Disney";  */
+/* the paper's material, Sec. 4.1): base colour plus ten parameters, all      */
+/* meant to lie in [0, 1].  Parameters of a segment, in this order:          */
+/*   base colour r g b, subsurface, metallic, specular, specular tint,        */
+/*   roughness, anisotropic, sheen, sheen tint, clearcoat, clearcoat gloss.   */
+/* f = (1 - metallic) (base/pi mix(F_d, F_ss, subsurface) + sheen F_W(h.l)     */
+/*     C_sheen) + D_s F_s G_s / (4 n.l n.v) + clearcoat/4 D_c F_c G_c /       */
+/*     (4 n.l n.v), with                                                       */
+/*   F_W(x) = (1 - x)^5 (Schlick's weight), tint = base / lum(base) with       */
+/*   lum = 0.3 r + 0.6 g + 0.1 b (1 if lum = 0),                               */
+/*   F_d = (1 + (F_D90 - 1) F_W(n.l)) (1 + (F_D90 - 1) F_W(n.v)),              */
+/*   F_D90 = 1/2 + 2 roughness (h.l)^2,                                         */
+/*   F_ss = 1.25 ((1 + (F_90 - 1) F_W(n.l)) (1 + (F_90 - 1) F_W(n.v))          */
+/*          (1 / (n.l + n.v) - 1/2) + 1/2), F_90 = roughness (h.l)^2,           */
+/*   C_sheen = mix(1, tint, sheen tint),                                        */
+/*   D_s anisotropic GGX with a_x = max(1e-3, r^2 / k), a_y = max(1e-3, r^2 k), */
+/*   k = sqrt(1 - 0.9 anisotropic): 1 / (pi a_x a_y ((h.x/a_x)^2 +            */
+/*   (h.y/a_y)^2 + (h.n)^2)^2), G_s the anisotropic Smith term                  */
+/*   G1(w) = 2 (w.n) / (w.n + sqrt((w.n)^2 + (a_x w.x)^2 + (a_y w.y)^2)) at    */
+/*   l and v, F_s = mix(C_s0, 1, F_W(h.l)),                                      */
+/*   C_s0 = mix(0.08 specular mix(1, tint, specular tint), base, metallic),    */
+/*   D_c = (a^2 - 1) / (pi ln(a^2) ((h.n)^2 a^2 + |h x n|^2)) (GTR1) with      */
+/*   a = mix(0.1, 0.001, clearcoat gloss), F_c = mix(0.04, 1, F_W(h.l)),       */
+/*   G_c the isotropic Smith term with a = 0.25.                                */
+/* The tangent x is the hit triangle's first edge projected onto the plane of */
+/* the shading normal, y = n x x.  Written in complex arithmetic: evaluated  */
+/* at parameters p + i 1e-30 e_j, the imaginary part is 1e-30 times the exact */
+/* derivative with respect to p_j (complex-step differentiation, Squire and   */
+/* Trapp 1998), with no cancellation; max() and the lum = 0 test look at the  */
+/* real part only.                                                            */
+/* ------------------------------------------------------------------------- */
+#include <complex.h>
+#define DS_N 13
+enum { DS_SUBSURFACE = 3, DS_METALLIC, DS_SPECULAR, DS_SPEC_TINT, DS_ROUGHNESS, DS_ANISO, DS_SHEEN,
+       DS_SHEEN_TINT, DS_CLEARCOAT, DS_CC_GLOSS };
+typedef double complex cplx;
+
+/* geometry of a (wo, wi) pair in the frame (x, y, n): cosines with n, with h,
+ * and the x, y components of wi, wo and h; sin^2 of h against n */
+typedef struct { double ci, co, ch, cd, ix, iy, ox, oy, hx, hy, sh2; int ok; } dgeom;
+
+static void disney_frame(v3 n, v3 e1, v3 *x, v3 *y, double *margin)
+{
+    v3 t = sub(e1, scl(n, dot(n, e1)));
+    double lt = sqrt(dot(t, t)), le = sqrt(dot(e1, e1));
+    if (margin) { double m = lt / (le > 0 ? le : 1.0) - 1e-6; if (fabs(m) < *margin) *margin = fabs(m); }
+    if (lt > 1e-6 * le) {
+        *x = scl(t, 1.0 / lt);
+        *y = cross(n, *x);
+    } else {
+        onb(n, x, y);
+    }
+}
+
+static dgeom disney_geom(v3 n, v3 x, v3 y, v3 wo, v3 wi)
+{
+    dgeom g;
+    memset(&g, 0, sizeof g);
+    g.ci = dot(n, wi);
+    g.co = dot(n, wo);
+    g.ok = g.ci > 0 && g.co > 0;
+    if (!g.ok) return g;
+    v3 h = nrm(add(wo, wi));
+    g.ch = dot(n, h);
+    g.cd = dot(wi, h);
+    g.ix = dot(wi, x); g.iy = dot(wi, y);
+    g.ox = dot(wo, x); g.oy = dot(wo, y);
+    g.hx = dot(h, x); g.hy = dot(h, y);
+    g.sh2 = sin2(n, h);
+    return g;
+}
+
+static cplx cmix(cplx a, cplx b, cplx t) { return a + (b - a) * t; }
+static cplx cmax_lo(cplx a, double lo) { return creal(a) < lo ? (cplx)lo : a; }
+static double schlick_w(double c) { double m = 1.0 - c; return m * m * m * m * m; }
+static cplx g1_aniso(double c, double wx, double wy, cplx ax, cplx ay)
+{
+    return 2.0 * c / (c + csqrt(c * c + (wx * ax) * (wx * ax) + (wy * ay) * (wy * ay)));
+}
+static double g1_iso(double c, double a)
+{
+    return 2.0 * c / (c + sqrt(a * a + (1.0 - a * a) * c * c));
+}
+
+/* f[3] of the Disney model for parameters p[13] (complex) and geometry g */
+static void disney_f(const cplx *p, const dgeom *g, cplx f[3])
+{
+    f[0] = f[1] = f[2] = 0;
+    if (!g->ok) return;
+    cplx lum = 0.3 * p[0] + 0.6 * p[1] + 0.1 * p[2];
+    cplx tint[3];
+    for (int c = 0; c < 3; ++c) tint[c] = creal(lum) > 0 ? p[c] / lum : (cplx)1.0;
+    double FL = schlick_w(g->ci), FV = schlick_w(g->co), FH = schlick_w(g->cd);
+    cplx r = p[DS_ROUGHNESS];
+    cplx fd90 = 0.5 + 2.0 * r * g->cd * g->cd;
+    cplx fd = (1.0 + (fd90 - 1.0) * FL) * (1.0 + (fd90 - 1.0) * FV);
+    cplx f90 = r * g->cd * g->cd;
+    cplx fss = 1.25 * ((1.0 + (f90 - 1.0) * FL) * (1.0 + (f90 - 1.0) * FV) * (1.0 / (g->ci + g->co) - 0.5) + 0.5);
+    cplx diff = cmix(fd, fss, p[DS_SUBSURFACE]) / ORC_PI;
+    cplx k = csqrt(1.0 - 0.9 * p[DS_ANISO]);
+    cplx ax = cmax_lo(r * r / k, 1e-3), ay = cmax_lo(r * r * k, 1e-3);
+    cplx tx = g->hx / ax, ty = g->hy / ay;
+    cplx dd = tx * tx + ty * ty + g->ch * g->ch;
+    cplx Ds = 1.0 / (ORC_PI * ax * ay * dd * dd);
+    cplx Gs = g1_aniso(g->ci, g->ix, g->iy, ax, ay) * g1_aniso(g->co, g->ox, g->oy, ax, ay);
+    cplx ac = cmix(0.1, 0.001, p[DS_CC_GLOSS]);
+    cplx a2 = ac * ac;
+    cplx Dc = (a2 - 1.0) / (ORC_PI * clog(a2) * (g->ch * g->ch * a2 + g->sh2));
+    double Fc = 0.04 + 0.96 * FH, Gc = g1_iso(g->ci, 0.25) * g1_iso(g->co, 0.25);
+    double den = 4.0 * g->ci * g->co;
+    cplx spec = Ds * Gs / den, coat = 0.25 * p[DS_CLEARCOAT] * Dc * Fc * Gc / den;
+    for (int c = 0; c < 3; ++c) {
+        cplx cs0 = cmix(p[DS_SPECULAR] * 0.08 * cmix(1.0, tint[c], p[DS_SPEC_TINT]), p[c], p[DS_METALLIC]);
+        cplx Fs = cmix(cs0, 1.0, FH);
+        cplx sheen = FH * p[DS_SHEEN] * cmix(1.0, tint[c], p[DS_SHEEN_TINT]);
+        f[c] = (diff * p[c] + sheen) * (1.0 - p[DS_METALLIC]) + Fs * spec + coat;
+    }
+}
+
+/* value f[3] and, with df != NULL, df[j][c] = d f_c / d p_j for all 13 j */
+static void disney_eval(const double *mp, const dgeom *g, double f[3], double df[DS_N][3])
+{
+    cplx p[DS_N], fc[3];
+    for (int j = 0; j < DS_N; ++j) p[j] = mp[j];
+    disney_f(p, g, fc);
+    for (int c = 0; c < 3; ++c) f[c] = creal(fc[c]);
+    if (!df) return;
+    const double hstep = 1e-30;
+    for (int j = 0; j < DS_N; ++j) {
+        p[j] = mp[j] + I * hstep;
+        disney_f(p, g, fc);
+        for (int c = 0; c < 3; ++c) df[j][c] = cimag(fc[c]) / hstep;
+        p[j] = mp[j];
+    }
+}
+
+/* Lobe probabilities of the sampler (at sampling parameters): diffuse
+ * (1 - metallic) lum(base), specular max(lum(C_s0 without tint), 0.02),
+ * clearcoat 0.1 clearcoat; normalised. */
+static void disney_lobes(const double *mp, double pl[3])
+{
+    double lum = 0.3 * mp[0] + 0.6 * mp[1] + 0.1 * mp[2];
+    double s0 = 0.08 * mp[DS_SPECULAR] + (lum - 0.08 * mp[DS_SPECULAR]) * mp[DS_METALLIC];
+    double w[3] = { fmax(1.0 - mp[DS_METALLIC], 0.0) * fmax(lum, 0.0), fmax(s0, 0.02), 0.1 * fmax(mp[DS_CLEARCOAT], 0.0) };
+    double t = w[0] + w[1] + w[2];
+    for (int i = 0; i < 3; ++i) pl[i] = w[i] / t;
+}
+
+static void disney_alphas(const double *mp, double *ax, double *ay, double *ac)
+{
+    double r = mp[DS_ROUGHNESS], k = sqrt(1.0 - 0.9 * mp[DS_ANISO]);
+    *ax = fmax(r * r / k, 1e-3);
+    *ay = fmax(r * r * k, 1e-3);
+    *ac = 0.1 + (0.001 - 0.1) * mp[DS_CC_GLOSS];
+}
+
+/* Solid-angle pdf of the sampler for wi. */
+static double disney_pdf(const double *mp, v3 n, v3 x, v3 y, v3 wo, v3 wi)
+{
+    double ci = dot(n, wi), co = dot(n, wo);
+    if (ci <= 0 || co <= 0) return 0;
+    double pl[3], ax, ay, ac;
+    disney_lobes(mp, pl);
+    disney_alphas(mp, &ax, &ay, &ac);
+    v3 h = nrm(add(wo, wi));
+    double ch = dot(n, h), oh = dot(wo, h);
+    double p = pl[0] * ci / ORC_PI;
+    if (ch > 0 && oh > 0) {
+        double tx = dot(h, x) / ax, ty = dot(h, y) / ay, dd = tx * tx + ty * ty + ch * ch;
+        double Ds = 1.0 / (ORC_PI * ax * ay * dd * dd);
+        double a2 = ac * ac;
+        double Dc = (a2 - 1.0) / (ORC_PI * log(a2) * (ch * ch * a2 + sin2(n, h)));
+        p += (pl[1] * Ds + pl[2] * Dc) * ch / (4.0 * oh);
+    }
+    return p;
+}
+
+/* Sample wi: u3 picks the lobe (0 diffuse, 1 specular, 2 clearcoat), (u4, u5)
+ * the direction: cosine hemisphere; the anisotropic GGX normal distribution
+ * (azimuth phi of (a_x cos 2 pi u5, a_y sin 2 pi u5), tan^2 theta_h =
+ * u4 / ((1 - u4) A) with A = cos^2 phi / a_x^2 + sin^2 phi / a_y^2); GTR1
+ * (cos^2 theta_h = (1 - a^(2 (1 - u4))) / (1 - a^2), phi = 2 pi u5), each
+ * half vector reflected about wo.  Returns 0 if wi is invalid. */
+static int disney_sample(const double *mp, v3 n, v3 x, v3 y, v3 wo, double u3, double u4, double u5, v3 *wi,
+                         int *lobe, double *margin)
+{
+    double pl[3], ax, ay, ac;
+    disney_lobes(mp, pl);
+    disney_alphas(mp, &ax, &ay, &ac);
+    if (margin) {
+        if (pl[0] > 0 && fabs(u3 - pl[0]) < *margin) *margin = fabs(u3 - pl[0]);
+        if (pl[2] > 0 && fabs(u3 - pl[0] - pl[1]) < *margin) *margin = fabs(u3 - pl[0] - pl[1]);
+    }
+    double c = cos(2.0 * ORC_PI * u5), s = sin(2.0 * ORC_PI * u5);
+    if (u3 < pl[0]) {
+        *lobe = 0;
+        double r = sqrt(u4), z = sqrt(fmax(0.0, 1.0 - u4));
+        *wi = add(add(scl(x, r * c), scl(y, r * s)), scl(n, z));
+        return 1;
+    }
+    double ch, sh, cp, sp;
+    if (u3 < pl[0] + pl[1]) {
+        *lobe = 1;
+        double vx = ax * c, vy = ay * s, lv = sqrt(vx * vx + vy * vy);
+        cp = vx / lv; sp = vy / lv;
+        double A = cp * cp / (ax * ax) + sp * sp / (ay * ay);
+        double den = (1.0 - u4) * A + u4;
+        ch = sqrt((1.0 - u4) * A / den);
+        sh = sqrt(u4 / den);
+    } else {
+        *lobe = 2;
+        double L = log(ac * ac);
+        ch = sqrt(-expm1((1.0 - u4) * L) / (1.0 - ac * ac));
+        sh = sqrt(ac * ac * expm1(-u4 * L) / (1.0 - ac * ac));
+        cp = c; sp = s;
+    }
+    v3 h = add(add(scl(x, sh * cp), scl(y, sh * sp)), scl(n, ch));
+    double oh = dot(wo, h);
+    if (margin && fabs(oh) < *margin) *margin = fabs(oh);
+    if (oh <= 0) return 0;
+    *wi = sub(scl(h, 2.0 * oh), wo);
+    return 1;
+}
+
+/* Exported for the Disney pins: f[3], pdf, then df [13][3] (row-major). */
+void orc_disney_eval(const double *mp, const double n_[3], const double x_[3], const double wo_[3],
+                     const double wi_[3], double out[4 + 3 * DS_N])
+{
+    v3 n = mk(n_[0], n_[1], n_[2]), t = mk(x_[0], x_[1], x_[2]);
+    v3 wo = mk(wo_[0], wo_[1], wo_[2]), wi = mk(wi_[0], wi_[1], wi_[2]);
+    v3 x, y;
+    disney_frame(n, t, &x, &y, NULL);
+    dgeom g = disney_geom(n, x, y, wo, wi);
+    double df[DS_N][3];
+    disney_eval(mp, &g, out, df);
+    out[3] = disney_pdf(mp, n, x, y, wo, wi);
+    for (int j = 0; j < DS_N; ++j)
+        for (int c = 0; c < 3; ++c) out[4 + 3 * j + c] = df[j][c];
+}
+
+int orc_disney_sample(const double *mp, const double n_[3], const double x_[3], const double wo_[3], double u3,
+                      double u4, double u5, double wi_out[3])
+{
+    v3 n = mk(n_[0], n_[1], n_[2]), t = mk(x_[0], x_[1], x_[2]), wo = mk(wo_[0], wo_[1], wo_[2]);
+    v3 x, y, wi;
+    int lobe;
+    disney_frame(n, t, &x, &y, NULL);
+    if (!disney_sample(mp, n, x, y, wo, u3, u4, u5, &wi, &lobe, NULL)) return -1;
+    wi_out[0] = wi.x; wi_out[1] = wi.y; wi_out[2] = wi.z;
+    return lobe;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Light selection: discrete distribution over emitter triangles with weight  */
 /* area * max(lum(e), 1e-3 * max_k lum(e_k)); uniform over area if every      */
 /* emission is zero.  The paper keeps per-object probabilities proportional   */
@@ -641,13 +905,13 @@ static lightdist build_lights(const orc_scene *s, const double *sp)
     L.cdf = (double *)malloc(sizeof(double) * (size_t)(s->nlt + 1));
     double maxl = 0;
     for (int k = 0; k < s->ne; ++k) {
-        double l = lum3(sp + 7 * s->ns + 3 * k);
+        double l = lum3(sp + s->nm * s->ns + 3 * k);
         if (l > maxl) maxl = l;
     }
     double acc = 0;
     for (int64_t j = 0; j < s->nlt; ++j) {
         int k = s->seg_emitter[s->seg[s->light_tri[j]]];
-        double l = lum3(sp + 7 * s->ns + 3 * k);
+        double l = lum3(sp + s->nm * s->ns + 3 * k);
         double w = maxl > 0 ? s->light_area[j] * fmax(l, 1e-3 * maxl) : s->light_area[j];
         acc += w;
         L.cdf[j] = acc;
@@ -678,7 +942,7 @@ static double light_prob(const lightdist *L, int64_t j)
 /* Path tracing with per-factor derivative bookkeeping.                       */
 /* ------------------------------------------------------------------------- */
 #define ORC_MAXD 16
-#define ORC_MAXDER 12
+#define ORC_MAXDER 16
 
 /* A 3-channel factor of a path contribution with its sparse derivative. */
 typedef struct {
@@ -1067,9 +1331,9 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
             if (w > 0) {
                 double prof = C->o->emission_profile ? cos_emit : 1.0;
                 factor phi; phi.n = 0;
-                const double *e = p + 7 * s->ns + 3 * em;
+                const double *e = p + s->nm * s->ns + 3 * em;
                 for (int c = 0; c < 3; ++c) phi.v[c] = e[c] * prof * w;
-                int base = 7 * s->ns + 3 * em;
+                int base = s->nm * s->ns + 3 * em;
                 fadd(&phi, base + 0, prof * w, 0, 0);
                 fadd(&phi, base + 1, 0, prof * w, 0);
                 fadd(&phi, base + 2, 0, 0, prof * w);
@@ -1095,7 +1359,10 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
         if (dot(ng, wo) < 0) { ngf = scl(ng, -1.0); ns = scl(ns, -1.0); }
         NEAR(dot(ns, wo));
         if (dot(ns, wo) <= 0) { h = fnv(h, ev | 2u); break; }   /* shading normal faces away */
-        const double *mp = p + 7 * seg, *msp = sp + 7 * seg;
+        const double *mp = p + s->nm * seg, *msp = sp + s->nm * seg;
+        /* Disney: tangent frame from the hit triangle's first edge */
+        v3 tx = ns, ty = ns;
+        if (s->material == 1) disney_frame(ns, e1, &tx, &ty, M ? &mg : NULL);
         if (ns.z != 0.0) NEAR(ns.z);   /* the tangent frame switches sign convention at n.z = 0 */
         double u[8];
         vertex_uniforms(C->o->seed, C->o->stream_tag, C->o->iteration, path_id, k, u);
@@ -1141,8 +1408,14 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
             }
             ev |= (uint32_t)(lj << 8) | (vis << 2);
             if (vis) {
-                double spec, dspec;
-                spec_term(ns, wo, wl, mp[6], &spec, &dspec);
+                double spec = 0, dspec = 0, fl[3], dfl[DS_N][3];
+                if (s->material == 1) {
+                    dgeom gl = disney_geom(ns, tx, ty, wo, wl);
+                    disney_eval(mp, &gl, fl, dfl);
+                } else {
+                    spec_term(ns, wo, wl, mp[6], &spec, &dspec);
+                    for (int c = 0; c < 3; ++c) fl[c] = mp[c] / ORC_PI + mp[3 + c] * spec;
+                }
                 double cx = dot(ns, wl);
                 NEAR(cx);
                 if (cx > 0) {
@@ -1151,28 +1424,33 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
                     double w = 1.0;
                     if (mis >= 2) {
                         double pl = parea * d2 / cy;
-                        double pb = brdf_pdf(msp, ns, wo, wl);
+                        double pb = s->material == 1 ? disney_pdf(msp, ns, tx, ty, wo, wl) : brdf_pdf(msp, ns, wo, wl);
                         if (guided) pb = cg * mixture_pdf_d(gmix, wl) + (1.0 - cg) * pb;
                         w = mis_w(pl, pb, mis);
                     }
                     double prof = C->o->emission_profile ? cy : 1.0;
                     double g = cx * cy / d2 * w / parea * prof;   /* everything but f and e */
-                    const double *e = p + 7 * s->ns + 3 * lk;
+                    const double *e = p + s->nm * s->ns + 3 * lk;
                     factor phi; phi.n = 0;
                     for (int c = 0; c < 3; ++c)
-                        phi.v[c] = (mp[c] / ORC_PI + mp[3 + c] * spec) * e[c] * g;
-                    int mb = 7 * seg, eb = 7 * s->ns + 3 * lk;
-                    fadd(&phi, mb + 0, e[0] * g / ORC_PI, 0, 0);
-                    fadd(&phi, mb + 1, 0, e[1] * g / ORC_PI, 0);
-                    fadd(&phi, mb + 2, 0, 0, e[2] * g / ORC_PI);
-                    fadd(&phi, mb + 3, spec * e[0] * g, 0, 0);
-                    fadd(&phi, mb + 4, 0, spec * e[1] * g, 0);
-                    fadd(&phi, mb + 5, 0, 0, spec * e[2] * g);
-                    fadd(&phi, mb + 6, mp[3] * dspec * e[0] * g, mp[4] * dspec * e[1] * g,
-                         mp[5] * dspec * e[2] * g);
-                    fadd(&phi, eb + 0, (mp[0] / ORC_PI + mp[3] * spec) * g, 0, 0);
-                    fadd(&phi, eb + 1, 0, (mp[1] / ORC_PI + mp[4] * spec) * g, 0);
-                    fadd(&phi, eb + 2, 0, 0, (mp[2] / ORC_PI + mp[5] * spec) * g);
+                        phi.v[c] = fl[c] * e[c] * g;
+                    int mb = s->nm * seg, eb = s->nm * s->ns + 3 * lk;
+                    if (s->material == 1) {
+                        for (int j = 0; j < DS_N; ++j)
+                            fadd(&phi, mb + j, dfl[j][0] * e[0] * g, dfl[j][1] * e[1] * g, dfl[j][2] * e[2] * g);
+                    } else {
+                        fadd(&phi, mb + 0, e[0] * g / ORC_PI, 0, 0);
+                        fadd(&phi, mb + 1, 0, e[1] * g / ORC_PI, 0);
+                        fadd(&phi, mb + 2, 0, 0, e[2] * g / ORC_PI);
+                        fadd(&phi, mb + 3, spec * e[0] * g, 0, 0);
+                        fadd(&phi, mb + 4, 0, spec * e[1] * g, 0);
+                        fadd(&phi, mb + 5, 0, 0, spec * e[2] * g);
+                        fadd(&phi, mb + 6, mp[3] * dspec * e[0] * g, mp[4] * dspec * e[1] * g,
+                             mp[5] * dspec * e[2] * g);
+                    }
+                    fadd(&phi, eb + 0, fl[0] * g, 0, 0);
+                    fadd(&phi, eb + 1, 0, fl[1] * g, 0);
+                    fadd(&phi, eb + 2, 0, 0, fl[2] * g);
                     double tau[3];
                     term_grad(a, na, &phi, wc, grad, tau);
                     for (int c = 0; c < 3; ++c) L[c] += tau[c];
@@ -1191,11 +1469,16 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
             wi = mixture_sample_d(gmix, u[3], u[4], u[5], M ? &mg : NULL);
             ok = 1;
             ev |= 64u;
+        } else if (s->material == 1) {
+            ok = disney_sample(msp, ns, tx, ty, wo, u[3], u[4], u[5], &wi, &lobe, M ? &mg : NULL);
         } else {
             ok = brdf_sample(msp, ns, wo, u[3], u[4], u[5], &wi, &lobe);
         }
-        ev |= (uint32_t)lobe << 3;
-        if (!use_guide) {
+        /* lobe in the event hash: 1 at bit 3, 2 (Disney clearcoat) at bit 7 */
+        ev |= (uint32_t)(lobe & 1) << 3 | (uint32_t)(lobe >> 1) << 7;
+        if (!use_guide && s->material == 1) {
+            if (ok) { NEAR(dot(wi, ngf)); NEAR(dot(wi, ns)); }
+        } else if (!use_guide) {
             double ps = lobe_prob(msp);
             if (ps > 0 && ps < 1) NEAR(u[3] - ps);
             if (ok) { NEAR(dot(wi, ngf)); NEAR(dot(wi, ns)); }
@@ -1203,19 +1486,29 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
         }
         if (use_guide && ok) { NEAR(dot(wi, ngf)); NEAR(dot(wi, ns)); }
         if (!ok || dot(wi, ngf) <= 0 || dot(wi, ns) <= 0) { h = fnv(h, ev | 16u); break; }
-        double pdf = brdf_pdf(msp, ns, wo, wi);
+        double pdf = s->material == 1 ? disney_pdf(msp, ns, tx, ty, wo, wi) : brdf_pdf(msp, ns, wo, wi);
         if (guided) pdf = cg * mixture_pdf_d(gmix, wi) + (1.0 - cg) * pdf;
         if (!(pdf > 0)) { h = fnv(h, ev | 16u); break; }
-        double spec, dspec, specs, dspecs;
-        spec_term(ns, wo, wi, mp[6], &spec, &dspec);
-        spec_term(ns, wo, wi, msp[6], &specs, &dspecs);
+        double spec = 0, dspec = 0, specs, dspecs, fk[3], fks[3], dfk[DS_N][3];
+        if (s->material == 1) {
+            dgeom gk = disney_geom(ns, tx, ty, wo, wi);
+            disney_eval(mp, &gk, fk, dfk);
+            disney_eval(msp, &gk, fks, NULL);
+        } else {
+            spec_term(ns, wo, wi, mp[6], &spec, &dspec);
+            spec_term(ns, wo, wi, msp[6], &specs, &dspecs);
+            for (int c = 0; c < 3; ++c) {
+                fk[c] = mp[c] / ORC_PI + mp[3 + c] * spec;
+                fks[c] = msp[c] / ORC_PI + msp[3 + c] * specs;
+            }
+        }
         double ci = dot(ns, wi);
         double g = ci / pdf;
         factor *ak = &a[na];
         ak->n = 0;
-        for (int c = 0; c < 3; ++c) ak->v[c] = (mp[c] / ORC_PI + mp[3 + c] * spec) * g;
+        for (int c = 0; c < 3; ++c) ak->v[c] = fk[c] * g;
         double ts[3];
-        for (int c = 0; c < 3; ++c) ts[c] = (msp[c] / ORC_PI + msp[3 + c] * specs) * g;
+        for (int c = 0; c < 3; ++c) ts[c] = fks[c] * g;
         /* Russian roulette on the sampling-parameter throughput (detached). */
         double q = 1.0;
         if (C->o->rr_depth >= 0 && k >= C->o->rr_depth) {
@@ -1232,14 +1525,19 @@ static void trace_path_v(const ctx *C, v3 org, v3 dir, uint64_t path_id, const d
             r[8] = Tc[0]; r[9] = Tc[1]; r[10] = Tc[2]; r[11] = pdf;
             r[12] = wi.x; r[13] = wi.y; r[14] = wi.z; r[15] = 1;
         }
-        int mb = 7 * seg;
-        fadd(ak, mb + 0, g / ORC_PI, 0, 0);
-        fadd(ak, mb + 1, 0, g / ORC_PI, 0);
-        fadd(ak, mb + 2, 0, 0, g / ORC_PI);
-        fadd(ak, mb + 3, spec * g, 0, 0);
-        fadd(ak, mb + 4, 0, spec * g, 0);
-        fadd(ak, mb + 5, 0, 0, spec * g);
-        fadd(ak, mb + 6, mp[3] * dspec * g, mp[4] * dspec * g, mp[5] * dspec * g);
+        int mb = s->nm * seg;
+        if (s->material == 1) {
+            /* 1/q of the roulette is a constant factor of every derivative */
+            for (int j = 0; j < DS_N; ++j) fadd(ak, mb + j, dfk[j][0] * g, dfk[j][1] * g, dfk[j][2] * g);
+        } else {
+            fadd(ak, mb + 0, g / ORC_PI, 0, 0);
+            fadd(ak, mb + 1, 0, g / ORC_PI, 0);
+            fadd(ak, mb + 2, 0, 0, g / ORC_PI);
+            fadd(ak, mb + 3, spec * g, 0, 0);
+            fadd(ak, mb + 4, 0, spec * g, 0);
+            fadd(ak, mb + 5, 0, 0, spec * g);
+            fadd(ak, mb + 6, mp[3] * dspec * g, mp[4] * dspec * g, mp[5] * dspec * g);
+        }
         na++;
         h = fnv(h, ev);
         prev_pdf = pdf;
@@ -1290,7 +1588,7 @@ int64_t orc_run(const orc_scene *s, const orc_cams *cams, const double *params,
                 double *path_L, double *margins, double *conds, double *vertices, double *gconds)
 {
     const double *sp = sampling_params ? sampling_params : params;
-    int64_t P = 7 * (int64_t)s->ns + 3 * (int64_t)s->ne;
+    int64_t P = (int64_t)s->nm * s->ns + 3 * (int64_t)s->ne;
     lightdist L = build_lights(s, sp);
     ctx C = { s, params, sp, &L, o, 0.0, { 0, 0, 0 } };
     int64_t npix = o->pixel_list ? o->num_pixels

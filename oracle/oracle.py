@@ -43,6 +43,10 @@ def lib():
         L.orc_scene_create.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64,
                                        ctypes.c_int32, P, ctypes.c_int32]
         L.orc_scene_free.argtypes = [P]
+        L.orc_scene_set_material.argtypes = [P, ctypes.c_int32]
+        L.orc_disney_eval.argtypes = [P, P, P, P, P, P]
+        L.orc_disney_sample.restype = ctypes.c_int
+        L.orc_disney_sample.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
         L.orc_scene_diag.restype = ctypes.c_double
         L.orc_scene_diag.argtypes = [P]
         L.orc_scene_num_light_tris.restype = ctypes.c_int64
@@ -139,6 +143,28 @@ def brdf_sample(mp, n, wo, u3, u4, u5):
     return lobe, out
 
 
+DISNEY_PARAMS = ("base_r", "base_g", "base_b", "subsurface", "metallic", "specular", "specular_tint",
+                 "roughness", "anisotropic", "sheen", "sheen_tint", "clearcoat", "clearcoat_gloss")
+
+
+def disney_eval(mp, n, x, wo, wi):
+    """Disney model (13 parameters mp): (f[3], pdf, df [13, 3]) with df the
+    derivatives of f by complex-step differentiation; x is the tangent hint
+    (projected onto the plane of n)."""
+    arr = [np.ascontiguousarray(v, dtype=np.float64) for v in (mp, n, x, wo, wi)]
+    out = np.zeros(4 + 3 * 13)
+    lib().orc_disney_eval(*[_ptr(v) for v in arr], _ptr(out))
+    return out[:3].copy(), out[3], out[4:].reshape(13, 3).copy()
+
+
+def disney_sample(mp, n, x, wo, u3, u4, u5):
+    """(lobe or -1, wi) of the Disney sampler."""
+    arr = [np.ascontiguousarray(v, dtype=np.float64) for v in (mp, n, x, wo)]
+    out = np.zeros(3)
+    lobe = lib().orc_disney_sample(*[_ptr(v) for v in arr], float(u3), float(u4), float(u5), _ptr(out))
+    return lobe, out
+
+
 def guide_eval(weights, feat, seg):
     """Mixture parameters [n, 40] (per lobe mu xyz, kappa, weight) of the
     guide network with float32 weights, evaluated in float64."""
@@ -188,9 +214,11 @@ def adam(params, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8, scale=None, l
 
 class Scene:
     """Oracle-side scene: positions, optional per-vertex normals, triangles,
-    per-triangle segment ids, and the emitter segments (Sec. 4.2-4.3)."""
+    per-triangle segment ids, and the emitter segments (Sec. 4.2-4.3).
+    material 0: Lambert + GGX, 7 parameters per segment; 1: the Disney model
+    of Sec. 4.1, 13 parameters per segment (DISNEY_PARAMS)."""
 
-    def __init__(self, verts, tris, tri_seg, num_segments, emitter_seg, normals=None):
+    def __init__(self, verts, tris, tri_seg, num_segments, emitter_seg, normals=None, material=0):
         self._keep = [np.ascontiguousarray(verts, dtype=np.float32),
                       None if normals is None else np.ascontiguousarray(normals, dtype=np.float32),
                       np.ascontiguousarray(tris, dtype=np.int32),
@@ -199,9 +227,12 @@ class Scene:
         v, n, t, s, e = self._keep
         self.num_segments = int(num_segments)
         self.num_emitters = int(e.size)
-        self.P = 7 * self.num_segments + 3 * self.num_emitters
+        self.material = int(material)
+        self.nm = 13 if self.material == 1 else 7
+        self.P = self.nm * self.num_segments + 3 * self.num_emitters
         self.h = lib().orc_scene_create(_ptr(v), v.shape[0], _ptr(n), _ptr(t), _ptr(s),
                                         t.shape[0], self.num_segments, _ptr(e), e.size)
+        lib().orc_scene_set_material(self.h, self.material)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

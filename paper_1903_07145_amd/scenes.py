@@ -664,6 +664,50 @@ def random_soup(n, seed=0, extent=1.0):
     return v, f
 
 
+# Disney material model (Sec. 4.1: base colour and ten parameters, all in
+# [0, 1]): per segment, in this order
+DISNEY_PARAMS = ("base_r", "base_g", "base_b", "subsurface", "metallic", "specular", "specular_tint",
+                 "roughness", "anisotropic", "sheen", "sheen_tint", "clearcoat", "clearcoat_gloss")
+
+
+def disney(scene, seed=0):
+    """The scene with the Disney material model: 13 parameters per segment
+    instead of 7, emission unchanged.  The base colour is the segment's
+    diffuse albedo; the other ten are seeded draws: subsurface, specular,
+    specular tint, sheen and sheen tint ~ U(0, 1); metallic 0 with
+    probability 0.6, else U(0.2, 1); roughness ~ U(0.25, 0.9); anisotropic
+    ~ U(0, 0.8); clearcoat 0 with probability 0.5, else U(0, 1); clearcoat
+    gloss ~ U(0, 0.7).  Every parameter is trainable with scale 1 and
+    bounds [0, 1]; the emission entries keep their scale and bounds."""
+    rng = np.random.default_rng(seed)
+    S = scene["num_segments"]
+    E = len(scene["emitter_seg"])
+    p7 = scene["params"][:7 * S].reshape(S, 7).astype(np.float64)
+    d = np.zeros((S, 13))
+    d[:, 0:3] = p7[:, 0:3]
+    d[:, 3] = rng.uniform(0, 1, S)
+    d[:, 4] = np.where(rng.random(S) < 0.6, 0.0, rng.uniform(0.2, 1.0, S))
+    d[:, 5] = rng.uniform(0, 1, S)
+    d[:, 6] = rng.uniform(0, 1, S)
+    d[:, 7] = rng.uniform(0.25, 0.9, S)
+    d[:, 8] = rng.uniform(0, 0.8, S)
+    d[:, 9] = rng.uniform(0, 1, S)
+    d[:, 10] = rng.uniform(0, 1, S)
+    d[:, 11] = np.where(rng.random(S) < 0.5, 0.0, rng.uniform(0, 1, S))
+    d[:, 12] = rng.uniform(0, 0.7, S)
+    out = dict(scene)
+    out["name"] = scene["name"] + "_disney"
+    out["material"] = 1
+    out["params"] = np.concatenate([d.reshape(-1), scene["params"][7 * S:]]).astype(np.float32)
+    n = 13 * S
+    out["scale"] = np.concatenate([np.ones(n), scene["scale"][7 * S:]]).astype(np.float32)
+    out["lo"] = np.concatenate([np.zeros(n), scene["lo"][7 * S:]]).astype(np.float32)
+    out["hi"] = np.concatenate([np.ones(n), scene["hi"][7 * S:]]).astype(np.float32)
+    out["trainable"] = np.concatenate([np.ones(n), scene["trainable"][7 * S:]]).astype(np.uint8)
+    assert out["params"].size == 13 * S + 3 * E
+    return out
+
+
 def scene_arrays(scene):
     """The subset of keys ipt_scene_build and the oracle take."""
     return dict(verts=scene["verts"], normals=scene["normals"], tris=scene["tris"],

@@ -19,7 +19,7 @@ def banner(msg):
 def both(sc):
     g = ipt.Scene.from_dict(sc)
     o = oracle.Scene(sc["verts"], sc["tris"], sc["tri_seg"], sc["num_segments"], sc["emitter_seg"],
-                     sc["normals"])
+                     sc["normals"], material=sc.get("material", 0))
     return g, o
 
 
