@@ -25,14 +25,23 @@
  *     freed by the matching _free.  Per-call scratch space is the caller's
  *     workspace.
  *
- * Parameter vector (float32, raw physical values, length P = 7 S + 3 E):
- *   segment s   [7s .. 7s+6]  kd_r kd_g kd_b  ks_r ks_g ks_b  alpha
- *   emitter k   [7S+3k .. +2] e_r e_g e_b     (radiance of segment emitter_seg[k])
- * Material model: f = kd/pi + ks D(h) G1(o) G1(i) / (4 cos_o cos_i), GGX D with
- * alpha = roughness clamped to [1e-3, 1], separable Smith G1, no Fresnel (a
- * reduced stand-in for the Disney model of Sec. 4.1).  Emission: constant
- * radiance e, or the profile e (w.n)_+ of Sec. 4.3 (emission_profile = 1);
- * emitters emit on the side their triangle winding faces.
+ * Parameter vector (float32, raw physical values, length P = M S + 3 E with
+ * M material parameters per segment, fixed per scene by ipt_build_opts):
+ *   segment s   [M s .. M s + M-1]  material parameters of the segment
+ *   emitter k   [M S+3k .. +2]      e_r e_g e_b (radiance of segment emitter_seg[k])
+ * Material models (Sec. 3.3 material unknowns, Sec. 4.1):
+ *   IPT_MATERIAL_GGX (M = 7, the default): kd_r kd_g kd_b ks_r ks_g ks_b alpha;
+ *     f = kd/pi + ks D(h) G1(o) G1(i) / (4 cos_o cos_i), GGX D with alpha
+ *     clamped to [1e-3, 1], separable Smith G1, no Fresnel.
+ *   IPT_MATERIAL_DISNEY (M = 13): the Disney model of Sec. 4.1 (Burley
+ *     2012): base_r base_g base_b subsurface metallic specular specular_tint
+ *     roughness anisotropic sheen sheen_tint clearcoat clearcoat_gloss, each
+ *     meant for [0, 1] (the caller's Adam bounds keep them there).  Its
+ *     anisotropy uses a tangent frame per vertex: the hit triangle's first edge
+ *     (vertex 1 - vertex 0) projected onto the shading plane.
+ * Emission: constant radiance e, or the profile e (w.n)_+ of Sec. 4.3
+ * (emission_profile = 1); emitters emit on the side their triangle winding
+ * faces.
  *
  * Random numbers: Philox4x32-10, key = (seed_lo ^ stream_tag*0x9E3779B9,
  * seed_hi), counter = (path_lo, path_hi, 2*vertex + half, iteration), uniform
@@ -119,13 +128,15 @@ typedef struct {
     int32_t params_global;    /* 1: parameters in global memory (ipt_param_storage) */
     int32_t node_bytes;       /* bytes per BVH node of the traversal (128: 4-wide, 64: binary);
                                  num_nodes counts these nodes */
+    int32_t material_model;   /* the ipt_material_model of the scene */
+    int32_t params_per_segment; /* M: 7 or 13 */
 } ipt_scene_info_t;
 
 /* Where the BVH is built.  Both builders apply the same rule (binned SAH,
  * 32 slabs per axis, C_trav = C_isect = 1, leaves of at most 4 triangles)
  * and give the same tree; the host builder is kept as a reference. */
 typedef enum { IPT_BVH_GPU = 0, IPT_BVH_HOST = 1 } ipt_bvh_builder;
-/* Where the path kernels keep the parameter vector (7 S + 3 E floats) and
+/* Where the path kernels keep the parameter vector (M S + 3 E floats) and
  * the adjoint its gradient.  LDS: a copy per block and per-block float64
  * partial gradients summed in a fixed order (deterministic).  GLOBAL: read
  * through the caches, and the adjoint adds float64 atomics into R replicas of
@@ -134,9 +145,13 @@ typedef enum { IPT_BVH_GPU = 0, IPT_BVH_HOST = 1 } ipt_bvh_builder;
  * replica varies; for many segments, e.g. one per triangle, where contention
  * is low).  AUTO: LDS up to 4096 parameters. */
 typedef enum { IPT_PARAMS_AUTO = 0, IPT_PARAMS_GLOBAL = 1 } ipt_param_storage;
+/* The material model of every segment of a scene (see the parameter vector
+ * above); any other value is IPT_ERR_INVALID_ARG. */
+typedef enum { IPT_MATERIAL_GGX = 0, IPT_MATERIAL_DISNEY = 1 } ipt_material_model;
 typedef struct {
     int32_t bvh_builder;      /* an ipt_bvh_builder */
     int32_t param_storage;    /* an ipt_param_storage */
+    int32_t material_model;   /* an ipt_material_model */
 } ipt_build_opts;
 
 /* Build a scene: upload geometry, build the BVH on the GPU (binned SAH,

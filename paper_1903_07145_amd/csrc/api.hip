@@ -67,6 +67,7 @@ struct ipt_scene_s {
     int* d_ovf_rays = nullptr;   // overflow stacks of ipt_trace_rays
     int64_t nt = 0, nv = 0, nnodes = 0;
     int S = 0, E = 0, nlt = 0, depth = 0, has_normals = 0, bvh_builder = 0, params_global = 0;
+    int mat = 0, nm = 7;   // material model and its parameters per segment
     double sah = 0.0, build_ms = 0.0;
     float diag = 0.0f;
     float bb_lo[3] = {0, 0, 0}, bb_hi[3] = {0, 0, 0};
@@ -213,6 +214,10 @@ extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const f
     const int storage = bopts ? bopts->param_storage : IPT_PARAMS_AUTO;
     if (storage != IPT_PARAMS_AUTO && storage != IPT_PARAMS_GLOBAL)
         return fail(IPT_ERR_INVALID_ARG, "unknown param_storage %d", storage);
+    const int mat = bopts ? bopts->material_model : IPT_MATERIAL_GGX;
+    if (mat != IPT_MATERIAL_GGX && mat != IPT_MATERIAL_DISNEY)
+        return fail(IPT_ERR_INVALID_ARG, "unknown material_model %d", mat);
+    const int nm = mat == IPT_MATERIAL_DISNEY ? 13 : 7;
     hipStream_t st = (hipStream_t)hip_stream;
     if (!out) return fail(IPT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -245,7 +250,7 @@ extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const f
         if (seg_emitter[s] >= 0) return fail(IPT_ERR_BAD_SCENE, "segment %d listed twice as emitter", s);
         seg_emitter[s] = k;
     }
-    int64_t P = 7 * (int64_t)num_segments + 3 * (int64_t)num_emitters;
+    int64_t P = nm * (int64_t)num_segments + 3 * (int64_t)num_emitters;
     if (P > kMaxParams)
         return fail(IPT_ERR_NOT_SUPPORTED, "parameter vector too long (%lld > %lld)", (long long)P, (long long)kMaxParams);
 
@@ -384,6 +389,8 @@ extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const f
     s->nnodes = nnodes;
     s->S = num_segments;
     s->E = num_emitters;
+    s->mat = mat;
+    s->nm = nm;
     s->nlt = (int)lights.size();
     s->depth = depth;
     s->has_normals = normals != nullptr;
@@ -401,6 +408,7 @@ extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const f
     s->dev.pos_of = s->d_pos_of;
     s->dev.S = num_segments;
     s->dev.E = num_emitters;
+    s->dev.nm = nm;
     s->dev.nlt = s->nlt;
     s->dev.tmin = (float)(1e-6 * diag);
     *out = s;
@@ -436,6 +444,8 @@ extern "C" ipt_status ipt_scene_info(ipt_scene_t s, ipt_scene_info_t* out) {
     out->bvh_builder = s->bvh_builder;
     out->params_global = s->params_global;
     out->node_bytes = kNodeWidth == 4 ? 128 : 64;
+    out->material_model = s->mat;
+    out->params_per_segment = s->nm;
     return IPT_OK;
 }
 
@@ -490,8 +500,9 @@ struct Plan {
 // or IPT_BLOCKS_PER_CU when set (tuning).
 static int path_grid(const ipt_scene_s* s, int P, int frozen, int gk) {
     const int pg = s->params_global;
-    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, gk, pg), gk, pg);
-    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, gk, pg), gk, pg));
+    int occ = path_blocks_per_cu(kColor, path_lds_bytes(kColor, P, frozen, s->S, s->nlt, gk, pg), gk, pg, s->mat);
+    occ = std::min(occ, path_blocks_per_cu(kGradFwd, path_lds_bytes(kGradFwd, P, frozen, s->S, s->nlt, gk, pg), gk, pg,
+                                           s->mat));
     static const int forced = [] {
         const char* e = std::getenv("IPT_BLOCKS_PER_CU");
         return e ? std::atoi(e) : 0;
@@ -513,7 +524,7 @@ static void split_samples(int64_t npix, int spp, int grid, int& spc, int& nchunk
 }
 
 static void make_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t npix, bool with_loss, Plan& pl) {
-    int P = 7 * s->S + 3 * s->E;
+    int P = s->nm * s->S + 3 * s->E;
     const int guided = o->guide != nullptr;
     pl.grid = path_grid(s, P, 1, guide_kind(o));
     size_t off = 0;
@@ -567,7 +578,8 @@ static PathArgs base_args(const ipt_scene_s* s, const ipt_cameras* cams, const f
     a.params = params;
     a.sparams = sp ? sp : params;
     a.frozen = (sp && sp != params) ? 1 : 0;
-    a.P = 7 * s->S + 3 * s->E;
+    a.P = s->nm * s->S + 3 * s->E;
+    a.mat = s->mat;
     a.cdf = (const float*)(ws + pl.off_cdf);
     a.rng.k0 = (uint32_t)o->seed ^ (o->stream_tag * 0x9E3779B9u);
     a.rng.k1 = (uint32_t)(o->seed >> 32);
@@ -656,7 +668,7 @@ static ipt_status do_grad(ipt_scene_t s, const ipt_cameras* cams, const float* p
         HIP_OK(timed_launch(s, kGradFwd, a, grid, lds_f, st));
         if (a.guided) HIP_OK(launch_guide_records(a, st));
         // the replay pulls tiles, so it runs on as many blocks as are resident
-        int grid_r = std::min(grid, s->num_cu * std::max(1, path_blocks_per_cu(kReplay, lds_r, 0, a.params_global)));
+        int grid_r = std::min(grid, s->num_cu * std::max(1, path_blocks_per_cu(kReplay, lds_r, 0, a.params_global, a.mat)));
         HIP_OK(launch_zero_u32(a.work, 1, st));
         HIP_OK(timed_launch(s, kReplay, a, grid_r, lds_r, st));
         if (!a.params_global) HIP_OK(launch_grad_reduce(a.grad_part, grid_r, a.P, grad, b > 0 ? 1 : 0, st));
@@ -713,7 +725,7 @@ static ipt_status scratch_for_device(int dev, unsigned char** out) {
 // Layout of the colour pass's scratch for a grid of at most
 // kStaticBlocksPerCu blocks per CU; returns the bytes it needs.
 static size_t static_render_plan(const ipt_scene_s* s, const ipt_render_opts* o, int64_t npix, Plan& pl) {
-    const int P = 7 * s->S + 3 * s->E;
+    const int P = s->nm * s->S + 3 * s->E;
     pl.grid = std::min(path_grid(s, P, 1, guide_kind(o)), s->num_cu * kStaticBlocksPerCu);
     size_t off = 0;
     pl.off_counters = off; off = al256(off + 64 * sizeof(unsigned));

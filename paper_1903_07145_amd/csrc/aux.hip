@@ -25,7 +25,7 @@ hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {
 // threads scans a contiguous run, the run totals are scanned in LDS, and the
 // runs are rescanned with their offsets.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void light_cdf_kernel(const int4* lights, int nlt, int S, int E,
+__global__ __launch_bounds__(1024) void light_cdf_kernel(const int4* lights, int nlt, int S, int E, int nm,
                                                          const float* sp, float* cdf) {
     __shared__ float part[1024];
     __shared__ float maxl_sh;
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(1024) void light_cdf_kernel(const int4* lights, int
     if (tid == 0) {
         float m = 0.0f;
         for (int k = 0; k < E; ++k) {
-            const float* e = sp + 7 * S + 3 * k;
+            const float* e = sp + nm * S + 3 * k;
             m = fmaxf(m, (e[0] + e[1] + e[2]) * (1.0f / 3.0f));
         }
         maxl_sh = m;
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(1024) void light_cdf_kernel(const int4* lights, int
         int4 L = lights[j];
         float area = __int_as_float(L.z);
         if (!(maxl > 0.0f)) return area;
-        const float* e = sp + 7 * S + 3 * L.y;
+        const float* e = sp + nm * S + 3 * L.y;
         float l = (e[0] + e[1] + e[2]) * (1.0f / 3.0f);
         return area * fmaxf(l, 1e-3f * maxl);
     };
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(1024) void light_cdf_kernel(const int4* lights, int
 
 hipError_t launch_light_cdf(const SceneDev& sc, const float* sparams, float* cdf, hipStream_t st) {
     if (sc.nlt <= 0) return hipSuccess;
-    hipLaunchKernelGGL(light_cdf_kernel, dim3(1), dim3(1024), 0, st, sc.lights, sc.nlt, sc.S, sc.E,
+    hipLaunchKernelGGL(light_cdf_kernel, dim3(1), dim3(1024), 0, st, sc.lights, sc.nlt, sc.S, sc.E, sc.nm,
                        sparams, cdf);
     return hipGetLastError();
 }

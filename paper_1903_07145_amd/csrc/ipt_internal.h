@@ -43,6 +43,7 @@ struct SceneDev {
     const int* seg_emitter;// [S]: emitter index or -1
     const int* pos_of;     // [nt]: input triangle id -> leaf position
     int S, E, nlt;
+    int nm;                // material parameters per segment: 7 (Lambert + GGX) or 13 (Disney)
     float tmin;            // ray epsilon (1e-6 of the scene diagonal)
 };
 
@@ -101,6 +102,7 @@ struct PathArgs {
                                    // partials grad_part[gridDim.x][P])
     int grad_copies;
     int count_stats;               // accumulate KStats into err->k[mode]
+    int mat;                       // material model: 0 Lambert + GGX, 1 Disney (selects the kernels)
     // learned proposal (one-sample MIS with BRDF sampling)
     GuideDev gd;
     int guided;                    // a guide is attached (checkpoint plane ck_d is written)
@@ -114,7 +116,7 @@ struct PathArgs {
 };
 
 size_t path_lds_bytes(int mode, int P, int frozen, int S, int nlt, int guide_kind = 0, int params_global = 0);
-int path_blocks_per_cu(int mode, size_t lds, int guide_kind = 0, int params_global = 0);
+int path_blocks_per_cu(int mode, size_t lds, int guide_kind = 0, int params_global = 0, int mat = 0);
 hipError_t launch_guide_records(const PathArgs& a, hipStream_t st);
 hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st);
 // guide handle internals (guide.hip)

@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ipt_internal.h"
+#include "disney.h"
 
 namespace ipt {
 
@@ -413,6 +414,7 @@ __device__ __forceinline__ void lds_add(double* g, int i, float x) {
 // ---------------------------------------------------------------------------
 struct Shade {
     V3 p0, e1, e2, x, ng, ngf, ns, wo;
+    V3 tx, ty;   // tangent frame of the Disney model (set by mat_frame)
     int tri, orig, seg, light, em;
     float u, v, t, cos_emit;
 };
@@ -441,6 +443,75 @@ __device__ __forceinline__ void make_shade(const SceneDev& sc, const Lds& lds, c
     }
     g.ngf = g.ng;
     if (dot(g.ng, g.wo) < 0.0f) { g.ngf = g.ng * -1.0f; g.ns = g.ns * -1.0f; }
+}
+
+// ---------------------------------------------------------------------------
+// Material models (compile-time): 0 Lambert + GGX, 7 parameters per segment;
+// 1 Disney (Sec. 4.1), 13.  The kernels see a material through these
+// overloads only.
+// ---------------------------------------------------------------------------
+template <int MAT> struct MatSel { using M = Mat; static constexpr int NP = 7; };
+template <> struct MatSel<1> { using M = DMat; static constexpr int NP = kDisneyParams; };
+
+template <int MAT>
+__device__ __forceinline__ typename MatSel<MAT>::M mat_load(const float* p, int seg) {
+    if constexpr (MAT == 1) return load_dmat(p, seg);
+    else return load_mat(p, seg);
+}
+// The Disney model's anisotropy needs a tangent frame at the vertex.
+template <int MAT>
+__device__ __forceinline__ void mat_frame(Shade& g) {
+    if constexpr (MAT == 1) disney_frame(g.ns, g.e1, g.tx, g.ty);
+}
+// f(wo, wi); for Lambert + GGX also the GGX factor and its alpha derivative,
+// which the adjoint uses directly (the Disney adjoint differentiates f).
+__device__ __forceinline__ V3 mat_f(const Mat& m, const Shade& g, V3 wi, float& spec, float& dspec) {
+    spec_term(g.ns, g.wo, wi, m.alpha, spec, dspec);
+    return m.kd * kInvPi + m.ks * spec;
+}
+__device__ __forceinline__ V3 mat_f(const DMat& m, const Shade& g, V3 wi, float& spec, float& dspec) {
+    spec = dspec = 0.0f;
+    return disney_value(m, disney_geom(g.ns, g.tx, g.ty, g.wo, wi));
+}
+__device__ __forceinline__ V3 mat_f_only(const Mat& m, const Shade& g, V3 wi) {
+    return m.kd * kInvPi + m.ks * spec_only(g.ns, g.wo, wi, m.alpha);
+}
+__device__ __forceinline__ V3 mat_f_only(const DMat& m, const Shade& g, V3 wi) {
+    return disney_value(m, disney_geom(g.ns, g.tx, g.ty, g.wo, wi));
+}
+__device__ __forceinline__ float mat_pdf(const Mat& m, const Shade& g, V3 wi) { return brdf_pdf(m, g.ns, g.wo, wi); }
+__device__ __forceinline__ float mat_pdf(const DMat& m, const Shade& g, V3 wi) {
+    return disney_pdf(m, g.ns, g.tx, g.ty, g.wo, wi);
+}
+__device__ __forceinline__ bool mat_sample(const Mat& m, const Shade& g, float u3, float u4, float u5, V3& wi,
+                                           int& lobe) {
+    return brdf_sample(m, g.ns, g.wo, u3, u4, u5, wi, lobe);
+}
+__device__ __forceinline__ bool mat_sample(const DMat& m, const Shade& g, float u3, float u4, float u5, V3& wi,
+                                           int& lobe) {
+    return disney_sample(m, g.ns, g.tx, g.ty, g.wo, u3, u4, u5, wi, lobe);
+}
+template <class M> struct MatNP { static constexpr int value = 7; };
+template <> struct MatNP<DMat> { static constexpr int value = kDisneyParams; };
+
+// Adjoint of f at one vertex: w . d f / d theta_seg added to the block's
+// gradient, for a channel weight w (the Lambert + GGX terms use the factors
+// spec, dspec kept from the evaluation).
+__device__ __forceinline__ void mat_grad(double* grad, int mb, const Mat& m, const Shade&, V3, V3 w, float spec,
+                                         float dspec) {
+    lds_add(grad, mb + 0, w.x * kInvPi);
+    lds_add(grad, mb + 1, w.y * kInvPi);
+    lds_add(grad, mb + 2, w.z * kInvPi);
+    lds_add(grad, mb + 3, w.x * spec);
+    lds_add(grad, mb + 4, w.y * spec);
+    lds_add(grad, mb + 5, w.z * spec);
+    lds_add(grad, mb + 6, dot(w, m.ks) * dspec);
+}
+__device__ __forceinline__ void mat_grad(double* grad, int mb, const DMat& m, const Shade& g, V3 wi, V3 w, float,
+                                         float) {
+    const DGeom dg = disney_geom(g.ns, g.tx, g.ty, g.wo, wi);
+#pragma unroll 1
+    for (int j = 0; j < kDisneyParams; ++j) lds_add(grad, mb + j, dot(w, disney_dparam(m, dg, j)));
 }
 
 // MIS weight of an emitter hit at vertex k reached by a direction sampled
@@ -502,10 +573,11 @@ struct NeeC {
 // The light-sample contribution assuming the shadow ray is unoccluded.
 // pb >= 0 overrides the BRDF-sampling density of the light direction (the
 // combined density when a guide is used).
+template <class M>
 __device__ __forceinline__ NeeC nee_contrib(const PathArgs& a, const Lds& lds, const float* cdf, const Shade& g,
-                                            const Mat& m, const Mat& ms, const NeeS& n, float pb_in = -1.0f) {
+                                            const M& m, const M& ms, const NeeS& n, float pb_in = -1.0f) {
     NeeC r;
-    spec_term(g.ns, g.wo, n.wl, m.alpha, r.spec, r.dspec);
+    r.spec = r.dspec = 0.0f;
     float cx = dot(g.ns, n.wl);
     r.valid = cx > 0.0f;
     r.c = v3(0.0f, 0.0f, 0.0f);
@@ -517,14 +589,14 @@ __device__ __forceinline__ NeeC nee_contrib(const PathArgs& a, const Lds& lds, c
     float w = 1.0f;
     if (a.mis >= 2) {
         float pl = parea * n.d2 / n.cy;
-        float pb = pb_in >= 0.0f ? pb_in : brdf_pdf(ms, g.ns, g.wo, n.wl);
+        float pb = pb_in >= 0.0f ? pb_in : mat_pdf(ms, g, n.wl);
         w = mis_weight(pl, pb, a.mis);
     }
     float prof = a.profile ? n.cy : 1.0f;
     r.g = cx * n.cy / n.d2 * w / parea * prof;
-    const float* ep = lds.params + 7 * a.sc.S + 3 * n.lk;
+    const float* ep = lds.params + MatNP<M>::value * a.sc.S + 3 * n.lk;
     r.e = v3(ep[0], ep[1], ep[2]);
-    r.f = m.kd * kInvPi + m.ks * r.spec;
+    r.f = mat_f(m, g, n.wl, r.spec, r.dspec);
     r.c = r.f * r.e * r.g;
     return r;
 }
@@ -541,7 +613,8 @@ struct ContS {
 // validity (above both the geometric and the shading surface, pdf > 0),
 // a = f cos / pdf at params, the same at sampling params (for Russian
 // roulette), and the roulette decision.
-__device__ __forceinline__ ContS cont_eval(const PathArgs& a, const Shade& g, const Mat& m, const Mat& ms, V3 wi,
+template <class M>
+__device__ __forceinline__ ContS cont_eval(const PathArgs& a, const Shade& g, const M& m, const M& ms, V3 wi,
                                            float pdf, int lobe, const float u[8], int k, V3 Ts) {
     ContS c;
     c.wi = wi;
@@ -554,12 +627,12 @@ __device__ __forceinline__ ContS cont_eval(const PathArgs& a, const Shade& g, co
     c.g = c.spec = c.dspec = 0.0f;
     c.ok = pdf > 0.0f && dot(wi, g.ngf) > 0.0f && dot(wi, g.ns) > 0.0f;
     if (!c.ok) return c;
-    spec_term(g.ns, g.wo, wi, m.alpha, c.spec, c.dspec);
+    const V3 f = mat_f(m, g, wi, c.spec, c.dspec);
     float ci = dot(g.ns, wi);
     c.g = ci / pdf;
-    c.av = (m.kd * kInvPi + m.ks * c.spec) * c.g;
+    c.av = f * c.g;
     c.ts = c.av;
-    if (a.frozen) c.ts = (ms.kd * kInvPi + ms.ks * spec_only(g.ns, g.wo, wi, ms.alpha)) * c.g;
+    if (a.frozen) c.ts = mat_f_only(ms, g, wi) * c.g;
     c.alive = true;
     if (a.rr_depth >= 0 && k >= a.rr_depth) {
         c.qrr = fminf(fmaxf(maxc(Ts * c.ts), 0.1f), 0.95f);
@@ -585,8 +658,8 @@ __device__ __forceinline__ V3 guide_sample(const float* mix, float u3, float u4,
     return mixture_sample(mix, u3, u4, u5);
 }
 
-template <int GUIDE>
-__device__ __forceinline__ ContS cont_sample(const PathArgs& a, const Shade& g, const Mat& m, const Mat& ms,
+template <int GUIDE, class M>
+__device__ __forceinline__ ContS cont_sample(const PathArgs& a, const Shade& g, const M& m, const M& ms,
                                              const float u[8], int k, V3 Ts, const float* mix, bool& used_guide) {
     V3 wi = v3(0.0f, 0.0f, 1.0f);
     int lobe = 0;
@@ -595,11 +668,11 @@ __device__ __forceinline__ ContS cont_sample(const PathArgs& a, const Shade& g, 
     if (GUIDE && mix && u[7] < a.gmix) {
         used_guide = true;
         wi = guide_sample<GUIDE>(mix, u[3], u[4], u[5]);
-        pdf = a.gmix * guide_pdf<GUIDE>(mix, wi) + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, wi);
+        pdf = a.gmix * guide_pdf<GUIDE>(mix, wi) + (1.0f - a.gmix) * mat_pdf(ms, g, wi);
     } else {
-        bool okd = brdf_sample(ms, g.ns, g.wo, u[3], u[4], u[5], wi, lobe);
+        bool okd = mat_sample(ms, g, u[3], u[4], u[5], wi, lobe);
         if (okd && dot(wi, g.ngf) > 0.0f && dot(wi, g.ns) > 0.0f) {
-            pdf = brdf_pdf(ms, g.ns, g.wo, wi);
+            pdf = mat_pdf(ms, g, wi);
             if (GUIDE && mix) pdf = a.gmix * guide_pdf<GUIDE>(mix, wi) + (1.0f - a.gmix) * pdf;
         }
     }
@@ -615,7 +688,8 @@ struct ContDir {
     bool ok;      // BRDF technique: a direction above the surface
     bool guide;   // the proposal's technique was chosen
 };
-__device__ __forceinline__ ContDir cont_direction_cached(const PathArgs& a, const Shade& g, const Mat& ms,
+template <class M>
+__device__ __forceinline__ ContDir cont_direction_cached(const PathArgs& a, const Shade& g, const M& ms,
                                                          const float u[8], const float* row) {
     ContDir c;
     c.lobe = 0;
@@ -625,17 +699,18 @@ __device__ __forceinline__ ContDir cont_direction_cached(const PathArgs& a, cons
         c.ok = true;
     } else {
         c.wi = v3(0.0f, 0.0f, 1.0f);
-        c.ok = brdf_sample(ms, g.ns, g.wo, u[3], u[4], u[5], c.wi, c.lobe) && dot(c.wi, g.ngf) > 0.0f &&
+        c.ok = mat_sample(ms, g, u[3], u[4], u[5], c.wi, c.lobe) && dot(c.wi, g.ngf) > 0.0f &&
                dot(c.wi, g.ns) > 0.0f;
     }
     return c;
 }
 // ... then, with the proposal's density q of that direction, the combined
 // density and the continuation weight (as cont_sample).
-__device__ __forceinline__ ContS cont_finish_cached(const PathArgs& a, const Shade& g, const Mat& m, const Mat& ms,
+template <class M>
+__device__ __forceinline__ ContS cont_finish_cached(const PathArgs& a, const Shade& g, const M& m, const M& ms,
                                                     const float u[8], int k, V3 Ts, const ContDir& c, float q) {
     float pdf = 0.0f;
-    if (c.guide || c.ok) pdf = a.gmix * q + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, c.wi);
+    if (c.guide || c.ok) pdf = a.gmix * q + (1.0f - a.gmix) * mat_pdf(ms, g, c.wi);
     return cont_eval(a, g, m, ms, c.wi, pdf, c.lobe, u, k, Ts);
 }
 
@@ -703,8 +778,9 @@ enum Phase { kNeedPixel = 0, kClosest = 1, kShadow = 2, kExit = 3 };
 #ifndef IPT_TRAV_EXIT_LANES
 #define IPT_TRAV_EXIT_LANES 16
 #endif
-// GUIDE: 0 none, 1 bfloat16 MFMA evaluation, 2 float32 VALU evaluation
-template <int MODE, int GUIDE, int PG>
+// GUIDE: 0 none, 1 bfloat16 MFMA evaluation, 2 float32 VALU evaluation, 3 cached
+// proposal; MAT: the material model (MatSel)
+template <int MODE, int GUIDE, int PG, int MAT>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU_GUIDED : IPT_WAVES_PER_EU,
                                    8))) void path_sm_kernel(
@@ -874,7 +950,7 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
                         float w = emit_weight(a, cdf, lights, g, k, prev_pdf);
                         if (w > 0.0f) {
                             float prof = a.profile ? g.cos_emit : 1.0f;
-                            const float* e = lds.params + 7 * sc.S + 3 * g.em;
+                            const float* e = lds.params + MatSel<MAT>::NP * sc.S + 3 * g.em;
                             V3 c = v3(e[0], e[1], e[2]) * (prof * w);
                             cpart = c;
                             L = L + T * c;
@@ -932,8 +1008,9 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
             uint32_t flags = 0;
             bool shoot = false;
             V3 av = v3(0.0f, 0.0f, 0.0f);
-            Mat m = load_mat(lds.params, g.seg);
-            Mat ms = a.frozen ? load_mat(lds.sparams, g.seg) : m;
+            mat_frame<MAT>(g);
+            const typename MatSel<MAT>::M m = mat_load<MAT>(lds.params, g.seg);
+            const typename MatSel<MAT>::M ms = a.frozen ? mat_load<MAT>(lds.sparams, g.seg) : m;
             float u[8];
             vertex_uniforms(a.rng, pid, k, u);
             float pb_nee = -1.0f;
@@ -964,7 +1041,7 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
                 float q_wi, q_wl;
                 cached_pdf2(mix, cd.wi, n.shoot ? n.wl : cd.wi, q_wi, q_wl);
                 if (n.shoot) {
-                    pb_nee = a.gmix * q_wl + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, n.wl);
+                    pb_nee = a.gmix * q_wl + (1.0f - a.gmix) * mat_pdf(ms, g, n.wl);
                     take_nee(n);
                 }
                 cs = cont_finish_cached(a, g, m, ms, u, k, Ts, cd, q_wi);
@@ -975,13 +1052,14 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
                     ev |= (uint32_t)n.lj << 8;
                     if (n.shoot) {
                         if (GUIDE && mix)
-                            pb_nee = a.gmix * guide_pdf<GUIDE>(mix, n.wl) + (1.0f - a.gmix) * brdf_pdf(ms, g.ns, g.wo, n.wl);
+                            pb_nee = a.gmix * guide_pdf<GUIDE>(mix, n.wl) + (1.0f - a.gmix) * mat_pdf(ms, g, n.wl);
                         take_nee(n);
                     }
                 }
                 cs = cont_sample<GUIDE>(a, g, m, ms, u, k, Ts, mix, used_guide);
             }
-            ev |= (uint32_t)cs.lobe << 3;
+            // lobe 1 at bit 3, lobe 2 (the Disney clearcoat) at bit 7
+            ev |= (uint32_t)(cs.lobe & 1) << 3 | (uint32_t)(cs.lobe >> 1) << 7;
             if (used_guide) ev |= 64u;
             if (!cs.ok) {
                 evtail = 16u;
@@ -1073,6 +1151,7 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
 // ---------------------------------------------------------------------------
 // Adjoint replay: one lane per pixel, tiles pulled by blocks.
 // ---------------------------------------------------------------------------
+template <int MAT>
 __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& wk, uint64_t pid, int64_t q, int s,
                             V3 org, V3 dir, V3 wpix) {
     const SceneDev& sc = a.sc;
@@ -1122,15 +1201,16 @@ __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& 
             float w = emit_weight(a, cdf, lights, g, k, prev_pdf);
             if (w > 0.0f) {
                 float prof = a.profile ? g.cos_emit : 1.0f;
-                int eb = 7 * sc.S + 3 * g.em;
+                int eb = MatSel<MAT>::NP * sc.S + 3 * g.em;
                 lds_add(lds.grad, eb + 0, wT.x * prof * w);
                 lds_add(lds.grad, eb + 1, wT.y * prof * w);
                 lds_add(lds.grad, eb + 2, wT.z * prof * w);
             }
         }
         if (k == a.D + 1 || dot(g.ns, g.wo) <= 0.0f) return;
-        Mat m = load_mat(lds.params, g.seg);
-        Mat ms = a.frozen ? load_mat(lds.sparams, g.seg) : m;
+        mat_frame<MAT>(g);
+        const typename MatSel<MAT>::M m = mat_load<MAT>(lds.params, g.seg);
+        const typename MatSel<MAT>::M ms = a.frozen ? mat_load<MAT>(lds.sparams, g.seg) : m;
         float u[8];
         vertex_uniforms(a.rng, pid, k, u);
         float4 dk = a.guided ? a.ck_d[ck] : make_float4(0.0f, 0.0f, 0.0f, -1.0f);
@@ -1149,15 +1229,10 @@ __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& 
                 // with a guide the forward pass stored the combined density of wl
                 NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n, dk.w);
                 if (nc.valid) {
-                    int mb = 7 * g.seg, eb = 7 * sc.S + 3 * n.lk;
+                    constexpr int NP = MatSel<MAT>::NP;
+                    int mb = NP * g.seg, eb = NP * sc.S + 3 * n.lk;
                     V3 we = wT * nc.e * nc.g;
-                    lds_add(lds.grad, mb + 0, we.x * kInvPi);
-                    lds_add(lds.grad, mb + 1, we.y * kInvPi);
-                    lds_add(lds.grad, mb + 2, we.z * kInvPi);
-                    lds_add(lds.grad, mb + 3, we.x * nc.spec);
-                    lds_add(lds.grad, mb + 4, we.y * nc.spec);
-                    lds_add(lds.grad, mb + 5, we.z * nc.spec);
-                    lds_add(lds.grad, mb + 6, dot(we, m.ks) * nc.dspec);
+                    mat_grad(lds.grad, mb, m, g, n.wl, we, nc.spec, nc.dspec);
                     V3 wf = wT * nc.f * nc.g;
                     lds_add(lds.grad, eb + 0, wf.x);
                     lds_add(lds.grad, eb + 1, wf.y);
@@ -1175,15 +1250,8 @@ __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& 
             cs = cont_sample<0>(a, g, m, ms, u, k, Ts, nullptr, ug);
         }
         float rq = 1.0f / cs.qrr;
-        int mb = 7 * g.seg;
         V3 wr = wT * Rn * (cs.g * rq);
-        lds_add(lds.grad, mb + 0, wr.x * kInvPi);
-        lds_add(lds.grad, mb + 1, wr.y * kInvPi);
-        lds_add(lds.grad, mb + 2, wr.z * kInvPi);
-        lds_add(lds.grad, mb + 3, wr.x * cs.spec);
-        lds_add(lds.grad, mb + 4, wr.y * cs.spec);
-        lds_add(lds.grad, mb + 5, wr.z * cs.spec);
-        lds_add(lds.grad, mb + 6, dot(wr, m.ks) * cs.dspec);
+        mat_grad(lds.grad, MatSel<MAT>::NP * g.seg, m, g, cs.wi, wr, cs.spec, cs.dspec);
         T = T * (cs.av * rq);
         Ts = Ts * cs.ts * rq;
         prev_pdf = cs.pdf;
@@ -1193,7 +1261,7 @@ __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& 
     }
 }
 
-template <int PG>
+template <int PG, int MAT>
 __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned tile_sh;
@@ -1236,7 +1304,7 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
             if (a.jitter) jitter_uniforms(a.rng, pid, j0, j1);
             V3 o, d;
             camera_ray(a, view, (float)px + j0, (float)py + j1, o, d);
-            replay_path(a, lds, st, wk, pid, q, s, o, d, wpix);
+            replay_path<MAT>(a, lds, st, wk, pid, q, s, o, d, wpix);
             ++npaths;
         }
     }
@@ -1330,47 +1398,58 @@ static int occ(K kern, size_t lds) {
     return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 
-template <int MODE, int PG>
+template <int MODE, int PG, int MAT>
 static int path_occ(int gk, size_t lds) {
     switch (gk) {
-        case 1: return occ(path_sm_kernel<MODE, 1, PG>, lds);
-        case 2: return occ(path_sm_kernel<MODE, 2, PG>, lds);
-        case 3: return occ(path_sm_kernel<MODE, 3, PG>, lds);
-        default: return occ(path_sm_kernel<MODE, 0, PG>, lds);
+        case 1: return occ(path_sm_kernel<MODE, 1, PG, MAT>, lds);
+        case 2: return occ(path_sm_kernel<MODE, 2, PG, MAT>, lds);
+        case 3: return occ(path_sm_kernel<MODE, 3, PG, MAT>, lds);
+        default: return occ(path_sm_kernel<MODE, 0, PG, MAT>, lds);
     }
 }
 
-template <int MODE, int PG>
+template <int MODE, int PG, int MAT>
 static void launch_path_kind(int gk, const PathArgs& a, int grid, size_t lds, hipStream_t st) {
     switch (gk) {
-        case 1: hipLaunchKernelGGL((path_sm_kernel<MODE, 1, PG>), dim3(grid), dim3(kBlock), lds, st, a); break;
-        case 2: hipLaunchKernelGGL((path_sm_kernel<MODE, 2, PG>), dim3(grid), dim3(kBlock), lds, st, a); break;
-        case 3: hipLaunchKernelGGL((path_sm_kernel<MODE, 3, PG>), dim3(grid), dim3(kBlock), lds, st, a); break;
-        default: hipLaunchKernelGGL((path_sm_kernel<MODE, 0, PG>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        case 1: hipLaunchKernelGGL((path_sm_kernel<MODE, 1, PG, MAT>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((path_sm_kernel<MODE, 2, PG, MAT>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        case 3: hipLaunchKernelGGL((path_sm_kernel<MODE, 3, PG, MAT>), dim3(grid), dim3(kBlock), lds, st, a); break;
+        default: hipLaunchKernelGGL((path_sm_kernel<MODE, 0, PG, MAT>), dim3(grid), dim3(kBlock), lds, st, a); break;
     }
 }
 
-int path_blocks_per_cu(int mode, size_t lds, int gk, int pg) {
-    if (mode == kColor) return pg ? path_occ<kColor, 1>(gk, lds) : path_occ<kColor, 0>(gk, lds);
-    if (mode == kGradFwd) return pg ? path_occ<kGradFwd, 1>(gk, lds) : path_occ<kGradFwd, 0>(gk, lds);
-    return pg ? occ(replay_kernel<1>, lds) : occ(replay_kernel<0>, lds);
+template <int MAT>
+static int blocks_per_cu_mat(int mode, size_t lds, int gk, int pg) {
+    if (mode == kColor) return pg ? path_occ<kColor, 1, MAT>(gk, lds) : path_occ<kColor, 0, MAT>(gk, lds);
+    if (mode == kGradFwd) return pg ? path_occ<kGradFwd, 1, MAT>(gk, lds) : path_occ<kGradFwd, 0, MAT>(gk, lds);
+    return pg ? occ(replay_kernel<1, MAT>, lds) : occ(replay_kernel<0, MAT>, lds);
+}
+
+int path_blocks_per_cu(int mode, size_t lds, int gk, int pg, int mat) {
+    return mat == 1 ? blocks_per_cu_mat<1>(mode, lds, gk, pg) : blocks_per_cu_mat<0>(mode, lds, gk, pg);
+}
+
+template <int MAT>
+static void launch_paths_mat(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st) {
+    const int pg = a.params_global;
+    if (mode == kColor) {
+        if (pg) launch_path_kind<kColor, 1, MAT>(a.guide_kind, a, grid, lds, st);
+        else launch_path_kind<kColor, 0, MAT>(a.guide_kind, a, grid, lds, st);
+    } else if (mode == kGradFwd) {
+        if (pg) launch_path_kind<kGradFwd, 1, MAT>(a.guide_kind, a, grid, lds, st);
+        else launch_path_kind<kGradFwd, 0, MAT>(a.guide_kind, a, grid, lds, st);
+    } else if (pg) {
+        hipLaunchKernelGGL((replay_kernel<1, MAT>), dim3(grid), dim3(kBlock), lds, st, a);
+    } else {
+        hipLaunchKernelGGL((replay_kernel<0, MAT>), dim3(grid), dim3(kBlock), lds, st, a);
+    }
 }
 
 // The proposal is compiled in only when it is sampled (guide_mix > 0); kind
-// as in PathArgs::guide_kind.
+// as in PathArgs::guide_kind, material model as in PathArgs::mat.
 hipError_t launch_paths(int mode, const PathArgs& a, int grid, size_t lds, hipStream_t st) {
-    const int pg = a.params_global;
-    if (mode == kColor) {
-        if (pg) launch_path_kind<kColor, 1>(a.guide_kind, a, grid, lds, st);
-        else launch_path_kind<kColor, 0>(a.guide_kind, a, grid, lds, st);
-    } else if (mode == kGradFwd) {
-        if (pg) launch_path_kind<kGradFwd, 1>(a.guide_kind, a, grid, lds, st);
-        else launch_path_kind<kGradFwd, 0>(a.guide_kind, a, grid, lds, st);
-    } else if (pg) {
-        hipLaunchKernelGGL(replay_kernel<1>, dim3(grid), dim3(kBlock), lds, st, a);
-    } else {
-        hipLaunchKernelGGL(replay_kernel<0>, dim3(grid), dim3(kBlock), lds, st, a);
-    }
+    if (a.mat == 1) launch_paths_mat<1>(mode, a, grid, lds, st);
+    else launch_paths_mat<0>(mode, a, grid, lds, st);
     return hipGetLastError();
 }
 

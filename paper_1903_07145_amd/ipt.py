@@ -63,15 +63,19 @@ class SceneInfo(ctypes.Structure):
                 ("sah_cost", ctypes.c_double), ("build_ms", ctypes.c_double), ("scene_diag", ctypes.c_float),
                 ("nonfinite_paths", ctypes.c_uint64), ("stack_overflows", ctypes.c_uint64),
                 ("bvh_builder", ctypes.c_int32), ("params_global", ctypes.c_int32),
-                ("node_bytes", ctypes.c_int32)]
+                ("node_bytes", ctypes.c_int32), ("material_model", ctypes.c_int32),
+                ("params_per_segment", ctypes.c_int32)]
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("bvh_builder", ctypes.c_int32), ("param_storage", ctypes.c_int32)]
+    _fields_ = [("bvh_builder", ctypes.c_int32), ("param_storage", ctypes.c_int32),
+                ("material_model", ctypes.c_int32)]
 
 
 BVH_GPU, BVH_HOST = 0, 1
 PARAMS_AUTO, PARAMS_GLOBAL = 0, 1
+MATERIAL_GGX, MATERIAL_DISNEY = 0, 1
+PARAMS_PER_SEGMENT = {MATERIAL_GGX: 7, MATERIAL_DISNEY: 13}
 
 
 class KernelProfile(ctypes.Structure):
@@ -202,7 +206,7 @@ class Scene:
     """A built scene on the current device (ipt_scene_build)."""
 
     def __init__(self, verts, tris, tri_seg, num_segments, emitter_seg, normals=None, bvh_builder=BVH_GPU,
-                 param_storage=PARAMS_AUTO):
+                 param_storage=PARAMS_AUTO, material=MATERIAL_GGX):
         v = np.ascontiguousarray(verts, np.float32)
         t = np.ascontiguousarray(tris, np.int32)
         s = np.ascontiguousarray(tri_seg, np.int32)
@@ -210,10 +214,13 @@ class Scene:
         n = None if normals is None else np.ascontiguousarray(normals, np.float32)
         self.num_segments = int(num_segments)
         self.num_emitters = int(e.size)
-        self.P = 7 * self.num_segments + 3 * self.num_emitters
+        self.material = int(material)
+        if self.material not in PARAMS_PER_SEGMENT:
+            raise ValueError("unknown material model %r" % (material,))
+        self.P = PARAMS_PER_SEGMENT[self.material] * self.num_segments + 3 * self.num_emitters
         h = ctypes.c_void_p()
         torch.cuda.init()
-        bo = BuildOpts(int(bvh_builder), int(param_storage))
+        bo = BuildOpts(int(bvh_builder), int(param_storage), self.material)
         _check(lib().ipt_scene_build_ex(v.ctypes.data_as(ctypes.c_void_p), v.shape[0],
                                         None if n is None else n.ctypes.data_as(ctypes.c_void_p),
                                         t.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p),
@@ -225,7 +232,8 @@ class Scene:
     @classmethod
     def from_dict(cls, sc, bvh_builder=BVH_GPU, param_storage=PARAMS_AUTO):
         return cls(sc["verts"], sc["tris"], sc["tri_seg"], sc["num_segments"], sc["emitter_seg"],
-                   sc.get("normals"), bvh_builder=bvh_builder, param_storage=param_storage)
+                   sc.get("normals"), bvh_builder=bvh_builder, param_storage=param_storage,
+                   material=sc.get("material", MATERIAL_GGX))
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -165,13 +165,13 @@ def mask_report(hash_g, r, gcond=None, label="", use_margin=True):
     return out
 
 
-def emission_linearity(w, img, grad, params, S, label=""):
+def emission_linearity(w, img, grad, params, S, label="", nm=7):
     """The estimate is linear in the emission: per path, sum_k e_k dL/de_k = L,
     so for any subset of paths sum_j w_j . I_j = sum_k e_k g_k with the
     gradient g of sum_j w_j . I_j.  Exact up to float32 rounding; it holds
     path by path, so it applies to paths whose float32 trajectory departs
     from float64's as well."""
-    lhs = float(np.dot(np.asarray(params, np.float64)[7 * S:], grad[7 * S:]))
+    lhs = float(np.dot(np.asarray(params, np.float64)[nm * S:], grad[nm * S:]))
     rhs = float(np.sum(np.asarray(w, np.float64) * img))
     scale = float(np.sum(np.abs(np.asarray(w, np.float64) * img))) + 1e-30
     banner("%s emission linearity: sum e dI/de %.6e vs w.I %.6e (rel %.1e of sum |w I|)" % (

@@ -1,0 +1,152 @@
+"""The Disney material model (Sec. 4.1; Burley 2012) on the GPU, through the
+C ABI, against the oracle's complex-step Disney estimator on the same seeded
+inputs: 13 parameters per segment through the colour pass, the gradient
+forward pass with its checkpoints and the adjoint replay.
+
+Scenes: Cornell box (flat normals, the tangent frame from each triangle's
+first edge) and a crop of the 50k-triangle room (smooth cylinder normals),
+both with seeded Disney parameters (metallic, anisotropic and clearcoat
+segments among them).  Protocol as for the Lambert + GGX model: events
+compared path by path, then tiers by the oracle's conditioning probe -- tight
+(pixels at 1e-4, gradients at 1e-3), loose (1e-2), irregular (mean radiance
+within 5 standard errors; the GPU gradient's exact linearity in emission)."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from _gpu import (LOOSE_REL, banner, both, chaotic_agreement, check_mismatches, emission_linearity, gpu_grad,
+                  gpu_render, mask_report, oracle_opts, rel_err)
+from paper_1903_07145_amd import ipt, scenes
+
+pytestmark = pytest.mark.gpu
+
+PIX_REL = 1e-4
+GRAD_REL = 1e-3
+NM = 13
+
+
+def _grad_err(gg, go):
+    rms = math.sqrt(np.mean(go ** 2)) + 1e-30
+    return np.abs(gg - go) / np.maximum(np.abs(go), 1e-2 * rms)
+
+
+def _tiered(label, sc, g, o, dc, params, kw, pix=None, sp=None, w=None, min_tight=0.8, min_tight_g=0.8):
+    """Events, tiers, pixels and gradients of one configuration; returns the
+    tight-tier GPU and oracle gradients."""
+    npix = dc["num_views"] * dc["width"] * dc["height"] if pix is None else pix.size
+    if w is None:
+        w = np.random.default_rng(7).normal(size=(npix, 3))
+    _, h_g, pL_g = gpu_render(g, dc, params, kw, pixel_list=pix, sampling_params=sp, want_path_L=True)
+    r = o.run(sc["cams"], params, sampling_params=sp, pixel_list=pix, w=w, want_hash=True, want_margin=True,
+              want_cond=True, want_path_L=True, **oracle_opts(kw))
+    check_mismatches(h_g, r, 3, 1e-5, label=label, depth=kw["max_depth"])
+    mk = mask_report(h_g, r, gcond=r["gcond"], label=label)
+    assert mk["f_tight"] >= min_tight and mk["f_tight_g"] >= min_tight_g, mk
+    t = mk["tight"]
+    img_g, _ = gpu_render(g, dc, params, kw, pixel_list=pix, sampling_params=sp, mask=t)
+    ro = o.run(sc["cams"], params, sampling_params=sp, pixel_list=pix, path_mask=t.astype(np.uint8),
+               **oracle_opts(kw))
+    mean = np.abs(r["image"]).mean()
+    err = rel_err(img_g, ro["image"], 1e-4 * mean)
+    banner("%s: tight pixels rel err p50 %.2e p99 %.2e max %.2e" % ((label,) + tuple(np.percentile(err, [50, 99, 100]))))
+    assert err.max() <= PIX_REL, err.max()
+    lo = mk["loose"]
+    e2 = rel_err(pL_g[lo], r["path_L"][lo], 1e-4 * mean)
+    banner("%s: %d loose paths, rel err max %.2e" % (label, lo.sum(), e2.max(initial=0)))
+    assert e2.max(initial=0) <= LOOSE_REL
+    chaotic_agreement(pL_g[mk["irregular"]], r["path_L"][mk["irregular"]], label=label)
+    out = None
+    for tier, bar in (("tight_g", GRAD_REL), ("loose_g", LOOSE_REL)):
+        m = mk[tier]
+        gg = gpu_grad(g, dc, params, w, kw, pixel_list=pix, mask=m, sampling_params=sp)
+        go = o.run(sc["cams"], params, sampling_params=sp, pixel_list=pix, w=w, path_mask=m.astype(np.uint8),
+                   want_grad=True, **oracle_opts(kw))["grad"]
+        e = _grad_err(gg, go)
+        banner("%s: %s gradient over %d paths, rel err p50 %.2e max %.2e (bar %.0e)" % (
+            label, tier, m.sum(), np.median(e), e.max(), bar))
+        assert e.max() <= bar, (tier, e.max(), int(np.argmax(e)))
+        if out is None:
+            out = (gg, go)
+    ir = mk["irregular_g"]
+    gi = gpu_grad(g, dc, params, w, kw, pixel_list=pix, mask=ir, sampling_params=sp)
+    img_i, _ = gpu_render(g, dc, params, kw, pixel_list=pix, sampling_params=sp, mask=ir)
+    emission_linearity(w, img_i, gi, params, sc["num_segments"], label="%s %d irregular paths:" % (label, ir.sum()),
+                       nm=NM)
+    return out
+
+
+@pytest.fixture(scope="module")
+def cornell_disney():
+    sc = scenes.disney(scenes.cornell(), seed=4)
+    g, o = both(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    return sc, g, o, dc
+
+
+def test_disney_scene_info_and_bad_model(cornell_disney):
+    sc, g, _, _ = cornell_disney
+    inf = g.info()
+    assert inf["material_model"] == ipt.MATERIAL_DISNEY and inf["params_per_segment"] == NM
+    assert g.P == NM * sc["num_segments"] + 3 * len(sc["emitter_seg"]) == sc["params"].size
+    # the C ABI rejects an unknown model before it allocates anything
+    v = np.ascontiguousarray(sc["verts"], np.float32)
+    t = np.ascontiguousarray(sc["tris"], np.int32)
+    s = np.ascontiguousarray(sc["tri_seg"], np.int32)
+    e = np.ascontiguousarray(sc["emitter_seg"], np.int32)
+    h = ctypes.c_void_p()
+    bo = ipt.BuildOpts(0, 0, 7)
+    st = ipt.lib().ipt_scene_build_ex(v.ctypes.data_as(ctypes.c_void_p), v.shape[0], None,
+                                      t.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p),
+                                      t.shape[0], sc["num_segments"], e.ctypes.data_as(ctypes.c_void_p), e.size,
+                                      ctypes.byref(bo), None, ctypes.byref(h))
+    assert st == 1 and not h.value
+    assert b"material_model" in ipt.lib().ipt_last_error()
+
+
+@pytest.mark.parametrize("mis", [0, 2, 3])
+def test_disney_render_and_grad_parity_cornell(cornell_disney, mis):
+    banner("Disney parity cornell mis=%d" % mis)
+    sc, g, o, dc = cornell_disney
+    kw = dict(seed=41, stream_tag=2, iteration=3, spp=4, max_depth=3, mis=mis)
+    gg, go = _tiered("disney cornell mis=%d" % mis, sc, g, o, dc, sc["params"], kw)
+    # every one of the 13 parameters of a visible segment has a live derivative
+    live = np.count_nonzero(go[:NM * sc["num_segments"]].reshape(-1, NM), axis=0)
+    assert (live > 0).all(), live
+
+
+@pytest.mark.parametrize("D,rr", [(7, 3), (7, 2)])
+def test_disney_grad_parity_cornell_rr(cornell_disney, D, rr):
+    """Russian roulette on the Disney throughput at the benchmark's depth."""
+    banner("Disney parity cornell D=%d rr=%d" % (D, rr))
+    sc, g, o, dc = cornell_disney
+    kw = dict(seed=43, stream_tag=2, iteration=5, spp=4, max_depth=D, rr_depth=rr, mis=2)
+    _tiered("disney cornell D=%d rr=%d" % (D, rr), sc, g, o, dc, sc["params"], kw)
+
+
+def test_disney_frozen_sampling_and_emission_profile(cornell_disney):
+    """Rendering parameters away from the sampling ones (the sampler, the
+    light-sampling MIS weights and the roulette stay at the sampling
+    parameters) with the cosine emission profile."""
+    sc, g, o, dc = cornell_disney
+    rng = np.random.default_rng(9)
+    p = sc["params"].copy()
+    n = NM * sc["num_segments"]
+    p[:n] = np.clip(p[:n] + rng.uniform(-0.2, 0.2, n), 0.0, 1.0).astype(np.float32)
+    kw = dict(seed=44, stream_tag=2, iteration=2, spp=4, max_depth=5, rr_depth=2, mis=2, emission_profile=1)
+    _tiered("disney cornell frozen", sc, g, o, dc, p, kw, sp=sc["params"])
+
+
+@pytest.mark.parametrize("D,rr", [(5, -1), (7, 3)])
+def test_disney_room_crop(D, rr):
+    banner("Disney room crop D=%d rr=%d" % (D, rr))
+    sc = scenes.disney(scenes.room(), seed=6)
+    g, o = both(sc)
+    dc = ipt.make_cameras(sc["cams"])
+    W, H = sc["cams"]["width"], sc["cams"]["height"]
+    rng = np.random.default_rng(4)
+    pix = np.sort(rng.choice(4 * W * H, size=1500, replace=False)).astype(np.int64)
+    kw = dict(seed=21, stream_tag=2, iteration=2, spp=16, max_depth=D, rr_depth=rr, mis=2)
+    _tiered("disney room D=%d rr=%d" % (D, rr), sc, g, o, dc, sc["params"], kw, pix=pix, min_tight=0.7,
+            min_tight_g=0.7)
