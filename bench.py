@@ -10,7 +10,7 @@ Prints ONE JSON line.  value = gradient paths per second of the whole step
 (B paths / step time); the breakdown gives colour paths/s and the
 fwd+adjoint-only gradient paths/s.  The roofline entry is for the dominant
 kernel, timed with HIP events inside the library on the stream it runs on;
-algorithmic bytes come from the kernels' own work counters (BVH nodes x 112 B read
+algorithmic bytes come from the kernels' own work counters (BVH nodes x 64 B read
 + triangles x 48 B + checkpoint traffic).  cpu_baseline times the FP64 oracle
 on a bounded pixel sample on this host's cores.
 """
@@ -36,9 +36,10 @@ HBM_PEAK_GBS = 8000.0
 VALU_WAVE_INST_PEAK = 256 * 4 * 2.4e9 / 4
 VALU_LANE_INST_PEAK = VALU_WAVE_INST_PEAK * 64
 TRI_B = 48
-# BVH node bytes read per visit: 4-wide nodes (128 B in memory) read seven
-# float4 rows (boxes and child references, 112 B); binary nodes 64 B
-NODE_READ_B = {128: 112, 64: 64}
+# BVH node bytes read per visit, by (children, bytes per node): 4-wide nodes
+# with quantized boxes read their four float4 rows (64 B), with float boxes
+# seven of their eight (112 B); binary nodes 64 B
+NODE_READ_B = {(4, 64): 64, (4, 128): 112, (2, 64): 64}
 # checkpoint traffic per path vertex: the gradient forward pass writes the hit
 # record, a and c (3 x 16 B); the backward sweep reads a and c back (32 B) and
 # writes the suffix radiance (16 B), in the forward pass when a guide collects
@@ -240,7 +241,7 @@ def main():
     log("step %.1f ms (wall %.1f ms): colour %.1f ms, grad fwd %.1f ms, replay %.1f ms" % (
         ms_step, 1e3 * wall / args.steps, ms_col, k_fwd["total_ms"] / args.steps, k_rep["total_ms"] / args.steps))
 
-    node_b = NODE_READ_B[info["node_bytes"]]
+    node_b = NODE_READ_B[(info["node_width"], info["node_bytes"])]
 
     def kbytes(k, extra_per_vertex):
         return k["nodes"] * node_b + k["tris"] * TRI_B + k["vertices"] * extra_per_vertex

@@ -126,10 +126,12 @@ typedef struct {
     uint64_t stack_overflows; /* traversals that ran out of stack */
     int32_t bvh_builder;      /* the ipt_bvh_builder that built the BVH */
     int32_t params_global;    /* 1: parameters in global memory (ipt_param_storage) */
-    int32_t node_bytes;       /* bytes per BVH node of the traversal (128: 4-wide, 64: binary);
-                                 num_nodes counts these nodes */
+    int32_t node_bytes;       /* bytes per BVH node of the traversal (64: 4-wide with quantized
+                                 child boxes, the default, or binary; 128: 4-wide with float
+                                 boxes); num_nodes counts these nodes */
     int32_t material_model;   /* the ipt_material_model of the scene */
     int32_t params_per_segment; /* M: 7 or 13 */
+    int32_t node_width;       /* children per BVH node of the traversal: 4 or 2 */
 } ipt_scene_info_t;
 
 /* Where the BVH is built.  Both builders apply the same rule (binned SAH,

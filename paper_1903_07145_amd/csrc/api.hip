@@ -85,6 +85,90 @@ struct ipt_scene_s {
 static int bits_i(float f) { int i; std::memcpy(&i, &f, sizeof i); return i; }
 static float bits_f(int i) { float f; std::memcpy(&f, &i, sizeof f); return f; }
 
+// Quantized 4-wide nodes (after Ylitie, Karras and Laine 2017, "Efficient
+// incoherent ray traversal on GPUs through compressed wide BVHs"): the
+// four child boxes as 8-bit grid coordinates relative to a per-node origin,
+// with a power-of-two cell size per axis.  Layout per node, 4 float4 = 64 B:
+//   row 0: origin x, y, z (float); biased exponents e_x, e_y, e_z (bytes 0-2)
+//   row 1: x lo, x hi, y lo, y hi of the four children (one byte per child)
+//   row 2: z lo, z hi, 0, 0
+//   row 3: the four child references (as the float layout)
+// A plane decodes to origin + q 2^e.  Every decoded box contains its child's
+// float box widened by delta = 2^-20 of the node's largest extent on every
+// side: that margin covers the rounding of the traversal's
+// fma(q, 2^e / d, (origin - o) / d) for ray origins within or near the node,
+// and the slab test's relative slack covers origins far from it.  An empty
+// slot (reference kNone) has q lo = 255, q hi = 0; the traversal skips it by
+// its reference.
+static void quantize_bvh4(std::vector<float4>& b4) {
+    const size_t n = b4.size() / 8;
+    std::vector<float4> q(4 * n);
+    for (size_t id = 0; id < n; ++id) {
+        const float4* o = &b4[8 * id];
+        const float lo[3][4] = {{o[0].x, o[0].y, o[0].z, o[0].w}, {o[2].x, o[2].y, o[2].z, o[2].w},
+                                {o[4].x, o[4].y, o[4].z, o[4].w}};
+        const float hi[3][4] = {{o[1].x, o[1].y, o[1].z, o[1].w}, {o[3].x, o[3].y, o[3].z, o[3].w},
+                                {o[5].x, o[5].y, o[5].z, o[5].w}};
+        const int ref[4] = {bits_i(o[6].x), bits_i(o[6].y), bits_i(o[6].z), bits_i(o[6].w)};
+        bool valid[4];
+        double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int j = 0; j < 4; ++j) {
+            valid[j] = ref[j] != kNone;
+            if (!valid[j]) continue;
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = std::min(mn[a], (double)lo[a][j]);
+                mx[a] = std::max(mx[a], (double)hi[a][j]);
+            }
+        }
+        float org[3] = {0, 0, 0};
+        int ex[3] = {0, 0, 0};
+        uint8_t ql[3][4], qh[3][4];
+        double ext = 0.0;
+        for (int a = 0; a < 3; ++a)
+            if (mx[a] >= mn[a]) ext = std::max(ext, mx[a] - mn[a]);
+        // a node of points (extent 0) still gets a positive margin
+        const double delta = std::ldexp(std::max(ext, 1e-30), -20);
+        for (int a = 0; a < 3; ++a) {
+            for (int j = 0; j < 4; ++j) { ql[a][j] = 255; qh[a][j] = 0; }
+            if (!(mx[a] >= mn[a])) continue;   // no valid child
+            // origin: a float at or below the lowest plane minus the margin
+            float og = (float)(mn[a] - delta);
+            while ((double)og > mn[a] - delta) og = std::nextafter(og, -INFINITY);
+            org[a] = og;
+            const double span = mx[a] + delta - (double)og;
+            int e = (int)std::ceil(std::log2(span / 255.0));
+            e = std::max(e, -126);
+            for (;; ++e) {
+                const double cell = std::ldexp(1.0, e);
+                bool ok = true;
+                for (int j = 0; j < 4 && ok; ++j) {
+                    if (!valid[j]) continue;
+                    double l = std::floor((lo[a][j] - delta - (double)og) / cell);
+                    double h = std::ceil((hi[a][j] + delta - (double)og) / cell);
+                    // the decoded planes (exact: og + q 2^e in double) enclose the widened box
+                    while (l > 0 && (double)og + l * cell > lo[a][j] - delta) l -= 1.0;
+                    while ((double)og + h * cell < hi[a][j] + delta) h += 1.0;
+                    if (l < 0 || h > 255) { ok = false; break; }
+                    ql[a][j] = (uint8_t)l;
+                    qh[a][j] = (uint8_t)h;
+                }
+                if (ok) break;
+            }
+            ex[a] = e;
+        }
+        auto pack = [](const uint8_t b[4]) {
+            return bits_f((int)((uint32_t)b[0] | (uint32_t)b[1] << 8 | (uint32_t)b[2] << 16 | (uint32_t)b[3] << 24));
+        };
+        const uint32_t ew = (uint32_t)(ex[0] + 127) | (uint32_t)(ex[1] + 127) << 8 | (uint32_t)(ex[2] + 127) << 16;
+        float4* d = &q[4 * id];
+        d[0] = make_float4(org[0], org[1], org[2], bits_f((int)ew));
+        d[1] = make_float4(pack(ql[0]), pack(qh[0]), pack(ql[1]), pack(qh[1]));
+        d[2] = make_float4(pack(ql[2]), pack(qh[2]), 0.0f, 0.0f);
+        d[3] = o[6];
+    }
+    b4.swap(q);
+}
+
 static hipError_t collapse_bvh4(float4*& d_nodes, int64_t& nnodes, hipStream_t st) {
     std::vector<float4> b2(4 * (size_t)nnodes);
     hipError_t e = hipMemcpyAsync(b2.data(), d_nodes, sizeof(float4) * b2.size(), hipMemcpyDeviceToHost, st);
@@ -146,6 +230,7 @@ static hipError_t collapse_bvh4(float4*& d_nodes, int64_t& nnodes, hipStream_t s
                            bits_f(ref[3]));
         o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
+    if (kNodeQuant) quantize_bvh4(b4);
     float4* d4 = nullptr;
     e = hipMalloc((void**)&d4, sizeof(float4) * b4.size());
     if (e == hipSuccess) e = hipMemcpyAsync(d4, b4.data(), sizeof(float4) * b4.size(), hipMemcpyHostToDevice, st);
@@ -443,7 +528,8 @@ extern "C" ipt_status ipt_scene_info(ipt_scene_t s, ipt_scene_info_t* out) {
     out->stack_overflows = c.overflow;
     out->bvh_builder = s->bvh_builder;
     out->params_global = s->params_global;
-    out->node_bytes = kNodeWidth == 4 ? 128 : 64;
+    out->node_bytes = 16 * kNodeRows;
+    out->node_width = kNodeWidth;
     out->material_model = s->mat;
     out->params_per_segment = s->nm;
     return IPT_OK;

@@ -18,6 +18,14 @@ constexpr int kNone = 0x7FFFFFFF; // empty child slot
 #define IPT_NODE_WIDTH 4
 #endif
 constexpr int kNodeWidth = IPT_NODE_WIDTH;
+// 4-wide nodes with quantized child boxes (64 B, four float4 loads per
+// visit) instead of float boxes (128 B, seven loads)
+#ifndef IPT_NODE_QUANT
+#define IPT_NODE_QUANT 1
+#endif
+constexpr int kNodeQuant = (IPT_NODE_WIDTH == 4) ? IPT_NODE_QUANT : 0;
+// float4 rows per node in the node array
+constexpr int kNodeRows = kNodeWidth == 4 ? (kNodeQuant ? 4 : 8) : 4;
 constexpr int kMaxDepth = 16;     // max scattering vertices per path
 constexpr int kMaxLdsLights = 1024;
 constexpr int kMaxLdsParams = 4096;  // larger parameter vectors stay in global memory
@@ -35,7 +43,7 @@ constexpr uint32_t kCkDrop = 1u << 30;   // (vertex 1) path dropped: non-finite
 
 // Device view of a built scene.
 struct SceneDev {
-    const float4* nodes;   // 4 x float4 per node: child boxes + (child0, child1)
+    const float4* nodes;   // kNodeRows float4 per node (layouts in api.hip)
     const float4* tris;    // 3 x float4 per leaf-ordered triangle:
                            //   (v0, orig id), (v1, segment), (v2, light index or -1)
     const float4* nrm;     // 3 x float4 per leaf-ordered triangle, or NULL

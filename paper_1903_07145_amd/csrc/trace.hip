@@ -216,6 +216,7 @@ __device__ __forceinline__ void trav_init(Trav& tv, float tmax, Stack& st, Work&
 #define IPT_NODE_BREAK 4
 #endif
 
+
 // Advances the lanes' traversals; returns true for a lane whose traversal
 // has finished (its hit is then in tv.best).  With exit_lanes > 0 the call
 // also returns, after at least one node phase and one leaf phase (so every
@@ -227,6 +228,8 @@ __device__ bool traverse_resume(const SceneDev& sc, const Ray& r, float tmin, fl
                                 bool any, Stack& st, Work& wk, Trav& tv, int exit_lanes) {
     int cur = tv.cur, pend = tv.pend, best_orig = tv.best_orig;
     Hit best = tv.best;
+    // direction signs: which byte row of a quantized node is an axis's near plane
+    const bool negx = r.inv.x < 0.0f, negy = r.inv.y < 0.0f, negz = r.inv.z < 0.0f;
     auto next_from_stack = [&]() -> int { return (st.sp > 0 && !st.overflow) ? st.pop() : kTravDone; };
     while (true) {
         // ---- node phase ----
@@ -246,17 +249,54 @@ __device__ bool traverse_resume(const SceneDev& sc, const Ray& r, float tmin, fl
             if (inner && kNodeWidth == 4) {
                 // four children: the nearest hit next, the others pushed far to near
                 wk.nodes++;
-                const float4* n = sc.nodes + 8 * (size_t)cur;
-                const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], cr = n[6];
                 const float inf = __builtin_inff();
-                // an empty slot's box is +inf on every axis, so its entry
-                // distance is +inf and it sorts last without a check
                 float t[4];
-                int c[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
-                t[0] = box_entry(r, v3(lx.x, ly.x, lz.x), v3(hx.x, hy.x, hz.x), tmin, best.t, sc.tmin);
-                t[1] = box_entry(r, v3(lx.y, ly.y, lz.y), v3(hx.y, hy.y, hz.y), tmin, best.t, sc.tmin);
-                t[2] = box_entry(r, v3(lx.z, ly.z, lz.z), v3(hx.z, hy.z, hz.z), tmin, best.t, sc.tmin);
-                t[3] = box_entry(r, v3(lx.w, ly.w, lz.w), v3(hx.w, hy.w, hz.w), tmin, best.t, sc.tmin);
+                int c[4];
+                if constexpr (kNodeQuant) {
+                    // quantized child boxes: a plane is origin + q 2^e, so its
+                    // slab distance is fma(q, 2^e / d, (origin - o) / d); the
+                    // direction's sign picks each axis's near and far byte rows
+                    const float4* n = sc.nodes + 4 * (size_t)cur;
+                    const float4 h = n[0], qa = n[1], qb = n[2], cr = n[3];
+                    c[0] = __float_as_int(cr.x); c[1] = __float_as_int(cr.y);
+                    c[2] = __float_as_int(cr.z); c[3] = __float_as_int(cr.w);
+                    const uint32_t ew = __float_as_uint(h.w);
+                    const V3 A = v3(ldexpf(r.inv.x, (int)(ew & 0xffu) - 127),
+                                    ldexpf(r.inv.y, (int)((ew >> 8) & 0xffu) - 127),
+                                    ldexpf(r.inv.z, (int)((ew >> 16) & 0xffu) - 127));
+                    const V3 B = v3((h.x - r.o.x) * r.inv.x, (h.y - r.o.y) * r.inv.y, (h.z - r.o.z) * r.inv.z);
+                    const uint32_t xl = __float_as_uint(qa.x), xh = __float_as_uint(qa.y);
+                    const uint32_t yl = __float_as_uint(qa.z), yh = __float_as_uint(qa.w);
+                    const uint32_t zl = __float_as_uint(qb.x), zh = __float_as_uint(qb.y);
+                    const uint32_t xn = negx ? xh : xl, xf = negx ? xl : xh;
+                    const uint32_t yn = negy ? yh : yl, yf = negy ? yl : yh;
+                    const uint32_t zn = negz ? zh : zl, zf = negz ? zl : zh;
+                    const float tmx = best.t + sc.tmin;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int sh = 8 * i;
+                        const float nx = fmaf((float)((xn >> sh) & 0xffu), A.x, B.x);
+                        const float fx = fmaf((float)((xf >> sh) & 0xffu), A.x, B.x);
+                        const float ny = fmaf((float)((yn >> sh) & 0xffu), A.y, B.y);
+                        const float fy = fmaf((float)((yf >> sh) & 0xffu), A.y, B.y);
+                        const float nz = fmaf((float)((zn >> sh) & 0xffu), A.z, B.z);
+                        const float fz = fmaf((float)((zf >> sh) & 0xffu), A.z, B.z);
+                        const float tn = fmaxf(fmaxf(nx, ny), fmaxf(nz, tmin));
+                        const float tf = fminf(fminf(fx, fy), fminf(fz, tmx));
+                        t[i] = (tn <= tf * 1.0000005f && c[i] != kNone) ? tn : inf;
+                    }
+                } else {
+                    // float child boxes; an empty slot's box is +inf on every
+                    // axis, so its entry distance is +inf and it sorts last
+                    const float4* n = sc.nodes + 8 * (size_t)cur;
+                    const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], cr = n[6];
+                    c[0] = __float_as_int(cr.x); c[1] = __float_as_int(cr.y);
+                    c[2] = __float_as_int(cr.z); c[3] = __float_as_int(cr.w);
+                    t[0] = box_entry(r, v3(lx.x, ly.x, lz.x), v3(hx.x, hy.x, hz.x), tmin, best.t, sc.tmin);
+                    t[1] = box_entry(r, v3(lx.y, ly.y, lz.y), v3(hx.y, hy.y, hz.y), tmin, best.t, sc.tmin);
+                    t[2] = box_entry(r, v3(lx.z, ly.z, lz.z), v3(hx.z, hy.z, hz.z), tmin, best.t, sc.tmin);
+                    t[3] = box_entry(r, v3(lx.w, ly.w, lz.w), v3(hx.w, hy.w, hz.w), tmin, best.t, sc.tmin);
+                }
                 // sorting network on (t, child) with selects, no branches;
                 // equal distances keep their slot order
                 auto cas = [&](int i, int j) {

@@ -64,7 +64,7 @@ class SceneInfo(ctypes.Structure):
                 ("nonfinite_paths", ctypes.c_uint64), ("stack_overflows", ctypes.c_uint64),
                 ("bvh_builder", ctypes.c_int32), ("params_global", ctypes.c_int32),
                 ("node_bytes", ctypes.c_int32), ("material_model", ctypes.c_int32),
-                ("params_per_segment", ctypes.c_int32)]
+                ("params_per_segment", ctypes.c_int32), ("node_width", ctypes.c_int32)]
 
 
 class BuildOpts(ctypes.Structure):

@@ -83,7 +83,7 @@ def test_gpu_build_matches_host_builder_and_brute_force(case):
         # of at most four: at least L = ceil(nt / 4) leaves, so at least L - 1
         # binary nodes, or ceil((L - 1) / 3) nodes of four children
         leaves = (nt + 3) // 4
-        lower = (leaves - 1 + 2) // 3 if ig["node_bytes"] == 128 else leaves - 1
+        lower = (leaves - 1 + 2) // 3 if ig["node_width"] == 4 else leaves - 1
         assert ig["num_nodes"] >= lower
         assert ig["sah_cost"] <= 1.5 * ih["sah_cost"]
     n = 1024 if nt > 100000 else (4096 if nt > 10000 else 16384)
