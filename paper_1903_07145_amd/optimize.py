@@ -13,6 +13,7 @@ Every step runs in the HIP library; this module only sequences the calls.
 """
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -240,7 +241,8 @@ def cell_area_for(sc, cells):
 def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guide_steps=10, guide_lr=2e-3,
              guide_batch=16384, record_stride=None, target_rmse=1e-2, stop_at_target=False, target=None,
              g=None, log=None, spp=None, lr=None, lr_schedule="const", masks=None, lr_final=None, log_every=10,
-             fixed=None, beta2=0.999, guide_cells=0, guide_every=1, p_init=None, mis=2):
+             fixed=None, beta2=0.999, guide_cells=0, guide_every=1, p_init=None, mis=2, state=None,
+             stop_after=None, want_state=False):
     """Runs the optimisation; returns a dict with the RMSE/loss history and timings.
 
     The time to target is taken on the RMSE over masks[0] (identifiable
@@ -251,7 +253,16 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
     the path kernels sample the cached proposal (about that many cells per
     side, refilled after every training call) instead of evaluating the
     network at every vertex; guide_every: training (and refill) every that
-    many iterations."""
+    many iterations.
+
+    The headline is the RMSE over every trainable parameter; the time to
+    target is recorded for it (time_to_target_all) and for masks[0]
+    (time_to_target).  state (a previous call's result["state"]) resumes a
+    run: parameters, Adam moments, iteration, elapsed time, history and,
+    with a guide, its weights and training records (its own Adam moments
+    restart).  stop_after ends this call after that many iterations, so a run
+    longer than one process can be split; the learning-rate schedule spans
+    all `iters`."""
     cfg = sc["render"]
     iters = iters or cfg["iters"]
     spp = spp or cfg["spp"]
@@ -292,10 +303,24 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
     g.workspace(dc, ipt.render_opts(spp=spp, max_depth=D, rr_depth=rr, guide=gd, guide_mix=guide_mix if gd else 0.0,
                                     guide_cached=cached))
     hist = dict(it=[], t=[], rmse=[], rmse_all=[], rmse_id=[], loss=[], guide_loss=[], groups=[])
+    it0, t_prev, t_hit, t_hit_all = 0, 0.0, None, None
+    if state is not None:
+        params.copy_(torch.as_tensor(state["params"], device="cuda"))
+        m.copy_(torch.as_tensor(state["m"], device="cuda"))
+        v.copy_(torch.as_tensor(state["v"], device="cuda"))
+        it0, t_prev = int(state["it"]), float(state["t"])
+        hist = state["hist"]
+        t_hit, t_hit_all = state.get("t_hit"), state.get("t_hit_all")
+        if gd is not None and state.get("guide_w") is not None:
+            gd.set_weights(state["guide_w"])
+            if state.get("guide_rec") is not None and len(state["guide_rec"]):
+                gd.add_records(state["guide_rec"])
+            if cached:
+                gd.cache_build(gd.cell_area)
+    it_end = iters if stop_after is None else min(iters, it0 + stop_after)
     torch.cuda.synchronize()
-    t0 = time.time()
-    t_hit = None
-    for it in range(iters):
+    t0 = time.time() - t_prev
+    for it in range(it0, it_end):
         mix = guide_mix if (gd is not None and it >= warmup) else 0.0
         kw = dict(seed=1000 * seed + 11, iteration=it, spp=spp, max_depth=D, rr_depth=rr, mis=mis)
         co = ipt.render_opts(stream_tag=TAG_A, guide=gd if mix > 0 else None, guide_mix=mix, guide_cached=cached, **kw)
@@ -321,23 +346,50 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         hist["guide_loss"].append(gl)
         hist["groups"].append(group_rmse(params, p_true, scale, tr, sc["num_segments"])
                               if (it % log_every == 0 or it == iters - 1) else None)
+        if t_hit_all is None and hist["rmse_all"][-1] <= target_rmse:
+            t_hit_all = t
         if t_hit is None and r <= target_rmse:
             t_hit = t
             if stop_at_target:
                 break
         if log and (it % log_every == 0 or it == iters - 1):
             gr = " ".join("%s %.3f" % kv for kv in hist["groups"][-1].items())
-            log("it %4d  t %7.2fs  loss %.5f  rmse %.4f (all %.4f, identifiable %.4f; %s)%s" % (
-                it, t, hist["loss"][-1], r, hist["rmse_all"][-1], hist["rmse_id"][-1], gr,
+            log("it %4d  t %7.2fs  loss %.5f  rmse all %.4f (headline subset %.4f, identifiable %.4f; %s)%s" % (
+                it, t, hist["loss"][-1], hist["rmse_all"][-1], r, hist["rmse_id"][-1], gr,
                 "" if gl is None else "  guide loss %.4f" % gl))
     err = ((params - p_true) / scale).cpu().numpy()
     worst = [(int(i), float(err[i])) for i in np.argsort(-np.abs(err * masks[0]))[:8]]
     optimize.last = dict(params=params, guide=gd, target=target, g=g, dc=dc, fixed=fixed,
                          init=torch.as_tensor(p0, device="cuda"))
-    return dict(history=hist, time_to_target=t_hit, final_rmse=hist["rmse"][-1],
+    out_state = None
+    if want_state:
+        out_state = dict(params=params.cpu().numpy(), m=m.cpu().numpy(), v=v.cpu().numpy(), it=it_end,
+                         t=hist["t"][-1] if hist["t"] else 0.0, hist=hist, t_hit=t_hit, t_hit_all=t_hit_all,
+                         guide_w=None if gd is None else gd.get_weights(),
+                         guide_rec=None if gd is None else gd.read_records().cpu().numpy())
+    return dict(history=hist, time_to_target=t_hit, time_to_target_all=t_hit_all, final_rmse=hist["rmse"][-1],
                 final_rmse_all=hist["rmse_all"][-1], final_rmse_id=hist["rmse_id"][-1], seconds=hist["t"][-1],
                 iters=len(hist["it"]), guide=guide, seed=seed, n_head=int(masks[0].sum()),
-                n_id=int(masks[1].sum()), worst=worst)
+                n_id=int(masks[1].sum()), worst=worst, done=it_end >= iters, state=out_state)
+
+
+def save_state(path, st):
+    """A run's state for resuming: arrays in path.npz, the rest in path.json."""
+    arrays = {k: np.asarray(st[k]) for k in ("params", "m", "v", "guide_w", "guide_rec") if st.get(k) is not None}
+    np.savez(path + ".npz", **arrays)
+    meta = {k: st[k] for k in ("it", "t", "hist", "t_hit", "t_hit_all")}
+    with open(path + ".json", "w") as f:
+        json.dump(meta, f)
+
+
+def load_state(path):
+    if not (os.path.exists(path + ".npz") and os.path.exists(path + ".json")):
+        return None
+    with np.load(path + ".npz") as z:
+        st = {k: z[k] for k in z.files}
+    with open(path + ".json") as f:
+        st.update(json.load(f))
+    return st
 
 
 def paper_setting_masks(sc, cov, sigma=None, max_sigma=2.5e-3):
@@ -854,6 +906,10 @@ def main(argv=None):
     ap.add_argument("--log-every", type=int, default=10)
     ap.add_argument("--lr-schedule", default="const", choices=["const", "cos"])
     ap.add_argument("--out", default=None, help="JSON lines file for the histories")
+    ap.add_argument("--state-dir", default=None,
+                    help="resume each seed's run from its state file there, if present, and save it after this call")
+    ap.add_argument("--stop-after", type=int, default=None,
+                    help="iterations in this call (the schedule still spans --iters); with --state-dir")
     ap.add_argument("--paper-setting", action="store_true",
                     help="the paper's setting: every segment emissive, zero init, batches of --batch pixels at "
                          "--spp paths each, L1 loss, L1 emission regulariser --lam, Adam lr 5e-3")
@@ -966,11 +1022,27 @@ def main(argv=None):
             sc["trainable"].sum(), (fixed & tr).sum()))
     for seed in a.seeds:
         log("workload %s seed %d guide %s" % (a.workload, seed, a.guide))
+        st_path = None
+        state = None
+        if a.state_dir:
+            os.makedirs(a.state_dir, exist_ok=True)
+            st_path = os.path.join(a.state_dir, "state_%s_seed%d_%s" % (a.workload, seed, "guide" if a.guide else "brdf"))
+            state = load_state(st_path)
+            if state is not None:
+                log("resuming from %s at iteration %d (%.1f s elapsed)" % (st_path, state["it"], state["t"]))
         res = optimize(sc, iters=a.iters, seed=seed, guide=a.guide, guide_mix=a.guide_mix, warmup=a.warmup,
                        guide_steps=a.guide_steps, target_rmse=a.target_rmse, target=target, g=g, log=log,
                        lr=a.lr, lr_schedule=a.lr_schedule, masks=masks, spp=a.spp, lr_final=a.lr_final,
                        log_every=a.log_every, fixed=fixed, beta2=a.beta2, guide_cells=a.guide_cells,
-                       guide_every=a.guide_every, mis=a.mis)
+                       guide_every=a.guide_every, mis=a.mis, state=state, stop_after=a.stop_after,
+                       want_state=st_path is not None)
+        if st_path is not None:
+            save_state(st_path, res["state"])
+        res.pop("state")
+        if not res["done"]:
+            log("seed %d: stopped at iteration %d of %d (%.1f s); state saved to %s" % (
+                seed, res["iters"], a.iters or sc["render"]["iters"], res["seconds"], st_path))
+            continue
         if a.variance and a.guide:
             L = optimize.last
             vs = gradient_variance(g, dc, sc, L["params"], target, L["guide"], tr & ~fixed, K=a.variance,
@@ -990,9 +1062,10 @@ def main(argv=None):
         if a.out:
             with open(a.out, "a") as f:
                 f.write(line + "\n")
-        log("seed %d: final rmse %.4f (all %.4f, identifiable %.4f) after %d iters in %.1fs; time to %.0e: %s; "
-            "worst %s" % (seed, res["final_rmse"], res["final_rmse_all"], res["final_rmse_id"], res["iters"],
-                          res["seconds"], a.target_rmse, res["time_to_target"], res["worst"]))
+        log("seed %d: final rmse over all trainable parameters %.4f (headline subset %.4f, identifiable %.4f) "
+            "after %d iters in %.1fs; time to %.0e: all %s, subset %s; worst %s" % (
+                seed, res["final_rmse_all"], res["final_rmse"], res["final_rmse_id"], res["iters"], res["seconds"],
+                a.target_rmse, res["time_to_target_all"], res["time_to_target"], res["worst"]))
 
 
 if __name__ == "__main__":
