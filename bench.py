@@ -57,7 +57,7 @@ def log(msg):
 # sources the path kernels are built from: HBM traffic measured by counters
 # is reported only while these still hash to the profiled version
 KERNEL_SOURCES = ["paper_1903_07145_amd/csrc/" + f for f in
-                  ("trace.hip", "ipt_math.h", "ipt_internal.h", "guide_dev.h", "api.hip")] + \
+                  ("trace.hip", "ipt_math.h", "ipt_internal.h", "guide_dev.h", "disney.h", "api.hip")] + \
                  ["paper_1903_07145_amd/build.py"]
 
 
@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--guide-cells", type=int, default=0,
                     help="with --guide: sample the cached proposal (about this many cells per side, refilled "
                          "after each training call) instead of evaluating the network at every path vertex")
+    ap.add_argument("--material", default="ggx", choices=["ggx", "disney"],
+                    help="material model of every segment: Lambert + GGX (7 parameters, the workloads' own) or the "
+                         "Disney model (13 parameters, seeded values; the same geometry, lights and views)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain device copy of 256 MiB three times (the kernel whose FETCH_SIZE and "
                          "WRITE_SIZE counters scale those of the path kernels to bytes) and exit")
@@ -152,6 +155,8 @@ def main():
     torch.cuda.set_device(0)
     t0 = time.time()
     sc = scenes.WORKLOADS[args.workload]()
+    if args.material == "disney":
+        sc = scenes.disney(sc, seed=11)
     cfg = sc["render"]
     log("scene %s: %d triangles, %d segments, %d emitters (%.1fs)" % (
         sc["name"], sc["tris"].shape[0], sc["num_segments"], len(sc["emitter_seg"]), time.time() - t0))
@@ -330,7 +335,8 @@ def cpu_baseline(sc, cfg, params, target, budget_s):
     from oracle import oracle
 
     t0 = time.time()
-    o = oracle.Scene(sc["verts"], sc["tris"], sc["tri_seg"], sc["num_segments"], sc["emitter_seg"], sc["normals"])
+    o = oracle.Scene(sc["verts"], sc["tris"], sc["tri_seg"], sc["num_segments"], sc["emitter_seg"], sc["normals"],
+                     material=sc.get("material", 0))
     log("oracle BVH %.1fs" % (time.time() - t0))
     V, W, H = sc["cams"]["cam_to_world"].shape[0], sc["cams"]["width"], sc["cams"]["height"]
     npix = V * W * H

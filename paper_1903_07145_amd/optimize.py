@@ -168,9 +168,13 @@ def identifiable_masks(sc, cov, min_pixels=100, min_ks=0.05, min_emitter_pixels=
     all_id: kd_e plus specular reflectance of the seen segments, and their
     roughness where the true specular reflectance (mean RGB) is >= min_ks.
     With sigma (target_precision), a parameter also needs sigma <= max_sigma
-    (a quarter of the 1e-2 RMSE target): the target must be able to pin it."""
+    (a quarter of the 1e-2 RMSE target): the target must be able to pin it.
+    Disney material (13 per segment): the base colour plays the albedo's
+    part, and all_id takes every parameter of a seen segment (their
+    identifiability is left to sigma)."""
     S = sc["num_segments"]
     P = sc["params"].size
+    nm = params_per_segment(sc)
     tr = sc["trainable"].astype(bool)
     emit = set(int(x) for x in sc["emitter_seg"])
     kd_e = np.zeros(P, bool)
@@ -178,14 +182,17 @@ def identifiable_masks(sc, cov, min_pixels=100, min_ks=0.05, min_emitter_pixels=
     for s in range(S):
         if cov[s] < min_pixels or s in emit:
             continue
-        kd_e[7 * s:7 * s + 3] = True
+        kd_e[nm * s:nm * s + 3] = True
+        if nm != 7:
+            all_id[nm * s:nm * s + nm] = True
+            continue
         all_id[7 * s:7 * s + 6] = True
         if sc["params"][7 * s + 3:7 * s + 6].mean() >= min_ks:
             all_id[7 * s + 6] = True
     for k, s in enumerate(sc["emitter_seg"]):
         if cov[s] >= min_emitter_pixels:
-            kd_e[7 * S + 3 * k:7 * S + 3 * k + 3] = True
-            all_id[7 * S + 3 * k:7 * S + 3 * k + 3] = True
+            kd_e[nm * S + 3 * k:nm * S + 3 * k + 3] = True
+            all_id[nm * S + 3 * k:nm * S + 3 * k + 3] = True
     if sigma is not None:
         ok = sigma <= max_sigma
         kd_e &= ok
@@ -201,14 +208,15 @@ def unrecoverable_mask(sc, cov, min_pixels=100, min_emitter_pixels=16):
     indirect light on a seen one), so the optimisation holds them at their true
     values."""
     S = sc["num_segments"]
+    nm = params_per_segment(sc)
     fixed = np.zeros(sc["params"].size, bool)
     emit = set(int(x) for x in sc["emitter_seg"])
     for s in range(S):
         if cov[s] < min_pixels or s in emit:
-            fixed[7 * s:7 * s + 7] = True
+            fixed[nm * s:nm * s + nm] = True
     for k, s in enumerate(sc["emitter_seg"]):
         if cov[s] < min_emitter_pixels:
-            fixed[7 * S + 3 * k:7 * S + 3 * k + 3] = True
+            fixed[nm * S + 3 * k:nm * S + 3 * k + 3] = True
     return fixed
 
 
@@ -219,13 +227,22 @@ def param_rmse(params, p_true, scale, trainable):
     return float(torch.sqrt(torch.mean(d * d)))
 
 
-def group_rmse(params, p_true, scale, trainable, S):
-    """RMSE per parameter group (diffuse, specular, roughness, emission)."""
+def params_per_segment(sc):
+    return 13 if sc.get("material", 0) == 1 else 7
+
+
+def group_rmse(params, p_true, scale, trainable, S, nm=7):
+    """RMSE per parameter group: diffuse, specular, roughness, emission
+    (Lambert + GGX); base colour, the ten other parameters, emission
+    (Disney, nm = 13)."""
     d = ((params - p_true) / scale).cpu().numpy()
     t = trainable.cpu().numpy().astype(bool)
     idx = np.arange(d.size)
-    groups = dict(kd=(idx < 7 * S) & (idx % 7 < 3), ks=(idx < 7 * S) & (idx % 7 >= 3) & (idx % 7 < 6),
-                  alpha=(idx < 7 * S) & (idx % 7 == 6), e=idx >= 7 * S)
+    if nm == 7:
+        groups = dict(kd=(idx < 7 * S) & (idx % 7 < 3), ks=(idx < 7 * S) & (idx % 7 >= 3) & (idx % 7 < 6),
+                      alpha=(idx < 7 * S) & (idx % 7 == 6), e=idx >= 7 * S)
+    else:
+        groups = dict(base=(idx < nm * S) & (idx % nm < 3), other=(idx < nm * S) & (idx % nm >= 3), e=idx >= nm * S)
     return {k: float(np.sqrt(np.mean(d[m & t] ** 2))) for k, m in groups.items() if (m & t).any()}
 
 
@@ -259,8 +276,8 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
     target is recorded for it (time_to_target_all) and for masks[0]
     (time_to_target).  state (a previous call's result["state"]) resumes a
     run: parameters, Adam moments, iteration, elapsed time, history and,
-    with a guide, its weights and training records (its own Adam moments
-    restart).  stop_after ends this call after that many iterations, so a run
+    with a guide, its weights and up to STATE_RECORDS of its training records
+    (its own Adam moments restart).  stop_after ends this call after that many iterations, so a run
     longer than one process can be split; the learning-rate schedule spans
     all `iters`."""
     cfg = sc["render"]
@@ -344,7 +361,7 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         hist["rmse_id"].append(param_rmse(params, p_true, scale, m_id))
         hist["loss"].append(float(loss.cpu()))
         hist["guide_loss"].append(gl)
-        hist["groups"].append(group_rmse(params, p_true, scale, tr, sc["num_segments"])
+        hist["groups"].append(group_rmse(params, p_true, scale, tr, sc["num_segments"], params_per_segment(sc))
                               if (it % log_every == 0 or it == iters - 1) else None)
         if t_hit_all is None and hist["rmse_all"][-1] <= target_rmse:
             t_hit_all = t
@@ -366,11 +383,16 @@ def optimize(sc, iters=None, seed=7, guide=False, guide_mix=0.5, warmup=50, guid
         out_state = dict(params=params.cpu().numpy(), m=m.cpu().numpy(), v=v.cpu().numpy(), it=it_end,
                          t=hist["t"][-1] if hist["t"] else 0.0, hist=hist, t_hit=t_hit, t_hit_all=t_hit_all,
                          guide_w=None if gd is None else gd.get_weights(),
-                         guide_rec=None if gd is None else gd.read_records().cpu().numpy())
+                         guide_rec=None if gd is None else gd.read_records(
+                             min(gd.records(), gd.capacity, STATE_RECORDS)).cpu().numpy())
     return dict(history=hist, time_to_target=t_hit, time_to_target_all=t_hit_all, final_rmse=hist["rmse"][-1],
                 final_rmse_all=hist["rmse_all"][-1], final_rmse_id=hist["rmse_id"][-1], seconds=hist["t"][-1],
                 iters=len(hist["it"]), guide=guide, seed=seed, n_head=int(masks[0].sum()),
                 n_id=int(masks[1].sum()), worst=worst, done=it_end >= iters, state=out_state)
+
+
+# training records kept in a saved state (a part of the ring: 16 MiB)
+STATE_RECORDS = 1 << 18
 
 
 def save_state(path, st):
@@ -906,6 +928,8 @@ def main(argv=None):
     ap.add_argument("--log-every", type=int, default=10)
     ap.add_argument("--lr-schedule", default="const", choices=["const", "cos"])
     ap.add_argument("--out", default=None, help="JSON lines file for the histories")
+    ap.add_argument("--material", default="ggx", choices=["ggx", "disney"],
+                    help="material model: the workload's Lambert + GGX, or the Disney model (seeded parameters)")
     ap.add_argument("--state-dir", default=None,
                     help="resume each seed's run from its state file there, if present, and save it after this call")
     ap.add_argument("--stop-after", type=int, default=None,
@@ -933,6 +957,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     sc = scenes.WORKLOADS[a.workload]()
+    if a.material == "disney":
+        sc = scenes.disney(sc, seed=11)
     if a.fine_texture:
         log = lambda s: print("[optimize] " + s, file=sys.stderr, flush=True)
         for seed in a.seeds:
