@@ -17,9 +17,9 @@
 // 0.25.  The tangent x is the hit triangle's first edge projected onto the
 // plane of the shading normal, y = n x x.
 //
-// The evaluator is written once as a template over the scalar type: float
-// for values, Dual (a value and one directional derivative, forward-mode
-// differentiation) for the derivative with respect to one parameter.
+// disney_value evaluates f; disney_grad is its adjoint, written out by hand
+// (reverse mode): for a channel weight w it returns w . d f / d p_j for all
+// 13 parameters in one pass that costs about two evaluations.
 #pragma once
 #include "ipt_math.h"
 
@@ -30,43 +30,6 @@ enum DisneyParam {
     kDsSubsurface = 3, kDsMetallic, kDsSpecular, kDsSpecTint, kDsRoughness, kDsAniso, kDsSheen, kDsSheenTint,
     kDsClearcoat, kDsCcGloss
 };
-
-struct Dual {
-    float v, d;
-    Dual() = default;
-    __device__ __forceinline__ Dual(float v_, float d_ = 0.0f) : v(v_), d(d_) {}
-};
-__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual{a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ Dual operator+(Dual a, float b) { return Dual{a.v + b, a.d}; }
-__device__ __forceinline__ Dual operator+(float a, Dual b) { return Dual{a + b.v, b.d}; }
-__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual{a.v - b.v, a.d - b.d}; }
-__device__ __forceinline__ Dual operator-(Dual a, float b) { return Dual{a.v - b, a.d}; }
-__device__ __forceinline__ Dual operator-(float a, Dual b) { return Dual{a - b.v, -b.d}; }
-__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual{a.v * b.v, a.d * b.v + a.v * b.d}; }
-__device__ __forceinline__ Dual operator*(Dual a, float b) { return Dual{a.v * b, a.d * b}; }
-__device__ __forceinline__ Dual operator*(float a, Dual b) { return Dual{a * b.v, a * b.d}; }
-__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
-    const float q = a.v / b.v;
-    return Dual{q, (a.d - q * b.d) / b.v};
-}
-__device__ __forceinline__ Dual operator/(Dual a, float b) { return Dual{a.v / b, a.d / b}; }
-__device__ __forceinline__ Dual operator/(float a, Dual b) {
-    const float q = a / b.v;
-    return Dual{q, -q * b.d / b.v};
-}
-__device__ __forceinline__ Dual dsqrt(Dual a) {
-    const float s = sqrtf(a.v);
-    return Dual{s, a.d * 0.5f / s};
-}
-__device__ __forceinline__ float dsqrt(float a) { return sqrtf(a); }
-__device__ __forceinline__ Dual dlog(Dual a) { return Dual{logf(a.v), a.d / a.v}; }
-__device__ __forceinline__ float dlog(float a) { return logf(a); }
-__device__ __forceinline__ float val(float a) { return a; }
-__device__ __forceinline__ float val(Dual a) { return a.v; }
-template <class T>
-__device__ __forceinline__ T max_lo(T a, float lo) {
-    return val(a) < lo ? T(lo) : a;
-}
 
 struct DMat {
     float p[kDisneyParams];
@@ -123,50 +86,48 @@ __device__ __forceinline__ float schlick_w(float c) {
     float m2 = m * m;
     return m2 * m2 * m;
 }
-template <class T>
-__device__ __forceinline__ T g1_aniso(float c, float wx, float wy, T ax, T ay) {
-    T tx = wx * ax, ty = wy * ay;
-    return 2.0f * c / (c + dsqrt(c * c + tx * tx + ty * ty));
+__device__ __forceinline__ float g1_aniso(float c, float wx, float wy, float ax, float ay) {
+    const float tx = wx * ax, ty = wy * ay;
+    return 2.0f * c / (c + sqrtf(c * c + tx * tx + ty * ty));
 }
 __device__ __forceinline__ float g1_iso(float c, float a) { return 2.0f * c / (c + sqrtf(a * a + (1.0f - a * a) * c * c)); }
 
-// f (3 channels) for parameters p of scalar type T.
-template <class T>
-__device__ __forceinline__ void disney_f(const T* p, const DGeom& g, T f[3]) {
-    T lum = 0.3f * p[0] + 0.6f * p[1] + 0.1f * p[2];
-    const bool haslum = val(lum) > 0.0f;
+// f (3 channels) for parameters p.
+__device__ __forceinline__ void disney_f(const float* p, const DGeom& g, float f[3]) {
+    const float lum = 0.3f * p[0] + 0.6f * p[1] + 0.1f * p[2];
+    const bool haslum = lum > 0.0f;
     const float FL = schlick_w(g.ci), FV = schlick_w(g.co), FH = schlick_w(g.cd);
     const float cd2 = g.cd * g.cd;
-    T r = p[kDsRoughness];
-    T fd90 = 0.5f + 2.0f * cd2 * r;
-    T fd = (1.0f + (fd90 - 1.0f) * FL) * (1.0f + (fd90 - 1.0f) * FV);
-    T f90 = cd2 * r;
-    T fss = 1.25f * ((1.0f + (f90 - 1.0f) * FL) * (1.0f + (f90 - 1.0f) * FV) * (1.0f / (g.ci + g.co) - 0.5f) + 0.5f);
-    T diff = (fd + (fss - fd) * p[kDsSubsurface]) * kInvPi;
-    T k = dsqrt(1.0f - 0.9f * p[kDsAniso]);
-    T r2 = r * r;
-    T ax = max_lo(r2 / k, 1e-3f), ay = max_lo(r2 * k, 1e-3f);
-    T tx = g.hx / ax, ty = g.hy / ay;
-    T dd = tx * tx + ty * ty + g.ch * g.ch;
-    T Ds = 1.0f / (kPi * ax * ay * dd * dd);
-    T Gs = g1_aniso(g.ci, g.ix, g.iy, ax, ay) * g1_aniso(g.co, g.ox, g.oy, ax, ay);
-    T ac = 0.1f + (0.001f - 0.1f) * p[kDsCcGloss];
-    T a2 = ac * ac;
-    T Dc = (a2 - 1.0f) / (kPi * dlog(a2) * (g.ch * g.ch * a2 + g.sh2));
+    const float r = p[kDsRoughness];
+    const float fd90 = 0.5f + 2.0f * cd2 * r;
+    const float fd = (1.0f + (fd90 - 1.0f) * FL) * (1.0f + (fd90 - 1.0f) * FV);
+    const float f90 = cd2 * r;
+    const float fss = 1.25f * ((1.0f + (f90 - 1.0f) * FL) * (1.0f + (f90 - 1.0f) * FV) * (1.0f / (g.ci + g.co) - 0.5f) + 0.5f);
+    const float diff = (fd + (fss - fd) * p[kDsSubsurface]) * kInvPi;
+    const float k = sqrtf(1.0f - 0.9f * p[kDsAniso]);
+    const float r2 = r * r;
+    const float ax = fmaxf(r2 / k, 1e-3f), ay = fmaxf(r2 * k, 1e-3f);
+    const float tx = g.hx / ax, ty = g.hy / ay;
+    const float dd = tx * tx + ty * ty + g.ch * g.ch;
+    const float Ds = 1.0f / (kPi * ax * ay * dd * dd);
+    const float Gs = g1_aniso(g.ci, g.ix, g.iy, ax, ay) * g1_aniso(g.co, g.ox, g.oy, ax, ay);
+    const float ac = 0.1f + (0.001f - 0.1f) * p[kDsCcGloss];
+    const float a2 = ac * ac;
+    const float Dc = (a2 - 1.0f) / (kPi * logf(a2) * (g.ch * g.ch * a2 + g.sh2));
     const float Fc = 0.04f + 0.96f * FH;
     const float Gc = g1_iso(g.ci, 0.25f) * g1_iso(g.co, 0.25f);
     const float rden = 1.0f / (4.0f * g.ci * g.co);
-    T spec = Ds * Gs * rden;
-    T coat = (0.25f * Fc * Gc * rden) * p[kDsClearcoat] * Dc;
-    T om = 1.0f - p[kDsMetallic];
+    const float spec = Ds * Gs * rden;
+    const float coat = (0.25f * Fc * Gc * rden) * p[kDsClearcoat] * Dc;
+    const float om = 1.0f - p[kDsMetallic];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        T tint = haslum ? p[c] / lum : T(1.0f);
-        T ts = 1.0f + (tint - 1.0f) * p[kDsSpecTint];
-        T s0 = 0.08f * p[kDsSpecular] * ts;
-        T cs0 = s0 + (p[c] - s0) * p[kDsMetallic];
-        T Fs = cs0 + (1.0f - cs0) * FH;
-        T sheen = FH * p[kDsSheen] * (1.0f + (tint - 1.0f) * p[kDsSheenTint]);
+        const float tint = haslum ? p[c] / lum : 1.0f;
+        const float ts = 1.0f + (tint - 1.0f) * p[kDsSpecTint];
+        const float s0 = 0.08f * p[kDsSpecular] * ts;
+        const float cs0 = s0 + (p[c] - s0) * p[kDsMetallic];
+        const float Fs = cs0 + (1.0f - cs0) * FH;
+        const float sheen = FH * p[kDsSheen] * (1.0f + (tint - 1.0f) * p[kDsSheenTint]);
         f[c] = (diff * p[c] + sheen) * om + Fs * spec + coat;
     }
 }
@@ -174,18 +135,131 @@ __device__ __forceinline__ void disney_f(const T* p, const DGeom& g, T f[3]) {
 __device__ __forceinline__ V3 disney_value(const DMat& m, const DGeom& g) {
     if (!g.ok) return v3(0.0f, 0.0f, 0.0f);
     float f[3];
-    disney_f<float>(m.p, g, f);
+    disney_f(m.p, g, f);
     return v3(f[0], f[1], f[2]);
 }
 
-// d f / d p_j (3 channels) by forward-mode differentiation.
-__device__ __forceinline__ V3 disney_dparam(const DMat& m, const DGeom& g, int j) {
-    Dual p[kDisneyParams];
+// Adjoint of f: G[j] = sum_c w_c d f_c / d p_j for all 13 parameters, the
+// forward quantities of disney_f followed by one reverse sweep.  A clamped
+// quantity (alpha at 1e-3, tint at lum = 0) passes no derivative.
+__device__ __forceinline__ void disney_grad(const DMat& m, const DGeom& g, V3 wv, float G[kDisneyParams]) {
 #pragma unroll
-    for (int i = 0; i < kDisneyParams; ++i) p[i] = Dual{m.p[i], i == j ? 1.0f : 0.0f};
-    Dual f[3];
-    disney_f<Dual>(p, g, f);
-    return v3(f[0].d, f[1].d, f[2].d);
+    for (int j = 0; j < kDisneyParams; ++j) G[j] = 0.0f;
+    if (!g.ok) return;
+    const float* p = m.p;
+    const float w[3] = {wv.x, wv.y, wv.z};
+    // ---- forward ----
+    const float lum = 0.3f * p[0] + 0.6f * p[1] + 0.1f * p[2];
+    const bool haslum = lum > 0.0f;
+    const float FL = schlick_w(g.ci), FV = schlick_w(g.co), FH = schlick_w(g.cd);
+    const float cd2 = g.cd * g.cd;
+    const float r = p[kDsRoughness];
+    const float fd90 = 0.5f + 2.0f * cd2 * r;
+    const float AL = 1.0f + (fd90 - 1.0f) * FL, AV = 1.0f + (fd90 - 1.0f) * FV;
+    const float fd = AL * AV;
+    const float f90 = cd2 * r;
+    const float BL = 1.0f + (f90 - 1.0f) * FL, BV = 1.0f + (f90 - 1.0f) * FV;
+    const float Q = 1.0f / (g.ci + g.co) - 0.5f;
+    const float fss = 1.25f * (BL * BV * Q + 0.5f);
+    const float sub = p[kDsSubsurface];
+    const float diff = (fd + (fss - fd) * sub) * kInvPi;
+    const float k = sqrtf(1.0f - 0.9f * p[kDsAniso]);
+    const float r2 = r * r;
+    const float axr = r2 / k, ayr = r2 * k;
+    const bool axl = axr >= 1e-3f, ayl = ayr >= 1e-3f;   // unclamped: derivatives pass
+    const float ax = axl ? axr : 1e-3f, ay = ayl ? ayr : 1e-3f;
+    const float tx = g.hx / ax, ty = g.hy / ay;
+    const float dd = tx * tx + ty * ty + g.ch * g.ch;
+    const float Ds = 1.0f / (kPi * ax * ay * dd * dd);
+    const float qix = g.ix * ax, qiy = g.iy * ay, qox = g.ox * ax, qoy = g.oy * ay;
+    const float si = sqrtf(g.ci * g.ci + qix * qix + qiy * qiy), so = sqrtf(g.co * g.co + qox * qox + qoy * qoy);
+    const float G1i = 2.0f * g.ci / (g.ci + si), G1o = 2.0f * g.co / (g.co + so);
+    const float Gs = G1i * G1o;
+    const float ac = 0.1f + (0.001f - 0.1f) * p[kDsCcGloss];
+    const float a2 = ac * ac;
+    const float L = logf(a2);
+    const float E = g.ch * g.ch * a2 + g.sh2;
+    const float Dc = (a2 - 1.0f) / (kPi * L * E);
+    const float Fc = 0.04f + 0.96f * FH;
+    const float Gc = g1_iso(g.ci, 0.25f) * g1_iso(g.co, 0.25f);
+    const float rden = 1.0f / (4.0f * g.ci * g.co);
+    const float spec = Ds * Gs * rden;
+    const float kc = 0.25f * Fc * Gc * rden;
+    const float met = p[kDsMetallic], om = 1.0f - met;
+    const float spc = p[kDsSpecular], stint = p[kDsSpecTint], sh = p[kDsSheen], shtint = p[kDsSheenTint];
+    // ---- reverse ----
+    float dp[3] = {0.0f, 0.0f, 0.0f};
+    float dspec = 0.0f, ddiff = 0.0f, dlum = 0.0f;
+    float gmet = 0.0f, gspc = 0.0f, gstint = 0.0f, gsh = 0.0f, gshtint = 0.0f;
+    const float W = w[0] + w[1] + w[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float pc = p[c];
+        const float tint = haslum ? pc / lum : 1.0f;
+        const float ts = 1.0f + (tint - 1.0f) * stint;
+        const float s0 = 0.08f * spc * ts;
+        const float cs0 = s0 + (pc - s0) * met;
+        const float Fs = cs0 + (1.0f - cs0) * FH;
+        const float shf = 1.0f + (tint - 1.0f) * shtint;
+        const float sheen = FH * sh * shf;
+        // f_c = (diff p_c + sheen_c) om + Fs_c spec + coat
+        const float X = w[c] * om;
+        gmet -= w[c] * (diff * pc + sheen);
+        ddiff += X * pc;
+        dp[c] += X * diff;
+        dspec += w[c] * Fs;
+        const float dcs0 = w[c] * spec * (1.0f - FH);
+        const float ds0 = dcs0 * om;
+        dp[c] += dcs0 * met;
+        gmet += dcs0 * (pc - s0);
+        gspc += ds0 * 0.08f * ts;
+        const float dts = ds0 * 0.08f * spc;
+        gstint += dts * (tint - 1.0f);
+        float dtint = dts * stint;
+        gsh += X * FH * shf;
+        gshtint += X * FH * sh * (tint - 1.0f);
+        dtint += X * FH * sh * shtint;
+        if (haslum) {
+            dp[c] += dtint / lum;
+            dlum -= dtint * tint / lum;
+        }
+    }
+    dp[0] += 0.3f * dlum;
+    dp[1] += 0.6f * dlum;
+    dp[2] += 0.1f * dlum;
+    // coat = kc p_cc Dc(ac), ac = 0.1 + (0.001 - 0.1) p_gloss
+    const float gcc = W * kc * Dc;
+    const float dDc = W * kc * p[kDsClearcoat];
+    const float dDc_da2 = Dc * (1.0f / (a2 - 1.0f) - 1.0f / (a2 * L) - g.ch * g.ch / E);
+    const float ggloss = dDc * dDc_da2 * 2.0f * ac * (0.001f - 0.1f);
+    // spec = Ds Gs rden
+    const float dDs = dspec * Gs * rden, dGs = dspec * Ds * rden;
+    const float dax = dDs * Ds * (4.0f * tx * tx / dd - 1.0f) / ax
+                    - dGs * (G1o * G1i * g.ix * g.ix * ax / (si * (g.ci + si)) + G1i * G1o * g.ox * g.ox * ax / (so * (g.co + so)));
+    const float day = dDs * Ds * (4.0f * ty * ty / dd - 1.0f) / ay
+                    - dGs * (G1o * G1i * g.iy * g.iy * ay / (si * (g.ci + si)) + G1i * G1o * g.oy * g.oy * ay / (so * (g.co + so)));
+    float dr2 = 0.0f, dk = 0.0f;
+    if (axl) { dr2 += dax / k; dk -= dax * axr / k; }
+    if (ayl) { dr2 += day * k; dk += day * r2; }
+    // diff = (fd (1 - sub) + fss sub) / pi
+    const float gsub = ddiff * (fss - fd) * kInvPi;
+    const float dfd = ddiff * (1.0f - sub) * kInvPi, dfss = ddiff * sub * kInvPi;
+    const float dfd90 = dfd * (AV * FL + AL * FV);
+    const float df90 = dfss * 1.25f * Q * (BV * FL + BL * FV);
+    const float dr = dr2 * 2.0f * r + dfd90 * 2.0f * cd2 + df90 * cd2;
+    G[0] = dp[0];
+    G[1] = dp[1];
+    G[2] = dp[2];
+    G[kDsSubsurface] = gsub;
+    G[kDsMetallic] = gmet;
+    G[kDsSpecular] = gspc;
+    G[kDsSpecTint] = gstint;
+    G[kDsRoughness] = dr;
+    G[kDsAniso] = dk * (-0.45f / k);
+    G[kDsSheen] = gsh;
+    G[kDsSheenTint] = gshtint;
+    G[kDsClearcoat] = gcc;
+    G[kDsCcGloss] = ggloss;
 }
 
 // Lobe probabilities of the sampler: diffuse (1 - metallic) lum(base),

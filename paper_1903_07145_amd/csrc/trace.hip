@@ -536,7 +536,8 @@ template <> struct MatNP<DMat> { static constexpr int value = kDisneyParams; };
 
 // Adjoint of f at one vertex: w . d f / d theta_seg added to the block's
 // gradient, for a channel weight w (the Lambert + GGX terms use the factors
-// spec, dspec kept from the evaluation).
+// spec, dspec kept from the evaluation; the Disney model its hand-written
+// reverse sweep).
 __device__ __forceinline__ void mat_grad(double* grad, int mb, const Mat& m, const Shade&, V3, V3 w, float spec,
                                          float dspec) {
     lds_add(grad, mb + 0, w.x * kInvPi);
@@ -549,9 +550,10 @@ __device__ __forceinline__ void mat_grad(double* grad, int mb, const Mat& m, con
 }
 __device__ __forceinline__ void mat_grad(double* grad, int mb, const DMat& m, const Shade& g, V3 wi, V3 w, float,
                                          float) {
-    const DGeom dg = disney_geom(g.ns, g.tx, g.ty, g.wo, wi);
-#pragma unroll 1
-    for (int j = 0; j < kDisneyParams; ++j) lds_add(grad, mb + j, dot(w, disney_dparam(m, dg, j)));
+    float G[kDisneyParams];
+    disney_grad(m, disney_geom(g.ns, g.tx, g.ty, g.wo, wi), w, G);
+#pragma unroll
+    for (int j = 0; j < kDisneyParams; ++j) lds_add(grad, mb + j, G[j]);
 }
 
 // MIS weight of an emitter hit at vertex k reached by a direction sampled
@@ -811,6 +813,12 @@ enum Phase { kNeedPixel = 0, kClosest = 1, kShadow = 2, kExit = 3 };
 #ifndef IPT_WAVES_PER_EU_GUIDED
 #define IPT_WAVES_PER_EU_GUIDED 2
 #endif
+// The Disney kernels hold two 13-float materials (rendering and sampling
+// parameters) at each vertex: 3 waves per SIMD spill less (apartment with
+// the Disney material: step 183.0 ms at 3 waves, 187.0 at 4, 215.2 at 2).
+#ifndef IPT_WAVES_PER_EU_DISNEY
+#define IPT_WAVES_PER_EU_DISNEY 3
+#endif
 
 // A traversal call returns once no more than this many lanes of the wave
 // are still traversing (0: every traversal runs to completion in one call).
@@ -822,7 +830,8 @@ enum Phase { kNeedPixel = 0, kClosest = 1, kShadow = 2, kExit = 3 };
 // proposal; MAT: the material model (MatSel)
 template <int MODE, int GUIDE, int PG, int MAT>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU_GUIDED : IPT_WAVES_PER_EU,
+__attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU_GUIDED
+                                   : (MAT == 1 ? IPT_WAVES_PER_EU_DISNEY : IPT_WAVES_PER_EU),
                                    8))) void path_sm_kernel(
     PathArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
