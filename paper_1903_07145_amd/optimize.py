@@ -396,18 +396,20 @@ STATE_RECORDS = 1 << 18
 
 
 def save_state(path, st):
-    """A run's state for resuming: arrays in path.npz, the rest in path.json."""
+    """A run's state for resuming: arrays in path.arrays (numpy's zip
+    format), the rest in path.json."""
     arrays = {k: np.asarray(st[k]) for k in ("params", "m", "v", "guide_w", "guide_rec") if st.get(k) is not None}
-    np.savez(path + ".npz", **arrays)
+    with open(path + ".arrays", "wb") as f:
+        np.savez(f, **arrays)
     meta = {k: st[k] for k in ("it", "t", "hist", "t_hit", "t_hit_all")}
     with open(path + ".json", "w") as f:
         json.dump(meta, f)
 
 
 def load_state(path):
-    if not (os.path.exists(path + ".npz") and os.path.exists(path + ".json")):
+    if not (os.path.exists(path + ".arrays") and os.path.exists(path + ".json")):
         return None
-    with np.load(path + ".npz") as z:
+    with np.load(path + ".arrays") as z:
         st = {k: z[k] for k in z.files}
     with open(path + ".json") as f:
         st.update(json.load(f))
