@@ -1048,14 +1048,15 @@ def main(argv=None):
         "identifiable %d of %d trainable, %d held at their true values" % (
             (cov >= 100).sum(), cov.size, cov[sc["emitter_seg"]].tolist(), masks[0].sum(), masks[1].sum(),
             sc["trainable"].sum(), (fixed & tr).sum()))
-    # parameters the target cannot pin even to 0.25 (normalised) stay near
-    # their random start: their share of the all-parameter RMSE is a floor
+    # parameters the target cannot pin even to 0.25 (normalised) move little
+    # from their random start: their initial errors' share of the
+    # all-parameter RMSE is about where that RMSE levels off
     undetermined = fr & ~(sigma <= 0.25)
     for seed in a.seeds:
         log("workload %s seed %d guide %s" % (a.workload, seed, a.guide))
         e0 = (scenes.init_theta(sc, cfg["init"], seed=seed).astype(np.float64) - sc["params"]) / sc["scale"]
-        log("all-parameter RMSE floor from the %d free parameters the target does not determine (sigma > 0.25): "
-            "%.4f (their initial errors over the %d trainable parameters)" % (
+        log("initial-error share of the %d free parameters the target does not determine (sigma > 0.25): "
+            "RMSE %.4f over the %d trainable parameters (they move little)" % (
                 undetermined.sum(), np.sqrt(np.sum(e0[undetermined] ** 2) / max(1, tr.sum())), tr.sum()))
         st_path = None
         state = None
