@@ -1198,7 +1198,9 @@ __attribute__((amdgpu_waves_per_eu((GUIDE == 1 || GUIDE == 2) ? IPT_WAVES_PER_EU
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint replay: one lane per pixel, tiles pulled by blocks.
+// Adjoint replay.  replay_kernel (one lane per pixel, tiles pulled by blocks)
+// serves the check mode that re-traces paths; replay_sm_kernel below reads
+// the vertex checkpoints.
 // ---------------------------------------------------------------------------
 template <int MAT>
 __device__ void replay_path(const PathArgs& a, const Lds& lds, Stack& st, Work& wk, uint64_t pid, int64_t q, int s,
@@ -1365,6 +1367,186 @@ __global__ __launch_bounds__(kBlock) void replay_kernel(PathArgs a) {
     for (int i = tid; i < a.P; i += kBlock) out[i] = lds.grad[i];
 }
 
+// Adjoint replay from vertex checkpoints as a per-lane state machine (the
+// Disney material's replay): each pass of the loop replays one vertex of
+// every lane's current path, and a lane whose path has ended takes the next
+// one (the next sample of its unit, else a new unit, one atomic per wave)
+// instead of idling until the longest path of the wave is done.  Same
+// arithmetic, in the same order per path, as replay_path.
+template <int PG, int MAT>
+__global__ __launch_bounds__(kBlock) void replay_sm_kernel(PathArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    Lds lds;
+    carve_lds<PG>(a, kReplay, smem, lds);
+    const SceneDev& sc = a.sc;
+    const float* cdf = lds.lights_in_lds ? lds.cdf : a.cdf;
+    const int4* lights = lds.lights_in_lds ? lds.lights : sc.lights;
+    const int64_t npix_img = (int64_t)a.V * a.W * a.H;
+    const int64_t nunits = a.pix_count * a.nchunk;
+    const size_t plane = (size_t)a.pix_count;
+    const float inv_spp = 1.0f / (float)a.spp;
+    Work wk{0u, 0u, 0u, 0u, 0u};
+    uint32_t npaths = 0;
+    // unit of work: samples [s, s_end) of work pixel q
+    bool have_unit = false, exhausted = false;
+    int64_t q = 0, wi = 0, pix = 0;
+    int view = 0, px = 0, py = 0, s = 0, s_end = 0;
+    V3 wpix = v3(0.0f, 0.0f, 0.0f);
+    // path being replayed
+    bool in_path = false;
+    uint64_t pid = 0;
+    int k = 0;
+    V3 T = wpix, Ts = wpix, d = wpix;
+    float prev_pdf = 0.0f;
+
+    while (true) {
+        // ---- lanes without a path: next sample of the unit, else a new unit ----
+        while (true) {
+            if (!in_path && have_unit) {
+                while (s < s_end && !in_path) {
+                    pid = (uint64_t)pix * (uint64_t)a.spp + (uint64_t)s;
+                    const size_t pidx = (size_t)wi * a.spp + s;
+                    if (a.mask && a.mask[pidx] == 0) { ++s; continue; }
+                    ++npaths;
+                    if ((uint32_t)a.ck_hit[(size_t)s * plane + q].x & kCkDrop) { ++s; continue; }
+                    if (!a.guided) {
+                        const int klast = min(max(__float_as_int(a.ck_c[(size_t)s * plane + q].w), 0), a.D + 1);
+                        const V3 R = suffix_sweep(a, klast, s, q);
+                        if (!finite3(R)) {
+                            atomicAdd(&a.err->nonfinite, 1ull);
+                            ++s;
+                            continue;
+                        }
+                    }
+                    float j0 = 0.5f, j1 = 0.5f;
+                    if (a.jitter) jitter_uniforms(a.rng, pid, j0, j1);
+                    V3 o;
+                    camera_ray(a, view, (float)px + j0, (float)py + j1, o, d);
+                    T = v3(1.0f, 1.0f, 1.0f);
+                    Ts = T;
+                    prev_pdf = 0.0f;
+                    k = 1;
+                    in_path = true;
+                }
+                if (!in_path) have_unit = false;
+            }
+            const uint64_t need = __ballot(!in_path && !have_unit && !exhausted);
+            if (!need) break;
+            const int first = __ffsll((unsigned long long)need) - 1;
+            unsigned base = 0;
+            if (lane == first) base = atomicAdd(a.work, (unsigned)__popcll(need));
+            base = __shfl(base, first);
+            if (!in_path && !have_unit && !exhausted) {
+                const int64_t unit = (int64_t)base + (int64_t)__popcll(need & ((1ull << lane) - 1ull));
+                if (unit >= nunits) {
+                    exhausted = true;
+                } else {
+                    wk.units++;
+                    const int c = (int)(unit / a.pix_count);
+                    q = unit - (int64_t)c * a.pix_count;
+                    s = c * a.spc;
+                    s_end = min(a.spp, s + a.spc);
+                    wi = a.pix_begin + q;
+                    pix = a.pixel_list ? a.pixel_list[wi] : wi;
+                    if (pix >= 0 && pix < npix_img) {
+                        view = (int)(pix / ((int64_t)a.W * a.H));
+                        const int64_t rem = pix - (int64_t)view * a.W * a.H;
+                        py = (int)(rem / a.W);
+                        px = (int)(rem - (int64_t)py * a.W);
+                        wpix = v3(a.w[3 * wi] * inv_spp, a.w[3 * wi + 1] * inv_spp, a.w[3 * wi + 2] * inv_spp);
+                        have_unit = true;
+                    }
+                }
+            }
+        }
+        if (__ballot(in_path) == 0) break;   // every lane is exhausted
+        if (!in_path) continue;
+
+        // ---- vertex k of the lane's path ----
+        bool done = true;
+        const size_t ck = ((size_t)(k - 1) * a.spp + s) * plane + q;
+        const int4 rec = a.ck_hit[ck];
+        const uint32_t flags = (uint32_t)rec.x;
+        Hit hit;
+        hit.tri = (int)(flags & kCkTriMask) - 1;
+        hit.u = __int_as_float(rec.y);
+        hit.v = __int_as_float(rec.z);
+        hit.t = __int_as_float(rec.w);
+        if (hit.tri >= 0) {
+            wk.vertices++;
+            const float4 rr = a.ck_c[ck];
+            const V3 Rn = v3(rr.x, rr.y, rr.z);   // R_{k+1}
+            Shade g;
+            make_shade(sc, lds, hit, d, g);
+            const V3 wT = wpix * T;
+            // emission at this vertex: d/de = w_hit * profile
+            if (g.em >= 0 && g.cos_emit > 0.0f) {
+                const float w = emit_weight(a, cdf, lights, g, k, prev_pdf);
+                if (w > 0.0f) {
+                    const float prof = a.profile ? g.cos_emit : 1.0f;
+                    const int eb = MatSel<MAT>::NP * sc.S + 3 * g.em;
+                    lds_add(lds.grad, eb + 0, wT.x * prof * w);
+                    lds_add(lds.grad, eb + 1, wT.y * prof * w);
+                    lds_add(lds.grad, eb + 2, wT.z * prof * w);
+                }
+            }
+            if (k != a.D + 1 && dot(g.ns, g.wo) > 0.0f) {
+                mat_frame<MAT>(g);
+                const typename MatSel<MAT>::M m = mat_load<MAT>(lds.params, g.seg);
+                const typename MatSel<MAT>::M ms = a.frozen ? mat_load<MAT>(lds.sparams, g.seg) : m;
+                float u[8];
+                vertex_uniforms(a.rng, pid, k, u);
+                const float4 dk = a.guided ? a.ck_d[ck] : make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+                if (a.mis != 0 && sc.nlt > 0) {
+                    const NeeS n = nee_setup(sc, cdf, lights, g, u);
+                    if (n.shoot && (flags & kCkVis) != 0) {
+                        // with a guide the forward pass stored the combined density of wl
+                        const NeeC nc = nee_contrib(a, lds, cdf, g, m, ms, n, dk.w);
+                        if (nc.valid) {
+                            constexpr int NP = MatSel<MAT>::NP;
+                            const int mb = NP * g.seg, eb = NP * sc.S + 3 * n.lk;
+                            mat_grad(lds.grad, mb, m, g, n.wl, wT * nc.e * nc.g, nc.spec, nc.dspec);
+                            const V3 wf = wT * nc.f * nc.g;
+                            lds_add(lds.grad, eb + 0, wf.x);
+                            lds_add(lds.grad, eb + 1, wf.y);
+                            lds_add(lds.grad, eb + 2, wf.z);
+                        }
+                    }
+                }
+                if (flags & kCkCont) {
+                    ContS cs;
+                    if (a.guided) {
+                        // the sampled direction and its density come from the checkpoint
+                        cs = cont_eval(a, g, m, ms, v3(dk.x, dk.y, dk.z), a.ck_a[ck].w, 0, u, k, Ts);
+                    } else {
+                        bool ug;
+                        cs = cont_sample<0>(a, g, m, ms, u, k, Ts, nullptr, ug);
+                    }
+                    const float rq = 1.0f / cs.qrr;
+                    mat_grad(lds.grad, MatSel<MAT>::NP * g.seg, m, g, cs.wi, wT * Rn * (cs.g * rq), cs.spec, cs.dspec);
+                    T = T * (cs.av * rq);
+                    Ts = Ts * cs.ts * rq;
+                    prev_pdf = cs.pdf;
+                    d = cs.wi;
+                    ++k;
+                    done = false;
+                }
+            }
+        }
+        if (done) {
+            in_path = false;
+            ++s;
+        }
+    }
+    flush_stats(a, kReplay, wk, npaths);
+    if constexpr (PG) return;   // the atomics went straight to the accumulator copies
+    __syncthreads();
+    double* out = a.grad_part + (size_t)blockIdx.x * a.P;
+    for (int i = tid; i < a.P; i += kBlock) out[i] = lds.grad[i];
+}
+
 // ---------------------------------------------------------------------------
 // Guide training records from the gradient pass: after the forward pass and
 // its backward sweep, vertex k of a path holds its hit, the sampled
@@ -1471,6 +1653,7 @@ template <int MAT>
 static int blocks_per_cu_mat(int mode, size_t lds, int gk, int pg) {
     if (mode == kColor) return pg ? path_occ<kColor, 1, MAT>(gk, lds) : path_occ<kColor, 0, MAT>(gk, lds);
     if (mode == kGradFwd) return pg ? path_occ<kGradFwd, 1, MAT>(gk, lds) : path_occ<kGradFwd, 0, MAT>(gk, lds);
+    if constexpr (MAT == 1) return pg ? occ(replay_sm_kernel<1, MAT>, lds) : occ(replay_sm_kernel<0, MAT>, lds);
     return pg ? occ(replay_kernel<1, MAT>, lds) : occ(replay_kernel<0, MAT>, lds);
 }
 
@@ -1487,10 +1670,19 @@ static void launch_paths_mat(int mode, const PathArgs& a, int grid, size_t lds, 
     } else if (mode == kGradFwd) {
         if (pg) launch_path_kind<kGradFwd, 1, MAT>(a.guide_kind, a, grid, lds, st);
         else launch_path_kind<kGradFwd, 0, MAT>(a.guide_kind, a, grid, lds, st);
-    } else if (pg) {
-        hipLaunchKernelGGL((replay_kernel<1, MAT>), dim3(grid), dim3(kBlock), lds, st, a);
-    } else {
-        hipLaunchKernelGGL((replay_kernel<0, MAT>), dim3(grid), dim3(kBlock), lds, st, a);
+    } else if (a.replay_traverse || MAT == 0) {
+        // the lanes of a wave replay the same sample and vertex index of
+        // consecutive pixels, so their checkpoint reads coalesce: for the
+        // Lambert + GGX adjoint, whose work per vertex is light, that beats
+        // refilling idle lanes (apartment replay 12.9 ms here, 26.7 ms with
+        // replay_sm_kernel); the Disney adjoint, ten times the arithmetic per
+        // vertex, gains from the refill (27.1 -> 23.3 ms).  Also the check
+        // mode that re-traces each path instead of reading its checkpoints.
+        if (pg) hipLaunchKernelGGL((replay_kernel<1, MAT>), dim3(grid), dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((replay_kernel<0, MAT>), dim3(grid), dim3(kBlock), lds, st, a);
+    } else if constexpr (MAT == 1) {
+        if (pg) hipLaunchKernelGGL((replay_sm_kernel<1, MAT>), dim3(grid), dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((replay_sm_kernel<0, MAT>), dim3(grid), dim3(kBlock), lds, st, a);
     }
 }
 
