@@ -37,8 +37,10 @@ __device__ __forceinline__ bool finite3(V3 a) {
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32 x 32 -> 64-bit multiply per word gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -101,9 +103,11 @@ __device__ __forceinline__ Ray make_ray(V3 o, V3 d) {
     r.Sx = __fdiv_rn(comp(d, kx), dz);
     r.Sy = __fdiv_rn(comp(d, ky), dz);
     r.Sz = __fdiv_rn(1.0f, dz);
-    r.inv = v3(1.0f / (fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x)),
-               1.0f / (fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y)),
-               1.0f / (fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z)));
+    // the hardware reciprocal (1 ulp): the slab distances only cull boxes,
+    // and their relative slack covers it
+    r.inv = v3(__builtin_amdgcn_rcpf(fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x)),
+               __builtin_amdgcn_rcpf(fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y)),
+               __builtin_amdgcn_rcpf(fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z)));
     return r;
 }
 
