@@ -98,8 +98,12 @@ static float bits_f(int i) { float f; std::memcpy(&f, &i, sizeof f); return f; }
 // side: that margin covers the rounding of the traversal's
 // fma(q, 2^e / d, (origin - o) / d) for ray origins within or near the node,
 // and the slab test's relative slack covers origins far from it.  An empty
-// slot (reference kNone) has q lo = 255, q hi = 0; the traversal skips it by
-// its reference.
+// slot has q lo = 255, q hi = 0 (a box inside out, which the slab test
+// rejects unless the ray starts some 10^6 node extents away) and, as its
+// reference, the leaf code of the one-triangle leaf holding triangle 0
+// (~0): should the slack ever admit the slot, the traversal tests a real
+// triangle once more, which changes no hit, instead of following an
+// invalid reference.  The traversal then needs no reference check.
 static void quantize_bvh4(std::vector<float4>& b4) {
     const size_t n = b4.size() / 8;
     std::vector<float4> q(4 * n);
@@ -164,7 +168,9 @@ static void quantize_bvh4(std::vector<float4>& b4) {
         d[0] = make_float4(org[0], org[1], org[2], bits_f((int)ew));
         d[1] = make_float4(pack(ql[0]), pack(qh[0]), pack(ql[1]), pack(qh[1]));
         d[2] = make_float4(pack(ql[2]), pack(qh[2]), 0.0f, 0.0f);
-        d[3] = o[6];
+        int rq[4];
+        for (int j = 0; j < 4; ++j) rq[j] = valid[j] ? ref[j] : ~0;
+        d[3] = make_float4(bits_f(rq[0]), bits_f(rq[1]), bits_f(rq[2]), bits_f(rq[3]));
     }
     b4.swap(q);
 }

@@ -260,6 +260,9 @@ __device__ bool traverse_resume(const SceneDev& sc, const Ray& r, float tmin, fl
                     const float4 h = n[0], qa = n[1], qb = n[2], cr = n[3];
                     c[0] = __float_as_int(cr.x); c[1] = __float_as_int(cr.y);
                     c[2] = __float_as_int(cr.z); c[3] = __float_as_int(cr.w);
+                    // the references are needed only after the sort; tie them
+                    // to this point so their load issues with the box rows
+                    __asm__ volatile("" :: "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
                     const uint32_t ew = __float_as_uint(h.w);
                     const V3 A = v3(ldexpf(r.inv.x, (int)(ew & 0xffu) - 127),
                                     ldexpf(r.inv.y, (int)((ew >> 8) & 0xffu) - 127),
@@ -283,7 +286,7 @@ __device__ bool traverse_resume(const SceneDev& sc, const Ray& r, float tmin, fl
                         const float fz = fmaf((float)((zf >> sh) & 0xffu), A.z, B.z);
                         const float tn = fmaxf(fmaxf(nx, ny), fmaxf(nz, tmin));
                         const float tf = fminf(fminf(fx, fy), fminf(fz, tmx));
-                        t[i] = (tn <= tf * 1.0000005f && c[i] != kNone) ? tn : inf;
+                        t[i] = tn <= tf * 1.0000005f ? tn : inf;
                     }
                 } else {
                     // float child boxes; an empty slot's box is +inf on every
