@@ -54,10 +54,12 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-# sources the path kernels are built from: HBM traffic measured by counters
-# is reported only while these still hash to the profiled version
+# sources the path kernels and the tree they traverse are built from: the
+# counters (VALU work, HBM traffic) are reported only while these still hash
+# to the profiled version
 KERNEL_SOURCES = ["paper_1903_07145_amd/csrc/" + f for f in
-                  ("trace.hip", "ipt_math.h", "ipt_internal.h", "guide_dev.h", "disney.h", "api.hip")] + \
+                  ("trace.hip", "ipt_math.h", "ipt_internal.h", "guide_dev.h", "disney.h", "api.hip",
+                   "bvh_gpu.hip")] + \
                  ["paper_1903_07145_amd/build.py"]
 
 

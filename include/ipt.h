@@ -135,7 +135,7 @@ typedef struct {
 } ipt_scene_info_t;
 
 /* Where the BVH is built.  Both builders apply the same rule (binned SAH,
- * 32 slabs per axis, C_trav = C_isect = 1, leaves of at most 4 triangles)
+ * 32 slabs per axis, C_trav = C_isect = 1, leaves of at most 2 triangles)
  * and give the same tree; the host builder is kept as a reference. */
 typedef enum { IPT_BVH_GPU = 0, IPT_BVH_HOST = 1 } ipt_bvh_builder;
 /* Where the path kernels keep the parameter vector (M S + 3 E floats) and
@@ -157,7 +157,7 @@ typedef struct {
 } ipt_build_opts;
 
 /* Build a scene: upload geometry, build the BVH on the GPU (binned SAH,
- * leaves of at most 4 triangles), the leaf-ordered triangle layout and the
+ * leaves of at most 2 triangles), the leaf-ordered triangle layout and the
  * emitter table, all on hip_stream (the call synchronises it).
  * Inputs are HOST arrays: verts [nv][3], normals [nv][3] or NULL (flat
  * shading), tris [nt][3] vertex indices, tri_seg [nt] segment ids in

@@ -1,6 +1,6 @@
 // Binned SAH BVH build on the host (Wald, "On fast construction of SAH-based
 // bounding volume hierarchies", 2007): 32 bins per axis, C_trav = C_isect =
-// 1, leaves of at most 4 triangles.  The result is written in the layout
+// 1, leaves of at most 2 triangles.  The result is written in the layout
 // the traversal kernels read: depth-first "child pair" nodes (both child
 // boxes and both child references in one 64-byte record) and leaf-ordered
 // triangles.
@@ -40,7 +40,7 @@ struct BNode {
 };
 
 constexpr int kBins = 32;
-constexpr int kMaxLeaf = 4;
+constexpr int kMaxLeaf = 2;   // the GPU builder's leaf size
 
 // Slab of a centroid coordinate, clamped into [0, kBins - 1].
 inline int slab(float c, float lo, float k) {

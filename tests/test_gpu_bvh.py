@@ -13,6 +13,8 @@ from paper_1903_07145_amd import ipt, scenes
 
 pytestmark = pytest.mark.gpu
 
+LEAF_MAX = 2   # triangles per leaf at most (both builders)
+
 
 def _soup(n, seed):
     v, f = scenes.random_soup(n, seed=seed)
@@ -37,7 +39,9 @@ def _coincident(n, seed):
 
 CASES = {
     "one triangle": lambda: _soup(1, 1),
-    "four triangles (root leaf)": lambda: _soup(4, 2),
+    "two triangles (root leaf)": lambda: _soup(2, 8),
+    "three triangles": lambda: _soup(3, 9),
+    "four triangles": lambda: _soup(4, 2),
     "five triangles": lambda: _soup(5, 3),
     "cornell (36)": lambda: scenes.scene_arrays(scenes.cornell()),
     "soup 1024 (one block)": lambda: _soup(1024, 4),
@@ -80,9 +84,9 @@ def test_gpu_build_matches_host_builder_and_brute_force(case):
     else:
         # median cuts depend on the order inside a node, which the builders
         # keep differently; the tree still covers all triangles with leaves
-        # of at most four: at least L = ceil(nt / 4) leaves, so at least L - 1
-        # binary nodes, or ceil((L - 1) / 3) nodes of four children
-        leaves = (nt + 3) // 4
+        # of at most LEAF_MAX: at least L = ceil(nt / LEAF_MAX) leaves, so at
+        # least L - 1 binary nodes, or ceil((L - 1) / 3) nodes of four children
+        leaves = (nt + LEAF_MAX - 1) // LEAF_MAX
         lower = (leaves - 1 + 2) // 3 if ig["node_width"] == 4 else leaves - 1
         assert ig["num_nodes"] >= lower
         assert ig["sah_cost"] <= 1.5 * ih["sah_cost"]
