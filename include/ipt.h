@@ -135,7 +135,7 @@ typedef struct {
 } ipt_scene_info_t;
 
 /* Where the BVH is built.  Both builders apply the same rule (binned SAH,
- * 32 slabs per axis, C_trav = C_isect = 1, leaves of at most 2 triangles)
+ * 64 slabs per axis, C_trav = C_isect = 1, leaves of at most 2 triangles)
  * and give the same tree; the host builder is kept as a reference. */
 typedef enum { IPT_BVH_GPU = 0, IPT_BVH_HOST = 1 } ipt_bvh_builder;
 /* Where the path kernels keep the parameter vector (M S + 3 E floats) and

@@ -75,10 +75,12 @@ struct ipt_scene_s {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
 };
 
-// 4-wide nodes (default): every other level of the binary tree is folded
-// into its parent, so a node holds up to four children -- its grandchildren
-// where a child is an inner node, the child itself where it is a leaf -- with
-// the binary tree's (padded) child boxes.  Layout per node, 8 float4 =
+// 4-wide nodes (default): a node starts from a binary node's two children
+// and, while it has fewer than four, replaces its inner child of largest
+// surface area by that child's two children (the greedy collapse of wide
+// BVHs); leaves stay leaves, and the boxes are the binary tree's (padded)
+// child boxes.  Against folding exactly every other level, the apartment's
+// rays visit 15.0 instead of 16.2 nodes.  Layout per node, 8 float4 =
 // 128 B: lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of the four children, then the
 // four child references (inner node index, leaf code, or kNone), then
 // padding.  Children of a node are stored contiguously, depth first.
@@ -194,19 +196,33 @@ static hipError_t collapse_bvh4(float4*& d_nodes, int64_t& nnodes, hipStream_t s
     while (!stack.empty()) {
         const int id = stack.back();
         stack.pop_back();
+        // the binary node's children, then, while a slot is free, the inner
+        // child of largest surface area is replaced by its own children
         Ch c2[2], g[4];
         children(rec_of[id], c2);
         int m = 0;
-        for (int k = 0; k < 2; ++k) {
-            if (c2[k].ref == kNone) continue;
-            if (c2[k].ref >= 0) {
-                Ch gc[2];
-                children(c2[k].ref, gc);
-                for (int j = 0; j < 2; ++j)
-                    if (gc[j].ref != kNone) g[m++] = gc[j];
-            } else {
-                g[m++] = c2[k];
+        for (int k = 0; k < 2; ++k)
+            if (c2[k].ref != kNone) g[m++] = c2[k];
+        while (m < 4) {
+            int open = -1;
+            double best_area = -1.0;
+            for (int j = 0; j < m; ++j) {
+                if (g[j].ref < 0) continue;
+                const double dx = (double)g[j].hi[0] - g[j].lo[0], dy = (double)g[j].hi[1] - g[j].lo[1],
+                             dz = (double)g[j].hi[2] - g[j].lo[2];
+                const double area = dx * dy + dy * dz + dz * dx;
+                if (area > best_area) { best_area = area; open = j; }
             }
+            if (open < 0) break;
+            Ch gc[2];
+            children(g[open].ref, gc);
+            int k = 0;
+            for (int j = 0; j < 2; ++j) {
+                if (gc[j].ref == kNone) continue;
+                if (k++ == 0) g[open] = gc[j];
+                else g[m++] = gc[j];
+            }
+            if (k == 0) g[open] = g[--m];   // a record without children
         }
         int ref[4] = {kNone, kNone, kNone, kNone};
         std::vector<int> inner;

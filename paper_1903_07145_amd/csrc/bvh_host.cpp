@@ -1,5 +1,5 @@
 // Binned SAH BVH build on the host (Wald, "On fast construction of SAH-based
-// bounding volume hierarchies", 2007): 32 bins per axis, C_trav = C_isect =
+// bounding volume hierarchies", 2007): 64 bins per axis, C_trav = C_isect =
 // 1, leaves of at most 2 triangles.  The result is written in the layout
 // the traversal kernels read: depth-first "child pair" nodes (both child
 // boxes and both child references in one 64-byte record) and leaf-ordered
@@ -39,7 +39,7 @@ struct BNode {
     int first, count;   // primitive range in `idx` for a leaf
 };
 
-constexpr int kBins = 32;
+constexpr int kBins = 64;   // the GPU builder's slab count
 constexpr int kMaxLeaf = 2;   // the GPU builder's leaf size
 
 // Slab of a centroid coordinate, clamped into [0, kBins - 1].
