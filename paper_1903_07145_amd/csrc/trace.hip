@@ -210,10 +210,14 @@ __device__ __forceinline__ void trav_init(Trav& tv, float tmax, Stack& st, Work&
 
 // The node phase ends early once no more than this many lanes of the wave
 // are still looking for their first leaf (0: it runs until none is).
-// Apartment step: 166.7 ms at 0; 159.0 / 157.8 / 157.3 / 157.1 / 158.0 /
-// 169.9 / 204.3 ms at 2 / 3 / 4 / 6 / 8 / 16 / 32.
+// Apartment step with binary nodes: 166.7 ms at 0; 159.0 / 157.8 / 157.3 /
+// 157.1 / 158.0 / 169.9 / 204.3 ms at 2 / 3 / 4 / 6 / 8 / 16 / 32.  With
+// quantized four-child nodes and two-triangle leaves, whose leaf phase is
+// cheaper (testing the held leaves sooner also shortens the rays' best
+// distance): 125.9 / 123.2 / 122.4 ms at 2 / 4 / 8 in one run, and
+// 123.8 / 123.0 / 124.8 / 129.7 / 141.1 ms at 4 / 8 / 12 / 16 / 24 in another.
 #ifndef IPT_NODE_BREAK
-#define IPT_NODE_BREAK 4
+#define IPT_NODE_BREAK 8
 #endif
 
 
