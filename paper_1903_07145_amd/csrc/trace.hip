@@ -191,6 +191,16 @@ __device__ __forceinline__ void load_tri(const SceneDev& sc, int i, V3& p0, V3& 
 
 constexpr int kTravDone = (int)0x80000000;   // no node left (leaf codes are > INT_MIN)
 
+// Bytes 0 and 2 (or 1 and 3) of a quantized plane row, zero-extended into the
+// two 16-bit halves of a register: each half, read as fp16, is the subnormal
+// q 2^-24 (kernels keep fp16 denormals, the default fp16/fp64 denormal mode;
+// the BVH tests compare the hits with brute force bit for bit).
+typedef _Float16 h2x __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2x bytes02(uint32_t w) { return __builtin_bit_cast(h2x, w & 0x00ff00ffu); }
+__device__ __forceinline__ h2x bytes13(uint32_t w) {
+    return __builtin_bit_cast(h2x, __builtin_amdgcn_perm(w, w, 0x0c030c01u));
+}
+
 // Traversal state of one lane, kept across calls when a call returns early.
 struct Trav {
     int cur;        // next node: inner (>= 0), leaf code (< 0) or kTravDone
@@ -259,7 +269,10 @@ __device__ bool traverse_resume(const SceneDev& sc, const Ray& r, float tmin, fl
                 if constexpr (kNodeQuant) {
                     // quantized child boxes: a plane is origin + q 2^e, so its
                     // slab distance is fma(q, 2^e / d, (origin - o) / d); the
-                    // direction's sign picks each axis's near and far byte rows
+                    // direction's sign picks each axis's near and far byte rows.
+                    // The byte enters the fma as an fp16 operand of the
+                    // mixed-precision fma (one instruction per plane instead of
+                    // a conversion and an fma; the same value bit for bit)
                     const float4* n = sc.nodes + 4 * (size_t)cur;
                     const float4 h = n[0], qa = n[1], qb = n[2], cr = n[3];
                     c[0] = __float_as_int(cr.x); c[1] = __float_as_int(cr.y);
@@ -268,9 +281,12 @@ __device__ bool traverse_resume(const SceneDev& sc, const Ray& r, float tmin, fl
                     // to this point so their load issues with the box rows
                     __asm__ volatile("" :: "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
                     const uint32_t ew = __float_as_uint(h.w);
-                    const V3 A = v3(ldexpf(r.inv.x, (int)(ew & 0xffu) - 127),
-                                    ldexpf(r.inv.y, (int)((ew >> 8) & 0xffu) - 127),
-                                    ldexpf(r.inv.z, (int)((ew >> 16) & 0xffu) - 127));
+                    // A carries an extra 2^24: a byte q, widened to 16 bits, is
+                    // read as the fp16 subnormal q 2^-24, so the mixed-precision
+                    // fma forms q 2^e / d + B exactly, with no conversion
+                    const V3 A = v3(ldexpf(r.inv.x, (int)(ew & 0xffu) - 103),
+                                    ldexpf(r.inv.y, (int)((ew >> 8) & 0xffu) - 103),
+                                    ldexpf(r.inv.z, (int)((ew >> 16) & 0xffu) - 103));
                     const V3 B = v3((h.x - r.o.x) * r.inv.x, (h.y - r.o.y) * r.inv.y, (h.z - r.o.z) * r.inv.z);
                     const uint32_t xl = __float_as_uint(qa.x), xh = __float_as_uint(qa.y);
                     const uint32_t yl = __float_as_uint(qa.z), yh = __float_as_uint(qa.w);
@@ -279,15 +295,19 @@ __device__ bool traverse_resume(const SceneDev& sc, const Ray& r, float tmin, fl
                     const uint32_t yn = negy ? yh : yl, yf = negy ? yl : yh;
                     const uint32_t zn = negz ? zh : zl, zf = negz ? zl : zh;
                     const float tmx = best.t + sc.tmin;
+                    // 16-bit lanes of children 0 and 2, and of children 1 and 3
+                    const h2x e02[6] = {bytes02(xn), bytes02(xf), bytes02(yn), bytes02(yf), bytes02(zn), bytes02(zf)};
+                    const h2x e13[6] = {bytes13(xn), bytes13(xf), bytes13(yn), bytes13(yf), bytes13(zn), bytes13(zf)};
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int sh = 8 * i;
-                        const float nx = fmaf((float)((xn >> sh) & 0xffu), A.x, B.x);
-                        const float fx = fmaf((float)((xf >> sh) & 0xffu), A.x, B.x);
-                        const float ny = fmaf((float)((yn >> sh) & 0xffu), A.y, B.y);
-                        const float fy = fmaf((float)((yf >> sh) & 0xffu), A.y, B.y);
-                        const float nz = fmaf((float)((zn >> sh) & 0xffu), A.z, B.z);
-                        const float fz = fmaf((float)((zf >> sh) & 0xffu), A.z, B.z);
+                        const h2x* e = (i & 1) ? e13 : e02;
+                        const int hi = i >> 1;
+                        const float nx = fmaf((float)(hi ? e[0].y : e[0].x), A.x, B.x);
+                        const float fx = fmaf((float)(hi ? e[1].y : e[1].x), A.x, B.x);
+                        const float ny = fmaf((float)(hi ? e[2].y : e[2].x), A.y, B.y);
+                        const float fy = fmaf((float)(hi ? e[3].y : e[3].x), A.y, B.y);
+                        const float nz = fmaf((float)(hi ? e[4].y : e[4].x), A.z, B.z);
+                        const float fz = fmaf((float)(hi ? e[5].y : e[5].x), A.z, B.z);
                         const float tn = fmaxf(fmaxf(nx, ny), fmaxf(nz, tmin));
                         const float tf = fminf(fminf(fx, fy), fminf(fz, tmx));
                         t[i] = tn <= tf * 1.0000005f ? tn : inf;
