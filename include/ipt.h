@@ -165,7 +165,8 @@ typedef struct {
  * triangles of an emitter segment emit; every segment reflects.
  * Sec. 4.2 (per-vertex normals, per-object constant parameters).
  * Errors: IPT_ERR_INVALID_ARG (NULL/size), IPT_ERR_BAD_SCENE (index out of
- * range, non-finite vertex, degenerate emitter triangle, duplicate emitter),
+ * range, non-finite vertex or one with a coordinate beyond 1e12 in
+ * magnitude, degenerate emitter triangle, duplicate emitter),
  * IPT_ERR_NOT_SUPPORTED (more than 2^27 triangles, or a BVH deeper than the
  * traversal stack), IPT_ERR_OUT_OF_MEMORY / IPT_ERR_HIP (device). */
 ipt_status ipt_scene_build(const float *verts, int64_t nv, const float *normals,

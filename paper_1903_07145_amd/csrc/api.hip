@@ -334,8 +334,14 @@ extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const f
     if (num_segments < 1) return fail(IPT_ERR_INVALID_ARG, "num_segments < 1");
     if (num_emitters < 0 || (num_emitters > 0 && !emitter_seg))
         return fail(IPT_ERR_INVALID_ARG, "bad emitter list");
-    for (int64_t i = 0; i < 3 * nv; ++i)
+    // coordinates up to 1e12 in magnitude: the quantized node planes scale
+    // 1/d (at most 1e20) by 2^(e + 24) with cells 2^e of up to 2^33, which
+    // then stays finite
+    for (int64_t i = 0; i < 3 * nv; ++i) {
         if (!std::isfinite(verts[i])) return fail(IPT_ERR_BAD_SCENE, "vertex %lld is not finite", (long long)(i / 3));
+        if (std::fabs(verts[i]) > 1e12f)
+            return fail(IPT_ERR_BAD_SCENE, "vertex %lld has a coordinate beyond 1e12", (long long)(i / 3));
+    }
     if (normals)
         for (int64_t i = 0; i < nv; ++i) {
             float x = normals[3 * i], y = normals[3 * i + 1], z = normals[3 * i + 2];

@@ -13,9 +13,9 @@
 //  * a node of more than 1024 triangles ("large") is split one tree level at
 //    a time by passes spread over blocks of 1024 triangles: bin counts and
 //    bounds are formed in LDS and merged with global atomics, one wave costs
-//    the 189 candidate planes (one lane per axis), the partition is stable (per-chunk left counts,
-//    prefix-summed on the host) and the child bounds are reduced from the
-//    partitioned triangles;
+//    the 189 candidate planes (one lane per axis), the partition is stable
+//    (per-chunk left counts, prefix-summed on the host) and the child bounds
+//    are reduced from the partitioned triangles;
 //  * a node of at most 1024 triangles is finished by one block: its triangle
 //    ids stay in LDS while the block walks the subtree, continuing with the
 //    smaller child and pushing the larger one; the node held at least

@@ -55,6 +55,9 @@ def test_scene_build_validation(ipt):
     s = np.zeros(1, np.int32)
     st = L.ipt_scene_build(p(v2), 3, None, p(t), p(s), 1, 1, p(e), 0, None, ctypes.byref(h))
     assert st == 2 and b"finite" in L.ipt_last_error()
+    v2[0, 0] = -2e12                        # beyond the coordinate range
+    st = L.ipt_scene_build(p(v2), 3, None, p(t), p(s), 1, 1, p(e), 0, None, ctypes.byref(h))
+    assert st == 2 and b"beyond 1e12" in L.ipt_last_error()
     e2 = np.array([0, 0], np.int32)         # duplicate emitter
     st = L.ipt_scene_build(p(v), 3, None, p(t), p(s), 1, 1, p(e2), 2, None, ctypes.byref(h))
     assert st == 2
