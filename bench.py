@@ -59,7 +59,7 @@ def log(msg):
 # to the profiled version
 KERNEL_SOURCES = ["paper_1903_07145_amd/csrc/" + f for f in
                   ("trace.hip", "ipt_math.h", "ipt_internal.h", "guide_dev.h", "disney.h", "api.hip",
-                   "bvh_gpu.hip")] + \
+                   "bvh_gpu.hip", "bvh_wide.cpp")] + \
                  ["paper_1903_07145_amd/build.py"]
 
 

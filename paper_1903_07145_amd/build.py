@@ -7,7 +7,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libipt.so")
-SOURCES = ["api.hip", "trace.hip", "aux.hip", "guide.hip", "bvh_gpu.hip", "bvh_host.cpp"]
+SOURCES = ["api.hip", "trace.hip", "aux.hip", "guide.hip", "bvh_gpu.hip", "bvh_host.cpp", "bvh_wide.cpp"]
 ARCH = os.environ.get("IPT_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # no packed-FP32 instructions in device code

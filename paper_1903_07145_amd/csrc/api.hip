@@ -17,6 +17,7 @@
 #include "../../include/ipt.h"
 #include "bvh_gpu.h"
 #include "bvh_host.h"
+#include "bvh_wide.h"
 #include "ipt_internal.h"
 
 using namespace ipt;
@@ -75,187 +76,21 @@ struct ipt_scene_s {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
 };
 
-// 4-wide nodes (default): a node starts from a binary node's two children
-// and, while it has fewer than four, replaces its inner child of largest
-// surface area by that child's two children (the greedy collapse of wide
-// BVHs); leaves stay leaves, and the boxes are the binary tree's (padded)
-// child boxes.  Against folding exactly every other level, the apartment's
-// rays visit 15.0 instead of 16.2 nodes.  Layout per node, 8 float4 =
-// 128 B: lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of the four children, then the
-// four child references (inner node index, leaf code, or kNone), then
-// padding.  Children of a node are stored contiguously, depth first.
-static int bits_i(float f) { int i; std::memcpy(&i, &f, sizeof i); return i; }
-static float bits_f(int i) { float f; std::memcpy(&f, &i, sizeof f); return f; }
-
-// Quantized 4-wide nodes (after Ylitie, Karras and Laine 2017, "Efficient
-// incoherent ray traversal on GPUs through compressed wide BVHs"): the
-// four child boxes as 8-bit grid coordinates relative to a per-node origin,
-// with a power-of-two cell size per axis.  Layout per node, 4 float4 = 64 B:
-//   row 0: origin x, y, z (float); biased exponents e_x, e_y, e_z (bytes 0-2)
-//   row 1: x lo, x hi, y lo, y hi of the four children (one byte per child)
-//   row 2: z lo, z hi, 0, 0
-//   row 3: the four child references (as the float layout)
-// A plane decodes to origin + q 2^e.  Every decoded box contains its child's
-// float box widened by delta = 2^-20 of the node's largest extent on every
-// side: that margin covers the rounding of the traversal's
-// fma(q, 2^e / d, (origin - o) / d) for ray origins within or near the node,
-// and the slab test's relative slack covers origins far from it.  An empty
-// slot has q lo = 255, q hi = 0 (a box inside out, which the slab test
-// rejects unless the ray starts some 10^6 node extents away) and, as its
-// reference, the leaf code of the one-triangle leaf holding triangle 0
-// (~0): should the slack ever admit the slot, the traversal tests a real
-// triangle once more, which changes no hit, instead of following an
-// invalid reference.  The traversal then needs no reference check.
-static void quantize_bvh4(std::vector<float4>& b4) {
-    const size_t n = b4.size() / 8;
-    std::vector<float4> q(4 * n);
-    for (size_t id = 0; id < n; ++id) {
-        const float4* o = &b4[8 * id];
-        const float lo[3][4] = {{o[0].x, o[0].y, o[0].z, o[0].w}, {o[2].x, o[2].y, o[2].z, o[2].w},
-                                {o[4].x, o[4].y, o[4].z, o[4].w}};
-        const float hi[3][4] = {{o[1].x, o[1].y, o[1].z, o[1].w}, {o[3].x, o[3].y, o[3].z, o[3].w},
-                                {o[5].x, o[5].y, o[5].z, o[5].w}};
-        const int ref[4] = {bits_i(o[6].x), bits_i(o[6].y), bits_i(o[6].z), bits_i(o[6].w)};
-        bool valid[4];
-        double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int j = 0; j < 4; ++j) {
-            valid[j] = ref[j] != kNone;
-            if (!valid[j]) continue;
-            for (int a = 0; a < 3; ++a) {
-                mn[a] = std::min(mn[a], (double)lo[a][j]);
-                mx[a] = std::max(mx[a], (double)hi[a][j]);
-            }
-        }
-        float org[3] = {0, 0, 0};
-        int ex[3] = {0, 0, 0};
-        uint8_t ql[3][4], qh[3][4];
-        double ext = 0.0;
-        for (int a = 0; a < 3; ++a)
-            if (mx[a] >= mn[a]) ext = std::max(ext, mx[a] - mn[a]);
-        // a node of points (extent 0) still gets a positive margin
-        const double delta = std::ldexp(std::max(ext, 1e-30), -20);
-        for (int a = 0; a < 3; ++a) {
-            for (int j = 0; j < 4; ++j) { ql[a][j] = 255; qh[a][j] = 0; }
-            if (!(mx[a] >= mn[a])) continue;   // no valid child
-            // origin: a float at or below the lowest plane minus the margin
-            float og = (float)(mn[a] - delta);
-            while ((double)og > mn[a] - delta) og = std::nextafter(og, -INFINITY);
-            org[a] = og;
-            const double span = mx[a] + delta - (double)og;
-            int e = (int)std::ceil(std::log2(span / 255.0));
-            e = std::max(e, -126);
-            for (;; ++e) {
-                const double cell = std::ldexp(1.0, e);
-                bool ok = true;
-                for (int j = 0; j < 4 && ok; ++j) {
-                    if (!valid[j]) continue;
-                    double l = std::floor((lo[a][j] - delta - (double)og) / cell);
-                    double h = std::ceil((hi[a][j] + delta - (double)og) / cell);
-                    // the decoded planes (exact: og + q 2^e in double) enclose the widened box
-                    while (l > 0 && (double)og + l * cell > lo[a][j] - delta) l -= 1.0;
-                    while ((double)og + h * cell < hi[a][j] + delta) h += 1.0;
-                    if (l < 0 || h > 255) { ok = false; break; }
-                    ql[a][j] = (uint8_t)l;
-                    qh[a][j] = (uint8_t)h;
-                }
-                if (ok) break;
-            }
-            ex[a] = e;
-        }
-        auto pack = [](const uint8_t b[4]) {
-            return bits_f((int)((uint32_t)b[0] | (uint32_t)b[1] << 8 | (uint32_t)b[2] << 16 | (uint32_t)b[3] << 24));
-        };
-        const uint32_t ew = (uint32_t)(ex[0] + 127) | (uint32_t)(ex[1] + 127) << 8 | (uint32_t)(ex[2] + 127) << 16;
-        float4* d = &q[4 * id];
-        d[0] = make_float4(org[0], org[1], org[2], bits_f((int)ew));
-        d[1] = make_float4(pack(ql[0]), pack(qh[0]), pack(ql[1]), pack(qh[1]));
-        d[2] = make_float4(pack(ql[2]), pack(qh[2]), 0.0f, 0.0f);
-        int rq[4];
-        for (int j = 0; j < 4; ++j) rq[j] = valid[j] ? ref[j] : ~0;
-        d[3] = make_float4(bits_f(rq[0]), bits_f(rq[1]), bits_f(rq[2]), bits_f(rq[3]));
-    }
-    b4.swap(q);
-}
-
-static hipError_t collapse_bvh4(float4*& d_nodes, int64_t& nnodes, hipStream_t st) {
-    std::vector<float4> b2(4 * (size_t)nnodes);
-    hipError_t e = hipMemcpyAsync(b2.data(), d_nodes, sizeof(float4) * b2.size(), hipMemcpyDeviceToHost, st);
+// Four-child nodes (default): the binary tree's child-pair records are
+// collapsed and quantized on the host (bvh_wide.cpp) and uploaded in place of
+// the binary ones; *levels receives the number of node levels.
+static hipError_t collapse_bvh4(float4*& d_nodes, int64_t& nnodes, int* levels, hipStream_t st) {
+    static_assert(kWideNone == kNone, "empty child slot marker");
+    std::vector<float> pairs(16 * (size_t)nnodes);
+    hipError_t e = hipMemcpyAsync(pairs.data(), d_nodes, sizeof(float) * pairs.size(), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return e;
-    struct Ch { float lo[3], hi[3]; int ref; };
-    auto children = [&](int r, Ch out[2]) {
-        const float4* n = &b2[4 * (size_t)r];
-        out[0] = Ch{{n[0].x, n[0].y, n[0].z}, {n[0].w, n[1].x, n[1].y}, bits_i(n[3].x)};
-        out[1] = Ch{{n[1].z, n[1].w, n[2].x}, {n[2].y, n[2].z, n[2].w}, bits_i(n[3].y)};
-    };
-    std::vector<int> rec_of{0};        // 4-wide node id -> binary record
-    std::vector<float4> b4;
-    b4.reserve(8 * (size_t)nnodes);
-    std::vector<int> stack{0};         // 4-wide node ids to write
-    b4.resize(8);
-    while (!stack.empty()) {
-        const int id = stack.back();
-        stack.pop_back();
-        // the binary node's children, then, while a slot is free, the inner
-        // child of largest surface area is replaced by its own children
-        Ch c2[2], g[4];
-        children(rec_of[id], c2);
-        int m = 0;
-        for (int k = 0; k < 2; ++k)
-            if (c2[k].ref != kNone) g[m++] = c2[k];
-        while (m < 4) {
-            int open = -1;
-            double best_area = -1.0;
-            for (int j = 0; j < m; ++j) {
-                if (g[j].ref < 0) continue;
-                const double dx = (double)g[j].hi[0] - g[j].lo[0], dy = (double)g[j].hi[1] - g[j].lo[1],
-                             dz = (double)g[j].hi[2] - g[j].lo[2];
-                const double area = dx * dy + dy * dz + dz * dx;
-                if (area > best_area) { best_area = area; open = j; }
-            }
-            if (open < 0) break;
-            Ch gc[2];
-            children(g[open].ref, gc);
-            int k = 0;
-            for (int j = 0; j < 2; ++j) {
-                if (gc[j].ref == kNone) continue;
-                if (k++ == 0) g[open] = gc[j];
-                else g[m++] = gc[j];
-            }
-            if (k == 0) g[open] = g[--m];   // a record without children
-        }
-        int ref[4] = {kNone, kNone, kNone, kNone};
-        std::vector<int> inner;
-        for (int j = 0; j < m; ++j) {
-            if (g[j].ref >= 0) {
-                ref[j] = (int)rec_of.size();
-                rec_of.push_back(g[j].ref);
-                b4.resize(b4.size() + 8);
-                inner.push_back(ref[j]);
-            } else {
-                ref[j] = g[j].ref;
-            }
-        }
-        for (size_t k = inner.size(); k-- > 0;) stack.push_back(inner[k]);
-        // an empty slot gets lo = hi = +inf on every axis: the slab test
-        // gives it an entry distance of +inf (never entered)
-        const float inf = std::numeric_limits<float>::infinity();
-        float v[6][4];
-        for (int j = 0; j < 4; ++j)
-            for (int a = 0; a < 3; ++a) {
-                v[2 * a][j] = j < m ? g[j].lo[a] : inf;
-                v[2 * a + 1][j] = j < m ? g[j].hi[a] : inf;
-            }
-        float4* o = &b4[8 * (size_t)id];
-        for (int row = 0; row < 6; ++row) o[row] = make_float4(v[row][0], v[row][1], v[row][2], v[row][3]);
-        o[6] = make_float4(bits_f(ref[0]), bits_f(ref[1]), bits_f(ref[2]),
-                           bits_f(ref[3]));
-        o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-    if (kNodeQuant) quantize_bvh4(b4);
+    std::vector<float> wide;
+    const int64_t n4 = collapse_wide(pairs, wide, levels);
+    if (kNodeQuant) quantize_wide(wide);
     float4* d4 = nullptr;
-    e = hipMalloc((void**)&d4, sizeof(float4) * b4.size());
-    if (e == hipSuccess) e = hipMemcpyAsync(d4, b4.data(), sizeof(float4) * b4.size(), hipMemcpyHostToDevice, st);
+    e = hipMalloc((void**)&d4, sizeof(float) * wide.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(d4, wide.data(), sizeof(float) * wide.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         hipFree(d4);
@@ -263,7 +98,7 @@ static hipError_t collapse_bvh4(float4*& d_nodes, int64_t& nnodes, hipStream_t s
     }
     hipFree(d_nodes);
     d_nodes = d4;
-    nnodes = (int64_t)rec_of.size();
+    nnodes = n4;
     return hipSuccess;
 }
 
@@ -463,18 +298,20 @@ extern "C" ipt_status ipt_scene_build_ex(const float* verts, int64_t nv, const f
         sah = bvh.sah_cost;
         nnodes = bvh.num_nodes;
     }
+    int levels = depth;   // node levels of the traversal's tree
     if (kNodeWidth == 4) {
-        e = collapse_bvh4(s->d_nodes, nnodes, st);
+        e = collapse_bvh4(s->d_nodes, nnodes, &levels, st);
         if (e != hipSuccess) {
             ipt_scene_free(s);
             return fail(IPT_ERR_HIP, "BVH layout: %s", hipGetErrorString(e));
         }
     }
     auto t1 = std::chrono::steady_clock::now();
-    // a node pushes at most width - 1 entries
-    if ((kNodeWidth == 4 ? 3 * ((depth + 1) / 2) : depth) > kShortStack + kOvfDepth) {
+    // a node pushes at most width - 1 entries, so the stack holds at most
+    // that many per level of the path to the current node
+    if ((kNodeWidth - 1) * levels > kShortStack + kOvfDepth) {
         ipt_scene_free(s);
-        return fail(IPT_ERR_NOT_SUPPORTED, "BVH depth %d exceeds the traversal stack", depth);
+        return fail(IPT_ERR_NOT_SUPPORTED, "BVH of %d node levels exceeds the traversal stack", levels);
     }
 
     // leaf-ordered triangle records, shading normals, inverse permutation, light table

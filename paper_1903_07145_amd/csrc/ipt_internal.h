@@ -12,8 +12,9 @@ constexpr int kBlock = 256;       // threads per block of the path kernels
 constexpr int kShortStack = 16;   // per-lane LDS stack entries (power of two)
 constexpr int kOvfDepth = 48;     // per-lane global overflow entries
 constexpr int kNone = 0x7FFFFFFF; // empty child slot
-// BVH node width of the traversal: 4 (binary levels folded pairwise into
-// 128 B nodes) or 2 (the binary tree's 64 B child-pair nodes)
+// BVH node width of the traversal: 4 (the binary tree collapsed into
+// four-child nodes on the host, bvh_wide.cpp) or 2 (the binary tree's 64 B
+// child-pair nodes)
 #ifndef IPT_NODE_WIDTH
 #define IPT_NODE_WIDTH 4
 #endif
