@@ -120,7 +120,7 @@ typedef struct {
     int64_t num_triangles, num_vertices, num_nodes, num_light_triangles;
     int32_t num_segments, num_emitters, bvh_depth, has_normals;
                               /* bvh_depth: levels of the binary SAH tree (the
-                                 four-child tree of the traversal has 55-60% as many) */
+                                 four-child tree of the traversal has about 60% as many or fewer) */
     double sah_cost;          /* SAH cost of the BVH (C_trav = C_isect = 1) */
     double build_ms;          /* wall time of the BVH build */
     float scene_diag;
