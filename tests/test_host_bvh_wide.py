@@ -14,7 +14,9 @@ Cornell box and the 50k-triangle room:
 * every quantized child box (origin + q 2^e, decoded exactly) contains the
   float child box widened by 2^-20 of the node's largest extent; empty slots
   hold an inside-out box (q lo 255, q hi 0) and the reference ~0;
-* the reported number of node levels is the tree's depth."""
+* the reported number of node levels is the tree's depth;
+* the node visit's float32 slab test, emulated, admits every ancestor box of
+  a hit (a build without the margin fails it)."""
 import ctypes
 import os
 import shutil
@@ -183,3 +185,100 @@ def test_collapse_and_quantization(harness, case):
     for row, want in zip(range(6), (255, 0, 255, 0, 255, 0)):
         assert (qb[:, row][~valid] == want).all()
     assert (qrefs[~valid] == -1).all() and np.array_equal(qrefs[valid], refs[valid])
+
+
+def _f32(x):
+    return np.float32(x)
+
+
+@pytest.mark.parametrize("case,nrays", [("soup 20000", 1500), ("room (50k)", 1500)])
+def test_quantized_boxes_admit_every_hit_in_float32(harness, case, nrays):
+    """The node visit's float32 slab test, emulated on the CPU (planes as
+    q 2^-24 times 1/d scaled by 2^(e+24), plus (origin - o)/d; one rounding
+    per plane; the relative slack 1.0000005), admits every ancestor box of a
+    triangle for a ray that reaches that triangle, with the ray's far limit
+    at that hit (the tightest the traversal uses): from origins anywhere in
+    and around the scene and from points on other triangles (continuation
+    rays, with the scene's tmin).  This is what makes the quantized tree
+    conservative; 1/d is perturbed by up to 2 ulp, more than the hardware
+    reciprocal's error."""
+    verts, tris = CASES[case]()
+    verts = np.asarray(verts, np.float32)
+    tris = np.asarray(tris, np.int32)
+    qnodes, order, _ = _build(harness, verts, tris, 1)
+    fnodes, _, _ = _build(harness, verts, tris, 0)
+    _, _, refs = _float_layout(fnodes)
+    # parent links: (node, slot) of every inner node and of every leaf position
+    parent = {}
+    leaf_of = {}
+    for n in range(refs.shape[0]):
+        for j in range(4):
+            r = int(refs[n, j])
+            if r == NONE:
+                continue
+            if r >= 0:
+                parent[r] = (n, j)
+            else:
+                code = ~r
+                for pos in range(code >> 3, (code >> 3) + (code & 7) + 1):
+                    leaf_of[pos] = (n, j)
+    pos_of_tri = np.empty(tris.shape[0], np.int64)
+    pos_of_tri[order] = np.arange(tris.shape[0])
+    org = qnodes[:, 0:3]
+    ew = qnodes[:, 3].view(np.uint32)
+    qrows = qnodes[:, 4:10].view(np.uint32)
+    lo_s, hi_s = verts.min(axis=0).astype(np.float64), verts.max(axis=0).astype(np.float64)
+    diag = float(np.linalg.norm(hi_s - lo_s))
+    tmin = _f32(1e-6 * diag)
+    rng = np.random.default_rng(17)
+
+    def admits(n, j, o, inv, tmx):
+        ns, fs = [], []
+        for a in range(3):
+            e = int((ew[n] >> (8 * a)) & 0xFF) - 127
+            A = np.ldexp(np.float64(inv[a]), e)                   # exact: 1/d times 2^e
+            B = _f32(_f32(org[n, a] - o[a]) * inv[a])
+            ql = float((qrows[n, 2 * a] >> (8 * j)) & 0xFF)
+            qh = float((qrows[n, 2 * a + 1] >> (8 * j)) & 0xFF)
+            tl, th = _f32(ql * A + np.float64(B)), _f32(qh * A + np.float64(B))
+            near, far = (th, tl) if inv[a] < 0 else (tl, th)
+            ns.append(near)
+            fs.append(far)
+        tn = max(max(ns[0], ns[1]), max(ns[2], tmin))
+        tf = min(min(fs[0], fs[1]), min(fs[2], tmx))
+        return tn <= _f32(tf * _f32(1.0000005))
+
+    bad = 0
+    for i in range(nrays):
+        t_id = int(rng.integers(tris.shape[0]))
+        b = rng.dirichlet([1.0, 1.0, 1.0])
+        P = (b[:, None] * verts[tris[t_id]].astype(np.float64)).sum(axis=0)
+        if i % 2 == 0:   # an origin in or around the scene
+            O = rng.uniform(lo_s - 0.1 * (hi_s - lo_s), hi_s + 0.1 * (hi_s - lo_s))
+        else:            # a continuation ray from another triangle's surface
+            s_id = int(rng.integers(tris.shape[0]))
+            b2 = rng.dirichlet([1.0, 1.0, 1.0])
+            O = (b2[:, None] * verts[tris[s_id]].astype(np.float64)).sum(axis=0)
+        d = P - O
+        dist = float(np.linalg.norm(d))
+        if dist < 1e-3 * diag:
+            continue
+        d = (d / dist).astype(np.float32)
+        o = O.astype(np.float32)
+        inv = np.empty(3, np.float32)
+        for a in range(3):
+            da = d[a] if abs(d[a]) > 1e-20 else np.float32(np.copysign(1e-20, d[a]))
+            x = _f32(np.float32(1.0) / da)
+            inv[a] = np.nextafter(np.nextafter(x, np.float32(np.inf if rng.random() < 0.5 else -np.inf)),
+                                  np.float32(np.inf if rng.random() < 0.5 else -np.inf)) if rng.random() < 0.7 else x
+        # the far limit the traversal uses once this hit is the best: t + tmin
+        tmx = _f32(_f32(dist) + tmin)
+        n, j = leaf_of[int(pos_of_tri[t_id])]
+        while True:
+            if not admits(n, j, o, inv, tmx):
+                bad += 1
+                break
+            if n == 0:
+                break
+            n, j = parent[n]
+    assert bad == 0, bad
