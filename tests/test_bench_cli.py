@@ -21,3 +21,19 @@ def test_several_ranks_are_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_committed_counters_match_the_sources():
+    """The committed counter summaries were taken at the current kernel and
+    BVH-builder sources, so the bench line carries measured VALU work and HBM
+    traffic; after a change to those sources the profiles must be taken again
+    (until then the bench reports them as null)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    for workload in ("apartment", "apartment_disney"):
+        for kernel in ("colour", "grad_forward", "adjoint_replay"):
+            c = bench.measured_counters(kernel, workload)
+            assert {"valu_insts_per_launch", "lane_util", "hbm_bytes_per_launch"} <= set(c), (
+                "profiles/ holds no counters of %s (%s) for kernel sources %s" % (
+                    kernel, workload, bench.kernel_source_hash()))
+            assert 0.0 < c["lane_util"] <= 1.0 and c["valu_insts_per_launch"] > 0 and c["hbm_bytes_per_launch"] > 0
