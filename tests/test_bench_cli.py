@@ -30,7 +30,7 @@ def test_committed_counters_match_the_sources():
     (until then the bench reports them as null)."""
     sys.path.insert(0, ROOT)
     import bench
-    for workload in ("apartment", "apartment_disney"):
+    for workload in ("apartment", "apartment_disney", "office_floor"):
         for kernel in ("colour", "grad_forward", "adjoint_replay"):
             c = bench.measured_counters(kernel, workload)
             assert {"valu_insts_per_launch", "lane_util", "hbm_bytes_per_launch"} <= set(c), (
