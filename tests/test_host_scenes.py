@@ -153,3 +153,49 @@ def test_subdivide_shares_midpoints_and_keeps_area():
             n = np.cross(v[f[c, 1]] - v[f[c, 0]], v[f[c, 2]] - v[f[c, 0]])
             assert np.dot(n, n0) > 0 and np.linalg.norm(np.cross(n, n0)) < 1e-9 * np.linalg.norm(n0) ** 2
     assert abs(area.sum() - area0.sum()) < 1e-9
+
+
+def test_workload_recipes():
+    """The synthetic workloads have the sizes the benchmarks are quoted on:
+    apartment (about 500k triangles, 128 segments, 8 emitters, 16 views of
+    640x480, 8 spp, depth 7, roulette from depth 3) and office floor (about
+    2M triangles, 256 segments, 16 emitters, 30 views, 64 spp, depth 8); the
+    parameter vector is 7 S + 3 E with the emission after the materials."""
+    for make, tri, S, E, V, spp, D in ((scenes.apartment, 500000, 128, 8, 16, 8, 7),
+                                       (scenes.office_floor, 2000000, 256, 16, 30, 64, 8)):
+        sc = make()
+        nt = sc["tris"].shape[0]
+        assert abs(nt - tri) <= 0.01 * tri, nt
+        assert sc["num_segments"] == S and len(sc["emitter_seg"]) == E
+        assert np.asarray(sc["cams"]["cam_to_world"]).reshape(-1, 4, 4).shape[0] == V
+        assert (sc["cams"]["width"], sc["cams"]["height"]) == (640, 480)
+        r = sc["render"]
+        assert (r["spp"], r["max_depth"], r["rr_depth"]) == (spp, D, 3)
+        assert sc["params"].size == 7 * S + 3 * E
+        assert sc["tri_seg"].min() >= 0 and sc["tri_seg"].max() < S
+        assert np.isfinite(sc["verts"]).all() and sc["tris"].min() >= 0 and sc["tris"].max() < len(sc["verts"])
+        for k in ("scale", "lo", "hi", "trainable"):
+            assert sc[k].size == sc["params"].size, k
+        # bounds are on the normalised parameters (value / scale)
+        u = sc["params"] / sc["scale"]
+        assert ((u >= sc["lo"] - 1e-6) & (u <= sc["hi"] + 1e-6)).all()
+
+
+def test_disney_recipe():
+    """The Disney variant: 13 parameters per segment, the base colour taken
+    from the diffuse albedo, every material parameter in [0, 1] with its
+    stated distribution's range, emission unchanged after the materials."""
+    base = scenes.room()
+    sc = scenes.disney(base, seed=6)
+    S, E = sc["num_segments"], len(sc["emitter_seg"])
+    assert sc["material"] == 1 and sc["params"].size == 13 * S + 3 * E
+    d = sc["params"][:13 * S].reshape(S, 13)
+    p7 = base["params"][:7 * S].reshape(S, 7)
+    assert np.array_equal(d[:, 0:3], p7[:, 0:3])
+    assert np.array_equal(sc["params"][13 * S:], base["params"][7 * S:])
+    assert ((d >= 0) & (d <= 1)).all()
+    assert ((d[:, 7] >= 0.25) & (d[:, 7] <= 0.9)).all()        # roughness
+    assert (d[:, 8] <= 0.8).all() and (d[:, 12] <= 0.7).all()  # anisotropic, clearcoat gloss
+    assert ((d[:, 4] == 0) | (d[:, 4] >= 0.2)).all()            # metallic: 0 or U(0.2, 1)
+    assert (d[:, 4] == 0).any() and (d[:, 4] > 0).any() and (d[:, 11] == 0).any() and (d[:, 11] > 0).any()
+    assert (sc["trainable"][:13 * S] == 1).all() and (sc["scale"][:13 * S] == 1).all()
